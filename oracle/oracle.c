@@ -1,0 +1,476 @@
+/*
+ * oracle.c -- plain, slow, literal FP64 CPU oracle for the preconditioned
+ * Bi-CGSTAB Poisson solver of Pennati et al., "A Parallel and Highly-Portable
+ * HPC Poisson Solver: Preconditioned Bi-CGSTAB with alpaka" (arXiv 2503.08935).
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this file's library. The GPU library neither links
+ * nor calls it, and this file includes nothing from the GPU library.
+ *
+ * Conventions (shared by specification, not by code, with the GPU library):
+ *   - unknowns are the interior nodes of an nx*ny*nz grid with one spacing h,
+ *     stored x-fastest: idx = i + nx*(j + ny*k); zero Dirichlet boundary, so a
+ *     neighbour outside the grid reads as +0.0;
+ *   - no floating-point contraction (built with -ffp-contract=off, no fast-math);
+ *   - every dot product is the exact sum of the exact products, rounded once to
+ *     the nearest double (ties to even).
+ *
+ * What pins each function (tests/test_oracle_*.py):
+ *   orc_dot          exact rational arithmetic on random and adversarial vectors
+ *   orc_interval     dense eigenvalues of the Kronecker-sum matrix, n <= 8
+ *   orc_apply_A      discrete sine modes (closed-form eigenvalues), dense
+ *                    Kronecker assembly, exactness on tensor quadratics
+ *   orc_chebyshev    closed-form Chebyshev residual polynomial on sine modes,
+ *                    minimax spectral bound of A*M^-1 on dense matrices
+ *   orc_chebyshev_f32  the same closed forms to FP32 accuracy
+ *   orc_bicgstab     dense direct solves, finite termination on k eigenmodes,
+ *                    manufactured solution and its O(h^2) error, power-of-two
+ *                    Jacobi scaling identity
+ */
+#include <math.h>
+#include <omp.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_BREAKDOWN (-5)
+#define ORC_ERR_NONFINITE (-6)
+
+#define PC_NONE 0
+#define PC_JACOBI 1
+#define PC_CHEBYSHEV 2
+#define PC_BLOCK_JACOBI 3
+
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------- */
+/* Exact dot product.                                                         */
+/* A Kulisch-style long accumulator: value = sum_c cell[c] * 2^(32c - OFF).   */
+/* Each product x*y of doubles is formed exactly as a 106-bit integer times a */
+/* power of two and added digit by digit, so the sum is exact whatever the    */
+/* order, and it is rounded to double once at the end.                        */
+/* ------------------------------------------------------------------------- */
+#define ACC_OFF 2176   /* 2^-2176 < smallest product 2^-2148 */
+#define ACC_CELLS 140  /* top weight 2^(32*140-2176) = 2^2304 > largest sum */
+
+typedef struct {
+    int64_t c[ACC_CELLS];
+    int64_t nadd;
+    int nan, pinf, ninf;
+} acc_t;
+
+static void acc_init(acc_t *a) { memset(a, 0, sizeof(*a)); }
+
+/* carry-propagate so every cell but the top one lies in [0, 2^32) */
+static void acc_normalize(acc_t *a)
+{
+    int64_t carry = 0;
+    for (int c = 0; c < ACC_CELLS - 1; ++c) {
+        int64_t v = a->c[c] + carry;
+        int64_t low = v & 0xffffffffLL;
+        carry = (v - low) / 4294967296LL; /* exact: v - low is a multiple of 2^32 */
+        a->c[c] = low;
+    }
+    a->c[ACC_CELLS - 1] += carry;
+    a->nadd = 0;
+}
+
+/* split a finite double into sign, 53-bit integer significand and exponent */
+static void split_double(double v, int *neg, uint64_t *m, int *e)
+{
+    uint64_t bits;
+    memcpy(&bits, &v, 8);
+    *neg = (int)(bits >> 63);
+    int ef = (int)((bits >> 52) & 0x7ff);
+    uint64_t frac = bits & ((1ULL << 52) - 1);
+    if (ef == 0) { *m = frac; *e = -1074; }
+    else { *m = frac | (1ULL << 52); *e = ef - 1075; }
+}
+
+static void acc_add_product(acc_t *a, double x, double y)
+{
+    if (!isfinite(x) || !isfinite(y)) {
+        double p = x * y;
+        if (isnan(p)) a->nan = 1;
+        else if (p > 0) a->pinf = 1;
+        else if (p < 0) a->ninf = 1;
+        return;
+    }
+    if (x == 0.0 || y == 0.0) return;
+    int nx_, ny_, ex, ey;
+    uint64_t mx, my;
+    split_double(x, &nx_, &mx, &ex);
+    split_double(y, &ny_, &my, &ey);
+    unsigned __int128 M = (unsigned __int128)mx * (unsigned __int128)my;
+    int neg = nx_ ^ ny_;
+    int P = ex + ey + ACC_OFF; /* bit position of M's least significant bit */
+    int cell = P >> 5, sh = P & 31;
+    for (int q = 0; q < 4; ++q) {
+        uint64_t ch = (uint64_t)(M >> (32 * q)) & 0xffffffffULL;
+        if (!ch) continue;
+        uint64_t v = ch << sh; /* < 2^63 */
+        int64_t lo = (int64_t)(v & 0xffffffffULL), hi = (int64_t)(v >> 32);
+        if (neg) { a->c[cell + q] -= lo; a->c[cell + q + 1] -= hi; }
+        else { a->c[cell + q] += lo; a->c[cell + q + 1] += hi; }
+    }
+    /* each cell gains < 2^33 per product: normalise long before 2^63 */
+    if (++a->nadd >= (1LL << 28)) acc_normalize(a);
+}
+
+static void acc_merge(acc_t *dst, const acc_t *src)
+{
+    for (int c = 0; c < ACC_CELLS; ++c) dst->c[c] += src->c[c];
+    dst->nan |= src->nan; dst->pinf |= src->pinf; dst->ninf |= src->ninf;
+    acc_normalize(dst);
+}
+
+static int acc_bit(const acc_t *a, int b) { return (int)((a->c[b >> 5] >> (b & 31)) & 1); }
+
+/* round the exact accumulated value to the nearest double, ties to even */
+static double acc_round(acc_t *a)
+{
+    if (a->nan || (a->pinf && a->ninf)) return NAN;
+    if (a->pinf) return INFINITY;
+    if (a->ninf) return -INFINITY;
+    acc_normalize(a);
+    int neg = a->c[ACC_CELLS - 1] < 0;
+    if (neg) {
+        for (int c = 0; c < ACC_CELLS; ++c) a->c[c] = -a->c[c];
+        acc_normalize(a);
+    }
+    int top = -1;
+    for (int c = ACC_CELLS - 1; c >= 0; --c)
+        if (a->c[c]) { top = c; break; }
+    if (top < 0) return 0.0;
+    int T = 32 * top + 31;
+    while (!acc_bit(a, T)) --T;                   /* most significant set bit */
+    int lsb = T - 52;                               /* keep 53 bits ... */
+    if (lsb < ACC_OFF - 1074) lsb = ACC_OFF - 1074; /* ... or fewer if subnormal */
+    uint64_t mant = 0;
+    for (int b = T; b >= lsb; --b) mant = (mant << 1) | (uint64_t)acc_bit(a, b);
+    int rbit = lsb >= 1 ? acc_bit(a, lsb - 1) : 0;
+    int sticky = 0;
+    for (int b = lsb - 2; b >= 0 && !sticky; --b) {
+        if ((b & 31) == 31 && a->c[b >> 5] == 0) { b -= 31; continue; }
+        sticky = acc_bit(a, b);
+    }
+    if (rbit && (sticky || (mant & 1))) mant += 1;
+    double r = ldexp((double)mant, lsb - ACC_OFF);
+    return neg ? -r : r;
+}
+
+/* sum_i x_i*y_i, exact then rounded once; independent of thread count */
+double orc_dot(const double *x, const double *y, int64_t n)
+{
+    acc_t total;
+    acc_init(&total);
+#pragma omp parallel
+    {
+        acc_t a;
+        acc_init(&a);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) acc_add_product(&a, x[i], y[i]);
+        acc_normalize(&a);
+#pragma omp critical
+        acc_merge(&total, &a);
+    }
+    return acc_round(&total);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spectrum (Background section: eigenvalues of the Dirichlet matrix D,      */
+/* eq. eigenvaluesPoissonDirichletMatrix; Kronecker-sum eigenvalues,          */
+/* eqs. lambdaMin and lambdaMax).                                             */
+/* ------------------------------------------------------------------------- */
+/* i-th eigenvalue (i = 1..n) of D = tridiag(-1, 2, -1) of order n */
+double orc_dirichlet_eig(int i, int n)
+{
+    double s = sin((double)i * M_PI / (2.0 * (double)(n + 1)));
+    return 4.0 * s * s;
+}
+
+/* lambda_min / lambda_max of A = Kronecker sum of D_n/h^2 over the three axes;
+   block > 0 gives the spectrum of one block x block x block diagonal block
+   (each axis clipped to the grid extent), the local matrix R_s A R_s^T */
+void orc_interval(int nx, int ny, int nz, double h, int block, double *lmin, double *lmax)
+{
+    int n[3] = {nx, ny, nz};
+    if (block > 0)
+        for (int d = 0; d < 3; ++d) if (n[d] > block) n[d] = block;
+    double h2 = h * h;
+    *lmin = orc_dirichlet_eig(1, n[0]) / h2 + orc_dirichlet_eig(1, n[1]) / h2 +
+            orc_dirichlet_eig(1, n[2]) / h2;
+    *lmax = orc_dirichlet_eig(n[0], n[0]) / h2 + orc_dirichlet_eig(n[1], n[1]) / h2 +
+            orc_dirichlet_eig(n[2], n[2]) / h2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The operator (eq. matrix_p with O = D on every axis): for uniform spacing  */
+/* (A u)_ijk = (6 u_ijk - six neighbours) / h^2, neighbours outside the grid  */
+/* are zero. With block > 0 a neighbour in another block also reads as zero,  */
+/* which is the block-diagonal part R_s A R_s^T of eq. blockJacobiPreconditioner. */
+/* ------------------------------------------------------------------------- */
+#define IDX(i, j, k) ((size_t)(i) + (size_t)nx * ((size_t)(j) + (size_t)ny * (size_t)(k)))
+
+static int nb_ok(int a, int b, int n, int block)
+{
+    if (b < 0 || b >= n) return 0;
+    if (block > 0 && a / block != b / block) return 0;
+    return 1;
+}
+
+void orc_apply_A(int nx, int ny, int nz, double h, int block, const double *u, double *out)
+{
+    double ih2 = 1.0 / (h * h);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double c = u[IDX(i, j, k)];
+                double xm = nb_ok(i, i - 1, nx, block) ? u[IDX(i - 1, j, k)] : 0.0;
+                double xp = nb_ok(i, i + 1, nx, block) ? u[IDX(i + 1, j, k)] : 0.0;
+                double ym = nb_ok(j, j - 1, ny, block) ? u[IDX(i, j - 1, k)] : 0.0;
+                double yp = nb_ok(j, j + 1, ny, block) ? u[IDX(i, j + 1, k)] : 0.0;
+                double zm = nb_ok(k, k - 1, nz, block) ? u[IDX(i, j, k - 1)] : 0.0;
+                double zp = nb_ok(k, k + 1, nz, block) ? u[IDX(i, j, k + 1)] : 0.0;
+                out[IDX(i, j, k)] = (6.0 * c - xm - xp - ym - yp - zm - zp) * ih2;
+            }
+}
+
+/* the same operator on FP32 data in FP32 arithmetic (mixed-precision preconditioner) */
+static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, const float *u, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                float c = u[IDX(i, j, k)];
+                float xm = nb_ok(i, i - 1, nx, block) ? u[IDX(i - 1, j, k)] : 0.0f;
+                float xp = nb_ok(i, i + 1, nx, block) ? u[IDX(i + 1, j, k)] : 0.0f;
+                float ym = nb_ok(j, j - 1, ny, block) ? u[IDX(i, j - 1, k)] : 0.0f;
+                float yp = nb_ok(j, j + 1, ny, block) ? u[IDX(i, j + 1, k)] : 0.0f;
+                float zm = nb_ok(k, k - 1, nz, block) ? u[IDX(i, j, k - 1)] : 0.0f;
+                float zp = nb_ok(k, k + 1, nz, block) ? u[IDX(i, j, k + 1)] : 0.0f;
+                out[IDX(i, j, k)] = (6.0f * c - xm - xp - ym - yp - zm - zp) * ih2;
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chebyshev iteration (Alg. 2) for A x = b on the interval [lo, hi], with   */
+/* theta, delta, sigma of eq. chebyshevQuantities. The degree m is the       */
+/* number of iterations of the algorithm (iterMax): m = 0 returns z = b/theta */
+/* and m = 1 returns y; for m >= 2 the loop runs i = 2..m and returns w.      */
+/* block > 0 uses the block-diagonal operator (BJ(CI) / GNoComm(CI)).         */
+/* ------------------------------------------------------------------------- */
+void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
+                   const double *b, double *x)
+{
+    size_t N = (size_t)nx * ny * nz;
+    double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
+    double rho_old = 1.0 / sigma;
+    double rho_cur = 1.0 / (2.0 * sigma - rho_old);
+    if (m == 0) {
+        for (size_t q = 0; q < N; ++q) x[q] = b[q] / theta;
+        return;
+    }
+    double *z = malloc(N * 8), *y = malloc(N * 8), *w = malloc(N * 8), *Av = malloc(N * 8);
+    for (size_t q = 0; q < N; ++q) z[q] = b[q] / theta;
+    orc_apply_A(nx, ny, nz, h, block, b, Av);
+    for (size_t q = 0; q < N; ++q) y[q] = 2.0 * rho_cur / delta * (2.0 * b[q] - Av[q] / theta);
+    for (int i = 2; i <= m; ++i) {
+        rho_old = rho_cur;
+        rho_cur = 1.0 / (2.0 * sigma - rho_old);
+        orc_apply_A(nx, ny, nz, h, block, y, Av);
+        for (size_t q = 0; q < N; ++q)
+            w[q] = rho_cur * (2.0 * sigma * y[q] + 2.0 / delta * (b[q] - Av[q]) - rho_old * z[q]);
+        double *tmp = z; z = y; y = w; w = tmp; /* z <- y, y <- w */
+    }
+    memcpy(x, y, N * 8); /* after the last rotation y holds w */
+    free(z); free(y); free(w); free(Av);
+}
+
+/* Mixed precision: the same steps with every scalar coefficient computed in
+   FP64 and rounded once to FP32, the input rounded once to FP32, and all vector
+   arithmetic in FP32. The FP32 result is returned widened (exactly) to FP64. */
+void orc_chebyshev_f32(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
+                       const double *b, double *x)
+{
+    size_t N = (size_t)nx * ny * nz;
+    double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
+    double rho_old = 1.0 / sigma;
+    double rho_cur = 1.0 / (2.0 * sigma - rho_old);
+    float theta_f = (float)theta;
+    float ih2_f = (float)(1.0 / (h * h));
+    float *bf = malloc(N * 4);
+    for (size_t q = 0; q < N; ++q) bf[q] = (float)b[q];
+    if (m == 0) {
+        for (size_t q = 0; q < N; ++q) x[q] = (double)(bf[q] / theta_f);
+        free(bf);
+        return;
+    }
+    float *z = malloc(N * 4), *y = malloc(N * 4), *w = malloc(N * 4), *Av = malloc(N * 4);
+    for (size_t q = 0; q < N; ++q) z[q] = bf[q] / theta_f;
+    apply_A_f32(nx, ny, nz, ih2_f, block, bf, Av);
+    float c1 = (float)(2.0 * rho_cur / delta);
+    for (size_t q = 0; q < N; ++q) y[q] = c1 * (2.0f * bf[q] - Av[q] / theta_f);
+    float two_sigma = (float)(2.0 * sigma), two_over_delta = (float)(2.0 / delta);
+    for (int i = 2; i <= m; ++i) {
+        rho_old = rho_cur;
+        rho_cur = 1.0 / (2.0 * sigma - rho_old);
+        float rc = (float)rho_cur, ro = (float)rho_old;
+        apply_A_f32(nx, ny, nz, ih2_f, block, y, Av);
+        for (size_t q = 0; q < N; ++q)
+            w[q] = rc * (two_sigma * y[q] + two_over_delta * (bf[q] - Av[q]) - ro * z[q]);
+        float *tmp = z; z = y; y = w; w = tmp;
+    }
+    for (size_t q = 0; q < N; ++q) x[q] = (double)y[q];
+    free(bf); free(z); free(y); free(w); free(Av);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Preconditioner dispatch M^-1 v (Table 1 and Methodology section).          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int nx, ny, nz;
+    double h;
+    int precond, degree, mixed, block, bj_global;
+    double lmin_scale, lmax_scale, jacobi_diag;
+} pc_t;
+
+/* the eigenvalue interval handed to the Chebyshev iteration */
+void orc_cheb_interval(int nx, int ny, int nz, double h, int precond, int block, int bj_global,
+                       double lmin_scale, double lmax_scale, double *lo, double *hi)
+{
+    int local = (precond == PC_BLOCK_JACOBI && !bj_global) ? block : 0;
+    double a, b;
+    orc_interval(nx, ny, nz, h, local, &a, &b);
+    *lo = a * lmin_scale;
+    *hi = b * lmax_scale;
+}
+
+static void apply_pc(const pc_t *pc, const double *v, double *out)
+{
+    size_t N = (size_t)pc->nx * pc->ny * pc->nz;
+    if (pc->precond == PC_JACOBI) {
+        double d = pc->jacobi_diag > 0 ? pc->jacobi_diag : 6.0 * (1.0 / (pc->h * pc->h));
+        if (pc->mixed) {
+            float df = (float)d;
+            for (size_t q = 0; q < N; ++q) out[q] = (double)((float)v[q] / df);
+        } else {
+            for (size_t q = 0; q < N; ++q) out[q] = v[q] / d;
+        }
+        return;
+    }
+    double lo, hi;
+    orc_cheb_interval(pc->nx, pc->ny, pc->nz, pc->h, pc->precond, pc->block, pc->bj_global,
+                      pc->lmin_scale, pc->lmax_scale, &lo, &hi);
+    int blk = pc->precond == PC_BLOCK_JACOBI ? pc->block : 0;
+    if (pc->mixed)
+        orc_chebyshev_f32(pc->nx, pc->ny, pc->nz, pc->h, blk, lo, hi, pc->degree, v, out);
+    else
+        orc_chebyshev(pc->nx, pc->ny, pc->nz, pc->h, blk, lo, hi, pc->degree, v, out);
+}
+
+/* one preconditioner application, exported for kernel-level parity tests */
+void orc_precond(int nx, int ny, int nz, double h, int precond, int degree, int mixed, int block,
+                 int bj_global, double lmin_scale, double lmax_scale, const double *v, double *out)
+{
+    pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global, lmin_scale, lmax_scale, 0.0};
+    if (precond == PC_NONE) {
+        memcpy(out, v, (size_t)nx * ny * nz * 8);
+        return;
+    }
+    apply_pc(&pc, v, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Right-preconditioned Bi-CGSTAB, Alg. 1, with the scalar formulas of Alg. 3 */
+/* (beta = (rho_i alpha_i)/(rho_{i-1} omega_i)). The stopping test          */
+/* ||r|| < tol ||b|| is evaluated on squares: r.r < (tol*tol)*(b.b).          */
+/* trace (optional, 4*maxit doubles): per iteration alpha, omega, rho_{i-1},  */
+/* and the squared residual norm tested at exit of that iteration.            */
+/* ------------------------------------------------------------------------- */
+int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, int precond,
+                 int degree, int mixed, double tol, int maxit, double lmin_scale,
+                 double lmax_scale, int block, int bj_global, double jacobi_diag, double *trace,
+                 double *rr0_out, int *iters, int *half)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || maxit < 1) return ORC_ERR_ARG;
+    size_t N = (size_t)nx * ny * nz;
+    pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global,
+               lmin_scale, lmax_scale, jacobi_diag};
+    *iters = 0;
+    *half = 0;
+    double *r = malloc(N * 8), *rt = malloc(N * 8), *p = malloc(N * 8), *w = malloc(N * 8),
+           *t = malloc(N * 8), *ph = malloc(N * 8), *sh = malloc(N * 8);
+    int status = ORC_NOT_CONVERGED;
+
+    /* r0 = b - A x0, r~ = r0, p0 = r0, rho0 = r~.r0 */
+    orc_apply_A(nx, ny, nz, h, 0, x, w);
+    for (size_t q = 0; q < N; ++q) r[q] = b[q] - w[q];
+    memcpy(rt, r, N * 8);
+    memcpy(p, r, N * 8);
+    double bb = orc_dot(b, b, (int64_t)N);
+    double tol2bb = (tol * tol) * bb;
+    double rho = orc_dot(rt, r, (int64_t)N);
+    double rr = orc_dot(r, r, (int64_t)N);
+    if (rr0_out) *rr0_out = rr;
+    if (!isfinite(bb) || !isfinite(rr)) { status = ORC_ERR_NONFINITE; goto out; }
+    if (bb == 0.0) { memset(x, 0, N * 8); status = ORC_OK; goto out; }
+    if (rr < tol2bb) { status = ORC_OK; goto out; }
+
+    for (int i = 1; i <= maxit; ++i) {
+        *iters = i;
+        /* solve M p^ = p */
+        const double *php = p;
+        if (precond != PC_NONE) { apply_pc(&pc, p, ph); php = ph; }
+        /* w = A p^, alpha = rho / (r~ . w) */
+        orc_apply_A(nx, ny, nz, h, 0, php, w);
+        double d = orc_dot(rt, w, (int64_t)N);
+        if (!isfinite(d)) { status = ORC_ERR_NONFINITE; goto out; }
+        if (d == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
+        double alpha = rho / d;
+        /* s = r - alpha w, kept in r */
+        for (size_t q = 0; q < N; ++q) r[q] = r[q] - alpha * w[q];
+        double ss = orc_dot(r, r, (int64_t)N);
+        if (trace) { trace[4 * (i - 1)] = alpha; trace[4 * (i - 1) + 2] = rho; }
+        if (!isfinite(ss)) { status = ORC_ERR_NONFINITE; goto out; }
+        if (ss < tol2bb) { /* half-step exit of Alg. 1 */
+            for (size_t q = 0; q < N; ++q) x[q] = x[q] + alpha * php[q];
+            if (trace) { trace[4 * (i - 1) + 1] = 0.0; trace[4 * (i - 1) + 3] = ss; }
+            *half = 1;
+            status = ORC_OK;
+            goto out;
+        }
+        /* solve M s^ = s, t = A s^, omega = (t.s)/(t.t) */
+        const double *shp = r;
+        if (precond != PC_NONE) { apply_pc(&pc, r, sh); shp = sh; }
+        orc_apply_A(nx, ny, nz, h, 0, shp, t);
+        double ts = orc_dot(t, r, (int64_t)N);
+        double tt = orc_dot(t, t, (int64_t)N);
+        if (!isfinite(ts) || !isfinite(tt)) { status = ORC_ERR_NONFINITE; goto out; }
+        if (tt == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
+        double omega = ts / tt;
+        /* x = x + alpha p^ + omega s^, r = s - omega t */
+        for (size_t q = 0; q < N; ++q) x[q] = x[q] + alpha * php[q] + omega * shp[q];
+        for (size_t q = 0; q < N; ++q) r[q] = r[q] - omega * t[q];
+        double rho_new = orc_dot(rt, r, (int64_t)N);
+        rr = orc_dot(r, r, (int64_t)N);
+        if (trace) { trace[4 * (i - 1) + 1] = omega; trace[4 * (i - 1) + 3] = rr; }
+        if (!isfinite(rho_new) || !isfinite(rr)) { status = ORC_ERR_NONFINITE; goto out; }
+        if (rr < tol2bb) { status = ORC_OK; goto out; }
+        if (rho_new == 0.0 || omega == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
+        double beta = (rho_new * alpha) / (rho * omega);
+        /* p = r + beta (p - omega w) */
+        for (size_t q = 0; q < N; ++q) p[q] = r[q] + beta * (p[q] - omega * w[q]);
+        rho = rho_new;
+    }
+    status = ORC_NOT_CONVERGED;
+out:
+    free(r); free(rt); free(p); free(w); free(t); free(ph); free(sh);
+    return status;
+}
