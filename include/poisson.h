@@ -1,0 +1,198 @@
+/*
+ * poisson.h -- C ABI of the MI355X (gfx950) preconditioned Bi-CGSTAB solver for
+ * the 3D Poisson equation, after Pennati et al., "A Parallel and Highly-Portable
+ * HPC Poisson Solver: Preconditioned Bi-CGSTAB with alpaka" (arXiv 2503.08935).
+ *
+ * Problem (Background section, eq. poisson and eq. matrix_p): -lap(u) = f on
+ * the interior nodes of an nx x ny x nz grid with spacing h, second-order
+ * central differences (matrix D of eq. matrix_dirichlet on every axis), zero
+ * Dirichlet boundary. The matrix is never formed: A u is a 7-point stencil,
+ *   (A u)_ijk = (6 u_ijk - u_{i-1} - u_{i+1} - u_{j-1} - u_{j+1} - u_{k-1} - u_{k+1}) / h^2,
+ * with neighbours outside the grid equal to zero.
+ *
+ * Layout of every vector argument: contiguous, x fastest,
+ *   idx = i + nx * (j + ny * k),  0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
+ * grid node (i, j, k) sits at ((i+1) h, (j+1) h, (k+1) h).
+ *
+ * Conventions for every call:
+ *   - the return value is a status code: 0 = OK, > 0 informational, < 0 error;
+ *   - out-parameters are written only on success; a failed create sets *out = NULL;
+ *   - no C++ exception crosses this boundary (an internal failure returns
+ *     POISSON_ERR_INTERNAL);
+ *   - device pointers are HIP device (or managed) allocations owned by the
+ *     caller, 16-byte aligned; they must stay valid and unmodified until the
+ *     call that uses them has returned (solve) or reported a final status (poll);
+ *   - a context or server is not thread-safe; distinct objects are independent.
+ */
+#ifndef POISSON_H
+#define POISSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    POISSON_OK = 0,
+    POISSON_NOT_CONVERGED = 1,   /* maxit reached; x holds the last iterate */
+    POISSON_PENDING = 2,         /* serving: request still queued or running */
+    POISSON_ERR_ARG = -1,        /* invalid argument; nothing was touched */
+    POISSON_ERR_NOMEM = -2,      /* device allocation failed / over budget */
+    POISSON_ERR_DEVICE = -3,     /* a HIP call failed (no GPU, bad pointer, ...) */
+    POISSON_ERR_UNSUPPORTED = -4,/* valid but not implemented (e.g. bc != 0) */
+    POISSON_ERR_BREAKDOWN = -5,  /* r~.A p^ = 0, t.t = 0, r~.r = 0 or omega = 0 */
+    POISSON_ERR_NONFINITE = -6,  /* a NaN or Inf reached a reduction */
+    POISSON_ERR_INTERNAL = -7
+};
+
+/* ---- preconditioners (Table 1 of the paper) ---------------------------- */
+enum {
+    POISSON_PC_NONE = 0,         /* plain Bi-CGSTAB (BiCGS) */
+    POISSON_PC_JACOBI = 1,       /* point Jacobi, M^-1 = diag(A)^-1 = (h^2/6) I */
+    POISSON_PC_CHEBYSHEV = 2,    /* G(CI): Chebyshev iteration (Alg. 2) of degree m on
+                                    the whole grid, interval [lambda_min, lambda_max] of
+                                    eqs. lambdaMin / lambdaMax */
+    POISSON_PC_BLOCK_JACOBI = 3  /* BJ(CI): Chebyshev of degree m on each non-overlapping
+                                    block x block x block sub-grid, neighbours across block
+                                    faces read as zero (eqs. blockJacobiPreconditioner and
+                                    systemBJpreconditioner), interval of one block; with
+                                    POISSON_OPT_BJ_GLOBAL_INTERVAL = 1 the global interval,
+                                    which is GNoComm(CI) */
+};
+
+/* ---- precision --------------------------------------------------------- */
+enum {
+    POISSON_FP64 = 0,            /* everything in FP64 */
+    POISSON_MIXED = 1            /* FP64 outer Bi-CGSTAB; the preconditioner is applied in
+                                    FP32: its input is rounded to FP32 once, its scalar
+                                    coefficients (computed in FP64) are rounded to FP32
+                                    once, all its arithmetic is FP32, and its output p^ / s^
+                                    is stored in FP32 and widened exactly where FP64 uses it */
+};
+
+/* ---- options (poisson_set_option keys) ---------------------------------- */
+enum {
+    POISSON_OPT_PRECISION = 1,          /* POISSON_FP64 (default) or POISSON_MIXED */
+    POISSON_OPT_BLOCK = 2,              /* Block-Jacobi block edge, >= 2 (default 64) */
+    POISSON_OPT_LMIN_SCALE = 3,         /* lambda_min multiplier (default 1); the paper
+                                           uses 100 (256^3) and 10 (64^3) */
+    POISSON_OPT_LMAX_SCALE = 4,         /* lambda_max multiplier (default 1); paper: 1 - 1e-4 */
+    POISSON_OPT_BJ_GLOBAL_INTERVAL = 5, /* 0 = BJ(CI) local interval (default), 1 = GNoComm(CI) */
+    POISSON_OPT_GRAPH_ITERS = 6,        /* iterations per captured HIP graph / per host poll
+                                           (default 8, 1..256) */
+    POISSON_OPT_USE_GRAPH = 7,          /* 1 = replay captured HIP graphs (default), 0 = launch */
+    POISSON_OPT_DEBUG_BREAKDOWN_AT = 8  /* testing: force omega = 0 at this iteration (-1 off) */
+};
+
+/* ---- solver context ----------------------------------------------------- */
+typedef struct poisson_ctx poisson_ctx;
+
+/* Create a context for an nx x ny x nz interior grid with spacing h.
+   bc: bit f (x-, x+, y-, y+, z-, z+) set = Neumann on face f; only 0 (zero
+   Dirichlet on every face) is supported, other values give ERR_UNSUPPORTED.
+   Host-only: no device memory is touched until the first solve. Errors:
+   ERR_ARG if a size < 1, nx*ny*nz > 2^34, h not finite and > 0, or out == NULL. */
+int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **out);
+
+/* Set an option (keys above). ERR_ARG for an unknown key or an out-of-range value. */
+int poisson_set_option(poisson_ctx *c, int key, double value);
+
+/* Stream used by every later call on this context (a hipStream_t; NULL = the
+   null stream). The caller keeps the stream alive. */
+int poisson_set_stream(poisson_ctx *c, void *hip_stream);
+
+/* Solve A x = rhs with right-preconditioned Bi-CGSTAB (Alg. 1 of the paper; the
+   scalar formulas and kernel order of Alg. 3).
+   rhs, x : device FP64 vectors of nx*ny*nz entries; x holds the initial guess
+            on entry and the solution (or the last iterate) on return.
+   precond: POISSON_PC_*; degree: Chebyshev degree m = number of operator
+            applications per preconditioner apply (0..64; ignored for NONE/JACOBI).
+   tol    : relative tolerance in (0, 1); the stopping test is ||r||_2 < tol ||rhs||_2,
+            evaluated as r.r < (tol*tol) (rhs.rhs) on the recursively updated r, both at
+            the half step (s) and at the end of each iteration.
+   maxit  : iteration limit >= 1.
+   Synchronous on the context stream. Returns OK, NOT_CONVERGED, ERR_BREAKDOWN or
+   ERR_NONFINITE (x = last iterate, stats valid), or ERR_ARG / ERR_NOMEM /
+   ERR_DEVICE / ERR_UNSUPPORTED (nothing solved). rhs = 0 gives x = 0 and 0 iterations. */
+int poisson_solve(poisson_ctx *c, const double *rhs, double *x, int precond, int degree,
+                  double tol, int maxit);
+
+typedef struct {
+    size_t struct_size;         /* set by the caller to sizeof(poisson_stats_t) */
+    int status;                 /* status of the last solve */
+    int iterations;             /* index i of the exit iteration (a half-step exit counts i) */
+    int half_step_exit;         /* 1 if the solve stopped on s (Alg. 1 half step) */
+    int precond, degree, precision;
+    double relres_recursive;    /* sqrt(r.r / rhs.rhs) of the recursive residual at exit */
+    double relres_true;         /* ||rhs - A x|| / ||rhs||, recomputed in FP64 after the solve */
+    double lambda_min, lambda_max; /* interval given to the Chebyshev iteration */
+    double solve_ms;            /* host wall time of poisson_solve */
+    double loop_ms;             /* device time of the iteration loop (HIP events) */
+    double model_bytes;         /* algorithmic HBM bytes of the iteration loop */
+    double model_gbps;          /* model_bytes / loop_ms */
+    int history_len;            /* number of entries of history (iterations + 1) */
+    const double *history;      /* relative residual norm, [0] initial, [i] after iteration i;
+                                   owned by the context, valid until the next solve/destroy */
+} poisson_stats_t;
+
+/* Statistics of the last solve. ERR_ARG if nothing was solved yet or
+   out->struct_size < sizeof(poisson_stats_t). */
+int poisson_stats(const poisson_ctx *c, poisson_stats_t *out);
+
+/* Per-iteration scalars of the last solve, 4 doubles per iteration:
+   alpha_i, omega_i (0 at a half-step exit), rho_{i-1}, and the squared residual
+   norm tested at the exit of iteration i. Copies min(cap, iterations) rows to out
+   (host memory) and returns the number of rows copied (>= 0) or an error. */
+int poisson_trace(const poisson_ctx *c, double *out, int cap);
+
+/* Release everything the context owns. NULL-safe. */
+void poisson_destroy(poisson_ctx *c);
+
+/* Static description of a status code. */
+const char *poisson_strerror(int code);
+
+/* ---- single operations (asynchronous on the context stream unless noted) --- */
+
+/* out = A u with the grid operator of the context (u, out: device FP64). */
+int poisson_apply_operator(poisson_ctx *c, const double *u, double *out);
+
+/* out = M^-1 v, one preconditioner apply as used inside the solve, in the
+   precision set by POISSON_OPT_PRECISION: out is FP64 (POISSON_FP64) or FP32
+   (POISSON_MIXED). precond != NONE. v: device FP64. */
+int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double *v, void *out);
+
+/* *result = x . y over nx*ny*nz entries (device FP64), computed with the same
+   double-double tile reduction as the solver. Synchronous. */
+int poisson_dot(poisson_ctx *c, const double *x, const double *y, double *result);
+
+/* Kernel identifiers for poisson_kernel_bench. */
+enum {
+    POISSON_KERNEL_CHEB_STEP = 0,       /* one interior Chebyshev step (Alg. 2 loop body) */
+    POISSON_KERNEL_STENCIL_DOT = 1,     /* w = A p^ fused with r~.w */
+    POISSON_KERNEL_UPDATE_XR = 2        /* x and r updates fused with r~.r, r.r */
+};
+
+/* Launch one kernel `reps` times back to back on the context stream over the
+   workspace of the last solve (its values are overwritten), for timing with
+   events on that stream. precision selects the FP64 or FP32 variant.
+   Requires a previous successful poisson_solve with a plan that has the buffers
+   (Chebyshev degree >= 3 for CHEB_STEP). Asynchronous. */
+int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps);
+
+/* Algorithmic HBM bytes of one launch of that kernel on this grid. */
+double poisson_kernel_bytes(const poisson_ctx *c, int kernel, int precision);
+
+/* ---- synthetic inputs ---------------------------------------------------- */
+
+/* out[i] = 2 u_i - 1, u_i = (splitmix64(splitmix64(seed + G) + (i + 1) G) >> 11) 2^-53,
+   G = 0x9E3779B97F4A7C15, i = 0..n-1 (Steele, Lea and Flood, OOPSLA 2014). The
+   same bits as the host generator of the test-suite. Asynchronous on stream. */
+int poisson_fill_uniform(void *hip_stream, double *out, int64_t n, uint64_t seed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POISSON_H */

@@ -1,0 +1,107 @@
+// Internal types shared by the kernels and the host engine of libpoisson.
+//
+// A solve (or a batch of solves, for serving) is described to the kernels by
+// an array of Prob descriptors in device memory plus a tile list. Every kernel
+// walks tiles of TX x TY columns by kz planes; each tile belongs to one
+// problem. Reductions are per problem and deterministic: every tile writes a
+// double-double partial into its own slot and the last tile of the problem to
+// finish (atomic ticket) sums the slots in index order and updates that
+// problem's scalars. A problem's arithmetic therefore depends only on the
+// problem itself, never on which other problems share the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pz {
+
+constexpr int TX = 64;          // x extent of a tile = one wave64 row
+constexpr int TY = 4;           // y extent = waves per workgroup
+constexpr int NTHREADS = TX * TY;
+constexpr int MAXDEG = 64;      // largest Chebyshev degree
+constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double sums
+
+// vector slots of a problem
+enum Vec {
+    V_X = 0, V_B, V_R, V_RT, V_P, V_W, V_T, V_PH, V_SH, V_RA, V_RB, V_V32, V_COUNT
+};
+
+// status codes mirrored from poisson.h
+enum {
+    ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = -5, ST_NONFINITE = -6
+};
+
+// Per-problem scalar block (device). Written only by the last tile of a
+// reduction kernel, read by every tile at the start of later kernels.
+struct Scalars {
+    double rho, alpha, omega, beta;
+    double bb, tol2bb, rr, ss;
+    double rr_true, dot, pad_d[2];
+    int iter, done, status, half_pending;
+    int half, zero_x, pad_i[2];
+    unsigned ticket, pad_u[3];
+};
+
+struct Prob {
+    int nx, ny, nz, kz;          // grid and tile z-chunk
+    int tx, ty, tz, ntiles;      // tile counts
+    int block;                   // Block-Jacobi block edge (masked operator), 0 = none
+    int maxit, debug_breakdown_at, degree;
+    int hist_iters, pad_i[3];    // iterations recorded in hist
+    double ih2;                  // 1/(h*h)
+    double tol2;                 // tol*tol
+    double jac_d;                // diagonal of A = 6*ih2
+    double theta, c1, two_sigma, two_over_delta;
+    float ih2f, jac_df, thetaf, c1f, two_sigmaf, two_over_deltaf, padf[2];
+    double rc[MAXDEG + 1], ro[MAXDEG + 1];   // rho_cur, rho_old of Chebyshev step i
+    float rcf[MAXDEG + 1], rof[MAXDEG + 1];
+    void *vec[V_COUNT];
+    Scalars *sc;
+    double *partials;            // ntiles * PARTIAL_STRIDE
+    double *hist;                // 1 + 4*hist_iters, or null
+};
+
+// Tile work list of one launch.
+struct Work {
+    const Prob *probs;
+    const int *tile_prob;        // null: single problem 0, tile t is local tile t
+    const int *tile_local;
+    const int *count_dev;        // null: use count
+    int count;
+};
+
+// operations of the stencil kernel family
+enum SOp {
+    S_APPLY = 0,  // out = A u
+    S_CHEB1,      // y = c1 (2 v - A v / theta)                      (first Chebyshev step)
+    S_CHEB2,      // w = rc ((2 sigma y + (2/delta)(v - A y)) - ro v/theta)   (step 2)
+    S_CHEBK,      // w = rc ((2 sigma y + (2/delta)(v - A y)) - ro z)         (steps >= 3)
+    S_SDOT,       // w = A p^, dot r~.w -> alpha
+    S_SDOT2,      // t = A s^, dots t.s, t.t -> omega
+    S_INIT,       // r = b - A x0; r~ = p = r; dots r.r, b.b
+    S_TRUE        // dot (b - A x).(b - A x)
+};
+
+// operations of the elementwise kernel family
+enum EOp {
+    E_AXPY = 0,   // s = r - alpha w (in place), dot s.s -> half-step test
+    E_UPD,        // x = (x + alpha p^) + omega s^, r = s - omega t, dots r~.r, r.r -> beta
+    E_PUPD,       // p = r + beta (p - omega w)
+    E_DIV,        // out = v / d  (point Jacobi, or Chebyshev degree 0 with d = theta)
+    E_DOT         // dot x.y
+};
+
+struct KArgs {
+    int in, out, v, z;           // vector slots
+    int step;                    // Chebyshev step index (S_CHEB2 / S_CHEBK)
+    int second;                  // 1: belongs to the second half of the iteration
+    int divisor;                 // E_DIV: 0 = jac_d, 1 = theta
+    int x2;                      // E_DOT second operand slot / E_UPD s^ slot
+};
+
+// host-side launchers (device.hip)
+void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                    const KArgs &a);
+void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a);
+void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
+
+} // namespace pz

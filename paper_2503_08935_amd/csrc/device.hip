@@ -1,0 +1,629 @@
+// device.hip -- gfx950 kernels of the preconditioned Bi-CGSTAB Poisson solver.
+//
+// Two kernel families walk the same tiles (TX x TY columns, kz planes):
+//   k_stencil : z-marching 7-point stencil (the matrix-free operator of
+//               eq. matrix_p) fused with the consumer of A u: a Chebyshev step
+//               (Alg. 2), an outer Bi-CGSTAB matvec with its dot products
+//               (Alg. 3: KernelBiCGS1, KernelBiCGS3), the initial residual, or
+//               the true residual.
+//   k_elem    : streaming vector updates fused with their dot products
+//               (Alg. 3: KernelBiCGS2, KernelBiCGS4+5, KernelBiCGS6) and the
+//               point-Jacobi / degree-0 scaling.
+// Each thread owns one (i, j) column of its tile and marches k upward keeping
+// u(k-1), u(k), u(k+1) in registers; x and y neighbours come through the
+// caches (the wave's own row and the adjacent waves' rows).
+//
+// Arithmetic contract (matched by the independent CPU oracle):
+//   * no contraction (built with -ffp-contract=off); the only FMA is the
+//     explicit error-free product of the dot products;
+//   * (A u) = ((((((6u - u_x-) - u_x+) - u_y-) - u_y+) - u_z-) - u_z+) * (1/(h*h));
+//   * vector updates evaluate left to right exactly as written in Alg. 1 / 2;
+//   * dot products: per thread Dot2 (TwoProduct + TwoSum, Ogita, Rump and
+//     Oishi 2005), then double-double additions (AccurateDWPlusDW, Joldes,
+//     Muller and Popescu 2017) in a fixed tree, rounded once. The result equals
+//     the correctly rounded dot product except when the exact value lies within
+//     about 1e-30 (relative, times the condition number) of a rounding tie.
+//   * scalar divisions are IEEE FP64 divisions.
+#include "common.h"
+
+namespace pz {
+
+// ------------------------------------------------------------------------
+// XCD-aware tile order: workgroup g runs on XCD g % 8 (round-robin dispatch);
+// give every XCD one contiguous range of tiles so neighbouring tiles, which
+// share halo rows and planes, meet in the same L2.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int remap_xcd(int g, int total)
+{
+    const int q = total >> 3, rem = total & 7;
+    const int x = g & 7, j = g >> 3;
+    return x * q + min(x, rem) + j;
+}
+
+// ------------------------------------------------------------------------
+// double-double arithmetic
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void fast_two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    e = b - (s - a);
+}
+
+// (hi, lo) += x * y
+__device__ __forceinline__ void dd_acc(double &hi, double &lo, double x, double y)
+{
+    const double p = x * y;
+    const double e = __builtin_fma(x, y, -p);
+    double s, r;
+    two_sum(hi, p, s, r);
+    hi = s;
+    lo = lo + (r + e);
+}
+
+// (zh, zl) = (ah, al) + (bh, bl)
+__device__ __forceinline__ void dd_add(double ah, double al, double bh, double bl, double &zh,
+                                       double &zl)
+{
+    double sh, sl, th, tl, vh, vl;
+    two_sum(ah, bh, sh, sl);
+    two_sum(al, bl, th, tl);
+    const double c = sl + th;
+    fast_two_sum(sh, c, vh, vl);
+    const double w = tl + vl;
+    fast_two_sum(vh, w, zh, zl);
+}
+
+// Reduce ND double-double values over the workgroup; result valid in thread 0.
+template <int ND>
+__device__ __forceinline__ void block_reduce_dd(double (&hi)[ND], double (&lo)[ND], double *lds)
+{
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double s, e;
+        two_sum(hi[d], lo[d], s, e);
+        hi[d] = s;
+        lo[d] = e;
+    }
+#pragma unroll
+    for (int off = TX / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const double oh = __shfl_xor(hi[d], off, TX);
+            const double ol = __shfl_xor(lo[d], off, TX);
+            dd_add(hi[d], lo[d], oh, ol, hi[d], lo[d]);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            lds[(wv * ND + d) * 2] = hi[d];
+            lds[(wv * ND + d) * 2 + 1] = lo[d];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double h = lds[d * 2], l = lds[d * 2 + 1];
+            for (int w = 1; w < TY; ++w)
+                dd_add(h, l, lds[(w * ND + d) * 2], lds[(w * ND + d) * 2 + 1], h, l);
+            hi[d] = h;
+            lo[d] = l;
+        }
+    }
+    __syncthreads();
+}
+
+// Publish this tile's partial sums; if this is the problem's last tile, sum
+// all partials in tile order and return true (res valid in thread 0).
+template <int ND>
+__device__ bool tile_commit(const Prob &P, int local, double (&hi)[ND], double (&lo)[ND],
+                            double *lds, int *flag, double (&res)[ND])
+{
+    block_reduce_dd<ND>(hi, lo, lds);
+    if (threadIdx.x == 0) {
+        double *pp = P.partials + (size_t)local * PARTIAL_STRIDE;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            pp[2 * d] = hi[d];
+            pp[2 * d + 1] = lo[d];
+        }
+        __threadfence();
+        const unsigned prev = atomicAdd(&P.sc->ticket, 1u);
+        *flag = prev == (unsigned)(P.ntiles - 1);
+    }
+    __syncthreads();
+    const bool last = *flag != 0;
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    const int nt = P.ntiles;
+    const int chunk = (nt + NTHREADS - 1) / NTHREADS;
+    const int b0 = threadIdx.x * chunk, b1 = min(b0 + chunk, nt);
+    double h2[ND], l2[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) h2[d] = l2[d] = 0.0;
+    const double *pp = P.partials;
+    for (int b = b0; b < b1; ++b) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            dd_add(h2[d], l2[d], pp[(size_t)b * PARTIAL_STRIDE + 2 * d],
+                   pp[(size_t)b * PARTIAL_STRIDE + 2 * d + 1], h2[d], l2[d]);
+    }
+    block_reduce_dd<ND>(h2, l2, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) res[d] = h2[d] + l2[d];
+        P.sc->ticket = 0;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------
+// scalar epilogues of the reductions (last tile, thread 0)
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void hist_put(const Prob &P, int it, int slot, double v)
+{
+    if (P.hist && it >= 1 && it <= P.hist_iters) P.hist[1 + 4 * (it - 1) + slot] = v;
+}
+
+__device__ __forceinline__ void fail(Scalars *sc, int status, int it)
+{
+    sc->status = status;
+    sc->done = 1;
+    sc->iter = it;
+}
+
+// r0 = b - A x0: rho0 = r~.r0 = r0.r0, tolerance on b.b
+__device__ void fin_init(const Prob &P, double rr, double bb)
+{
+    Scalars *sc = P.sc;
+    sc->bb = bb;
+    sc->tol2bb = P.tol2 * bb;
+    sc->rr = rr;
+    sc->rho = rr;
+    sc->ss = 0.0;
+    sc->alpha = sc->omega = sc->beta = 0.0;
+    sc->iter = 0;
+    sc->half = 0;
+    sc->half_pending = 0;
+    sc->zero_x = 0;
+    if (P.hist) P.hist[0] = rr;
+    if (!isfinite(bb) || !isfinite(rr)) {
+        sc->status = ST_NONFINITE;
+        sc->done = 1;
+    } else if (bb == 0.0) {
+        sc->zero_x = 1;
+        sc->status = ST_OK;
+        sc->done = 1;
+    } else if (rr < sc->tol2bb) {
+        sc->status = ST_OK;
+        sc->done = 1;
+    } else {
+        sc->status = ST_NOT_CONVERGED;
+        sc->done = 0;
+    }
+}
+
+// alpha_i = rho_{i-1} / (r~ . A p^_i)
+__device__ void fin_sdot(const Prob &P, double d)
+{
+    Scalars *sc = P.sc;
+    const int it = sc->iter + 1;
+    if (!isfinite(d)) return fail(sc, ST_NONFINITE, it);
+    if (d == 0.0) return fail(sc, ST_BREAKDOWN, it);
+    const double alpha = sc->rho / d;
+    sc->alpha = alpha;
+    hist_put(P, it, 0, alpha);
+    hist_put(P, it, 2, sc->rho);
+}
+
+// half-step test ||s|| < tol ||b|| of Alg. 1
+__device__ void fin_axpy(const Prob &P, double ss)
+{
+    Scalars *sc = P.sc;
+    const int it = sc->iter + 1;
+    if (!isfinite(ss)) return fail(sc, ST_NONFINITE, it);
+    if (ss < sc->tol2bb) {
+        sc->half_pending = 1;
+        sc->ss = ss;
+        hist_put(P, it, 1, 0.0);
+        hist_put(P, it, 3, ss);
+    }
+}
+
+// omega_i = (t . s) / (t . t)
+__device__ void fin_sdot2(const Prob &P, double ts, double tt)
+{
+    Scalars *sc = P.sc;
+    const int it = sc->iter + 1;
+    if (!isfinite(ts) || !isfinite(tt)) return fail(sc, ST_NONFINITE, it);
+    if (tt == 0.0) return fail(sc, ST_BREAKDOWN, it);
+    double omega = ts / tt;
+    if (it == P.debug_breakdown_at) omega = 0.0;
+    sc->omega = omega;
+}
+
+// end of iteration: convergence, rho_i = r~.r_i, beta_i = (rho_i alpha_i)/(rho_{i-1} omega_i)
+__device__ void fin_upd(const Prob &P, double rho_new, double rr)
+{
+    Scalars *sc = P.sc;
+    const int it = sc->iter + 1;
+    sc->iter = it;
+    if (sc->half_pending) {
+        sc->half_pending = 0;
+        sc->half = 1;
+        sc->rr = sc->ss;
+        sc->status = ST_OK;
+        sc->done = 1;
+        return;
+    }
+    hist_put(P, it, 1, sc->omega);
+    hist_put(P, it, 3, rr);
+    sc->rr = rr;
+    if (!isfinite(rho_new) || !isfinite(rr)) return fail(sc, ST_NONFINITE, it);
+    if (rr < sc->tol2bb) {
+        sc->status = ST_OK;
+        sc->done = 1;
+        return;
+    }
+    if (rho_new == 0.0 || sc->omega == 0.0) return fail(sc, ST_BREAKDOWN, it);
+    sc->beta = (rho_new * sc->alpha) / (sc->rho * sc->omega);
+    sc->rho = rho_new;
+    if (it >= P.maxit) {
+        sc->status = ST_NOT_CONVERGED;
+        sc->done = 1;
+    }
+}
+
+template <typename T> struct Coef;
+template <> struct Coef<double> {
+    static __device__ double ih2(const Prob &P) { return P.ih2; }
+    static __device__ double theta(const Prob &P) { return P.theta; }
+    static __device__ double c1(const Prob &P) { return P.c1; }
+    static __device__ double two_sigma(const Prob &P) { return P.two_sigma; }
+    static __device__ double two_over_delta(const Prob &P) { return P.two_over_delta; }
+    static __device__ double rc(const Prob &P, int i) { return P.rc[i]; }
+    static __device__ double ro(const Prob &P, int i) { return P.ro[i]; }
+    static __device__ double jac(const Prob &P) { return P.jac_d; }
+};
+template <> struct Coef<float> {
+    static __device__ float ih2(const Prob &P) { return P.ih2f; }
+    static __device__ float theta(const Prob &P) { return P.thetaf; }
+    static __device__ float c1(const Prob &P) { return P.c1f; }
+    static __device__ float two_sigma(const Prob &P) { return P.two_sigmaf; }
+    static __device__ float two_over_delta(const Prob &P) { return P.two_over_deltaf; }
+    static __device__ float rc(const Prob &P, int i) { return P.rcf[i]; }
+    static __device__ float ro(const Prob &P, int i) { return P.rof[i]; }
+    static __device__ float jac(const Prob &P) { return P.jac_df; }
+};
+
+// ------------------------------------------------------------------------
+// stencil family
+// TU: element type of the stencil input; TC: arithmetic type.
+// ------------------------------------------------------------------------
+template <int OP, typename TU, typename TC, bool MASK>
+__global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
+{
+    constexpr int ND = (OP == S_SDOT2 || OP == S_INIT) ? 2
+                       : (OP == S_SDOT || OP == S_TRUE) ? 1 : 0;
+    constexpr int NA = ND > 0 ? ND : 1;
+    __shared__ double lds[TY * 2 * 2];
+    __shared__ int flag;
+    const int total = W.count_dev ? *W.count_dev : W.count;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int t = remap_xcd(g, total);
+        const int pid = W.tile_prob ? W.tile_prob[t] : 0;
+        const int local = W.tile_prob ? W.tile_local[t] : t;
+        const Prob &P = W.probs[pid];
+        if (OP != S_INIT && OP != S_TRUE && OP != S_APPLY) {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+        const int i = tix * TX + lane, j = tiy * TY + wv;
+        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+        double hi[NA], lo[NA];
+#pragma unroll
+        for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
+
+        if (i < nx && j < ny) {
+            const size_t S = (size_t)nx * (size_t)ny;
+            size_t idx = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * (size_t)k0);
+            const TU *__restrict__ u = (const TU *)P.vec[A.in];
+            const int B = MASK ? P.block : 1;
+            const bool oxm = i > 0 && (!MASK || i % B != 0);
+            const bool oxp = i + 1 < nx && (!MASK || (i + 1) % B != 0);
+            const bool oym = j > 0 && (!MASK || j % B != 0);
+            const bool oyp = j + 1 < ny && (!MASK || (j + 1) % B != 0);
+            const TC ih2 = Coef<TC>::ih2(P);
+            // operation constants
+            TC cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
+            if constexpr (OP == S_CHEB1) {
+                cA = Coef<TC>::c1(P);
+                cB = Coef<TC>::theta(P);
+            } else if constexpr (OP == S_CHEB2 || OP == S_CHEBK) {
+                cA = Coef<TC>::rc(P, A.step);
+                cB = Coef<TC>::ro(P, A.step);
+                cC = Coef<TC>::two_sigma(P);
+                cD = Coef<TC>::two_over_delta(P);
+                cE = Coef<TC>::theta(P);
+            }
+            TC *out = (TC *)P.vec[A.out];
+            const TC *vv = (const TC *)P.vec[A.v];
+            const TC *zz = (const TC *)P.vec[A.z];
+            float *v32 = (float *)P.vec[V_V32];
+            const double *__restrict__ rt = (const double *)P.vec[V_RT];
+            const double *__restrict__ bv = (const double *)P.vec[V_B];
+            const double *sv = (const double *)P.vec[V_R];
+            double *rr = (double *)P.vec[V_R];
+            double *rtw = (double *)P.vec[V_RT];
+            double *pw = (double *)P.vec[V_P];
+
+            TC c = (TC)u[idx];
+            TC zm = (k0 > 0 && (!MASK || k0 % B != 0)) ? (TC)u[idx - S] : (TC)0;
+            for (int k = k0; k < k1; ++k, idx += S) {
+                const TC zr = (k + 1 < nz) ? (TC)u[idx + S] : (TC)0;
+                const bool zcut = MASK && ((k + 1) % B == 0);
+                const TC zp = zcut ? (TC)0 : zr;
+                const TC xm = oxm ? (TC)u[idx - 1] : (TC)0;
+                const TC xp = oxp ? (TC)u[idx + 1] : (TC)0;
+                const TC ym = oym ? (TC)u[idx - nx] : (TC)0;
+                const TC yp = oyp ? (TC)u[idx + nx] : (TC)0;
+                const TC a = (((((((TC)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                if constexpr (OP == S_APPLY) {
+                    out[idx] = a;
+                } else if constexpr (OP == S_CHEB1) {
+                    out[idx] = cA * ((TC)2 * c - a / cB);
+                    if constexpr (sizeof(TC) == 4) v32[idx] = c;
+                } else if constexpr (OP == S_CHEB2) {
+                    const TC v = vv[idx];
+                    const TC z = v / cE;
+                    out[idx] = cA * ((cC * c + cD * (v - a)) - cB * z);
+                } else if constexpr (OP == S_CHEBK) {
+                    const TC v = vv[idx];
+                    const TC z = zz[idx];
+                    out[idx] = cA * ((cC * c + cD * (v - a)) - cB * z);
+                } else if constexpr (OP == S_SDOT) {
+                    out[idx] = a;
+                    dd_acc(hi[0], lo[0], rt[idx], a);
+                } else if constexpr (OP == S_SDOT2) {
+                    out[idx] = a;
+                    const double s = sv[idx];
+                    dd_acc(hi[0], lo[0], a, s);
+                    dd_acc(hi[1], lo[1], a, a);
+                } else if constexpr (OP == S_INIT) {
+                    const double b = bv[idx];
+                    const double r = b - a;
+                    rr[idx] = r;
+                    rtw[idx] = r;
+                    pw[idx] = r;
+                    dd_acc(hi[0], lo[0], r, r);
+                    dd_acc(hi[1], lo[1], b, b);
+                } else if constexpr (OP == S_TRUE) {
+                    const double r = bv[idx] - a;
+                    dd_acc(hi[0], lo[0], r, r);
+                }
+                zm = zcut ? (TC)0 : c;
+                c = zr;
+            }
+        }
+        if constexpr (ND > 0) {
+            double res[NA];
+            if (tile_commit<NA>(P, local, hi, lo, lds, &flag, res) && threadIdx.x == 0) {
+                if constexpr (OP == S_SDOT) fin_sdot(P, res[0]);
+                else if constexpr (OP == S_SDOT2) fin_sdot2(P, res[0], res[1]);
+                else if constexpr (OP == S_INIT) fin_init(P, res[0], res[1]);
+                else if constexpr (OP == S_TRUE) P.sc->rr_true = res[0];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// elementwise family. TP: element type of p^ / s^ (E_UPD) or of the output (E_DIV).
+// ------------------------------------------------------------------------
+template <int OP, typename TP>
+__global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
+{
+    constexpr int ND = OP == E_UPD ? 2 : (OP == E_AXPY || OP == E_DOT) ? 1 : 0;
+    constexpr int NA = ND > 0 ? ND : 1;
+    __shared__ double lds[TY * 2 * 2];
+    __shared__ int flag;
+    const int total = W.count_dev ? *W.count_dev : W.count;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int t = remap_xcd(g, total);
+        const int pid = W.tile_prob ? W.tile_prob[t] : 0;
+        const int local = W.tile_prob ? W.tile_local[t] : t;
+        const Prob &P = W.probs[pid];
+        const Scalars *sc = P.sc;
+        if (OP != E_DOT) {
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        const bool half = OP == E_UPD && sc->half_pending;
+        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+        const int i = tix * TX + lane, j = tiy * TY + wv;
+        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+        double hi[NA], lo[NA];
+#pragma unroll
+        for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
+
+        if (i < nx && j < ny) {
+            const size_t S = (size_t)nx * (size_t)ny;
+            size_t idx = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * (size_t)k0);
+            const double alpha = sc->alpha, omega = sc->omega, beta = sc->beta;
+            if constexpr (OP == E_AXPY) {
+                double *r = (double *)P.vec[V_R];
+                const double *__restrict__ w = (const double *)P.vec[V_W];
+                for (int k = k0; k < k1; ++k, idx += S) {
+                    const double s = r[idx] - alpha * w[idx];
+                    r[idx] = s;
+                    dd_acc(hi[0], lo[0], s, s);
+                }
+            } else if constexpr (OP == E_UPD) {
+                double *x = (double *)P.vec[V_X];
+                const TP *ph = (const TP *)P.vec[A.in];
+                const TP *sh = (const TP *)P.vec[A.x2];
+                double *r = (double *)P.vec[V_R];
+                const double *__restrict__ tv = (const double *)P.vec[V_T];
+                const double *__restrict__ rt = (const double *)P.vec[V_RT];
+                if (half) {
+                    for (int k = k0; k < k1; ++k, idx += S)
+                        x[idx] = x[idx] + alpha * (double)ph[idx];
+                } else {
+                    for (int k = k0; k < k1; ++k, idx += S) {
+                        const double s = r[idx];
+                        const double shv = (double)sh[idx];
+                        x[idx] = (x[idx] + alpha * (double)ph[idx]) + omega * shv;
+                        const double rn = s - omega * tv[idx];
+                        r[idx] = rn;
+                        dd_acc(hi[0], lo[0], rt[idx], rn);
+                        dd_acc(hi[1], lo[1], rn, rn);
+                    }
+                }
+            } else if constexpr (OP == E_PUPD) {
+                double *p = (double *)P.vec[V_P];
+                const double *__restrict__ r = (const double *)P.vec[V_R];
+                const double *__restrict__ w = (const double *)P.vec[V_W];
+                for (int k = k0; k < k1; ++k, idx += S)
+                    p[idx] = r[idx] + beta * (p[idx] - omega * w[idx]);
+            } else if constexpr (OP == E_DIV) {
+                const double *__restrict__ v = (const double *)P.vec[A.in];
+                TP *out = (TP *)P.vec[A.out];
+                const TP d = A.divisor ? Coef<TP>::theta(P) : Coef<TP>::jac(P);
+                for (int k = k0; k < k1; ++k, idx += S) out[idx] = (TP)v[idx] / d;
+            } else if constexpr (OP == E_DOT) {
+                const double *__restrict__ xv = (const double *)P.vec[A.in];
+                const double *__restrict__ yv = (const double *)P.vec[A.x2];
+                for (int k = k0; k < k1; ++k, idx += S) dd_acc(hi[0], lo[0], xv[idx], yv[idx]);
+            }
+        }
+        if constexpr (ND > 0) {
+            double res[NA];
+            if (tile_commit<NA>(P, local, hi, lo, lds, &flag, res) && threadIdx.x == 0) {
+                if constexpr (OP == E_AXPY) fin_axpy(P, res[0]);
+                else if constexpr (OP == E_UPD) fin_upd(P, res[0], res[1]);
+                else if constexpr (OP == E_DOT) P.sc->dot = res[0];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// synthetic right-hand sides: counter-based splitmix64
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_fill_uniform(double *out, int64_t n, uint64_t key)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t v = mix64(key + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL);
+        const double u = (double)(v >> 11) * 0x1.0p-53;
+        out[i] = 2.0 * u - 1.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+template <int OP, typename TU, typename TC, bool M>
+static void ls(const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    hipLaunchKernelGGL((k_stencil<OP, TU, TC, M>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+}
+
+template <int OP, typename TU, typename TC>
+static void ls_mask(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    if (mask) ls<OP, TU, TC, true>(w, grid, s, a);
+    else ls<OP, TU, TC, false>(w, grid, s, a);
+}
+
+void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                    const KArgs &a)
+{
+    switch (op) {
+    case S_APPLY: ls<S_APPLY, double, double, false>(w, grid, s, a); break;
+    case S_CHEB1:
+        if (mixed) ls_mask<S_CHEB1, double, float>(mask, w, grid, s, a);
+        else ls_mask<S_CHEB1, double, double>(mask, w, grid, s, a);
+        break;
+    case S_CHEB2:
+        if (mixed) ls_mask<S_CHEB2, float, float>(mask, w, grid, s, a);
+        else ls_mask<S_CHEB2, double, double>(mask, w, grid, s, a);
+        break;
+    case S_CHEBK:
+        if (mixed) ls_mask<S_CHEBK, float, float>(mask, w, grid, s, a);
+        else ls_mask<S_CHEBK, double, double>(mask, w, grid, s, a);
+        break;
+    case S_SDOT:
+        if (mixed) ls<S_SDOT, float, double, false>(w, grid, s, a);
+        else ls<S_SDOT, double, double, false>(w, grid, s, a);
+        break;
+    case S_SDOT2:
+        if (mixed) ls<S_SDOT2, float, double, false>(w, grid, s, a);
+        else ls<S_SDOT2, double, double, false>(w, grid, s, a);
+        break;
+    case S_INIT: ls<S_INIT, double, double, false>(w, grid, s, a); break;
+    case S_TRUE: ls<S_TRUE, double, double, false>(w, grid, s, a); break;
+    default: break;
+    }
+}
+
+template <int OP, typename TP>
+static void le(const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    hipLaunchKernelGGL((k_elem<OP, TP>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+}
+
+void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    switch (op) {
+    case E_AXPY: le<E_AXPY, double>(w, grid, s, a); break;
+    case E_UPD:
+        if (mixed) le<E_UPD, float>(w, grid, s, a);
+        else le<E_UPD, double>(w, grid, s, a);
+        break;
+    case E_PUPD: le<E_PUPD, double>(w, grid, s, a); break;
+    case E_DIV:
+        if (mixed) le<E_DIV, float>(w, grid, s, a);
+        else le<E_DIV, double>(w, grid, s, a);
+        break;
+    case E_DOT: le<E_DOT, double>(w, grid, s, a); break;
+    default: break;
+    }
+}
+
+void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s)
+{
+    uint64_t key = seed + 0x9E3779B97F4A7C15ULL;
+    key = (key ^ (key >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    key = (key ^ (key >> 27)) * 0x94D049BB133111EBULL;
+    key = key ^ (key >> 31);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)blocks), dim3(256), 0, s, out, n, key);
+}
+
+} // namespace pz

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/poisson.h, and rejects invalid arguments
+before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_08935_amd as P
+from paper_2503_08935_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "poisson.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(poisson_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    L = P.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_header_is_plain_c():
+    text = open(os.path.join(ROOT, "include", "poisson.h")).read()
+    assert 'extern "C"' in text
+    for bad in ("torch", "std::", "hipStream_t", "class "):
+        assert bad not in re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+
+
+def test_create_validation():
+    L = P.lib()
+    ctx = ctypes.c_void_p()
+    for args in [(0, 4, 4, 0.1), (4, -1, 4, 0.1), (4, 4, 4, 0.0), (4, 4, 4, -1.0),
+                 (4, 4, 4, float("nan")), (4, 4, 4, float("inf")), (1 << 13, 1 << 13, 1 << 13, 0.1)]:
+        assert L.poisson_create(*args, 0, ctypes.byref(ctx)) == P.ERR_ARG
+        assert not ctx.value
+    assert L.poisson_create(4, 4, 4, 0.1, 1, ctypes.byref(ctx)) == P.ERR_UNSUPPORTED
+    assert L.poisson_create(4, 4, 4, 0.1, 0, None) == P.ERR_ARG
+    assert L.poisson_create(4, 4, 4, 0.1, 0, ctypes.byref(ctx)) == P.OK and ctx.value
+    L.poisson_destroy(ctx)
+    L.poisson_destroy(None)
+
+
+def test_options_and_solve_argument_checks():
+    L = P.lib()
+    s = P.Solver((8, 6, 4), 0.1)
+    c = s._ctx
+    assert L.poisson_set_option(c, 999, 1.0) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_PRECISION, 2.0) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_BLOCK, 1.0) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_BLOCK, 3.5) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_GRAPH_ITERS, 0.0) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_LMIN_SCALE, -1.0) == P.ERR_ARG
+    assert L.poisson_set_option(c, B.OPT_LMIN_SCALE, float("nan")) == P.ERR_ARG
+    for k, v in [(B.OPT_PRECISION, 1), (B.OPT_BLOCK, 16), (B.OPT_LMIN_SCALE, 100.0),
+                 (B.OPT_LMAX_SCALE, 1 - 1e-4), (B.OPT_BJ_GLOBAL_INTERVAL, 1),
+                 (B.OPT_GRAPH_ITERS, 16), (B.OPT_USE_GRAPH, 0), (B.OPT_DEBUG_BREAKDOWN_AT, -1)]:
+        assert L.poisson_set_option(c, k, float(v)) == P.OK
+    fake = ctypes.c_void_p(0x1000)
+    # argument errors are found before any device access
+    assert L.poisson_solve(c, None, fake, 2, 8, 1e-8, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 7, 8, 1e-8, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, 65, 1e-8, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, -1, 1e-8, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, 8, 0.0, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, 8, 1.0, 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, 8, float("nan"), 10) == P.ERR_ARG
+    assert L.poisson_solve(c, fake, fake, 2, 8, 1e-8, 0) == P.ERR_ARG
+    st = B.Stats()
+    st.struct_size = ctypes.sizeof(B.Stats)
+    assert L.poisson_stats(c, ctypes.byref(st)) == P.ERR_ARG  # nothing solved yet
+    assert L.poisson_kernel_bench(c, 0, 0, 1) == P.ERR_ARG     # no plan yet
+    s.close()
+
+
+def test_degenerate_chebyshev_interval_rejected():
+    L = P.lib()
+    one = P.Solver((1, 1, 1), 0.5)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.poisson_solve(one._ctx, fake, fake, P.PC_CHEBYSHEV, 4, 1e-8, 10) == P.ERR_ARG
+    one.close()
+
+
+def test_strerror_covers_codes():
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
+        assert P.strerror(code) != "unknown status"
+    assert P.strerror(42) == "unknown status"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        B.lib()

@@ -1,0 +1,129 @@
+"""GPU solver parity against the CPU oracle through the C ABI: full solves on
+grids the oracle finishes in seconds (several tiles, ragged tails), iteration
+counts, solution vectors and the per-iteration scalars alpha, omega, rho."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_08935_amd as P
+from paper_2503_08935_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-9  # solution parity bar (relative 2-norm)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_solve(shape, h, f, pc, m, tol, maxit=5000, x0=None, **opts):
+    with P.Solver(shape, h, **opts) as s:
+        b = dev(f)
+        x = dev(x0) if x0 is not None else torch.zeros_like(b)
+        st = s.solve(b, x, pc, m, tol, maxit)
+        torch.cuda.synchronize()
+        return st, s.stats(), s.trace(), x.cpu().numpy()
+
+
+def oracle_pc(pc):
+    return {P.PC_NONE: oracle.PC_NONE, P.PC_JACOBI: oracle.PC_JACOBI,
+            P.PC_CHEBYSHEV: oracle.PC_CHEBYSHEV, P.PC_BLOCK_JACOBI: oracle.PC_BLOCK_JACOBI}[pc]
+
+
+def check_parity(shape, h, f, pc, m, tol, mixed=False, block=64, bj_global=0, lmin=1.0, lmax=1.0,
+                 maxit=5000):
+    opts = dict(precision=P.MIXED if mixed else P.FP64, block=block, bj_global_interval=bj_global,
+                lmin_scale=lmin, lmax_scale=lmax)
+    st, stats, tr, x = gpu_solve(shape, h, f, pc, m, tol, maxit, **opts)
+    ref = oracle.bicgstab(f, h, pc=oracle_pc(pc), degree=m, mixed=mixed, tol=tol, maxit=maxit,
+                          block=block, bj_global=bj_global, lmin_scale=lmin, lmax_scale=lmax)
+    assert st == ref.status
+    assert abs(stats["iterations"] - ref.iterations) <= 1
+    rel = np.linalg.norm(x - ref.x) / max(np.linalg.norm(ref.x), 1e-300)
+    assert rel <= REL_TOL, rel
+    return st, stats, tr, x, ref
+
+
+def test_manufactured_32_one_iteration(gpu):
+    n = 32
+    h = workloads.spacing(n)
+    f = workloads.manufactured((n, n, n))
+    st, stats, tr, x, ref = check_parity((n, n, n), h, f, P.PC_NONE, 0, 1e-8)
+    assert (st, stats["iterations"], stats["half_step_exit"]) == (P.OK, 1, 1)
+    assert np.array_equal(x, ref.x)
+    c = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+    assert np.abs(x - c * workloads.manufactured_u((n, n, n))).max() < 1e-12
+
+
+SOLVES = [
+    dict(pc=P.PC_NONE, m=0),
+    dict(pc=P.PC_JACOBI, m=0),
+    dict(pc=P.PC_CHEBYSHEV, m=4),
+    dict(pc=P.PC_CHEBYSHEV, m=8),
+    dict(pc=P.PC_BLOCK_JACOBI, m=8, block=16),
+    dict(pc=P.PC_BLOCK_JACOBI, m=6, block=16, bj_global=1, lmin=10.0, lmax=1 - 1e-4),
+    dict(pc=P.PC_CHEBYSHEV, m=8, mixed=True),
+    dict(pc=P.PC_CHEBYSHEV, m=4, mixed=True),
+    dict(pc=P.PC_BLOCK_JACOBI, m=8, block=16, mixed=True),
+    dict(pc=P.PC_JACOBI, m=0, mixed=True),
+    dict(pc=P.PC_CHEBYSHEV, m=1),
+    dict(pc=P.PC_CHEBYSHEV, m=0),
+]
+
+
+@pytest.mark.parametrize("case", SOLVES, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_full_solve_parity_ragged(gpu, case):
+    shape = (61, 47, 35)
+    h = workloads.spacing(61)
+    f = workloads.uniform_grid(2, shape)
+    st, stats, tr, x, ref = check_parity(shape, h, f, case["pc"], case["m"], 1e-8,
+                                         mixed=case.get("mixed", False),
+                                         block=case.get("block", 64),
+                                         bj_global=case.get("bj_global", 0),
+                                         lmin=case.get("lmin", 1.0), lmax=case.get("lmax", 1.0))
+    assert st == P.OK
+    # the reproducible reductions make the whole trajectory identical
+    assert stats["iterations"] == ref.iterations
+    assert np.array_equal(tr[:, 0], ref.alpha) and np.array_equal(tr[:, 1], ref.omega)
+    assert np.array_equal(tr[:, 2], ref.rho) and np.array_equal(tr[:, 3], ref.rr)
+    assert np.array_equal(x, ref.x)
+    assert stats["relres_true"] < 1.5e-8
+
+
+def test_graph_and_poll_interval_do_not_change_bits(gpu):
+    shape = (40, 33, 20)
+    h = workloads.spacing(40)
+    f = workloads.uniform_grid(9, shape)
+    outs = []
+    for use_graph, k in [(1, 8), (0, 3), (1, 1), (1, 64)]:
+        st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 4, 1e-10, use_graph=use_graph,
+                                     graph_iters=k)
+        outs.append((st, stats["iterations"], x))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1] and np.array_equal(o[2], outs[0][2])
+
+
+def test_special_cases(gpu):
+    shape = (20, 17, 9)
+    h = 0.05
+    z = np.zeros((9, 17, 20))
+    st, stats, tr, x = gpu_solve(shape, h, z, P.PC_CHEBYSHEV, 4, 1e-8, x0=np.ones_like(z))
+    assert st == P.OK and stats["iterations"] == 0 and np.all(x == 0)
+    f = workloads.uniform_grid(3, shape)
+    bad = f.copy()
+    bad[3, 4, 5] = np.inf
+    st, stats, tr, x = gpu_solve(shape, h, bad, P.PC_CHEBYSHEV, 4, 1e-8)
+    assert st == P.ERR_NONFINITE
+    st, stats, tr, x = gpu_solve(shape, h, f, P.PC_NONE, 0, 1e-12, maxit=1)
+    assert st == P.NOT_CONVERGED and stats["iterations"] == 1
+    ref = oracle.bicgstab(f, h, pc=oracle.PC_NONE, tol=1e-12, maxit=1)
+    assert np.array_equal(x, ref.x)
+    # x0 already the solution: zero iterations
+    xs = oracle.bicgstab(f, h, pc=oracle.PC_CHEBYSHEV, degree=4, tol=1e-13).x
+    st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 4, 1e-8, x0=xs)
+    assert st == P.OK and stats["iterations"] == 0
+    # forced omega = 0 at iteration 3 reports a breakdown there
+    st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 4, 1e-12, debug_breakdown_at=3)
+    assert st == P.ERR_BREAKDOWN and stats["iterations"] == 3 and np.all(np.isfinite(x))
