@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark: preconditioned Bi-CGSTAB for the 3D Poisson equation on one MI355X.
+
+One step = one full solve (setup, iterations, true residual) of the 512^3 FP64
+Chebyshev-8 Bi-CGSTAB on the unit cube, f ~ U[-1,1) (seed 4), x0 = 0, stopping at
+relative residual 1e-8. The right-hand side is generated on the device with the
+same counter-based generator as the host-side workloads, so inputs are resident
+in HBM before the timed region. Printed as one JSON line:
+  value        iterations per second over the timed solves (whole solves)
+  hbm_gbps     algorithmic bytes of the iteration loop / loop device time
+  tts_*        time to 1e-8 of the FP64 solve and of the mixed solve (FP32
+               Chebyshev inside FP64 Bi-CGSTAB), same right-hand side
+  roofline     dominant kernel (interior Chebyshev step, FP64), timed with HIP
+               events on the stream it runs on
+  cpu_baseline the CPU oracle on a bounded sample (2 iterations vs 1 iteration
+               of the same 512^3 solve; the difference is one iteration)
+  p99_solve_ms the serving stream: 2000 requests of n^3 grids, n uniform over
+               {32,48,64,96,128,192,256}, Poisson arrivals at 200/s, mixed
+               Chebyshev-4 to 1e-8, admitted by HBM footprint (serving.py)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "512³ Bi-CGSTAB iter/s + HBM GB/s; mixed vs FP64 time-to-1e-8; p99 solve ms"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="grid edge (n^3 interior unknowns)")
+    ap.add_argument("--degree", type=int, default=8)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-iters", type=int, default=4,
+                    help="iterations per server step (completion is observed per step)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_record(kernel_file, workload):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), valid only
+    while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        recs = json.load(open(path))
+    except Exception:
+        return None
+    src = open(os.path.join(ROOT, "paper_2503_08935_amd", "csrc", kernel_file), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()
+    for r in recs:
+        if r.get("workload") == workload and r.get("source_sha256") == sha:
+            return r.get("bytes_per_launch")
+    return None
+
+
+def cpu_baseline(n, h, degree, seed):
+    import numpy as np
+
+    import oracle
+    from paper_2503_08935_amd import workloads
+    shape = (n, n, n)
+    b = workloads.uniform_grid(seed, shape)
+    ts = []
+    for it in (1, 2):
+        t0 = time.perf_counter()
+        r = oracle.bicgstab(b, h, pc=oracle.PC_CHEBYSHEV, degree=degree, tol=1e-8, maxit=it)
+        ts.append(time.perf_counter() - t0)
+        log(f"cpu oracle maxit={it}: {ts[-1]:.2f} s (iterations {r.iterations})")
+        del r
+    del b
+    per_it = max(ts[1] - ts[0], 1e-9)
+    return {"value": 1.0 / per_it, "unit": "iter/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"one Bi-CGSTAB iteration of the {n}^3 FP64 Chebyshev-{degree} solve "
+                      f"(seed {seed}): time(maxit=2) - time(maxit=1), setup excluded",
+            "seconds_maxit1": ts[0], "seconds_maxit2": ts[1]}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the solver has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2503_08935_amd as P
+    from paper_2503_08935_amd import workloads
+
+    dev = torch.device("cuda:0")
+    n = a.n
+    shape = (n, n, n)
+    N = n ** 3
+    h = workloads.spacing(n)
+    stream = torch.cuda.Stream()  # default priority
+    log(f"grid {n}^3, FP64 Chebyshev-{a.degree}, tol {a.tol}")
+    with torch.cuda.stream(stream):
+        b = torch.empty(N, dtype=torch.float64, device=dev)
+        x = torch.zeros(N, dtype=torch.float64, device=dev)
+        P.fill_uniform(b, a.seed, stream)
+    stream.synchronize()
+
+    s64 = P.Solver(shape, h, stream=stream, precision=P.FP64)
+
+    def solve64():
+        with torch.cuda.stream(stream):
+            x.zero_()
+            st = s64.solve(b, x, P.PC_CHEBYSHEV, a.degree, a.tol, 5000)
+        if st != P.OK:
+            raise RuntimeError(f"FP64 solve status {st}")
+        return s64.stats()
+
+    for w in range(a.warmup):
+        st = solve64()
+        log(f"warmup {w}: {st['iterations']} iterations, {st['solve_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    iters = 0
+    loop_ms = 0.0
+    model_bytes = 0.0
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        st = solve64()
+        iters += st["iterations"]
+        loop_ms += st["loop_ms"]
+        model_bytes += st["model_bytes"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    last = stats[-1]
+    log(f"timed: {a.steps} solves, {iters} iterations in {wall:.3f} s, true relres "
+        f"{last['relres_true']:.3e}")
+    x64 = x.clone()
+
+    # dominant kernel: interior Chebyshev step, timed on the solver's stream
+    reps = a.kernel_reps
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    s64.kernel_bench(P.KERNEL_CHEB_STEP, P.FP64, 2)  # warm
+    e0.record(stream)
+    s64.kernel_bench(P.KERNEL_CHEB_STEP, P.FP64, reps)
+    e1.record(stream)
+    e1.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    k_bytes = s64.kernel_bytes(P.KERNEL_CHEB_STEP, P.FP64)
+    k_gbps = k_bytes / (k_ms * 1e6)
+    log(f"cheb_step FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic")
+    workload = f"cheb_step_fp64_{n}^3"
+    roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": PEAK_HBM_GBPS,
+                "unit": "GB/s", "frac": round(k_gbps / PEAK_HBM_GBPS, 4),
+                "traffic": traffic_record("device.hip", workload),
+                "kernel": "k_stencil<S_CHEBK,double,double,false>",
+                "kernel_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes}
+    s64.close()
+
+    out = {"metric": METRIC, "value": round(iters / wall, 3), "unit": "iter/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(wall * 1e3 / a.steps, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{n}^3 unit-cube Poisson, zero Dirichlet, f~U[-1,1) seed "
+                                  f"{a.seed}, FP64 Bi-CGSTAB + Chebyshev degree {a.degree}, "
+                                  f"analytic interval, tol {a.tol}, x0=0; one step = one solve",
+                      "grid": n, "unknowns": N, "precond": "chebyshev", "degree": a.degree,
+                      "tol": a.tol},
+           "iterations_per_solve": last["iterations"],
+           "hbm_gbps": round(model_bytes / (loop_ms * 1e6), 1),
+           "hbm_frac": round(model_bytes / (loop_ms * 1e6) / PEAK_HBM_GBPS, 4),
+           "tts_fp64_s": round(last["solve_ms"] / 1e3, 4),
+           "relres_true_fp64": last["relres_true"]}
+
+    if not a.no_mixed:
+        sm = P.Solver(shape, h, stream=stream, precision=P.MIXED)
+        xm = torch.zeros_like(x)
+        tts = []
+        for rep in range(2):
+            with torch.cuda.stream(stream):
+                xm.zero_()
+                st = sm.solve(b, xm, P.PC_CHEBYSHEV, a.degree, a.tol, 5000)
+            if st != P.OK:
+                raise RuntimeError(f"mixed solve status {st}")
+            ms = sm.stats()
+            tts.append(ms["solve_ms"] / 1e3)
+        torch.cuda.synchronize()
+        rel = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
+        out.update({"tts_mixed_s": round(min(tts), 4), "iterations_mixed": ms["iterations"],
+                    "mixed_speedup": round(out["tts_fp64_s"] / min(tts), 3),
+                    "relres_true_mixed": ms["relres_true"],
+                    "mixed_vs_fp64_rel_diff": rel,
+                    "hbm_gbps_mixed": round(ms["model_gbps"], 1)})
+        log(f"mixed: {ms['iterations']} iterations, {min(tts):.3f} s, rel diff vs FP64 {rel:.2e}")
+        sm.close()
+        del xm
+    out["roofline"] = roofline
+    del b, x, x64
+    torch.cuda.empty_cache()
+    if not a.no_serve:
+        from paper_2503_08935_amd import serving
+        log(f"serving stream: {a.serve_requests} requests at {a.serve_rate}/s ...")
+        sv = serving.run_stream(n_requests=a.serve_requests, rate=a.serve_rate, iters=a.serve_iters,
+                                progress=log)
+        log(f"serving: p50 {sv['p50_ms']:.0f} ms, p99 {sv['p99_ms']:.0f} ms, "
+            f"{sv['solves_per_s']:.1f} solves/s, utilization {sv['utilization']:.2f}")
+        out["p99_solve_ms"] = round(sv["p99_ms"], 1)
+        out["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sv.items()}
+        torch.cuda.empty_cache()
+    if not a.no_cpu:
+        log("cpu oracle baseline (bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(n, h, a.degree, a.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

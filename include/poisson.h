@@ -192,6 +192,73 @@ double poisson_kernel_bytes(const poisson_ctx *c, int kernel, int precision);
    same bits as the host generator of the test-suite. Asynchronous on stream. */
 int poisson_fill_uniform(void *hip_stream, double *out, int64_t n, uint64_t seed);
 
+/* ---- serving: continuous batching of many solves ------------------------ */
+/*
+ * A server owns one HBM arena of hbm_budget_bytes and up to max_slots running
+ * solves. Requests of any grid size are queued first-in first-out and admitted
+ * while a slot is free and the request's workspace (its Krylov vectors and
+ * reduction partials, poisson_server_footprint) fits in the arena. Running
+ * requests keep their vectors resident and are advanced together: every kernel
+ * of an iteration runs once per plan (precond, degree, precision) over the
+ * tiles of all running requests with that plan. Each request's arithmetic is
+ * independent of the others, so its result is bitwise the same alone, in any
+ * mix, and through poisson_solve (Block-Jacobi uses 64^3 blocks and the local
+ * interval; interval scales are 1).
+ */
+typedef struct poisson_server poisson_server;
+
+typedef struct {
+    size_t struct_size;         /* set by the caller to sizeof(poisson_server_info_t) */
+    int queued, active;         /* waiting for admission / running */
+    long completed;             /* finished requests (any status) */
+    long steps;                 /* poisson_server_step calls that did work */
+    size_t bytes_in_use, peak_bytes, budget_bytes; /* arena accounting */
+    double busy_ms;             /* device time of all steps (HIP events) */
+} poisson_server_info_t;
+
+enum { POISSON_SERVER_OPT_USE_GRAPH = 1 /* 1 = replay captured graphs (default), 0 = launch */ };
+
+/* Create a server. hip_stream: stream of all its work (NULL = null stream).
+   Host-only: the arena is allocated by the first poisson_server_step.
+   ERR_ARG if hbm_budget_bytes < 4096, max_slots outside 1..4096 or out == NULL. */
+int poisson_server_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream,
+                          poisson_server **out);
+
+/* Set a server option (POISSON_SERVER_OPT_*). */
+int poisson_server_set_option(poisson_server *s, int key, double value);
+
+/* Arena bytes a request of this plan needs (host-only). */
+int poisson_server_footprint(int nx, int ny, int nz, int precond, int degree, int precision,
+                             size_t *bytes);
+
+/* Queue one solve of A x = rhs (arguments as poisson_solve, plus the precision;
+   rhs and x are caller-owned device FP64 vectors that must stay valid until
+   poll reports a final status). Does no device work. *ticket identifies the
+   request. ERR_NOMEM if the request alone exceeds the arena; ERR_ARG /
+   ERR_UNSUPPORTED / ERR_DEVICE as poisson_solve. */
+int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, unsigned bc,
+                          const double *rhs, double *x, int precond, int degree, int precision,
+                          double tol, int maxit, uint64_t *ticket);
+
+/* One scheduling round: retire the requests found finished by the previous
+   round (true residual, stats, free the arena block and slot), admit queued
+   requests in order, compute their initial residuals, advance every running
+   request by `iters` iterations (1..4096), and read all requests' flags.
+   Synchronous. Returns the number of queued + running requests (>= 0). */
+int poisson_server_step(poisson_server *s, int iters);
+
+/* POISSON_PENDING while queued or running; otherwise the final status
+   (OK, NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE) and, if out != NULL, the
+   request's statistics (solve_ms = submit to completion, loop_ms = admission to
+   completion, both host wall time; no history). ERR_ARG for an unknown ticket. */
+int poisson_server_poll(poisson_server *s, uint64_t ticket, poisson_stats_t *out);
+
+/* Queue, arena and timing counters. */
+int poisson_server_info(const poisson_server *s, poisson_server_info_t *out);
+
+/* Release the server (waits for its stream). NULL-safe. */
+void poisson_server_destroy(poisson_server *s);
+
 #ifdef __cplusplus
 }
 #endif

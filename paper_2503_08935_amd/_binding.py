@@ -22,7 +22,11 @@ EXPORTS = [
     "poisson_stats", "poisson_trace", "poisson_destroy", "poisson_strerror",
     "poisson_apply_operator", "poisson_apply_precond", "poisson_dot", "poisson_kernel_bench",
     "poisson_kernel_bytes", "poisson_fill_uniform",
+    "poisson_server_create", "poisson_server_set_option", "poisson_server_footprint",
+    "poisson_server_submit", "poisson_server_step", "poisson_server_poll", "poisson_server_info",
+    "poisson_server_destroy",
 ]
+SERVER_OPT_USE_GRAPH = 1
 
 
 class Stats(ctypes.Structure):
@@ -35,6 +39,15 @@ class Stats(ctypes.Structure):
         ("solve_ms", ctypes.c_double), ("loop_ms", ctypes.c_double),
         ("model_bytes", ctypes.c_double), ("model_gbps", ctypes.c_double),
         ("history_len", ctypes.c_int), ("history", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_size_t), ("queued", ctypes.c_int), ("active", ctypes.c_int),
+        ("completed", ctypes.c_long), ("steps", ctypes.c_long),
+        ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+        ("budget_bytes", ctypes.c_size_t), ("busy_ms", ctypes.c_double),
     ]
 
 
@@ -74,6 +87,18 @@ def lib():
         L.poisson_kernel_bytes.argtypes = [vp, ip, ip]
         L.poisson_kernel_bytes.restype = ctypes.c_double
         L.poisson_fill_uniform.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_uint64]
+        L.poisson_server_create.argtypes = [ctypes.c_size_t, ip, vp, ctypes.POINTER(vp)]
+        L.poisson_server_set_option.argtypes = [vp, ip, ctypes.c_double]
+        L.poisson_server_footprint.argtypes = [ip, ip, ip, ip, ip, ip,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.poisson_server_submit.argtypes = [vp, ip, ip, ip, ctypes.c_double, ctypes.c_uint, vp, vp,
+                                            ip, ip, ip, ctypes.c_double, ip,
+                                            ctypes.POINTER(ctypes.c_uint64)]
+        L.poisson_server_step.argtypes = [vp, ip]
+        L.poisson_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Stats)]
+        L.poisson_server_info.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+        L.poisson_server_destroy.argtypes = [vp]
+        L.poisson_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -105,6 +130,12 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _stats_dict(s):
+    d = {k: getattr(s, k) for k, _ in Stats._fields_ if k not in ("history", "struct_size")}
+    d["history"] = [s.history[i] for i in range(s.history_len)] if s.history_len else []
+    return d
 
 
 class Solver:
@@ -165,9 +196,7 @@ class Solver:
         s = Stats()
         s.struct_size = ctypes.sizeof(Stats)
         _check(lib().poisson_stats(self._ctx, ctypes.byref(s)), "poisson_stats")
-        d = {k: getattr(s, k) for k, _ in Stats._fields_ if k not in ("history", "struct_size")}
-        d["history"] = [s.history[i] for i in range(s.history_len)]
-        return d
+        return _stats_dict(s)
 
     def trace(self):
         import numpy as np
@@ -217,3 +246,73 @@ def fill_uniform(out, seed, stream=None):
     import torch
     _check(lib().poisson_fill_uniform(_stream_handle(stream), _ptr(out, None, (torch.float64,)),
                                       out.numel(), int(seed)), "poisson_fill_uniform")
+
+
+def footprint(shape, precond, degree, precision):
+    """Arena bytes one request of this plan needs in a Server."""
+    nx, ny, nz = shape
+    b = ctypes.c_size_t()
+    _check(lib().poisson_server_footprint(nx, ny, nz, int(precond), int(degree), int(precision),
+                                          ctypes.byref(b)), "poisson_server_footprint")
+    return b.value
+
+
+class Server:
+    """Continuous-batching server (poisson_server_*): FIFO admission by HBM footprint."""
+
+    def __init__(self, budget_bytes, max_slots=64, stream=None, use_graph=True):
+        srv = ctypes.c_void_p()
+        self._stream = stream
+        _check(lib().poisson_server_create(int(budget_bytes), int(max_slots),
+                                           _stream_handle(stream), ctypes.byref(srv)),
+               "poisson_server_create")
+        self._srv = srv
+        if not use_graph:
+            _check(lib().poisson_server_set_option(srv, SERVER_OPT_USE_GRAPH, 0.0),
+                   "poisson_server_set_option")
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            lib().poisson_server_destroy(self._srv)
+            self._srv = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, rhs, x, shape, h, precond=PC_CHEBYSHEV, degree=4, precision=MIXED, tol=1e-8,
+               maxit=5000):
+        import torch
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        t = ctypes.c_uint64()
+        _check(lib().poisson_server_submit(self._srv, nx, ny, nz, float(h), 0,
+                                           _ptr(rhs, n, (torch.float64,)),
+                                           _ptr(x, n, (torch.float64,)), int(precond), int(degree),
+                                           int(precision), float(tol), int(maxit), ctypes.byref(t)),
+               "poisson_server_submit")
+        return t.value
+
+    def step(self, iters=8):
+        return _check(lib().poisson_server_step(self._srv, int(iters)), "poisson_server_step")
+
+    def poll(self, ticket):
+        """(status, stats) with status PENDING while not finished (stats None)."""
+        s = Stats()
+        s.struct_size = ctypes.sizeof(Stats)
+        st = lib().poisson_server_poll(self._srv, int(ticket), ctypes.byref(s))
+        if st == ERR_ARG:
+            raise PoissonError(st, "poisson_server_poll")
+        if st == PENDING:
+            return st, None
+        return st, _stats_dict(s)
+
+    def info(self):
+        i = ServerInfo()
+        i.struct_size = ctypes.sizeof(ServerInfo)
+        _check(lib().poisson_server_info(self._srv, ctypes.byref(i)), "poisson_server_info")
+        return {k: getattr(i, k) for k, _ in ServerInfo._fields_ if k != "struct_size"}

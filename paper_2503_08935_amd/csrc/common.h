@@ -15,7 +15,8 @@
 namespace pz {
 
 constexpr int TX = 64;          // x extent of a tile = one wave64 row
-constexpr int TY = 4;           // y extent = waves per workgroup
+constexpr int TY = 4;           // waves per workgroup
+constexpr int RY = 4;           // y rows per wave (a tile is TY*RY rows)
 constexpr int NTHREADS = TX * TY;
 constexpr int MAXDEG = 64;      // largest Chebyshev degree
 constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double sums

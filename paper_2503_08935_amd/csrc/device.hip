@@ -9,9 +9,10 @@
 //   k_elem    : streaming vector updates fused with their dot products
 //               (Alg. 3: KernelBiCGS2, KernelBiCGS4+5, KernelBiCGS6) and the
 //               point-Jacobi / degree-0 scaling.
-// Each thread owns one (i, j) column of its tile and marches k upward keeping
-// u(k-1), u(k), u(k+1) in registers; x and y neighbours come through the
-// caches (the wave's own row and the adjacent waves' rows).
+// Each wave owns RY rows of its tile and marches k upward keeping planes
+// k-1, k, k+1 of them in registers; x neighbours move between lanes by DPP
+// wave shifts. Streams read or written once bypass the caches' retention
+// (non-temporal hint) so the stencil input's halo re-reads stay in L2.
 //
 // Arithmetic contract (matched by the independent CPU oracle):
 //   * no contraction (built with -ffp-contract=off); the only FMA is the
@@ -24,21 +25,19 @@
 //     the correctly rounded dot product except when the exact value lies within
 //     about 1e-30 (relative, times the condition number) of a rounding tie.
 //   * scalar divisions are IEEE FP64 divisions.
+#include <type_traits>
+
 #include "common.h"
 
 namespace pz {
 
 // ------------------------------------------------------------------------
-// XCD-aware tile order: workgroup g runs on XCD g % 8 (round-robin dispatch);
-// give every XCD one contiguous range of tiles so neighbouring tiles, which
-// share halo rows and planes, meet in the same L2.
+// streaming accesses: vectors read or written once per kernel are accessed
+// with the non-temporal hint, so they do not displace the stencil input (whose
+// neighbour rows and planes are re-read from L2) from the caches
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int remap_xcd(int g, int total)
-{
-    const int q = total >> 3, rem = total & 7;
-    const int x = g & 7, j = g >> 3;
-    return x * q + min(x, rem) + j;
-}
+template <typename T> __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
 // ------------------------------------------------------------------------
 // double-double arithmetic
@@ -307,7 +306,49 @@ template <> struct Coef<float> {
 };
 
 // ------------------------------------------------------------------------
+// wave64 lane exchange: DPP wavefront shift by one lane (the lane without a
+// source reads 0) and lane broadcast
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double lane_prev(double v) // lane l gets lane l-1
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_next(double v) // lane l gets lane l+1
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// ------------------------------------------------------------------------
 // stencil family
+// A tile is TX columns in x (one wave64 row) by TY*RY rows in y (wave w owns
+// RY consecutive rows) by kz planes. Each thread marches k upward keeping
+// planes k-1, k and k+1 of its RY rows in registers. x neighbours come from
+// the adjacent lanes (DPP wave shift); the two x-halo values of every row
+// come from one load per wave and plane (lanes 0..RY-1 the left ones, lanes
+// 32..32+RY-1 the right ones); y neighbours inside a wave's rows are
+// registers and the two halo rows one load each.
 // TU: element type of the stencil input; TC: arithmetic type.
 // ------------------------------------------------------------------------
 template <int OP, typename TU, typename TC, bool MASK>
@@ -322,7 +363,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int t = remap_xcd(g, total);
+        const int t = g;
         const int pid = W.tile_prob ? W.tile_prob[t] : 0;
         const int local = W.tile_prob ? W.tile_local[t] : t;
         const Prob &P = W.probs[pid];
@@ -332,23 +373,36 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
         }
         const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
         const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
-        const int i = tix * TX + lane, j = tiy * TY + wv;
+        const int i0 = tix * TX, i = i0 + lane;
+        const int j0 = tiy * (TY * RY) + wv * RY;
         const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
         double hi[NA], lo[NA];
 #pragma unroll
         for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
 
-        if (i < nx && j < ny) {
-            const size_t S = (size_t)nx * (size_t)ny;
-            size_t idx = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * (size_t)k0);
+        if (j0 < ny) { // uniform within the wave
+            const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+            size_t base = (size_t)i + NXs * ((size_t)j0 + (size_t)ny * (size_t)k0);
             const TU *__restrict__ u = (const TU *)P.vec[A.in];
             const int B = MASK ? P.block : 1;
-            const bool oxm = i > 0 && (!MASK || i % B != 0);
-            const bool oxp = i + 1 < nx && (!MASK || (i + 1) % B != 0);
-            const bool oym = j > 0 && (!MASK || j % B != 0);
-            const bool oyp = j + 1 < ny && (!MASK || (j + 1) % B != 0);
+            const bool xin = i < nx;
+            const bool oxm = xin && i > 0 && (!MASK || i % B != 0);
+            const bool oxp = xin && i + 1 < nx && (!MASK || (i + 1) % B != 0);
+            bool rin[RY], oym[RY], oyp[RY];
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int j = j0 + r;
+                rin[r] = xin && j < ny;
+                oym[r] = rin[r] && j > 0 && (!MASK || j % B != 0);
+                oyp[r] = rin[r] && j + 1 < ny && (!MASK || (j + 1) % B != 0);
+            }
+            const bool ymh = xin && j0 > 0;
+            const bool yph = xin && j0 + RY < ny;
+            const int hrow = lane & 31;
+            const bool hload = hrow < RY && j0 + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+            const size_t hbase = (size_t)(lane < 32 ? i0 - 1 : i0 + TX) +
+                                 NXs * ((size_t)(j0 + hrow) + (size_t)ny * (size_t)k0);
             const TC ih2 = Coef<TC>::ih2(P);
-            // operation constants
             TC cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
             if constexpr (OP == S_CHEB1) {
                 cA = Coef<TC>::c1(P);
@@ -371,52 +425,89 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
             double *rtw = (double *)P.vec[V_RT];
             double *pw = (double *)P.vec[V_P];
 
-            TC c = (TC)u[idx];
-            TC zm = (k0 > 0 && (!MASK || k0 % B != 0)) ? (TC)u[idx - S] : (TC)0;
-            for (int k = k0; k < k1; ++k, idx += S) {
-                const TC zr = (k + 1 < nz) ? (TC)u[idx + S] : (TC)0;
+            // type of the streamed operands: the arithmetic type for the Chebyshev steps
+            using TO = typename std::conditional<(OP == S_CHEB2 || OP == S_CHEBK), TC, double>::type;
+            TC c[RY], zm[RY];
+            const bool zm0 = k0 > 0 && (!MASK || k0 % B != 0);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                c[r] = rin[r] ? (TC)u[base + r * NXs] : (TC)0;
+                zm[r] = (rin[r] && zm0) ? (TC)u[base + r * NXs - S] : (TC)0;
+            }
+            size_t hidx = hbase;
+            for (int k = k0; k < k1; ++k, base += S, hidx += S) {
+                const bool znext = k + 1 < nz;
                 const bool zcut = MASK && ((k + 1) % B == 0);
-                const TC zp = zcut ? (TC)0 : zr;
-                const TC xm = oxm ? (TC)u[idx - 1] : (TC)0;
-                const TC xp = oxp ? (TC)u[idx + 1] : (TC)0;
-                const TC ym = oym ? (TC)u[idx - nx] : (TC)0;
-                const TC yp = oyp ? (TC)u[idx + nx] : (TC)0;
-                const TC a = (((((((TC)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-                if constexpr (OP == S_APPLY) {
-                    out[idx] = a;
-                } else if constexpr (OP == S_CHEB1) {
-                    out[idx] = cA * ((TC)2 * c - a / cB);
-                    if constexpr (sizeof(TC) == 4) v32[idx] = c;
-                } else if constexpr (OP == S_CHEB2) {
-                    const TC v = vv[idx];
-                    const TC z = v / cE;
-                    out[idx] = cA * ((cC * c + cD * (v - a)) - cB * z);
-                } else if constexpr (OP == S_CHEBK) {
-                    const TC v = vv[idx];
-                    const TC z = zz[idx];
-                    out[idx] = cA * ((cC * c + cD * (v - a)) - cB * z);
-                } else if constexpr (OP == S_SDOT) {
-                    out[idx] = a;
-                    dd_acc(hi[0], lo[0], rt[idx], a);
-                } else if constexpr (OP == S_SDOT2) {
-                    out[idx] = a;
-                    const double s = sv[idx];
-                    dd_acc(hi[0], lo[0], a, s);
-                    dd_acc(hi[1], lo[1], a, a);
-                } else if constexpr (OP == S_INIT) {
-                    const double b = bv[idx];
-                    const double r = b - a;
-                    rr[idx] = r;
-                    rtw[idx] = r;
-                    pw[idx] = r;
-                    dd_acc(hi[0], lo[0], r, r);
-                    dd_acc(hi[1], lo[1], b, b);
-                } else if constexpr (OP == S_TRUE) {
-                    const double r = bv[idx] - a;
-                    dd_acc(hi[0], lo[0], r, r);
+                TC zr[RY];
+                TO o0[RY], o1[RY];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const size_t idx = base + r * NXs;
+                    zr[r] = (rin[r] && znext) ? (TC)u[idx + S] : (TC)0;
+                    o0[r] = o1[r] = (TO)0;
+                    if (rin[r]) {
+                        if constexpr (OP == S_CHEB2) o0[r] = ld_nt(vv + idx);
+                        if constexpr (OP == S_CHEBK) { o0[r] = ld_nt(vv + idx); o1[r] = ld_nt(zz + idx); }
+                        if constexpr (OP == S_SDOT) o0[r] = ld_nt(rt + idx);
+                        if constexpr (OP == S_SDOT2) o0[r] = ld_nt(sv + idx);
+                        if constexpr (OP == S_INIT || OP == S_TRUE) o0[r] = ld_nt(bv + idx);
+                    }
                 }
-                zm = zcut ? (TC)0 : c;
-                c = zr;
+                const TC ymv = ymh ? (TC)u[base - NXs] : (TC)0;
+                const TC ypv = yph ? (TC)u[base + RY * NXs] : (TC)0;
+                const TC he = hload ? (TC)u[hidx] : (TC)0;
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    TC xm = lane_prev(c[r]), xp = lane_next(c[r]);
+                    const TC el = read_lane(he, r), er = read_lane(he, 32 + r);
+                    if (lane == 0) xm = el;
+                    if (lane == TX - 1) xp = er;
+                    xm = oxm ? xm : (TC)0;
+                    xp = oxp ? xp : (TC)0;
+                    const TC ym = oym[r] ? (r == 0 ? ymv : c[r > 0 ? r - 1 : 0]) : (TC)0;
+                    const TC yp = oyp[r] ? (r == RY - 1 ? ypv : c[r < RY - 1 ? r + 1 : 0]) : (TC)0;
+                    const TC zp = zcut ? (TC)0 : zr[r];
+                    const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zm[r]) - zp) * ih2;
+                    if (rin[r]) {
+                        const size_t idx = base + r * NXs;
+                        if constexpr (OP == S_APPLY) {
+                            st_nt(out + idx, a);
+                        } else if constexpr (OP == S_CHEB1) {
+                            st_nt(out + idx, cA * ((TC)2 * c[r] - a / cB));
+                            if constexpr (sizeof(TC) == 4) st_nt(v32 + idx, c[r]);
+                        } else if constexpr (OP == S_CHEB2) {
+                            const TC v = (TC)o0[r];
+                            const TC z = v / cE;
+                            st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
+                        } else if constexpr (OP == S_CHEBK) {
+                            const TC v = (TC)o0[r], z = (TC)o1[r];
+                            st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
+                        } else if constexpr (OP == S_SDOT) {
+                            st_nt(out + idx, a);
+                            dd_acc(hi[0], lo[0], o0[r], a);
+                        } else if constexpr (OP == S_SDOT2) {
+                            st_nt(out + idx, a);
+                            dd_acc(hi[0], lo[0], a, o0[r]);
+                            dd_acc(hi[1], lo[1], a, a);
+                        } else if constexpr (OP == S_INIT) {
+                            const double b = o0[r];
+                            const double res = b - a;
+                            st_nt(rr + idx, res);
+                            st_nt(rtw + idx, res);
+                            st_nt(pw + idx, res);
+                            dd_acc(hi[0], lo[0], res, res);
+                            dd_acc(hi[1], lo[1], b, b);
+                        } else if constexpr (OP == S_TRUE) {
+                            const double res = o0[r] - a;
+                            dd_acc(hi[0], lo[0], res, res);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    zm[r] = zcut ? (TC)0 : c[r];
+                    c[r] = zr[r];
+                }
             }
         }
         if constexpr (ND > 0) {
@@ -432,7 +523,9 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
 }
 
 // ------------------------------------------------------------------------
-// elementwise family. TP: element type of p^ / s^ (E_UPD) or of the output (E_DIV).
+// elementwise family, same tiles; each thread streams its RY rows plane by
+// plane with all loads of a plane issued together.
+// TP: element type of p^ / s^ (E_UPD) or of the output (E_DIV).
 // ------------------------------------------------------------------------
 template <int OP, typename TP>
 __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
@@ -445,7 +538,7 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int t = remap_xcd(g, total);
+        const int t = g;
         const int pid = W.tile_prob ? W.tile_prob[t] : 0;
         const int local = W.tile_prob ? W.tile_local[t] : t;
         const Prob &P = W.probs[pid];
@@ -456,60 +549,110 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
         const bool half = OP == E_UPD && sc->half_pending;
         const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
         const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
-        const int i = tix * TX + lane, j = tiy * TY + wv;
+        const int i = tix * TX + lane;
+        const int j0 = tiy * (TY * RY) + wv * RY;
         const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
         double hi[NA], lo[NA];
 #pragma unroll
         for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
 
-        if (i < nx && j < ny) {
-            const size_t S = (size_t)nx * (size_t)ny;
-            size_t idx = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * (size_t)k0);
+        if (j0 < ny && i < nx) {
+            const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+            size_t base = (size_t)i + NXs * ((size_t)j0 + (size_t)ny * (size_t)k0);
+            bool rin[RY];
+#pragma unroll
+            for (int r = 0; r < RY; ++r) rin[r] = j0 + r < ny;
             const double alpha = sc->alpha, omega = sc->omega, beta = sc->beta;
-            if constexpr (OP == E_AXPY) {
-                double *r = (double *)P.vec[V_R];
-                const double *__restrict__ w = (const double *)P.vec[V_W];
-                for (int k = k0; k < k1; ++k, idx += S) {
-                    const double s = r[idx] - alpha * w[idx];
-                    r[idx] = s;
-                    dd_acc(hi[0], lo[0], s, s);
-                }
-            } else if constexpr (OP == E_UPD) {
-                double *x = (double *)P.vec[V_X];
-                const TP *ph = (const TP *)P.vec[A.in];
-                const TP *sh = (const TP *)P.vec[A.x2];
-                double *r = (double *)P.vec[V_R];
-                const double *__restrict__ tv = (const double *)P.vec[V_T];
-                const double *__restrict__ rt = (const double *)P.vec[V_RT];
-                if (half) {
-                    for (int k = k0; k < k1; ++k, idx += S)
-                        x[idx] = x[idx] + alpha * (double)ph[idx];
-                } else {
-                    for (int k = k0; k < k1; ++k, idx += S) {
-                        const double s = r[idx];
-                        const double shv = (double)sh[idx];
-                        x[idx] = (x[idx] + alpha * (double)ph[idx]) + omega * shv;
-                        const double rn = s - omega * tv[idx];
-                        r[idx] = rn;
-                        dd_acc(hi[0], lo[0], rt[idx], rn);
-                        dd_acc(hi[1], lo[1], rn, rn);
+            for (int k = k0; k < k1; ++k, base += S) {
+                if constexpr (OP == E_AXPY) {
+                    double *r_ = (double *)P.vec[V_R];
+                    const double *__restrict__ w = (const double *)P.vec[V_W];
+                    double a[RY], b[RY];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) { a[r] = ld_nt(r_ + base + r * NXs); b[r] = ld_nt(w + base + r * NXs); }
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) {
+                            const double s = a[r] - alpha * b[r];
+                            st_nt(r_ + base + r * NXs, s);
+                            dd_acc(hi[0], lo[0], s, s);
+                        }
+                } else if constexpr (OP == E_UPD) {
+                    double *x = (double *)P.vec[V_X];
+                    const TP *ph = (const TP *)P.vec[A.in];
+                    const TP *sh = (const TP *)P.vec[A.x2];
+                    double *r_ = (double *)P.vec[V_R];
+                    const double *__restrict__ tv = (const double *)P.vec[V_T];
+                    const double *__restrict__ rt = (const double *)P.vec[V_RT];
+                    double xv[RY], pv[RY];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) { xv[r] = ld_nt(x + base + r * NXs); pv[r] = (double)ld_nt(ph + base + r * NXs); }
+                    if (half) {
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+                            if (rin[r]) st_nt(x + base + r * NXs, xv[r] + alpha * pv[r]);
+                    } else {
+                        double sv[RY], shv[RY], tt[RY], rtv[RY];
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+                            if (rin[r]) {
+                                const size_t idx = base + r * NXs;
+                                sv[r] = ld_nt(r_ + idx);
+                                shv[r] = (double)ld_nt(sh + idx);
+                                tt[r] = ld_nt(tv + idx);
+                                rtv[r] = ld_nt(rt + idx);
+                            }
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+                            if (rin[r]) {
+                                const size_t idx = base + r * NXs;
+                                st_nt(x + idx, (xv[r] + alpha * pv[r]) + omega * shv[r]);
+                                const double rn = sv[r] - omega * tt[r];
+                                st_nt(r_ + idx, rn);
+                                dd_acc(hi[0], lo[0], rtv[r], rn);
+                                dd_acc(hi[1], lo[1], rn, rn);
+                            }
                     }
+                } else if constexpr (OP == E_PUPD) {
+                    double *p = (double *)P.vec[V_P];
+                    const double *__restrict__ r_ = (const double *)P.vec[V_R];
+                    const double *__restrict__ w = (const double *)P.vec[V_W];
+                    double a[RY], b[RY], c[RY];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) {
+                            const size_t idx = base + r * NXs;
+                            a[r] = ld_nt(r_ + idx);
+                            b[r] = ld_nt(p + idx);
+                            c[r] = ld_nt(w + idx);
+                        }
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) st_nt(p + base + r * NXs, a[r] + beta * (b[r] - omega * c[r]));
+                } else if constexpr (OP == E_DIV) {
+                    const double *__restrict__ v = (const double *)P.vec[A.in];
+                    TP *out = (TP *)P.vec[A.out];
+                    const TP d = A.divisor ? Coef<TP>::theta(P) : Coef<TP>::jac(P);
+                    double a[RY];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) a[r] = ld_nt(v + base + r * NXs);
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) st_nt(out + base + r * NXs, (TP)a[r] / d);
+                } else if constexpr (OP == E_DOT) {
+                    const double *__restrict__ xv = (const double *)P.vec[A.in];
+                    const double *__restrict__ yv = (const double *)P.vec[A.x2];
+                    double a[RY], b[RY];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) { a[r] = ld_nt(xv + base + r * NXs); b[r] = ld_nt(yv + base + r * NXs); }
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+                        if (rin[r]) dd_acc(hi[0], lo[0], a[r], b[r]);
                 }
-            } else if constexpr (OP == E_PUPD) {
-                double *p = (double *)P.vec[V_P];
-                const double *__restrict__ r = (const double *)P.vec[V_R];
-                const double *__restrict__ w = (const double *)P.vec[V_W];
-                for (int k = k0; k < k1; ++k, idx += S)
-                    p[idx] = r[idx] + beta * (p[idx] - omega * w[idx]);
-            } else if constexpr (OP == E_DIV) {
-                const double *__restrict__ v = (const double *)P.vec[A.in];
-                TP *out = (TP *)P.vec[A.out];
-                const TP d = A.divisor ? Coef<TP>::theta(P) : Coef<TP>::jac(P);
-                for (int k = k0; k < k1; ++k, idx += S) out[idx] = (TP)v[idx] / d;
-            } else if constexpr (OP == E_DOT) {
-                const double *__restrict__ xv = (const double *)P.vec[A.in];
-                const double *__restrict__ yv = (const double *)P.vec[A.x2];
-                for (int k = k0; k < k1; ++k, idx += S) dd_acc(hi[0], lo[0], xv[idx], yv[idx]);
             }
         }
         if constexpr (ND > 0) {
@@ -522,7 +665,6 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
         }
     }
 }
-
 // ------------------------------------------------------------------------
 // synthetic right-hand sides: counter-based splitmix64
 // ------------------------------------------------------------------------

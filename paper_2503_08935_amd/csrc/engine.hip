@@ -17,58 +17,11 @@
 #include <tuple>
 #include <vector>
 
-#include "common.h"
-#include "poisson.h"
+#include "plan.h"
 
 using namespace pz;
 
 namespace {
-
-bool debug_on()
-{
-    static int v = -1;
-    if (v < 0) v = getenv("POISSON_DEBUG") ? 1 : 0;
-    return v == 1;
-}
-
-#define HIPCHK(expr)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess) {                                                        \
-            if (debug_on())                                                            \
-                fprintf(stderr, "poisson: %s failed: %s (%s:%d)\n", #expr,            \
-                        hipGetErrorString(e_), __FILE__, __LINE__);                    \
-            return POISSON_ERR_DEVICE;                                                 \
-        }                                                                              \
-    } while (0)
-
-// ---- spectrum: eq. eigenvaluesPoissonDirichletMatrix, eqs. lambdaMin/lambdaMax ----
-double dirichlet_eig(int i, int n)
-{
-    const double s = sin((double)i * M_PI / (2.0 * (double)(n + 1)));
-    return 4.0 * s * s;
-}
-
-void grid_interval(int nx, int ny, int nz, double h, int block, double &lo, double &hi)
-{
-    int n[3] = {nx, ny, nz};
-    if (block > 0)
-        for (int &v : n) v = std::min(v, block);
-    const double h2 = h * h;
-    lo = dirichlet_eig(1, n[0]) / h2 + dirichlet_eig(1, n[1]) / h2 + dirichlet_eig(1, n[2]) / h2;
-    hi = dirichlet_eig(n[0], n[0]) / h2 + dirichlet_eig(n[1], n[1]) / h2 +
-         dirichlet_eig(n[2], n[2]) / h2;
-}
-
-int choose_kz(int tx, int ty, int nz)
-{
-    // z-chunk per tile: long chunks amortise the two halo planes, but keep at
-    // least ~2048 tiles so 256 CUs have several workgroups each
-    int kz = 64;
-    const long base = (long)tx * ty;
-    while (kz > 8 && base * ((nz + kz - 1) / kz) < 2048) kz /= 2;
-    return std::min(kz, std::max(nz, 1));
-}
 
 struct GraphKey {
     int pc, deg, mixed, iters;
@@ -80,12 +33,6 @@ struct GraphKey {
 
 constexpr int MAX_HIST_ITERS = 1 << 16; // per-iteration scalars kept on the device
 
-double now_ms()
-{
-    using namespace std::chrono;
-    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
 } // namespace
 
 struct poisson_ctx {
@@ -95,11 +42,10 @@ struct poisson_ctx {
     size_t N = 0;
     hipStream_t stream = nullptr;
     // options
-    int precision = POISSON_FP64, block = 64, bj_global = 0, graph_iters = 8, use_graph = 1;
-    int debug_bd = -1;
-    double lmin_scale = 1.0, lmax_scale = 1.0;
+    int precision = POISSON_FP64, graph_iters = 8, use_graph = 1;
+    PlanOpts opt;
     // tiling
-    int kz = 8, tx = 1, ty = 1, tz = 1, ntiles = 1;
+    int ntiles = 1;
     // device state
     bool dev = false;
     hipStream_t cap_stream = nullptr;
@@ -128,21 +74,6 @@ struct poisson_ctx {
 
 namespace {
 
-size_t vec_bytes(const poisson_ctx *c, int v, int pc, int deg, bool mixed)
-{
-    const size_t N = c->N;
-    const bool cheb = pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI;
-    const size_t tp = (mixed && pc != POISSON_PC_NONE) ? 4 : 8;
-    switch (v) {
-    case V_R: case V_RT: case V_P: case V_W: case V_T: return 8 * N;
-    case V_PH: case V_SH: return pc != POISSON_PC_NONE ? tp * N : 0;
-    case V_RA: return cheb && deg >= 2 ? tp * N : 0;
-    case V_RB: return cheb && deg >= 3 ? tp * N : 0;
-    case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
-    default: return 0;
-    }
-}
-
 int ensure_device(poisson_ctx *c)
 {
     if (c->dev) return POISSON_OK;
@@ -162,11 +93,10 @@ int ensure_device(poisson_ctx *c)
     return POISSON_OK;
 }
 
-// carve the workspace for a plan; grows (never shrinks) the allocation
+// size the workspace for a plan; grows (never shrinks) the allocation
 int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 {
-    size_t need = 0;
-    for (int v = 0; v < V_COUNT; ++v) need += (vec_bytes(c, v, pc, deg, mixed) + 255) & ~(size_t)255;
+    const size_t need = workspace_bytes(c->N, pc, deg, mixed);
     if (need > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -178,143 +108,17 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
         }
         c->ws_bytes = need;
     }
-    size_t off = 0;
-    for (int v = 0; v < V_COUNT; ++v) {
-        const size_t b = vec_bytes(c, v, pc, deg, mixed);
-        c->vec[v] = b ? c->ws + off : nullptr;
-        off += (b + 255) & ~(size_t)255;
-    }
+    Prob tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed);
+    for (int v = 0; v < V_COUNT; ++v) c->vec[v] = tmp.vec[v];
     return POISSON_OK;
 }
 
-// fill a descriptor: geometry, tolerance, Chebyshev coefficients (Alg. 2 scalars)
-int fill_prob(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
+int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 {
-    memset(&p, 0, sizeof(Prob));
-    p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.kz = c->kz;
-    p.tx = c->tx; p.ty = c->ty; p.tz = c->tz; p.ntiles = c->ntiles;
-    p.block = pc == POISSON_PC_BLOCK_JACOBI ? c->block : 0;
-    p.maxit = maxit;
-    p.debug_breakdown_at = c->debug_bd;
-    p.degree = deg;
-    p.ih2 = 1.0 / (c->h * c->h);
-    p.ih2f = (float)p.ih2;
-    p.tol2 = tol * tol;
-    p.jac_d = 6.0 * p.ih2;
-    p.jac_df = (float)p.jac_d;
-    c->plan_lo = c->plan_hi = 0;
-    if (pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI) {
-        const int local = (pc == POISSON_PC_BLOCK_JACOBI && !c->bj_global) ? c->block : 0;
-        double lo, hi;
-        grid_interval(c->nx, c->ny, c->nz, c->h, local, lo, hi);
-        lo = lo * c->lmin_scale;
-        hi = hi * c->lmax_scale;
-        if (!(lo > 0) || !(hi > lo) || !std::isfinite(hi)) return POISSON_ERR_ARG;
-        c->plan_lo = lo;
-        c->plan_hi = hi;
-        const double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
-        double rho_old = 1.0 / sigma;
-        double rho_cur = 1.0 / (2.0 * sigma - rho_old);
-        p.theta = theta;
-        p.c1 = 2.0 * rho_cur / delta;
-        p.two_sigma = 2.0 * sigma;
-        p.two_over_delta = 2.0 / delta;
-        for (int i = 2; i <= deg; ++i) {
-            rho_old = rho_cur;
-            rho_cur = 1.0 / (2.0 * sigma - rho_old);
-            p.rc[i] = rho_cur;
-            p.ro[i] = rho_old;
-        }
-        p.thetaf = (float)p.theta;
-        p.c1f = (float)p.c1;
-        p.two_sigmaf = (float)p.two_sigma;
-        p.two_over_deltaf = (float)p.two_over_delta;
-        for (int i = 0; i <= MAXDEG; ++i) {
-            p.rcf[i] = (float)p.rc[i];
-            p.rof[i] = (float)p.ro[i];
-        }
-    }
-    return POISSON_OK;
-}
-
-// preconditioner apply vout = M^-1 vin (Alg. 2; BJ(CI) with the masked operator)
-void enqueue_pc(const poisson_ctx *c, const Work &w, hipStream_t s, int pc, int m, bool mixed,
-                int vin, int vout, int second)
-{
-    if (pc == POISSON_PC_NONE) return;
-    const int grid = c->ntiles;
-    if (pc == POISSON_PC_JACOBI || m == 0) {
-        KArgs a{vin, vout, 0, 0, 0, second, pc == POISSON_PC_JACOBI ? 0 : 1, 0};
-        launch_elem(E_DIV, mixed, w, grid, s, a);
-        return;
-    }
-    const bool mask = pc == POISSON_PC_BLOCK_JACOBI;
-    KArgs a1{vin, m == 1 ? vout : (int)V_RA, 0, 0, 1, second, 0, 0};
-    launch_stencil(S_CHEB1, mixed, mask, w, grid, s, a1);
-    const int vsrc = mixed ? (int)V_V32 : vin;
-    for (int i = 2; i <= m; ++i) {
-        // step i reads y = buf(i-1), z = buf(i-2), writes buf(i) (in place over z)
-        // where buf(odd) = RA, buf(even) = RB, and the last step writes vout
-        const int y = ((i - 1) & 1) ? V_RA : V_RB;
-        const int z = ((i - 2) & 1) ? V_RA : V_RB;
-        const int out = i == m ? vout : ((i & 1) ? V_RA : V_RB);
-        KArgs a{y, out, vsrc, z, i, second, 0, 0};
-        launch_stencil(i == 2 ? S_CHEB2 : S_CHEBK, mixed, mask, w, grid, s, a);
-    }
-}
-
-// one Bi-CGSTAB iteration in the kernel order of Alg. 3
-void enqueue_iteration(const poisson_ctx *c, const Work &w, hipStream_t s, int pc, int m,
-                       bool mixed)
-{
-    const int grid = c->ntiles;
-    const bool pm = mixed && pc != POISSON_PC_NONE;
-    const int ph = pc == POISSON_PC_NONE ? V_P : V_PH;
-    const int sh = pc == POISSON_PC_NONE ? V_R : V_SH;
-    enqueue_pc(c, w, s, pc, m, mixed, V_P, V_PH, 0);                     // M p^ = p
-    launch_stencil(S_SDOT, pm, false, w, grid, s, KArgs{ph, V_W, 0, 0, 0, 0, 0, 0}); // w, alpha
-    launch_elem(E_AXPY, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});         // s, half step
-    enqueue_pc(c, w, s, pc, m, mixed, V_R, V_SH, 1);                     // M s^ = s
-    launch_stencil(S_SDOT2, pm, false, w, grid, s, KArgs{sh, V_T, 0, 0, 0, 1, 0, 0}); // t, omega
-    launch_elem(E_UPD, pm, w, grid, s, KArgs{ph, 0, 0, 0, 0, 0, 0, sh});           // x, r, beta
-    launch_elem(E_PUPD, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});         // p
-}
-
-// algorithmic bytes per unknown of one iteration of a plan
-double iteration_bytes(int pc, int m, bool mixed)
-{
-    const bool pm = mixed && pc != POISSON_PC_NONE;
-    const double tp = pm ? 4 : 8;
-    double pcb = 0;
-    if (pc == POISSON_PC_JACOBI || ((pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI) && m == 0))
-        pcb = 8 + tp;
-    else if (pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI) {
-        const double tc = mixed ? 4 : 8;
-        pcb = 8 + tc + (mixed ? 4 : 0);                 // first step: v, y (+ v32)
-        if (m >= 2) pcb += 3 * tc;                      // step 2: y, v, w
-        if (m >= 3) pcb += (m - 2) * 4 * tc;            // steps 3..m: y, v, z, w
-    }
-    double b = 2 * pcb;
-    b += tp + 16;                                        // w = A p^, r~.w
-    b += 24;                                             // s = r - alpha w
-    b += tp + 16;                                        // t = A s^, t.s, t.t
-    b += pc == POISSON_PC_NONE ? 56 : 48 + 2 * tp;       // x, r updates
-    b += 32;                                             // p update
-    return b;
-}
-
-int validate_ptr(const void *p)
-{
-    if (!p) return POISSON_ERR_ARG;
-    if (((uintptr_t)p) & 15) return POISSON_ERR_ARG;
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return POISSON_ERR_DEVICE;
-    }
-    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
-        return POISSON_ERR_ARG;
-    return POISSON_OK;
+    return fill_prob(p, c->nx, c->ny, c->nz, c->h, pc, deg, c->opt, tol, maxit, &c->plan_lo,
+                     &c->plan_hi);
 }
 
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
@@ -328,7 +132,7 @@ int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec
     Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles};
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) enqueue_iteration(c, w, c->cap_stream, pc, m, mixed);
+    for (int i = 0; i < iters; ++i) enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipGraphExec_t e = nullptr;
     HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -374,7 +178,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
         c->hist_cap = 1 + 4 * hist_iters;
     }
     Prob &p = c->h_prob[0];
-    if ((rc = fill_prob(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
+    if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
     for (int v = 0; v < V_COUNT; ++v) p.vec[v] = c->vec[v];
     p.vec[V_X] = x;
     p.vec[V_B] = (void *)rhs;
@@ -404,7 +208,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
             if (c->use_graph) {
                 HIPCHK(hipGraphLaunch(g, c->stream));
             } else {
-                for (int i = 0; i < K; ++i) enqueue_iteration(c, w, c->stream, pc, deg, mixed);
+                for (int i = 0; i < K; ++i) enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed);
                 HIPCHK(hipGetLastError());
             }
             if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -483,11 +287,7 @@ int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **
     if (!c) return POISSON_ERR_NOMEM;
     c->nx = nx; c->ny = ny; c->nz = nz; c->h = h; c->bc = bc;
     c->N = (size_t)nx * ny * nz;
-    c->tx = (nx + TX - 1) / TX;
-    c->ty = (ny + TY - 1) / TY;
-    c->kz = choose_kz(c->tx, c->ty, nz);
-    c->tz = (nz + c->kz - 1) / c->kz;
-    c->ntiles = c->tx * c->ty * c->tz;
+    c->ntiles = make_tiling(nx, ny, nz).ntiles;
     *out = c;
     return POISSON_OK;
 }
@@ -502,19 +302,19 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         return POISSON_OK;
     case POISSON_OPT_BLOCK:
         if (v < 2 || v > 4096 || v != std::floor(v)) return POISSON_ERR_ARG;
-        c->block = (int)v;
+        c->opt.block = (int)v;
         return POISSON_OK;
     case POISSON_OPT_LMIN_SCALE:
         if (!(v > 0)) return POISSON_ERR_ARG;
-        c->lmin_scale = v;
+        c->opt.lmin_scale = v;
         return POISSON_OK;
     case POISSON_OPT_LMAX_SCALE:
         if (!(v > 0)) return POISSON_ERR_ARG;
-        c->lmax_scale = v;
+        c->opt.lmax_scale = v;
         return POISSON_OK;
     case POISSON_OPT_BJ_GLOBAL_INTERVAL:
         if (v != 0 && v != 1) return POISSON_ERR_ARG;
-        c->bj_global = (int)v;
+        c->opt.bj_global = (int)v;
         return POISSON_OK;
     case POISSON_OPT_GRAPH_ITERS:
         if (v < 1 || v > 256 || v != std::floor(v)) return POISSON_ERR_ARG;
@@ -526,7 +326,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         return POISSON_OK;
     case POISSON_OPT_DEBUG_BREAKDOWN_AT:
         if (v != std::floor(v)) return POISSON_ERR_ARG;
-        c->debug_bd = (int)v;
+        c->opt.debug_bd = (int)v;
         return POISSON_OK;
     default:
         return POISSON_ERR_ARG;
@@ -551,14 +351,10 @@ int poisson_solve(poisson_ctx *c, const double *rhs, double *x, int precond, int
     if (precond != POISSON_PC_CHEBYSHEV && precond != POISSON_PC_BLOCK_JACOBI) degree = 0;
     if (!(tol > 0) || !(tol < 1)) return POISSON_ERR_ARG;
     if (maxit < 1 || maxit > 10000000) return POISSON_ERR_ARG;
-    if (precond == POISSON_PC_CHEBYSHEV || precond == POISSON_PC_BLOCK_JACOBI) {
+    if (is_cheb(precond)) {
         // reject a degenerate interval before touching the device
-        const int local = (precond == POISSON_PC_BLOCK_JACOBI && !c->bj_global) ? c->block : 0;
         double lo, hi;
-        grid_interval(c->nx, c->ny, c->nz, c->h, local, lo, hi);
-        lo *= c->lmin_scale;
-        hi *= c->lmax_scale;
-        if (!(lo > 0) || !(hi > lo)) return POISSON_ERR_ARG;
+        if (!cheb_interval(c->nx, c->ny, c->nz, c->h, precond, c->opt, lo, hi)) return POISSON_ERR_ARG;
     }
     try {
         c->have_stats = false;
@@ -629,7 +425,7 @@ static int prim_begin(poisson_ctx *c, int pc, int deg, bool mixed)
     int rc;
     if ((rc = ensure_device(c)) != POISSON_OK) return rc;
     Prob &p = c->h_prob[1];
-    if ((rc = fill_prob(c, p, pc, deg, 0.5, 1)) != POISSON_OK) return rc;
+    if ((rc = fill(c, p, pc, deg, 0.5, 1)) != POISSON_OK) return rc;
     p.sc = c->d_sc + 1;
     p.partials = c->d_partials + (size_t)c->ntiles * PARTIAL_STRIDE;
     p.hist = nullptr;
@@ -675,7 +471,7 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
         p.vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
         const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles};
-        enqueue_pc(c, w, c->stream, precond, degree, mixed, V_B, V_X, 0);
+        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, V_B, V_X, 0);
         HIPCHK(hipGetLastError());
         return POISSON_OK;
     } catch (...) {
@@ -723,7 +519,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
     if (precision != POISSON_FP64 && precision != POISSON_MIXED) return POISSON_ERR_ARG;
     const bool mixed = precision == POISSON_MIXED;
     if (mixed != (bool)c->plan_mixed) return POISSON_ERR_ARG;
-    const bool cheb = c->plan_pc == POISSON_PC_CHEBYSHEV || c->plan_pc == POISSON_PC_BLOCK_JACOBI;
+    const bool cheb = is_cheb(c->plan_pc);
     if (kernel == POISSON_KERNEL_CHEB_STEP && !(cheb && c->plan_deg >= 3)) return POISSON_ERR_ARG;
     if ((kernel == POISSON_KERNEL_STENCIL_DOT || kernel == POISSON_KERNEL_UPDATE_XR) &&
         c->plan_pc == POISSON_PC_NONE)

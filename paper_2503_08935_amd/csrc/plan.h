@@ -1,0 +1,58 @@
+// Host-side planning shared by single solves (engine.hip) and the batched
+// server (server.hip): tiling, the Chebyshev interval and coefficients, buffer
+// sizes, and the kernel sequence of one Bi-CGSTAB iteration.
+#pragma once
+#include <cstdio>
+#include <cstdlib>
+
+#include "common.h"
+#include "poisson.h"
+
+namespace pz {
+
+bool debug_on();
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            if (::pz::debug_on())                                                      \
+                fprintf(stderr, "poisson: %s failed: %s (%s:%d)\n", #expr,            \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                    \
+            return POISSON_ERR_DEVICE;                                                 \
+        }                                                                              \
+    } while (0)
+
+struct Tiling {
+    int tx, ty, kz, tz, ntiles;
+};
+
+struct PlanOpts {
+    int block = 64;          // Block-Jacobi block edge
+    int bj_global = 0;       // 1: GNoComm(CI), global interval on the masked operator
+    double lmin_scale = 1.0, lmax_scale = 1.0;
+    int debug_bd = -1;
+};
+
+Tiling make_tiling(int nx, int ny, int nz);
+bool is_cheb(int pc);
+// interval handed to the Chebyshev iteration; false if degenerate
+bool cheb_interval(int nx, int ny, int nz, double h, int pc, const PlanOpts &o, double &lo,
+                   double &hi);
+// geometry, tolerance and coefficients; vectors, scalars, partials are left null
+int fill_prob(Prob &p, int nx, int ny, int nz, double h, int pc, int deg, const PlanOpts &o,
+              double tol, int maxit, double *lo, double *hi);
+// bytes of vector slot v for a plan (0 if unused)
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed);
+// total workspace of a plan, each slot 256-byte aligned
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed);
+// carve a workspace into the vector slots of p
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed);
+void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int vin,
+                int vout, int second);
+void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed);
+double iteration_bytes(int pc, int m, bool mixed);
+int validate_ptr(const void *p);
+double now_ms();
+
+} // namespace pz

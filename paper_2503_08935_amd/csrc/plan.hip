@@ -1,0 +1,232 @@
+// plan.hip -- host-side planning shared by single solves and the server.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "plan.h"
+
+namespace pz {
+
+bool debug_on()
+{
+    static int v = -1;
+    if (v < 0) v = getenv("POISSON_DEBUG") ? 1 : 0;
+    return v == 1;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// i-th eigenvalue of the order-n Dirichlet matrix D (eq. eigenvaluesPoissonDirichletMatrix)
+static double dirichlet_eig(int i, int n)
+{
+    const double s = sin((double)i * M_PI / (2.0 * (double)(n + 1)));
+    return 4.0 * s * s;
+}
+
+// lambda_min, lambda_max of the Kronecker sum (eqs. lambdaMin, lambdaMax); with
+// block > 0 the spectrum of one block x block x block diagonal block
+static void grid_interval(int nx, int ny, int nz, double h, int block, double &lo, double &hi)
+{
+    int n[3] = {nx, ny, nz};
+    if (block > 0)
+        for (int &v : n) v = std::min(v, block);
+    const double h2 = h * h;
+    lo = dirichlet_eig(1, n[0]) / h2 + dirichlet_eig(1, n[1]) / h2 + dirichlet_eig(1, n[2]) / h2;
+    hi = dirichlet_eig(n[0], n[0]) / h2 + dirichlet_eig(n[1], n[1]) / h2 +
+         dirichlet_eig(n[2], n[2]) / h2;
+}
+
+Tiling make_tiling(int nx, int ny, int nz)
+{
+    Tiling t;
+    t.tx = (nx + TX - 1) / TX;
+    t.ty = (ny + TY * RY - 1) / (TY * RY);
+    // z-chunk per tile: long chunks amortise the two halo planes, but keep at
+    // least ~2048 tiles so 256 CUs have several workgroups each
+    int kz = 64;
+    const long base = (long)t.tx * t.ty;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < 2048) kz /= 2;
+    t.kz = std::min(kz, std::max(nz, 1));
+    t.tz = (nz + t.kz - 1) / t.kz;
+    t.ntiles = t.tx * t.ty * t.tz;
+    return t;
+}
+
+bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI; }
+
+bool cheb_interval(int nx, int ny, int nz, double h, int pc, const PlanOpts &o, double &lo,
+                   double &hi)
+{
+    const int local = (pc == POISSON_PC_BLOCK_JACOBI && !o.bj_global) ? o.block : 0;
+    grid_interval(nx, ny, nz, h, local, lo, hi);
+    lo = lo * o.lmin_scale;
+    hi = hi * o.lmax_scale;
+    return lo > 0 && hi > lo && std::isfinite(hi);
+}
+
+int fill_prob(Prob &p, int nx, int ny, int nz, double h, int pc, int deg, const PlanOpts &o,
+              double tol, int maxit, double *lo_out, double *hi_out)
+{
+    memset(&p, 0, sizeof(Prob));
+    const Tiling t = make_tiling(nx, ny, nz);
+    p.nx = nx; p.ny = ny; p.nz = nz; p.kz = t.kz;
+    p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
+    p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
+    p.maxit = maxit;
+    p.debug_breakdown_at = o.debug_bd;
+    p.degree = deg;
+    p.ih2 = 1.0 / (h * h);
+    p.ih2f = (float)p.ih2;
+    p.tol2 = tol * tol;
+    p.jac_d = 6.0 * p.ih2;
+    p.jac_df = (float)p.jac_d;
+    if (lo_out) *lo_out = 0;
+    if (hi_out) *hi_out = 0;
+    if (is_cheb(pc)) {
+        double lo, hi;
+        if (!cheb_interval(nx, ny, nz, h, pc, o, lo, hi)) return POISSON_ERR_ARG;
+        if (lo_out) *lo_out = lo;
+        if (hi_out) *hi_out = hi;
+        // Alg. 2 scalars: theta, delta, sigma (eq. chebyshevQuantities) and the
+        // rho recurrence rho_0 = 1/sigma, rho_i = 1/(2 sigma - rho_{i-1})
+        const double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
+        double rho_old = 1.0 / sigma;
+        double rho_cur = 1.0 / (2.0 * sigma - rho_old);
+        p.theta = theta;
+        p.c1 = 2.0 * rho_cur / delta;
+        p.two_sigma = 2.0 * sigma;
+        p.two_over_delta = 2.0 / delta;
+        for (int i = 2; i <= deg; ++i) {
+            rho_old = rho_cur;
+            rho_cur = 1.0 / (2.0 * sigma - rho_old);
+            p.rc[i] = rho_cur;
+            p.ro[i] = rho_old;
+        }
+        p.thetaf = (float)p.theta;
+        p.c1f = (float)p.c1;
+        p.two_sigmaf = (float)p.two_sigma;
+        p.two_over_deltaf = (float)p.two_over_delta;
+        for (int i = 0; i <= MAXDEG; ++i) {
+            p.rcf[i] = (float)p.rc[i];
+            p.rof[i] = (float)p.ro[i];
+        }
+    }
+    return POISSON_OK;
+}
+
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed)
+{
+    const bool cheb = is_cheb(pc);
+    const size_t tp = (mixed && pc != POISSON_PC_NONE) ? 4 : 8;
+    switch (v) {
+    case V_R: case V_RT: case V_P: case V_W: case V_T: return 8 * N;
+    case V_PH: case V_SH: return pc != POISSON_PC_NONE ? tp * N : 0;
+    case V_RA: return cheb && deg >= 2 ? tp * N : 0;
+    case V_RB: return cheb && deg >= 3 ? tp * N : 0;
+    case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
+    default: return 0;
+    }
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed)
+{
+    size_t need = 0;
+    for (int v = 0; v < V_COUNT; ++v) need += align256(vec_bytes(N, v, pc, deg, mixed));
+    return need;
+}
+
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed)
+{
+    size_t off = 0;
+    for (int v = 0; v < V_COUNT; ++v) {
+        const size_t b = vec_bytes(N, v, pc, deg, mixed);
+        if (v != V_X && v != V_B) p.vec[v] = b ? ws + off : nullptr;
+        off += align256(b);
+    }
+}
+
+// preconditioner apply vout = M^-1 vin (Alg. 2; BJ(CI) with the masked operator)
+void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int vin,
+                int vout, int second)
+{
+    if (pc == POISSON_PC_NONE) return;
+    if (pc == POISSON_PC_JACOBI || m == 0) {
+        KArgs a{vin, vout, 0, 0, 0, second, pc == POISSON_PC_JACOBI ? 0 : 1, 0};
+        launch_elem(E_DIV, mixed, w, grid, s, a);
+        return;
+    }
+    const bool mask = pc == POISSON_PC_BLOCK_JACOBI;
+    KArgs a1{vin, m == 1 ? vout : (int)V_RA, 0, 0, 1, second, 0, 0};
+    launch_stencil(S_CHEB1, mixed, mask, w, grid, s, a1);
+    const int vsrc = mixed ? (int)V_V32 : vin;
+    for (int i = 2; i <= m; ++i) {
+        // step i reads y = buf(i-1), z = buf(i-2), writes buf(i) (in place over z)
+        // where buf(odd) = RA, buf(even) = RB, and the last step writes vout
+        const int y = ((i - 1) & 1) ? V_RA : V_RB;
+        const int z = ((i - 2) & 1) ? V_RA : V_RB;
+        const int out = i == m ? vout : ((i & 1) ? V_RA : V_RB);
+        KArgs a{y, out, vsrc, z, i, second, 0, 0};
+        launch_stencil(i == 2 ? S_CHEB2 : S_CHEBK, mixed, mask, w, grid, s, a);
+    }
+}
+
+// one Bi-CGSTAB iteration in the kernel order of Alg. 3
+void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed)
+{
+    const bool pm = mixed && pc != POISSON_PC_NONE;
+    const int ph = pc == POISSON_PC_NONE ? V_P : V_PH;
+    const int sh = pc == POISSON_PC_NONE ? V_R : V_SH;
+    enqueue_pc(w, grid, s, pc, m, mixed, V_P, V_PH, 0);                            // M p^ = p
+    launch_stencil(S_SDOT, pm, false, w, grid, s, KArgs{ph, V_W, 0, 0, 0, 0, 0, 0});  // w, alpha
+    launch_elem(E_AXPY, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // s, half step
+    enqueue_pc(w, grid, s, pc, m, mixed, V_R, V_SH, 1);                            // M s^ = s
+    launch_stencil(S_SDOT2, pm, false, w, grid, s, KArgs{sh, V_T, 0, 0, 0, 1, 0, 0}); // t, omega
+    launch_elem(E_UPD, pm, w, grid, s, KArgs{ph, 0, 0, 0, 0, 0, 0, sh});            // x, r, beta
+    launch_elem(E_PUPD, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // p
+}
+
+// algorithmic bytes per unknown of one iteration of a plan
+double iteration_bytes(int pc, int m, bool mixed)
+{
+    const bool pm = mixed && pc != POISSON_PC_NONE;
+    const double tp = pm ? 4 : 8;
+    double pcb = 0;
+    if (pc == POISSON_PC_JACOBI || (is_cheb(pc) && m == 0))
+        pcb = 8 + tp;
+    else if (is_cheb(pc)) {
+        const double tc = mixed ? 4 : 8;
+        pcb = 8 + tc + (mixed ? 4 : 0);                 // first step: v, y (+ v32)
+        if (m >= 2) pcb += 3 * tc;                      // step 2: y, v, w
+        if (m >= 3) pcb += (m - 2) * 4 * tc;            // steps 3..m: y, v, z, w
+    }
+    double b = 2 * pcb;
+    b += tp + 16;                                        // w = A p^, r~.w
+    b += 24;                                             // s = r - alpha w
+    b += tp + 16;                                        // t = A s^, t.s, t.t
+    b += pc == POISSON_PC_NONE ? 56 : 48 + 2 * tp;       // x, r updates
+    b += 32;                                             // p update
+    return b;
+}
+
+int validate_ptr(const void *p)
+{
+    if (!p) return POISSON_ERR_ARG;
+    if (((uintptr_t)p) & 15) return POISSON_ERR_ARG;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return POISSON_ERR_DEVICE;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return POISSON_ERR_ARG;
+    return POISSON_OK;
+}
+
+} // namespace pz

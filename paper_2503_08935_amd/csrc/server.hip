@@ -1,0 +1,547 @@
+// server.hip -- continuous-batching solve server.
+//
+// Requests (one Poisson solve each, any grid size) are queued FIFO and
+// admitted while a slot is free and their workspace fits in a fixed HBM arena
+// (first-fit allocation, freed on retirement). Every admitted request keeps its
+// Krylov vectors resident in its arena block. poisson_server_step() retires
+// finished requests, admits new ones (one batched initial-residual launch for
+// all of them), then advances every running request by the same number of
+// Bi-CGSTAB iterations: each kernel of the iteration is launched once per plan
+// group (precond, degree, precision) over the tiles of all requests in the
+// group, from a captured HIP graph whose tile list and tile count live in
+// device memory, so the graph does not change when the batch does.
+// Reductions are per request and per tile, so a request's result is bitwise
+// the same alone, in any mix, and through poisson_solve().
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "plan.h"
+
+using namespace pz;
+
+namespace {
+
+constexpr int GRID = 2048;   // persistent workgroups of the batched kernels (multiple of 8)
+
+struct PlanKey {
+    int pc, deg, mixed;
+    bool operator<(const PlanKey &o) const
+    {
+        return std::tie(pc, deg, mixed) < std::tie(o.pc, o.deg, o.mixed);
+    }
+};
+
+struct Request {
+    uint64_t ticket;
+    int nx, ny, nz;
+    double h;
+    const double *rhs;
+    double *x;
+    int pc, deg, prec;
+    double tol;
+    int maxit;
+    size_t ws_bytes, footprint;
+    double t_submit;
+};
+
+struct Result {
+    int status;
+    poisson_stats_t st;
+};
+
+struct Slot {
+    bool active = false;
+    Request req{};
+    size_t off = 0;          // arena offset of the block
+    int ntiles = 0;
+    double t_admit = 0;
+    double lo = 0, hi = 0;
+};
+
+// first-fit allocator over [0, size) with coalescing of free ranges
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_; // offset -> length
+    void init(size_t s)
+    {
+        size = s;
+        free_.clear();
+        if (s) free_[0] = s;
+    }
+    bool alloc(size_t n, size_t &off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                const size_t noff = it->first + n;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct TileList {
+    int *d_prob = nullptr, *d_local = nullptr, *d_count = nullptr;
+    int cap = 0;
+    int count = 0;
+    std::vector<int> h_prob, h_local;
+};
+
+struct Group {
+    TileList tiles;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
+    int graph_cap = -1;       // capacity the graph was captured with
+    bool dirty = true;        // tile list must be rebuilt
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+} // namespace
+
+struct poisson_server {
+    size_t budget = 0;
+    int max_slots = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool dev = false;
+    bool use_graph = true;
+    char *arena_base = nullptr;
+    Arena arena;
+    size_t in_use = 0, peak = 0;
+    Prob *d_probs = nullptr, *h_probs = nullptr;
+    Scalars *d_sc = nullptr, *h_sc = nullptr;
+    std::vector<Slot> slots;
+    std::deque<Request> queue;
+    std::map<uint64_t, Result> results;
+    std::map<PlanKey, Group> groups;
+    TileList init_list, true_list;
+    uint64_t next_ticket = 1;
+    long steps = 0;
+    double busy_ms = 0;       // device time spent in steps
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+};
+
+namespace {
+
+int ensure_dev(poisson_server *s)
+{
+    if (s->dev) return POISSON_OK;
+    HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    if (hipMalloc(&s->arena_base, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        s->arena_base = nullptr;
+        return POISSON_ERR_NOMEM;
+    }
+    s->arena.init(s->budget);
+    HIPCHK(hipMalloc(&s->d_probs, s->max_slots * sizeof(Prob)));
+    HIPCHK(hipHostMalloc(&s->h_probs, s->max_slots * sizeof(Prob), hipHostMallocDefault));
+    HIPCHK(hipMalloc(&s->d_sc, s->max_slots * sizeof(Scalars)));
+    HIPCHK(hipMemset(s->d_sc, 0, s->max_slots * sizeof(Scalars)));
+    HIPCHK(hipHostMalloc(&s->h_sc, s->max_slots * sizeof(Scalars), hipHostMallocDefault));
+    memset(s->h_probs, 0, s->max_slots * sizeof(Prob));
+    memset(s->h_sc, 0, s->max_slots * sizeof(Scalars));
+    HIPCHK(hipEventCreate(&s->ev_a));
+    HIPCHK(hipEventCreate(&s->ev_b));
+    s->dev = true;
+    return POISSON_OK;
+}
+
+// upload a tile list, growing its device arrays if needed; returns whether the
+// device arrays moved (graphs that captured them must be re-captured)
+int upload_tiles(poisson_server *s, TileList &t, bool &moved)
+{
+    moved = false;
+    const int n = (int)t.h_prob.size();
+    if (n > t.cap || !t.d_count) {
+        const int cap = std::max(n, std::max(2 * t.cap, 4096));
+        if (t.d_prob) HIPCHK(hipFree(t.d_prob));
+        if (t.d_local) HIPCHK(hipFree(t.d_local));
+        t.d_prob = t.d_local = nullptr;
+        HIPCHK(hipMalloc(&t.d_prob, cap * sizeof(int)));
+        HIPCHK(hipMalloc(&t.d_local, cap * sizeof(int)));
+        if (!t.d_count) HIPCHK(hipMalloc(&t.d_count, sizeof(int)));
+        t.cap = cap;
+        moved = true;
+    }
+    t.count = n;
+    if (n) {
+        HIPCHK(hipMemcpyAsync(t.d_prob, t.h_prob.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                              s->stream));
+        HIPCHK(hipMemcpyAsync(t.d_local, t.h_local.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                              s->stream));
+    }
+    HIPCHK(hipMemcpyAsync(t.d_count, &t.count, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    // the host vectors are the source of async copies: keep them until the copy ran
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return POISSON_OK;
+}
+
+void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids)
+{
+    t.h_prob.clear();
+    t.h_local.clear();
+    for (int id : slot_ids)
+        for (int l = 0; l < s->slots[id].ntiles; ++l) {
+            t.h_prob.push_back(id);
+            t.h_local.push_back(l);
+        }
+}
+
+Work work_of(const poisson_server *s, const TileList &t)
+{
+    return Work{s->d_probs, t.d_prob, t.d_local, t.d_count, t.count};
+}
+
+int finish_requests(poisson_server *s, const std::vector<int> &ids)
+{
+    if (ids.empty()) return POISSON_OK;
+    for (int id : ids) {
+        const Slot &sl = s->slots[id];
+        if (s->h_sc[id].zero_x)
+            HIPCHK(hipMemsetAsync(sl.req.x, 0, (size_t)sl.req.nx * sl.req.ny * sl.req.nz * 8,
+                                  s->stream));
+    }
+    // true residual of every retiring request in one launch
+    list_tiles(s, s->true_list, ids);
+    bool moved;
+    int rc;
+    if ((rc = upload_tiles(s, s->true_list, moved)) != POISSON_OK) return rc;
+    launch_stencil(S_TRUE, false, false, work_of(s, s->true_list),
+                   std::min(GRID, std::max(8, s->true_list.count)), s->stream,
+                   KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(s->h_sc, s->d_sc, s->max_slots * sizeof(Scalars), hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double t = now_ms();
+    for (int id : ids) {
+        Slot &sl = s->slots[id];
+        const Scalars &sc = s->h_sc[id];
+        Result r;
+        memset(&r.st, 0, sizeof(r.st));
+        r.status = sc.status;
+        poisson_stats_t &st = r.st;
+        st.struct_size = sizeof(st);
+        st.status = sc.status;
+        st.iterations = sc.iter;
+        st.half_step_exit = sc.half;
+        st.precond = sl.req.pc;
+        st.degree = sl.req.deg;
+        st.precision = sl.req.prec;
+        st.relres_recursive = sc.bb > 0 ? std::sqrt(sc.rr / sc.bb) : 0.0;
+        st.relres_true = sc.bb > 0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
+        st.lambda_min = sl.lo;
+        st.lambda_max = sl.hi;
+        st.solve_ms = t - sl.req.t_submit;   // arrival to completion
+        st.loop_ms = t - sl.t_admit;         // admission to completion
+        const double N = (double)sl.req.nx * sl.req.ny * sl.req.nz;
+        st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED) * N *
+                         sc.iter;
+        st.model_gbps = 0;
+        s->results[sl.req.ticket] = r;
+        s->arena.release(sl.off, sl.req.footprint);
+        s->in_use -= sl.req.footprint;
+        sl.active = false;
+        for (auto &g : s->groups) g.second.dirty = true;
+    }
+    return POISSON_OK;
+}
+
+int capture_group(poisson_server *s, const PlanKey &k, Group &g)
+{
+    if (g.graph) {
+        (void)hipGraphExecDestroy(g.graph);
+        (void)hipGraphDestroy(g.graph_src);
+        g.graph = nullptr;
+        g.graph_src = nullptr;
+    }
+    const Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, 0};
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0);
+    HIPCHK(hipStreamEndCapture(s->cap_stream, &g.graph_src));
+    HIPCHK(hipGraphInstantiate(&g.graph, g.graph_src, nullptr, nullptr, 0));
+    g.graph_cap = g.tiles.cap;
+    return POISSON_OK;
+}
+
+int step_impl(poisson_server *s, int iters)
+{
+    int rc;
+    if ((rc = ensure_dev(s)) != POISSON_OK) return rc;
+    // 1. retire requests whose flag was seen at the end of a previous step
+    std::vector<int> done;
+    for (int i = 0; i < s->max_slots; ++i)
+        if (s->slots[i].active && s->h_sc[i].done) done.push_back(i);
+    if ((rc = finish_requests(s, done)) != POISSON_OK) return rc;
+
+    // 2. admit in arrival order while a slot is free and the block fits
+    std::vector<int> admitted;
+    while (!s->queue.empty()) {
+        int id = -1;
+        for (int i = 0; i < s->max_slots; ++i)
+            if (!s->slots[i].active) { id = i; break; }
+        if (id < 0) break;
+        Request &rq = s->queue.front();
+        size_t off;
+        if (!s->arena.alloc(rq.footprint, off)) break;
+        Slot &sl = s->slots[id];
+        sl.active = true;
+        sl.req = rq;
+        sl.off = off;
+        sl.t_admit = now_ms();
+        s->in_use += rq.footprint;
+        s->peak = std::max(s->peak, s->in_use);
+        s->queue.pop_front();
+        // descriptor: workspace, partials, scalars in the arena block
+        PlanOpts o;
+        Prob &p = s->h_probs[id];
+        if ((rc = fill_prob(p, sl.req.nx, sl.req.ny, sl.req.nz, sl.req.h, sl.req.pc, sl.req.deg, o,
+                            sl.req.tol, sl.req.maxit, &sl.lo, &sl.hi)) != POISSON_OK)
+            return rc;
+        sl.ntiles = p.ntiles;
+        char *blk = s->arena_base + off;
+        const size_t N = (size_t)sl.req.nx * sl.req.ny * sl.req.nz;
+        carve_workspace(p, blk, N, sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED);
+        p.vec[V_X] = sl.req.x;
+        p.vec[V_B] = (void *)sl.req.rhs;
+        p.partials = (double *)(blk + sl.req.ws_bytes);
+        p.sc = s->d_sc + id;
+        p.hist = nullptr;
+        p.hist_iters = 0;
+        HIPCHK(hipMemcpyAsync(s->d_probs + id, s->h_probs + id, sizeof(Prob), hipMemcpyHostToDevice,
+                              s->stream));
+        admitted.push_back(id);
+        s->groups[PlanKey{sl.req.pc, sl.req.deg, sl.req.prec}].dirty = true;
+    }
+    HIPCHK(hipEventRecord(s->ev_a, s->stream));
+    // 3. initial residuals of the new requests, one launch
+    if (!admitted.empty()) {
+        list_tiles(s, s->init_list, admitted);
+        bool moved;
+        if ((rc = upload_tiles(s, s->init_list, moved)) != POISSON_OK) return rc;
+        launch_stencil(S_INIT, false, false, work_of(s, s->init_list),
+                       std::min(GRID, std::max(8, s->init_list.count)), s->stream,
+                       KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
+        HIPCHK(hipGetLastError());
+    }
+    // 4. advance every running request, one batched sequence per plan group
+    for (auto &kv : s->groups) {
+        Group &g = kv.second;
+        if (g.dirty) {
+            std::vector<int> ids;
+            for (int i = 0; i < s->max_slots; ++i) {
+                const Slot &sl = s->slots[i];
+                const PlanKey k{sl.req.pc, sl.req.deg, sl.req.prec};
+                if (sl.active && !(k < kv.first) && !(kv.first < k)) ids.push_back(i);
+            }
+            list_tiles(s, g.tiles, ids);
+            bool moved;
+            if ((rc = upload_tiles(s, g.tiles, moved)) != POISSON_OK) return rc;
+            if (moved && g.graph) g.graph_cap = -1;
+            g.dirty = false;
+        }
+        if (g.tiles.count == 0) continue;
+        if (s->use_graph) {
+            if (g.graph_cap != g.tiles.cap && (rc = capture_group(s, kv.first, g)) != POISSON_OK)
+                return rc;
+            for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(g.graph, s->stream));
+        } else {
+            const Work w = work_of(s, g.tiles);
+            for (int i = 0; i < iters; ++i)
+                enqueue_iteration(w, GRID, s->stream, kv.first.pc, kv.first.deg, kv.first.mixed != 0);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    HIPCHK(hipEventRecord(s->ev_b, s->stream));
+    // 5. read every request's flags
+    HIPCHK(hipMemcpyAsync(s->h_sc, s->d_sc, s->max_slots * sizeof(Scalars), hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b));
+    s->busy_ms += ms;
+    ++s->steps;
+    // 6. retire what finished during this step, so poll reports it now
+    done.clear();
+    for (int i = 0; i < s->max_slots; ++i)
+        if (s->slots[i].active && s->h_sc[i].done) done.push_back(i);
+    if ((rc = finish_requests(s, done)) != POISSON_OK) return rc;
+    int active = 0;
+    for (const Slot &sl : s->slots) active += sl.active;
+    return active + (int)s->queue.size();
+}
+
+} // namespace
+
+extern "C" {
+
+int poisson_server_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream,
+                          poisson_server **out)
+{
+    if (!out) return POISSON_ERR_ARG;
+    *out = nullptr;
+    if (hbm_budget_bytes < 4096 || max_slots < 1 || max_slots > 4096) return POISSON_ERR_ARG;
+    poisson_server *s = new (std::nothrow) poisson_server;
+    if (!s) return POISSON_ERR_NOMEM;
+    s->budget = hbm_budget_bytes & ~(size_t)255;
+    s->max_slots = max_slots;
+    s->stream = (hipStream_t)hip_stream;
+    s->slots.resize(max_slots);
+    *out = s;
+    return POISSON_OK;
+}
+
+int poisson_server_set_option(poisson_server *s, int key, double value)
+{
+    if (!s || !std::isfinite(value)) return POISSON_ERR_ARG;
+    if (key == POISSON_SERVER_OPT_USE_GRAPH) {
+        if (value != 0 && value != 1) return POISSON_ERR_ARG;
+        s->use_graph = value != 0;
+        return POISSON_OK;
+    }
+    return POISSON_ERR_ARG;
+}
+
+int poisson_server_footprint(int nx, int ny, int nz, int precond, int degree, int precision,
+                             size_t *bytes)
+{
+    if (!bytes || nx < 1 || ny < 1 || nz < 1) return POISSON_ERR_ARG;
+    if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
+    if (precision != POISSON_FP64 && precision != POISSON_MIXED) return POISSON_ERR_ARG;
+    const size_t N = (size_t)nx * ny * nz;
+    const Tiling t = make_tiling(nx, ny, nz);
+    *bytes = workspace_bytes(N, precond, degree, precision == POISSON_MIXED) +
+             align256((size_t)t.ntiles * PARTIAL_STRIDE * sizeof(double));
+    return POISSON_OK;
+}
+
+int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, unsigned bc,
+                          const double *rhs, double *x, int precond, int degree, int precision,
+                          double tol, int maxit, uint64_t *ticket)
+{
+    if (!s || !ticket || !rhs || !x) return POISSON_ERR_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 || (double)nx * ny * nz > 17179869184.0) return POISSON_ERR_ARG;
+    if (!(h > 0) || !std::isfinite(h)) return POISSON_ERR_ARG;
+    if (bc != 0) return POISSON_ERR_UNSUPPORTED;
+    if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
+    if (is_cheb(precond) && (degree < 0 || degree > MAXDEG)) return POISSON_ERR_ARG;
+    if (!is_cheb(precond)) degree = 0;
+    if (precision != POISSON_FP64 && precision != POISSON_MIXED) return POISSON_ERR_ARG;
+    if (!(tol > 0) || !(tol < 1) || maxit < 1 || maxit > 10000000) return POISSON_ERR_ARG;
+    if (is_cheb(precond)) {
+        PlanOpts o;
+        double lo, hi;
+        if (!cheb_interval(nx, ny, nz, h, precond, o, lo, hi)) return POISSON_ERR_ARG;
+    }
+    size_t fp;
+    poisson_server_footprint(nx, ny, nz, precond, degree, precision, &fp);
+    if (fp > s->budget) return POISSON_ERR_NOMEM;
+    int rc;
+    if ((rc = validate_ptr(rhs)) != POISSON_OK) return rc;
+    if ((rc = validate_ptr(x)) != POISSON_OK) return rc;
+    Request r;
+    r.ticket = s->next_ticket++;
+    r.nx = nx; r.ny = ny; r.nz = nz; r.h = h;
+    r.rhs = rhs; r.x = x;
+    r.pc = precond; r.deg = degree; r.prec = precision;
+    r.tol = tol; r.maxit = maxit;
+    r.ws_bytes = workspace_bytes((size_t)nx * ny * nz, precond, degree, precision == POISSON_MIXED);
+    r.footprint = fp;
+    r.t_submit = now_ms();
+    s->queue.push_back(r);
+    *ticket = r.ticket;
+    return POISSON_OK;
+}
+
+int poisson_server_step(poisson_server *s, int iters)
+{
+    if (!s || iters < 1 || iters > 4096) return POISSON_ERR_ARG;
+    try {
+        return step_impl(s, iters);
+    } catch (...) {
+        return POISSON_ERR_INTERNAL;
+    }
+}
+
+int poisson_server_poll(poisson_server *s, uint64_t ticket, poisson_stats_t *out)
+{
+    if (!s || ticket == 0 || ticket >= s->next_ticket) return POISSON_ERR_ARG;
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return POISSON_PENDING;
+    if (out) {
+        if (out->struct_size < sizeof(poisson_stats_t)) return POISSON_ERR_ARG;
+        *out = it->second.st;
+    }
+    return it->second.status;
+}
+
+int poisson_server_info(const poisson_server *s, poisson_server_info_t *out)
+{
+    if (!s || !out || out->struct_size < sizeof(poisson_server_info_t)) return POISSON_ERR_ARG;
+    int active = 0;
+    for (const Slot &sl : s->slots) active += sl.active;
+    out->queued = (int)s->queue.size();
+    out->active = active;
+    out->completed = (long)s->results.size();
+    out->steps = s->steps;
+    out->bytes_in_use = s->in_use;
+    out->peak_bytes = s->peak;
+    out->budget_bytes = s->budget;
+    out->busy_ms = s->busy_ms;
+    return POISSON_OK;
+}
+
+void poisson_server_destroy(poisson_server *s)
+{
+    if (!s) return;
+    if (s->dev) {
+        (void)hipStreamSynchronize(s->stream);
+        for (auto &kv : s->groups) {
+            if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
+            if (kv.second.graph_src) (void)hipGraphDestroy(kv.second.graph_src);
+            for (int *p : {kv.second.tiles.d_prob, kv.second.tiles.d_local, kv.second.tiles.d_count})
+                if (p) (void)hipFree(p);
+        }
+        for (TileList *t : {&s->init_list, &s->true_list})
+            for (int *p : {t->d_prob, t->d_local, t->d_count})
+                if (p) (void)hipFree(p);
+        (void)hipFree(s->arena_base);
+        (void)hipFree(s->d_probs);
+        (void)hipFree(s->d_sc);
+        (void)hipHostFree(s->h_probs);
+        (void)hipHostFree(s->h_sc);
+        (void)hipEventDestroy(s->ev_a);
+        (void)hipEventDestroy(s->ev_b);
+        (void)hipStreamDestroy(s->cap_stream);
+    }
+    delete s;
+}
+
+} // extern "C"

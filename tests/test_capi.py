@@ -100,3 +100,43 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         B.lib()
+
+
+def test_server_host_side_checks():
+    L = P.lib()
+    srv = ctypes.c_void_p()
+    assert L.poisson_server_create(100, 4, None, ctypes.byref(srv)) == P.ERR_ARG
+    assert L.poisson_server_create(1 << 20, 0, None, ctypes.byref(srv)) == P.ERR_ARG
+    assert L.poisson_server_create(1 << 20, 4, None, None) == P.ERR_ARG
+    assert L.poisson_server_create(1 << 20, 4, None, ctypes.byref(srv)) == P.OK
+    fake = ctypes.c_void_p(0x1000)
+    t = ctypes.c_uint64()
+    # a request larger than the whole budget is rejected before any device access
+    assert L.poisson_server_submit(srv, 64, 64, 64, 1 / 65, 0, fake, fake, 2, 4, 1, 1e-8, 100,
+                                   ctypes.byref(t)) == P.ERR_NOMEM
+    assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 1, fake, fake, 2, 4, 1, 1e-8, 100,
+                                   ctypes.byref(t)) == P.ERR_UNSUPPORTED
+    assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 0, fake, fake, 2, 4, 5, 1e-8, 100,
+                                   ctypes.byref(t)) == P.ERR_ARG
+    assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 0, fake, fake, 2, 4, 1, 2.0, 100,
+                                   ctypes.byref(t)) == P.ERR_ARG
+    assert L.poisson_server_poll(srv, 1, None) == P.ERR_ARG       # no such ticket
+    assert L.poisson_server_step(srv, 0) == P.ERR_ARG
+    assert L.poisson_server_set_option(srv, 99, 1.0) == P.ERR_ARG
+    info = B.ServerInfo()
+    info.struct_size = ctypes.sizeof(B.ServerInfo)
+    assert L.poisson_server_info(srv, ctypes.byref(info)) == P.OK
+    assert info.queued == 0 and info.budget_bytes == 1 << 20
+    L.poisson_server_destroy(srv)
+    L.poisson_server_destroy(None)
+
+
+def test_footprint_model():
+    # mixed Chebyshev-4: r, r~, p, w, t in FP64 and p^, s^, two Chebyshev buffers and
+    # the FP32 copy of the input: 5*8 + 5*4 = 60 bytes per unknown, plus tile partials
+    n = 128
+    fp = P.footprint((n, n, n), P.PC_CHEBYSHEV, 4, P.MIXED)
+    assert 60 * n ** 3 <= fp <= 60 * n ** 3 + 64 * 1024 + 11 * 256
+    fp64 = P.footprint((n, n, n), P.PC_CHEBYSHEV, 8, P.FP64)
+    assert 72 * n ** 3 <= fp64 <= 72 * n ** 3 + 64 * 1024 + 11 * 256
+    assert P.footprint((n, n, n), P.PC_NONE, 0, P.FP64) < fp

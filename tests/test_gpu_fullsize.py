@@ -1,0 +1,183 @@
+"""Parity at full size (512^3 and 256^3), in the launch configuration the
+benchmark times.
+
+The oracle cannot finish a 512^3 solve in a test, so:
+  * single operations are checked on sampled outputs, each recomputed by the
+    oracle on its own window: the output at a point after m operator
+    applications depends only on the points within distance m, so the oracle
+    run on the (2m+1)^3 window around it (clipped to the grid, where the zero
+    boundary is the true one, or to the point's block for Block-Jacobi) gives
+    the exact value at the window centre;
+  * the first iterations of the 512^3 solve are compared against the oracle's
+    first iterations (fixed-K trajectory);
+  * full solves are checked through properties that hold at any size: the
+    true residual meets the tolerance, and two solutions x_a, x_b of the same
+    system satisfy ||x_a - x_b|| <= (||b - A x_a|| + ||b - A x_b||) / lambda_min.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_08935_amd as P
+from paper_2503_08935_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+N512 = 512
+
+
+def sample_points(n, count, seed, block=64):
+    rng = np.random.default_rng(seed)
+    pts = [rng.integers(0, n, 3) for _ in range(count)]
+    edge = [0, 1, n - 2, n - 1, block - 1, block, 2 * block - 1, n // 2]
+    for a in edge[:6]:
+        for b in edge[::3]:
+            pts.append(np.array([a, b, edge[(a + b) % len(edge)]]))
+    return [tuple(int(v) for v in p) for p in pts]
+
+
+def window_input(seed, n, lo, hi):
+    """u = workloads.uniform_grid(seed, (n, n, n)) restricted to the box [lo, hi)."""
+    (i0, j0, k0), (i1, j1, k1) = lo, hi
+    out = np.empty((k1 - k0, j1 - j0, i1 - i0))
+    for k in range(k0, k1):
+        for j in range(j0, j1):
+            start = i0 + n * (j + n * k)
+            out[k - k0, j - j0] = workloads.uniform(seed, i1 - i0, start=start)
+    return out
+
+
+def window_box(p, m, n, block=0):
+    lo, hi = [], []
+    for c in p:
+        a, b = max(c - m, 0), min(c + m + 1, n)
+        if block:
+            a, b = max(a, (c // block) * block), min(b, (c // block + 1) * block)
+        lo.append(a)
+        hi.append(b)
+    return tuple(lo), tuple(hi)
+
+
+@pytest.fixture(scope="module")
+def u512():
+    u = torch.empty(N512 ** 3, dtype=torch.float64, device="cuda:0")
+    P.fill_uniform(u, 7)
+    torch.cuda.synchronize()
+    return u
+
+
+def gather(t, pts, n):
+    idx = torch.tensor([i + n * (j + n * k) for i, j, k in pts], device=t.device)
+    return t[idx].double().cpu().numpy()
+
+
+def test_operator_sampled_512(gpu, u512):
+    n = N512
+    h = workloads.spacing(n)
+    with P.Solver((n, n, n), h) as s:
+        out = torch.empty_like(u512)
+        s.apply_operator(u512, out)
+        pts = sample_points(n, 400, 1)
+        got = gather(out, pts, n)
+    for p, g in zip(pts, got):
+        lo, hi = window_box(p, 1, n)
+        w = window_input(7, n, lo, hi)
+        ref = oracle.apply_A(w, h)[p[2] - lo[2], p[1] - lo[1], p[0] - lo[0]]
+        assert g == ref, p
+
+
+@pytest.mark.parametrize("pc,m,mixed", [(P.PC_CHEBYSHEV, 8, False), (P.PC_CHEBYSHEV, 8, True),
+                                        (P.PC_BLOCK_JACOBI, 8, False),
+                                        (P.PC_BLOCK_JACOBI, 8, True)])
+def test_preconditioner_sampled_512(gpu, u512, pc, m, mixed):
+    n = N512
+    h = workloads.spacing(n)
+    block = 64 if pc == P.PC_BLOCK_JACOBI else 0
+    with P.Solver((n, n, n), h, precision=P.MIXED if mixed else P.FP64) as s:
+        out = torch.empty(n ** 3, dtype=torch.float32 if mixed else torch.float64,
+                          device="cuda:0")
+        s.apply_precond(pc, m, u512, out)
+        pts = sample_points(n, 60, 2 + pc + int(mixed))
+        got = gather(out, pts, n)
+    lo_i, hi_i = oracle.interval((block, block, block) if block else (n, n, n), h)
+    for p, g in zip(pts, got):
+        lo, hi = window_box(p, m, n, block)
+        w = window_input(7, n, lo, hi)
+        ref = oracle.chebyshev(w, h, lo_i, hi_i, m, mixed=mixed)
+        assert g == ref[p[2] - lo[2], p[1] - lo[1], p[0] - lo[0]], p
+
+
+def gpu_run(shape, h, b, pc, m, tol, maxit, mixed=False):
+    with P.Solver(shape, h, precision=P.MIXED if mixed else P.FP64) as s:
+        x = torch.zeros_like(b)
+        st = s.solve(b, x, pc, m, tol, maxit)
+        torch.cuda.synchronize()
+        return st, s.stats(), s.trace(), x
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fixed_k_trajectory_512(gpu, mixed):
+    """Benchmark workload (512^3, f ~ U[-1,1) seed 4, Chebyshev-8): first 2 iterations."""
+    n = N512
+    h = workloads.spacing(n)
+    b = torch.empty(n ** 3, dtype=torch.float64, device="cuda:0")
+    P.fill_uniform(b, 4)
+    st, stats, tr, x = gpu_run((n, n, n), h, b, P.PC_CHEBYSHEV, 8, 1e-8, 2, mixed)
+    assert st == P.NOT_CONVERGED and stats["iterations"] == 2
+    xg = x.cpu().numpy()
+    del x
+    f = workloads.uniform_grid(4, (n, n, n))
+    ref = oracle.bicgstab(f, h, pc=oracle.PC_CHEBYSHEV, degree=8, mixed=mixed, tol=1e-8, maxit=2)
+    assert ref.iterations == 2
+    assert np.array_equal(tr[:, 0], ref.alpha) and np.array_equal(tr[:, 1], ref.omega)
+    assert np.array_equal(tr[:, 2], ref.rho) and np.array_equal(tr[:, 3], ref.rr)
+    assert np.array_equal(xg, ref.x.ravel())
+
+
+def test_full_solves_512_properties(gpu):
+    """FP64 and mixed Chebyshev-8 to 1e-8 (the benchmark) and Block-Jacobi(CI)
+    with 64^3 blocks vs Chebyshev-8 to 1e-10 on the noisy manufactured problem."""
+    n = N512
+    h = workloads.spacing(n)
+    lam_min = oracle.interval((n, n, n), h)[0]
+    b = torch.empty(n ** 3, dtype=torch.float64, device="cuda:0")
+    P.fill_uniform(b, 4)
+    bn = torch.linalg.vector_norm(b).item()
+    st64, s64, _, x64 = gpu_run((n, n, n), h, b, P.PC_CHEBYSHEV, 8, 1e-8, 5000)
+    stm, sm, _, xm = gpu_run((n, n, n), h, b, P.PC_CHEBYSHEV, 8, 1e-8, 5000, mixed=True)
+    assert st64 == stm == P.OK
+    assert s64["relres_true"] < 1.01e-8 and sm["relres_true"] < 1.01e-8
+    diff = torch.linalg.vector_norm(x64 - xm).item()
+    bound = (s64["relres_true"] + sm["relres_true"]) * bn / lam_min
+    assert diff <= bound
+    del x64, xm
+    f = torch.from_numpy(workloads.manufactured_noisy((n, n, n), 3).ravel()).to("cuda:0")
+    its = {}
+    for pc in (P.PC_BLOCK_JACOBI, P.PC_CHEBYSHEV):
+        st, s, _, x = gpu_run((n, n, n), h, f, pc, 8, 1e-10, 5000)
+        assert st == P.OK and s["relres_true"] < 1.05e-10
+        its[pc] = s["iterations"]
+        del x
+    # the global preconditioner needs fewer iterations than the block one
+    assert its[P.PC_CHEBYSHEV] < its[P.PC_BLOCK_JACOBI]
+
+
+@pytest.mark.parametrize("pc,m", [(P.PC_JACOBI, 0), (P.PC_CHEBYSHEV, 4), (P.PC_CHEBYSHEV, 8),
+                                  (P.PC_NONE, 0)])
+def test_fixed_k_trajectory_256(gpu, pc, m):
+    """256^3, f ~ U[-1,1) seed 2: first 5 iterations bitwise, then the full solve."""
+    n = 256
+    h = workloads.spacing(n)
+    b = torch.empty(n ** 3, dtype=torch.float64, device="cuda:0")
+    P.fill_uniform(b, 2)
+    st, stats, tr, x = gpu_run((n, n, n), h, b, pc, m, 1e-8, 5)
+    f = workloads.uniform_grid(2, (n, n, n))
+    opc = {P.PC_NONE: oracle.PC_NONE, P.PC_JACOBI: oracle.PC_JACOBI,
+           P.PC_CHEBYSHEV: oracle.PC_CHEBYSHEV}[pc]
+    ref = oracle.bicgstab(f, h, pc=opc, degree=m, tol=1e-8, maxit=5)
+    assert st == ref.status and stats["iterations"] == ref.iterations == 5
+    assert np.array_equal(tr[:, 0], ref.alpha) and np.array_equal(tr[:, 3], ref.rr)
+    assert np.array_equal(x.cpu().numpy(), ref.x.ravel())
+    st, stats, tr, x = gpu_run((n, n, n), h, b, pc, m, 1e-8, 5000)
+    assert st == P.OK and stats["relres_true"] < 1.05e-8

@@ -1,0 +1,154 @@
+"""Continuous-batching server: every request's result must equal, bit for bit,
+the same solve done alone (poisson_solve) and the CPU oracle's, whatever else
+shares the launches; admission is FIFO within the HBM budget."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_08935_amd as P
+from paper_2503_08935_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+OPC = {P.PC_NONE: oracle.PC_NONE, P.PC_JACOBI: oracle.PC_JACOBI,
+       P.PC_CHEBYSHEV: oracle.PC_CHEBYSHEV, P.PC_BLOCK_JACOBI: oracle.PC_BLOCK_JACOBI}
+
+REQS = [
+    # shape, seed, precond, degree, precision, tol
+    ((32, 32, 32), -1, P.PC_NONE, 0, P.FP64, 1e-8),
+    ((48, 48, 48), 11, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+    ((61, 47, 35), 12, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+    ((24, 24, 24), 13, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+    ((40, 33, 20), 14, P.PC_CHEBYSHEV, 8, P.FP64, 1e-10),
+    ((70, 66, 68), 15, P.PC_BLOCK_JACOBI, 6, P.FP64, 1e-8),
+    ((33, 21, 50), 16, P.PC_JACOBI, 0, P.MIXED, 1e-8),
+    ((64, 64, 64), 17, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+]
+
+
+def rhs_of(shape, seed):
+    return workloads.manufactured(shape) if seed < 0 else workloads.uniform_grid(seed, shape)
+
+
+def alone(shape, seed, pc, deg, prec, tol):
+    h = workloads.spacing(shape[0])
+    f = rhs_of(shape, seed)
+    with P.Solver(shape, h, precision=prec) as s:
+        b = torch.from_numpy(f).to("cuda:0")
+        x = torch.zeros_like(b)
+        st = s.solve(b, x, pc, deg, tol, 5000)
+        torch.cuda.synchronize()
+        return st, s.stats()["iterations"], x.cpu().numpy()
+
+
+def run_server(reqs, budget, slots, use_graph=True, iters=4, late=()):
+    """Submit reqs (the indices in `late` only after two steps); step to completion."""
+    out = {}
+    with P.Server(budget, slots, use_graph=use_graph) as srv:
+        bufs = {}
+
+        def submit(i):
+            shape, seed, pc, deg, prec, tol = reqs[i]
+            b = torch.from_numpy(rhs_of(shape, seed)).to("cuda:0")
+            x = torch.zeros_like(b)
+            bufs[i] = (b, x)
+            return srv.submit(b, x, shape, workloads.spacing(shape[0]), pc, deg, prec, tol, 5000)
+
+        tickets = {i: submit(i) for i in range(len(reqs)) if i not in late}
+        nsteps = 0
+        while True:
+            left = srv.step(iters)
+            nsteps += 1
+            if nsteps == 2:
+                for i in late:
+                    tickets[i] = submit(i)
+                left = max(left, 1)
+            if left == 0:
+                break
+            assert nsteps < 10000
+        for i, t in tickets.items():
+            st, stats = srv.poll(t)
+            out[i] = (st, stats, bufs[i][1].cpu().numpy())
+        info = srv.info()
+    return out, info
+
+
+def test_mixed_batch_bitwise_alone_and_oracle(gpu):
+    budget = 3 * max(P.footprint(r[0], r[2], r[3], r[4]) for r in REQS)
+    out, info = run_server(REQS, budget, slots=4, late=(3, 6))
+    assert info["peak_bytes"] <= info["budget_bytes"] == budget
+    assert info["completed"] == len(REQS) and info["active"] == 0 and info["queued"] == 0
+    for i, (shape, seed, pc, deg, prec, tol) in enumerate(REQS):
+        st, stats, x = out[i]
+        st1, it1, x1 = alone(shape, seed, pc, deg, prec, tol)
+        assert st == st1 == P.OK, (i, st, st1)
+        assert stats["iterations"] == it1
+        assert np.array_equal(x, x1), i
+        ref = oracle.bicgstab(rhs_of(shape, seed), workloads.spacing(shape[0]), pc=OPC[pc],
+                              degree=deg, mixed=prec == P.MIXED, tol=tol, maxit=5000)
+        assert ref.iterations == it1 and np.array_equal(x, ref.x), i
+        assert stats["relres_true"] < 1.5 * tol
+
+
+def test_graph_and_launch_paths_agree(gpu):
+    reqs = REQS[1:5]
+    budget = 2 * max(P.footprint(r[0], r[2], r[3], r[4]) for r in reqs)
+    a, _ = run_server(reqs, budget, 2, use_graph=True, iters=3)
+    b, _ = run_server(reqs, budget, 2, use_graph=False, iters=5)
+    for i in range(len(reqs)):
+        assert a[i][0] == b[i][0] and a[i][1]["iterations"] == b[i][1]["iterations"]
+        assert np.array_equal(a[i][2], b[i][2])
+
+
+def test_failures_are_isolated(gpu):
+    good = ((40, 36, 30), 21, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+    with P.Server(1 << 30, 8) as srv:
+        shape = good[0]
+        h = workloads.spacing(shape[0])
+        f = rhs_of(shape, good[1])
+        bad = f.copy()
+        bad[5, 6, 7] = np.nan
+        zero = np.zeros_like(f)
+        bufs = [torch.from_numpy(a).to("cuda:0") for a in (f, bad, zero)]
+        xs = [torch.zeros_like(b) for b in bufs]
+        xs[2].fill_(3.0)
+        ts = [srv.submit(b, x, shape, h, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8) for b, x in zip(bufs, xs)]
+        while srv.step(4):
+            pass
+        st = [srv.poll(t) for t in ts]
+        assert st[0][0] == P.OK and st[1][0] == P.ERR_NONFINITE
+        assert st[2][0] == P.OK and st[2][1]["iterations"] == 0
+        assert torch.count_nonzero(xs[2]).item() == 0
+    st1, it1, x1 = alone(shape, good[1], P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+    assert st[0][1]["iterations"] == it1 and np.array_equal(xs[0].cpu().numpy(), x1)
+
+
+def test_fifo_admission_and_budget(gpu):
+    # budget for exactly one 64^3 mixed request at a time: strict arrival order
+    shape = (64, 64, 64)
+    fp = P.footprint(shape, P.PC_CHEBYSHEV, 4, P.MIXED)
+    with P.Server(fp + 4096, 8) as srv:
+        h = workloads.spacing(64)
+        bufs, ts = [], []
+        for k in range(3):
+            b = torch.from_numpy(workloads.uniform_grid(30 + k, shape)).to("cuda:0")
+            x = torch.zeros_like(b)
+            bufs.append((b, x))
+            ts.append(srv.submit(b, x, shape, h, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8))
+        order = []
+        while True:
+            left = srv.step(2)
+            inf = srv.info()
+            assert inf["active"] <= 1 and inf["peak_bytes"] <= inf["budget_bytes"]
+            for t in ts:
+                if t not in order and srv.poll(t)[0] != P.PENDING:
+                    order.append(t)
+            if left == 0:
+                break
+        assert order == ts
+    with pytest.raises(P.PoissonError) as e:
+        with P.Server(fp // 2, 8) as srv:
+            b = torch.zeros(64 ** 3, dtype=torch.float64, device="cuda:0")
+            srv.submit(b, b.clone(), shape, h, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+    assert e.value.code == P.ERR_NOMEM
