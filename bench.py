@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-iters", type=int, default=4,
                     help="iterations per server step (completion is observed per step)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a reference dispatch of known "
+                         "size for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -114,6 +117,14 @@ def main():
     N = n ** 3
     h = workloads.spacing(n)
     stream = torch.cuda.Stream()  # default priority
+    if a.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     log(f"grid {n}^3, FP64 Chebyshev-{a.degree}, tol {a.tol}")
     with torch.cuda.stream(stream):
         b = torch.empty(N, dtype=torch.float64, device=dev)

@@ -4,11 +4,11 @@
  * HPC Poisson Solver: Preconditioned Bi-CGSTAB with alpaka" (arXiv 2503.08935).
  *
  * Problem (Background section, eq. poisson and eq. matrix_p): -lap(u) = f on
- * the interior nodes of an nx x ny x nz grid with spacing h, second-order
- * central differences (matrix D of eq. matrix_dirichlet on every axis), zero
- * Dirichlet boundary. The matrix is never formed: A u is a 7-point stencil,
+ * an nx x ny x nz grid with spacing h, second-order central differences
+ * (matrix D of eq. matrix_dirichlet, or N of eq. matrix_neuman on axes with a
+ * Neumann face; see poisson_create). The matrix is never formed: A u is a 7-point stencil,
  *   (A u)_ijk = (6 u_ijk - u_{i-1} - u_{i+1} - u_{j-1} - u_{j+1} - u_{k-1} - u_{k+1}) / h^2,
- * with neighbours outside the grid equal to zero.
+ * with neighbours outside the grid zero (Dirichlet) or mirrored (Neumann).
  *
  * Layout of every vector argument: contiguous, x fastest,
  *   idx = i + nx * (j + ny * k),  0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
@@ -42,7 +42,7 @@ enum {
     POISSON_ERR_ARG = -1,        /* invalid argument; nothing was touched */
     POISSON_ERR_NOMEM = -2,      /* device allocation failed / over budget */
     POISSON_ERR_DEVICE = -3,     /* a HIP call failed (no GPU, bad pointer, ...) */
-    POISSON_ERR_UNSUPPORTED = -4,/* valid but not implemented (e.g. bc != 0) */
+    POISSON_ERR_UNSUPPORTED = -4,/* valid but not supported (e.g. all faces Neumann) */
     POISSON_ERR_BREAKDOWN = -5,  /* r~.A p^ = 0, t.t = 0, r~.r = 0 or omega = 0 */
     POISSON_ERR_NONFINITE = -6,  /* a NaN or Inf reached a reduction */
     POISSON_ERR_INTERNAL = -7
@@ -90,11 +90,18 @@ enum {
 /* ---- solver context ----------------------------------------------------- */
 typedef struct poisson_ctx poisson_ctx;
 
-/* Create a context for an nx x ny x nz interior grid with spacing h.
-   bc: bit f (x-, x+, y-, y+, z-, z+) set = Neumann on face f; only 0 (zero
-   Dirichlet on every face) is supported, other values give ERR_UNSUPPORTED.
+/* Create a context for an nx x ny x nz grid with spacing h.
+   bc: bit f (x-, x+, y-, y+, z-, z+) set = homogeneous Neumann on face f, clear =
+   zero Dirichlet. Along an axis with a Neumann end the 1D operator is the matrix N
+   of eq. matrix_neuman: the outside neighbour is the mirror image of the inside one
+   (u_{-1} = u_1), so the boundary node itself is an unknown; the operator is then
+   non-symmetric. The Chebyshev interval uses the closed-form spectra of D and N
+   (one Neumann end: 4 sin^2((2k-1) pi/(4n)); two: 4 sin^2(k pi/(2(n-1)))).
    Host-only: no device memory is touched until the first solve. Errors:
-   ERR_ARG if a size < 1, nx*ny*nz > 2^34, h not finite and > 0, or out == NULL. */
+   ERR_ARG if a size < 1, nx*ny*nz > 2^34, h not finite and > 0, bc > 63, a Neumann
+   face on an axis of length 1, or out == NULL; ERR_UNSUPPORTED for bc = 63 (all
+   faces Neumann: singular). Chebyshev / Block-Jacobi need lambda_min > 0, so an
+   axis with two Neumann ends must be paired with a Dirichlet face elsewhere. */
 int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **out);
 
 /* Set an option (keys above). ERR_ARG for an unknown key or an out-of-range value. */

@@ -14,6 +14,7 @@ Preconditioned Bi-CGSTAB with alpaka", arXiv 2503.08935.
   - Block-Jacobi(CI) / GNoComm(CI): eqs. blockJacobiPreconditioner and
     systemBJpreconditioner, Methodology section
   - Bi-CGSTAB: Alg. 1 (half-step exit) with the scalar formulas of Alg. 3
+  - Neumann faces: the one-sided matrix N of eq. matrix_neuman (mirror ghost)
 """
 import ctypes
 import os
@@ -52,6 +53,25 @@ def lib():
         L.orc_dirichlet_eig.restype = ctypes.c_double
         L.orc_dirichlet_eig.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_interval.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_interval_bc.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int,
+                                                            ctypes.c_uint, dp, dp])
+        L.orc_apply_A_bc.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int,
+                                                           ctypes.c_uint, dp, dp])
+        for f in (L.orc_chebyshev_bc, L.orc_chebyshev_f32_bc):
+            f.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, ctypes.c_uint,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                dp, dp])
+        L.orc_precond_bc.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_uint] +
+                                     [ctypes.c_int] * 5 + [ctypes.c_double] * 2 + [dp, dp])
+        L.orc_cheb_interval_bc.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_uint] +
+                                           [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [dp, dp])
+        L.orc_bicgstab_bc.restype = ctypes.c_int
+        L.orc_bicgstab_bc.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_uint, dp,
+                                                            dp] +
+                                      [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int] +
+                                      [ctypes.c_double] * 2 + [ctypes.c_int] * 2 +
+                                      [ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)])
         L.orc_cheb_interval.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] +
                                         [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [dp, dp])
         L.orc_apply_A.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp]
@@ -101,19 +121,21 @@ def dirichlet_eig(i, n):
     return lib().orc_dirichlet_eig(int(i), int(n))
 
 
-def interval(shape, h, block=0):
-    """(lambda_min, lambda_max) of the grid operator, or of one diagonal block."""
+def interval(shape, h, block=0, bc=0):
+    """(lambda_min, lambda_max) of the grid operator, or an interval containing the
+    spectra of all its diagonal blocks. bc: bit f (x-, x+, y-, y+, z-, z+) = Neumann."""
     nx, ny, nz = shape
     lo, hi = ctypes.c_double(), ctypes.c_double()
-    lib().orc_interval(nx, ny, nz, h, block, ctypes.byref(lo), ctypes.byref(hi))
+    lib().orc_interval_bc(nx, ny, nz, h, block, bc, ctypes.byref(lo), ctypes.byref(hi))
     return lo.value, hi.value
 
 
-def cheb_interval(shape, h, precond, block=64, bj_global=0, lmin_scale=1.0, lmax_scale=1.0):
+def cheb_interval(shape, h, precond, block=64, bj_global=0, lmin_scale=1.0, lmax_scale=1.0,
+                  bc=0):
     nx, ny, nz = shape
     lo, hi = ctypes.c_double(), ctypes.c_double()
-    lib().orc_cheb_interval(nx, ny, nz, h, precond, block, bj_global, lmin_scale, lmax_scale,
-                            ctypes.byref(lo), ctypes.byref(hi))
+    lib().orc_cheb_interval_bc(nx, ny, nz, h, bc, precond, block, bj_global, lmin_scale,
+                               lmax_scale, ctypes.byref(lo), ctypes.byref(hi))
     return lo.value, hi.value
 
 
@@ -123,30 +145,30 @@ def _grid(u):
     return nx, ny, nz
 
 
-def apply_A(u, h, block=0):
+def apply_A(u, h, block=0, bc=0):
     u = _f64(u)
     out = np.empty_like(u)
     nx, ny, nz = _grid(u)
-    lib().orc_apply_A(nx, ny, nz, h, block, _dp(u), _dp(out))
+    lib().orc_apply_A_bc(nx, ny, nz, h, block, bc, _dp(u), _dp(out))
     return out
 
 
-def chebyshev(b, h, lo, hi, m, block=0, mixed=False):
+def chebyshev(b, h, lo, hi, m, block=0, mixed=False, bc=0):
     b = _f64(b)
     out = np.empty_like(b)
     nx, ny, nz = _grid(b)
-    f = lib().orc_chebyshev_f32 if mixed else lib().orc_chebyshev
-    f(nx, ny, nz, h, block, lo, hi, m, _dp(b), _dp(out))
+    f = lib().orc_chebyshev_f32_bc if mixed else lib().orc_chebyshev_bc
+    f(nx, ny, nz, h, block, bc, lo, hi, m, _dp(b), _dp(out))
     return out
 
 
 def precond(v, h, pc, degree=8, mixed=False, block=64, bj_global=0, lmin_scale=1.0,
-            lmax_scale=1.0):
+            lmax_scale=1.0, bc=0):
     v = _f64(v)
     out = np.empty_like(v)
     nx, ny, nz = _grid(v)
-    lib().orc_precond(nx, ny, nz, h, pc, degree, int(mixed), block, bj_global, lmin_scale,
-                      lmax_scale, _dp(v), _dp(out))
+    lib().orc_precond_bc(nx, ny, nz, h, bc, pc, degree, int(mixed), block, bj_global,
+                         lmin_scale, lmax_scale, _dp(v), _dp(out))
     return out
 
 
@@ -173,7 +195,7 @@ class Result:
 
 
 def bicgstab(b, h, pc=PC_NONE, degree=8, mixed=False, tol=1e-8, maxit=5000, x0=None,
-             lmin_scale=1.0, lmax_scale=1.0, block=64, bj_global=0, jacobi_diag=0.0):
+             lmin_scale=1.0, lmax_scale=1.0, block=64, bj_global=0, jacobi_diag=0.0, bc=0):
     """Right-preconditioned Bi-CGSTAB (Alg. 1); returns a Result."""
     b = _f64(b)
     x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
@@ -181,7 +203,8 @@ def bicgstab(b, h, pc=PC_NONE, degree=8, mixed=False, tol=1e-8, maxit=5000, x0=N
     trace = np.zeros((maxit, 4))
     it, half = ctypes.c_int(), ctypes.c_int()
     rr0 = ctypes.c_double()
-    st = lib().orc_bicgstab(nx, ny, nz, h, _dp(b), _dp(x), pc, degree, int(mixed), tol, maxit,
-                            lmin_scale, lmax_scale, block, bj_global, jacobi_diag, _dp(trace),
-                            ctypes.byref(rr0), ctypes.byref(it), ctypes.byref(half))
+    st = lib().orc_bicgstab_bc(nx, ny, nz, h, bc, _dp(b), _dp(x), pc, degree, int(mixed), tol,
+                               maxit, lmin_scale, lmax_scale, block, bj_global, jacobi_diag,
+                               _dp(trace), ctypes.byref(rr0), ctypes.byref(it),
+                               ctypes.byref(half))
     return Result(x, st, it.value, half.value, trace, rr0.value)

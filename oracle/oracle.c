@@ -26,6 +26,9 @@
  *   orc_bicgstab     dense direct solves, finite termination on k eigenmodes,
  *                    manufactured solution and its O(h^2) error, power-of-two
  *                    Jacobi scaling identity
+ *   *_bc variants    (Neumann faces, eq. matrix_neuman) dense assembly of the
+ *                    one-sided matrices, dense non-symmetric eigenvalues,
+ *                    cosine eigenmodes, dense solves with mixed faces
  */
 #include <math.h>
 #include <omp.h>
@@ -193,68 +196,152 @@ double orc_dirichlet_eig(int i, int n)
     return 4.0 * s * s;
 }
 
-/* lambda_min / lambda_max of A = Kronecker sum of D_n/h^2 over the three axes;
-   block > 0 gives the spectrum of one block x block x block diagonal block
-   (each axis clipped to the grid extent), the local matrix R_s A R_s^T */
-void orc_interval(int nx, int ny, int nz, double h, int block, double *lmin, double *lmax)
+/* Smallest and largest eigenvalue of the 1D operator of one axis of length n:
+   D (eq. matrix_dirichlet) when both ends are Dirichlet, N (eq. matrix_neuman)
+   when one end is Neumann, and N with both corner entries 2 when both are.
+   The paper gives no closed form for N; the eigenvectors of the one-sided case
+   are cos((2k-1) pi j / (2n)) (zero just past the Dirichlet end, mirrored at
+   the Neumann end), giving 4 sin^2((2k-1) pi / (4n)), k = 1..n; with two
+   Neumann ends they are cos(k pi j / (n-1)), giving 4 sin^2(k pi / (2(n-1))),
+   k = 0..n-1. These closed forms are pinned against dense eigenvalues. */
+static void axis_eigs(int n, int neu_lo, int neu_hi, double *mn, double *mx)
+{
+    if (!neu_lo && !neu_hi) {
+        *mn = orc_dirichlet_eig(1, n);
+        *mx = orc_dirichlet_eig(n, n);
+    } else if (neu_lo != neu_hi) {
+        double a = sin(1.0 * M_PI / (4.0 * (double)n));
+        double b = sin((double)(2 * n - 1) * M_PI / (4.0 * (double)n));
+        *mn = 4.0 * a * a;
+        *mx = 4.0 * b * b;
+    } else {
+        double b = sin((double)(n - 1) * M_PI / (2.0 * (double)(n - 1)));
+        *mn = 0.0;
+        *mx = 4.0 * b * b;
+    }
+}
+
+/* interval containing the spectra of all diagonal blocks of one axis: with
+   blocks, the first block keeps the low face's condition, the last the high
+   face's, the others are Dirichlet; a block shorter than `block` has its
+   spectrum inside that of the full-length block of the same type */
+static void axis_interval(int n, int block, int neu_lo, int neu_hi, double *mn, double *mx)
+{
+    if (block <= 0 || n <= block) {
+        axis_eigs(n, neu_lo, neu_hi, mn, mx);
+        return;
+    }
+    double a, b;
+    axis_eigs(block, 0, 0, mn, mx);
+    axis_eigs(block, neu_lo, 0, &a, &b);
+    if (a < *mn) *mn = a;
+    if (b > *mx) *mx = b;
+    axis_eigs(block, 0, neu_hi, &a, &b);
+    if (a < *mn) *mn = a;
+    if (b > *mx) *mx = b;
+}
+
+/* lambda_min / lambda_max of A = Kronecker sum of O/h^2 over the three axes
+   (eqs. lambdaMin, lambdaMax); bc bit f (x-, x+, y-, y+, z-, z+) = Neumann on
+   face f. block > 0 gives an interval containing the spectrum of every
+   block x block x block diagonal block R_s A R_s^T. */
+void orc_interval_bc(int nx, int ny, int nz, double h, int block, unsigned bc, double *lmin,
+                     double *lmax)
 {
     int n[3] = {nx, ny, nz};
-    if (block > 0)
-        for (int d = 0; d < 3; ++d) if (n[d] > block) n[d] = block;
+    double mn[3], mx[3];
+    for (int d = 0; d < 3; ++d)
+        axis_interval(n[d], block, (bc >> (2 * d)) & 1, (bc >> (2 * d + 1)) & 1, &mn[d], &mx[d]);
     double h2 = h * h;
-    *lmin = orc_dirichlet_eig(1, n[0]) / h2 + orc_dirichlet_eig(1, n[1]) / h2 +
-            orc_dirichlet_eig(1, n[2]) / h2;
-    *lmax = orc_dirichlet_eig(n[0], n[0]) / h2 + orc_dirichlet_eig(n[1], n[1]) / h2 +
-            orc_dirichlet_eig(n[2], n[2]) / h2;
+    *lmin = mn[0] / h2 + mn[1] / h2 + mn[2] / h2;
+    *lmax = mx[0] / h2 + mx[1] / h2 + mx[2] / h2;
+}
+
+void orc_interval(int nx, int ny, int nz, double h, int block, double *lmin, double *lmax)
+{
+    orc_interval_bc(nx, ny, nz, h, block, 0u, lmin, lmax);
 }
 
 /* ------------------------------------------------------------------------- */
-/* The operator (eq. matrix_p with O = D on every axis): for uniform spacing  */
-/* (A u)_ijk = (6 u_ijk - six neighbours) / h^2, neighbours outside the grid  */
-/* are zero. With block > 0 a neighbour in another block also reads as zero,  */
-/* which is the block-diagonal part R_s A R_s^T of eq. blockJacobiPreconditioner. */
+/* The operator (eq. matrix_p): for uniform spacing                          */
+/* (A u)_ijk = (6 u_ijk - six neighbours) / h^2. Outside a Dirichlet face a   */
+/* neighbour reads as zero (matrix D); outside a Neumann face it is the      */
+/* mirror image of the interior neighbour, u_{-1} = u_1 (the corner entry 2  */
+/* of matrix N, eq. matrix_neuman). With block > 0 a neighbour in another    */
+/* block also reads as zero: the block-diagonal part R_s A R_s^T of          */
+/* eq. blockJacobiPreconditioner.                                            */
 /* ------------------------------------------------------------------------- */
 #define IDX(i, j, k) ((size_t)(i) + (size_t)nx * ((size_t)(j) + (size_t)ny * (size_t)(k)))
 
-static int nb_ok(int a, int b, int n, int block)
+/* coordinate of the neighbour of a at a + d (d = +-1) along an axis of length n,
+   or -1 if it reads as zero */
+static int nbr(int a, int d, int n, int block, int neu_lo, int neu_hi)
 {
-    if (b < 0 || b >= n) return 0;
-    if (block > 0 && a / block != b / block) return 0;
-    return 1;
+    int b = a + d;
+    if (b < 0) {
+        if (!neu_lo) return -1;
+        b = a + 1; /* mirror ghost */
+    } else if (b >= n) {
+        if (!neu_hi) return -1;
+        b = a - 1;
+    }
+    if (b < 0 || b >= n) return -1;
+    /* the block-diagonal part drops every coupling between blocks, mirrored ones too */
+    if (block > 0 && a / block != b / block) return -1;
+    return b;
 }
 
-void orc_apply_A(int nx, int ny, int nz, double h, int block, const double *u, double *out)
+void orc_apply_A_bc(int nx, int ny, int nz, double h, int block, unsigned bc, const double *u,
+                    double *out)
 {
     double ih2 = 1.0 / (h * h);
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
+                int im = nbr(i, -1, nx, block, bc & 1, (bc >> 1) & 1);
+                int ip = nbr(i, +1, nx, block, bc & 1, (bc >> 1) & 1);
+                int jm = nbr(j, -1, ny, block, (bc >> 2) & 1, (bc >> 3) & 1);
+                int jp = nbr(j, +1, ny, block, (bc >> 2) & 1, (bc >> 3) & 1);
+                int km = nbr(k, -1, nz, block, (bc >> 4) & 1, (bc >> 5) & 1);
+                int kp = nbr(k, +1, nz, block, (bc >> 4) & 1, (bc >> 5) & 1);
                 double c = u[IDX(i, j, k)];
-                double xm = nb_ok(i, i - 1, nx, block) ? u[IDX(i - 1, j, k)] : 0.0;
-                double xp = nb_ok(i, i + 1, nx, block) ? u[IDX(i + 1, j, k)] : 0.0;
-                double ym = nb_ok(j, j - 1, ny, block) ? u[IDX(i, j - 1, k)] : 0.0;
-                double yp = nb_ok(j, j + 1, ny, block) ? u[IDX(i, j + 1, k)] : 0.0;
-                double zm = nb_ok(k, k - 1, nz, block) ? u[IDX(i, j, k - 1)] : 0.0;
-                double zp = nb_ok(k, k + 1, nz, block) ? u[IDX(i, j, k + 1)] : 0.0;
+                double xm = im >= 0 ? u[IDX(im, j, k)] : 0.0;
+                double xp = ip >= 0 ? u[IDX(ip, j, k)] : 0.0;
+                double ym = jm >= 0 ? u[IDX(i, jm, k)] : 0.0;
+                double yp = jp >= 0 ? u[IDX(i, jp, k)] : 0.0;
+                double zm = km >= 0 ? u[IDX(i, j, km)] : 0.0;
+                double zp = kp >= 0 ? u[IDX(i, j, kp)] : 0.0;
                 out[IDX(i, j, k)] = (6.0 * c - xm - xp - ym - yp - zm - zp) * ih2;
             }
 }
 
+void orc_apply_A(int nx, int ny, int nz, double h, int block, const double *u, double *out)
+{
+    orc_apply_A_bc(nx, ny, nz, h, block, 0u, u, out);
+}
+
 /* the same operator on FP32 data in FP32 arithmetic (mixed-precision preconditioner) */
-static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, const float *u, float *out)
+static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, unsigned bc, const float *u,
+                        float *out)
 {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
+                int im = nbr(i, -1, nx, block, bc & 1, (bc >> 1) & 1);
+                int ip = nbr(i, +1, nx, block, bc & 1, (bc >> 1) & 1);
+                int jm = nbr(j, -1, ny, block, (bc >> 2) & 1, (bc >> 3) & 1);
+                int jp = nbr(j, +1, ny, block, (bc >> 2) & 1, (bc >> 3) & 1);
+                int km = nbr(k, -1, nz, block, (bc >> 4) & 1, (bc >> 5) & 1);
+                int kp = nbr(k, +1, nz, block, (bc >> 4) & 1, (bc >> 5) & 1);
                 float c = u[IDX(i, j, k)];
-                float xm = nb_ok(i, i - 1, nx, block) ? u[IDX(i - 1, j, k)] : 0.0f;
-                float xp = nb_ok(i, i + 1, nx, block) ? u[IDX(i + 1, j, k)] : 0.0f;
-                float ym = nb_ok(j, j - 1, ny, block) ? u[IDX(i, j - 1, k)] : 0.0f;
-                float yp = nb_ok(j, j + 1, ny, block) ? u[IDX(i, j + 1, k)] : 0.0f;
-                float zm = nb_ok(k, k - 1, nz, block) ? u[IDX(i, j, k - 1)] : 0.0f;
-                float zp = nb_ok(k, k + 1, nz, block) ? u[IDX(i, j, k + 1)] : 0.0f;
+                float xm = im >= 0 ? u[IDX(im, j, k)] : 0.0f;
+                float xp = ip >= 0 ? u[IDX(ip, j, k)] : 0.0f;
+                float ym = jm >= 0 ? u[IDX(i, jm, k)] : 0.0f;
+                float yp = jp >= 0 ? u[IDX(i, jp, k)] : 0.0f;
+                float zm = km >= 0 ? u[IDX(i, j, km)] : 0.0f;
+                float zp = kp >= 0 ? u[IDX(i, j, kp)] : 0.0f;
                 out[IDX(i, j, k)] = (6.0f * c - xm - xp - ym - yp - zm - zp) * ih2;
             }
 }
@@ -266,8 +353,8 @@ static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, const floa
 /* and m = 1 returns y; for m >= 2 the loop runs i = 2..m and returns w.      */
 /* block > 0 uses the block-diagonal operator (BJ(CI) / GNoComm(CI)).         */
 /* ------------------------------------------------------------------------- */
-void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
-                   const double *b, double *x)
+void orc_chebyshev_bc(int nx, int ny, int nz, double h, int block, unsigned bc, double lo,
+                      double hi, int m, const double *b, double *x)
 {
     size_t N = (size_t)nx * ny * nz;
     double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
@@ -279,12 +366,12 @@ void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, doubl
     }
     double *z = malloc(N * 8), *y = malloc(N * 8), *w = malloc(N * 8), *Av = malloc(N * 8);
     for (size_t q = 0; q < N; ++q) z[q] = b[q] / theta;
-    orc_apply_A(nx, ny, nz, h, block, b, Av);
+    orc_apply_A_bc(nx, ny, nz, h, block, bc, b, Av);
     for (size_t q = 0; q < N; ++q) y[q] = 2.0 * rho_cur / delta * (2.0 * b[q] - Av[q] / theta);
     for (int i = 2; i <= m; ++i) {
         rho_old = rho_cur;
         rho_cur = 1.0 / (2.0 * sigma - rho_old);
-        orc_apply_A(nx, ny, nz, h, block, y, Av);
+        orc_apply_A_bc(nx, ny, nz, h, block, bc, y, Av);
         for (size_t q = 0; q < N; ++q)
             w[q] = rho_cur * (2.0 * sigma * y[q] + 2.0 / delta * (b[q] - Av[q]) - rho_old * z[q]);
         double *tmp = z; z = y; y = w; w = tmp; /* z <- y, y <- w */
@@ -296,8 +383,8 @@ void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, doubl
 /* Mixed precision: the same steps with every scalar coefficient computed in
    FP64 and rounded once to FP32, the input rounded once to FP32, and all vector
    arithmetic in FP32. The FP32 result is returned widened (exactly) to FP64. */
-void orc_chebyshev_f32(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
-                       const double *b, double *x)
+void orc_chebyshev_f32_bc(int nx, int ny, int nz, double h, int block, unsigned bc, double lo,
+                          double hi, int m, const double *b, double *x)
 {
     size_t N = (size_t)nx * ny * nz;
     double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
@@ -314,7 +401,7 @@ void orc_chebyshev_f32(int nx, int ny, int nz, double h, int block, double lo, d
     }
     float *z = malloc(N * 4), *y = malloc(N * 4), *w = malloc(N * 4), *Av = malloc(N * 4);
     for (size_t q = 0; q < N; ++q) z[q] = bf[q] / theta_f;
-    apply_A_f32(nx, ny, nz, ih2_f, block, bf, Av);
+    apply_A_f32(nx, ny, nz, ih2_f, block, bc, bf, Av);
     float c1 = (float)(2.0 * rho_cur / delta);
     for (size_t q = 0; q < N; ++q) y[q] = c1 * (2.0f * bf[q] - Av[q] / theta_f);
     float two_sigma = (float)(2.0 * sigma), two_over_delta = (float)(2.0 / delta);
@@ -322,13 +409,25 @@ void orc_chebyshev_f32(int nx, int ny, int nz, double h, int block, double lo, d
         rho_old = rho_cur;
         rho_cur = 1.0 / (2.0 * sigma - rho_old);
         float rc = (float)rho_cur, ro = (float)rho_old;
-        apply_A_f32(nx, ny, nz, ih2_f, block, y, Av);
+        apply_A_f32(nx, ny, nz, ih2_f, block, bc, y, Av);
         for (size_t q = 0; q < N; ++q)
             w[q] = rc * (two_sigma * y[q] + two_over_delta * (bf[q] - Av[q]) - ro * z[q]);
         float *tmp = z; z = y; y = w; w = tmp;
     }
     for (size_t q = 0; q < N; ++q) x[q] = (double)y[q];
     free(bf); free(z); free(y); free(w); free(Av);
+}
+
+void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
+                   const double *b, double *x)
+{
+    orc_chebyshev_bc(nx, ny, nz, h, block, 0u, lo, hi, m, b, x);
+}
+
+void orc_chebyshev_f32(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
+                       const double *b, double *x)
+{
+    orc_chebyshev_f32_bc(nx, ny, nz, h, block, 0u, lo, hi, m, b, x);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -339,17 +438,26 @@ typedef struct {
     double h;
     int precond, degree, mixed, block, bj_global;
     double lmin_scale, lmax_scale, jacobi_diag;
+    unsigned bc;
 } pc_t;
 
 /* the eigenvalue interval handed to the Chebyshev iteration */
-void orc_cheb_interval(int nx, int ny, int nz, double h, int precond, int block, int bj_global,
-                       double lmin_scale, double lmax_scale, double *lo, double *hi)
+void orc_cheb_interval_bc(int nx, int ny, int nz, double h, unsigned bc, int precond, int block,
+                          int bj_global, double lmin_scale, double lmax_scale, double *lo,
+                          double *hi)
 {
     int local = (precond == PC_BLOCK_JACOBI && !bj_global) ? block : 0;
     double a, b;
-    orc_interval(nx, ny, nz, h, local, &a, &b);
+    orc_interval_bc(nx, ny, nz, h, local, bc, &a, &b);
     *lo = a * lmin_scale;
     *hi = b * lmax_scale;
+}
+
+void orc_cheb_interval(int nx, int ny, int nz, double h, int precond, int block, int bj_global,
+                       double lmin_scale, double lmax_scale, double *lo, double *hi)
+{
+    orc_cheb_interval_bc(nx, ny, nz, h, 0u, precond, block, bj_global, lmin_scale, lmax_scale, lo,
+                         hi);
 }
 
 static void apply_pc(const pc_t *pc, const double *v, double *out)
@@ -366,25 +474,35 @@ static void apply_pc(const pc_t *pc, const double *v, double *out)
         return;
     }
     double lo, hi;
-    orc_cheb_interval(pc->nx, pc->ny, pc->nz, pc->h, pc->precond, pc->block, pc->bj_global,
-                      pc->lmin_scale, pc->lmax_scale, &lo, &hi);
+    orc_cheb_interval_bc(pc->nx, pc->ny, pc->nz, pc->h, pc->bc, pc->precond, pc->block,
+                         pc->bj_global, pc->lmin_scale, pc->lmax_scale, &lo, &hi);
     int blk = pc->precond == PC_BLOCK_JACOBI ? pc->block : 0;
     if (pc->mixed)
-        orc_chebyshev_f32(pc->nx, pc->ny, pc->nz, pc->h, blk, lo, hi, pc->degree, v, out);
+        orc_chebyshev_f32_bc(pc->nx, pc->ny, pc->nz, pc->h, blk, pc->bc, lo, hi, pc->degree, v,
+                             out);
     else
-        orc_chebyshev(pc->nx, pc->ny, pc->nz, pc->h, blk, lo, hi, pc->degree, v, out);
+        orc_chebyshev_bc(pc->nx, pc->ny, pc->nz, pc->h, blk, pc->bc, lo, hi, pc->degree, v, out);
 }
 
 /* one preconditioner application, exported for kernel-level parity tests */
-void orc_precond(int nx, int ny, int nz, double h, int precond, int degree, int mixed, int block,
-                 int bj_global, double lmin_scale, double lmax_scale, const double *v, double *out)
+void orc_precond_bc(int nx, int ny, int nz, double h, unsigned bc, int precond, int degree,
+                    int mixed, int block, int bj_global, double lmin_scale, double lmax_scale,
+                    const double *v, double *out)
 {
-    pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global, lmin_scale, lmax_scale, 0.0};
+    pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global, lmin_scale, lmax_scale,
+               0.0, bc};
     if (precond == PC_NONE) {
         memcpy(out, v, (size_t)nx * ny * nz * 8);
         return;
     }
     apply_pc(&pc, v, out);
+}
+
+void orc_precond(int nx, int ny, int nz, double h, int precond, int degree, int mixed, int block,
+                 int bj_global, double lmin_scale, double lmax_scale, const double *v, double *out)
+{
+    orc_precond_bc(nx, ny, nz, h, 0u, precond, degree, mixed, block, bj_global, lmin_scale,
+                   lmax_scale, v, out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -394,15 +512,15 @@ void orc_precond(int nx, int ny, int nz, double h, int precond, int degree, int 
 /* trace (optional, 4*maxit doubles): per iteration alpha, omega, rho_{i-1},  */
 /* and the squared residual norm tested at exit of that iteration.            */
 /* ------------------------------------------------------------------------- */
-int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, int precond,
-                 int degree, int mixed, double tol, int maxit, double lmin_scale,
-                 double lmax_scale, int block, int bj_global, double jacobi_diag, double *trace,
-                 double *rr0_out, int *iters, int *half)
+int orc_bicgstab_bc(int nx, int ny, int nz, double h, unsigned bc, const double *b, double *x,
+                    int precond, int degree, int mixed, double tol, int maxit, double lmin_scale,
+                    double lmax_scale, int block, int bj_global, double jacobi_diag, double *trace,
+                    double *rr0_out, int *iters, int *half)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || maxit < 1) return ORC_ERR_ARG;
     size_t N = (size_t)nx * ny * nz;
     pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global,
-               lmin_scale, lmax_scale, jacobi_diag};
+               lmin_scale, lmax_scale, jacobi_diag, bc};
     *iters = 0;
     *half = 0;
     double *r = malloc(N * 8), *rt = malloc(N * 8), *p = malloc(N * 8), *w = malloc(N * 8),
@@ -410,7 +528,7 @@ int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, i
     int status = ORC_NOT_CONVERGED;
 
     /* r0 = b - A x0, r~ = r0, p0 = r0, rho0 = r~.r0 */
-    orc_apply_A(nx, ny, nz, h, 0, x, w);
+    orc_apply_A_bc(nx, ny, nz, h, 0, bc, x, w);
     for (size_t q = 0; q < N; ++q) r[q] = b[q] - w[q];
     memcpy(rt, r, N * 8);
     memcpy(p, r, N * 8);
@@ -429,7 +547,7 @@ int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, i
         const double *php = p;
         if (precond != PC_NONE) { apply_pc(&pc, p, ph); php = ph; }
         /* w = A p^, alpha = rho / (r~ . w) */
-        orc_apply_A(nx, ny, nz, h, 0, php, w);
+        orc_apply_A_bc(nx, ny, nz, h, 0, bc, php, w);
         double d = orc_dot(rt, w, (int64_t)N);
         if (!isfinite(d)) { status = ORC_ERR_NONFINITE; goto out; }
         if (d == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
@@ -449,7 +567,7 @@ int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, i
         /* solve M s^ = s, t = A s^, omega = (t.s)/(t.t) */
         const double *shp = r;
         if (precond != PC_NONE) { apply_pc(&pc, r, sh); shp = sh; }
-        orc_apply_A(nx, ny, nz, h, 0, shp, t);
+        orc_apply_A_bc(nx, ny, nz, h, 0, bc, shp, t);
         double ts = orc_dot(t, r, (int64_t)N);
         double tt = orc_dot(t, t, (int64_t)N);
         if (!isfinite(ts) || !isfinite(tt)) { status = ORC_ERR_NONFINITE; goto out; }
@@ -473,4 +591,14 @@ int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, i
 out:
     free(r); free(rt); free(p); free(w); free(t); free(ph); free(sh);
     return status;
+}
+
+int orc_bicgstab(int nx, int ny, int nz, double h, const double *b, double *x, int precond,
+                 int degree, int mixed, double tol, int maxit, double lmin_scale,
+                 double lmax_scale, int block, int bj_global, double jacobi_diag, double *trace,
+                 double *rr0_out, int *iters, int *half)
+{
+    return orc_bicgstab_bc(nx, ny, nz, h, 0u, b, x, precond, degree, mixed, tol, maxit,
+                           lmin_scale, lmax_scale, block, bj_global, jacobi_diag, trace, rr0_out,
+                           iters, half);
 }

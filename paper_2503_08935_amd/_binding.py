@@ -285,12 +285,12 @@ class Server:
         self.close()
 
     def submit(self, rhs, x, shape, h, precond=PC_CHEBYSHEV, degree=4, precision=MIXED, tol=1e-8,
-               maxit=5000):
+               maxit=5000, bc=0):
         import torch
         nx, ny, nz = shape
         n = nx * ny * nz
         t = ctypes.c_uint64()
-        _check(lib().poisson_server_submit(self._srv, nx, ny, nz, float(h), 0,
+        _check(lib().poisson_server_submit(self._srv, nx, ny, nz, float(h), int(bc),
                                            _ptr(rhs, n, (torch.float64,)),
                                            _ptr(x, n, (torch.float64,)), int(precond), int(degree),
                                            int(precision), float(tol), int(maxit), ctypes.byref(t)),

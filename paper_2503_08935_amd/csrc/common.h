@@ -47,7 +47,9 @@ struct Prob {
     int tx, ty, tz, ntiles;      // tile counts
     int block;                   // Block-Jacobi block edge (masked operator), 0 = none
     int maxit, debug_breakdown_at, degree;
-    int hist_iters, pad_i[3];    // iterations recorded in hist
+    int hist_iters;              // iterations recorded in hist
+    unsigned bc;                 // bit f (x-, x+, y-, y+, z-, z+) = Neumann on face f
+    int pad_i[2];
     double ih2;                  // 1/(h*h)
     double tol2;                 // tol*tol
     double jac_d;                // diagonal of A = 6*ih2

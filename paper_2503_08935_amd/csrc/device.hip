@@ -386,15 +386,28 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
             const TU *__restrict__ u = (const TU *)P.vec[A.in];
             const int B = MASK ? P.block : 1;
             const bool xin = i < nx;
-            const bool oxm = xin && i > 0 && (!MASK || i % B != 0);
-            const bool oxp = xin && i + 1 < nx && (!MASK || (i + 1) % B != 0);
-            bool rin[RY], oym[RY], oyp[RY];
+            // neighbour selection per face: 0 = reads zero (Dirichlet face or another
+            // block), 1 = the neighbour, 2 = the mirror image across a Neumann face
+            // (u_{-1} = u_1, eq. matrix_neuman); mirrors also respect the block mask
+            const unsigned bc = P.bc;
+            const int sxm = !xin ? 0
+                            : i > 0 ? ((!MASK || i % B != 0) ? 1 : 0)
+                                    : (((bc & 1u) && nx >= 2) ? 2 : 0);
+            const int sxp = !xin ? 0
+                            : i + 1 < nx ? ((!MASK || (i + 1) % B != 0) ? 1 : 0)
+                                         : (((bc & 2u) && nx >= 2 && (!MASK || i % B != 0)) ? 2 : 0);
+            bool rin[RY];
+            int sym[RY], syp[RY];
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const int j = j0 + r;
                 rin[r] = xin && j < ny;
-                oym[r] = rin[r] && j > 0 && (!MASK || j % B != 0);
-                oyp[r] = rin[r] && j + 1 < ny && (!MASK || (j + 1) % B != 0);
+                sym[r] = !rin[r] ? 0
+                         : j > 0 ? ((!MASK || j % B != 0) ? 1 : 0)
+                                 : (((bc & 4u) && ny >= 2) ? 2 : 0);
+                syp[r] = !rin[r] ? 0
+                         : j + 1 < ny ? ((!MASK || (j + 1) % B != 0) ? 1 : 0)
+                                      : (((bc & 8u) && ny >= 2 && (!MASK || j % B != 0)) ? 2 : 0);
             }
             const bool ymh = xin && j0 > 0;
             const bool yph = xin && j0 + RY < ny;
@@ -427,17 +440,19 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
 
             // type of the streamed operands: the arithmetic type for the Chebyshev steps
             using TO = typename std::conditional<(OP == S_CHEB2 || OP == S_CHEBK), TC, double>::type;
-            TC c[RY], zm[RY];
-            const bool zm0 = k0 > 0 && (!MASK || k0 % B != 0);
+            TC c[RY], zm[RY]; // planes k and k-1 (unmasked values)
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 c[r] = rin[r] ? (TC)u[base + r * NXs] : (TC)0;
-                zm[r] = (rin[r] && zm0) ? (TC)u[base + r * NXs - S] : (TC)0;
+                zm[r] = (rin[r] && k0 > 0) ? (TC)u[base + r * NXs - S] : (TC)0;
             }
             size_t hidx = hbase;
             for (int k = k0; k < k1; ++k, base += S, hidx += S) {
                 const bool znext = k + 1 < nz;
-                const bool zcut = MASK && ((k + 1) % B == 0);
+                const int szm = k > 0 ? ((!MASK || k % B != 0) ? 1 : 0)
+                                      : (((bc & 16u) && nz >= 2) ? 2 : 0);
+                const int szp = znext ? ((!MASK || (k + 1) % B != 0) ? 1 : 0)
+                                      : (((bc & 32u) && nz >= 2 && (!MASK || k % B != 0)) ? 2 : 0);
                 TC zr[RY];
                 TO o0[RY], o1[RY];
 #pragma unroll
@@ -458,16 +473,19 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
                 const TC he = hload ? (TC)u[hidx] : (TC)0;
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
-                    TC xm = lane_prev(c[r]), xp = lane_next(c[r]);
+                    TC xl = lane_prev(c[r]), xr = lane_next(c[r]);
                     const TC el = read_lane(he, r), er = read_lane(he, 32 + r);
-                    if (lane == 0) xm = el;
-                    if (lane == TX - 1) xp = er;
-                    xm = oxm ? xm : (TC)0;
-                    xp = oxp ? xp : (TC)0;
-                    const TC ym = oym[r] ? (r == 0 ? ymv : c[r > 0 ? r - 1 : 0]) : (TC)0;
-                    const TC yp = oyp[r] ? (r == RY - 1 ? ypv : c[r < RY - 1 ? r + 1 : 0]) : (TC)0;
-                    const TC zp = zcut ? (TC)0 : zr[r];
-                    const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zm[r]) - zp) * ih2;
+                    if (lane == 0) xl = el;
+                    if (lane == TX - 1) xr = er;
+                    const TC yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
+                    const TC yr = r == RY - 1 ? ypv : c[r < RY - 1 ? r + 1 : 0];
+                    const TC xm = sxm == 1 ? xl : sxm == 2 ? xr : (TC)0;
+                    const TC xp = sxp == 1 ? xr : sxp == 2 ? xl : (TC)0;
+                    const TC ym = sym[r] == 1 ? yl : sym[r] == 2 ? yr : (TC)0;
+                    const TC yp = syp[r] == 1 ? yr : syp[r] == 2 ? yl : (TC)0;
+                    const TC zmv = szm == 1 ? zm[r] : szm == 2 ? zr[r] : (TC)0;
+                    const TC zpv = szp == 1 ? zr[r] : szp == 2 ? zm[r] : (TC)0;
+                    const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zmv) - zpv) * ih2;
                     if (rin[r]) {
                         const size_t idx = base + r * NXs;
                         if constexpr (OP == S_APPLY) {
@@ -505,7 +523,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
                 }
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
-                    zm[r] = zcut ? (TC)0 : c[r];
+                    zm[r] = c[r];
                     c[r] = zr[r];
                 }
             }
@@ -517,6 +535,236 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
                 else if constexpr (OP == S_SDOT2) fin_sdot2(P, res[0], res[1]);
                 else if constexpr (OP == S_INIT) fin_init(P, res[0], res[1]);
                 else if constexpr (OP == S_TRUE) P.sc->rr_true = res[0];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// FP32 Chebyshev steps (mixed precision) with two consecutive x points per
+// lane, so every access moves 8 bytes (4 bytes per lane wastes half of each
+// memory transaction slot). Same tiles as k_stencil: the wave's RY rows are
+// split between its two half-waves (RY/2 rows each), a half-wave covers the
+// tile's 64 x points as 32 lanes x 2. x neighbours inside a lane's pair are
+// registers, across lanes DPP wave shifts, at half-wave edges the x-halo
+// values. Pair accesses are single 8-/16-byte loads when nx is even (aligned)
+// and two scalar accesses otherwise. The arithmetic per point is that of the
+// scalar kernel.
+// ------------------------------------------------------------------------
+template <typename T> struct Pair { T a, b; };
+
+template <typename TU>
+__device__ __forceinline__ Pair<float> load_pair(const TU *p, bool ok0, bool ok1, bool vec)
+{
+    Pair<float> r{0.0f, 0.0f};
+    if (vec) {
+        if (ok0) {
+            if constexpr (sizeof(TU) == 8) {
+                const double2 v = *(const double2 *)p;
+                r.a = (float)v.x;
+                r.b = (float)v.y;
+            } else {
+                const float2 v = *(const float2 *)p;
+                r.a = v.x;
+                r.b = v.y;
+            }
+        }
+    } else {
+        if (ok0) r.a = (float)p[0];
+        if (ok1) r.b = (float)p[1];
+    }
+    return r;
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ Pair<float> load_pair_nt(const float *p, bool ok0, bool ok1, bool vec)
+{
+    Pair<float> r{0.0f, 0.0f};
+    if (vec) {
+        if (ok0) {
+            const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
+            r.a = v.x;
+            r.b = v.y;
+        }
+    } else {
+        if (ok0) r.a = __builtin_nontemporal_load(p);
+        if (ok1) r.b = __builtin_nontemporal_load(p + 1);
+    }
+    return r;
+}
+
+__device__ __forceinline__ void store_pair_nt(float *p, float a, float b, bool ok0, bool ok1,
+                                              bool vec)
+{
+    if (vec) {
+        if (ok0) {
+            const f32x2 v = {a, b};
+            __builtin_nontemporal_store(v, (f32x2 *)p);
+        }
+    } else {
+        if (ok0) __builtin_nontemporal_store(a, p);
+        if (ok1) __builtin_nontemporal_store(b, p + 1);
+    }
+}
+
+// neighbour selection of one point along one axis: 0 zero, 1 neighbour, 2 mirror
+__device__ __forceinline__ int sel_lo(int a, int n, bool mask, int B, bool neu)
+{
+    return a > 0 ? ((!mask || a % B != 0) ? 1 : 0) : ((neu && n >= 2) ? 2 : 0);
+}
+__device__ __forceinline__ int sel_hi(int a, int n, bool mask, int B, bool neu)
+{
+    return a + 1 < n ? ((!mask || (a + 1) % B != 0) ? 1 : 0)
+                     : ((neu && n >= 2 && (!mask || a % B != 0)) ? 2 : 0);
+}
+
+template <int OP, typename TU, bool MASK>
+__global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
+{
+    static_assert(OP == S_CHEB1 || OP == S_CHEB2 || OP == S_CHEBK, "Chebyshev steps only");
+    constexpr int RH = RY / 2;
+    const int total = W.count_dev ? *W.count_dev : W.count;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int half = lane >> 5, hl = lane & 31;
+
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int pid = W.tile_prob ? W.tile_prob[g] : 0;
+        const int local = W.tile_prob ? W.tile_local[g] : g;
+        const Prob &P = W.probs[pid];
+        {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+        const int i0 = tix * TX;
+        const int x0 = i0 + 2 * hl;
+        const int jw = tiy * (TY * RY) + wv * RY; // the wave's first row
+        const int jh = jw + half * RH;            // this half-wave's first row
+        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+        if (jw >= ny) continue; // uniform within the wave (no barriers below)
+
+        const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+        const bool vec = (nx & 1) == 0;
+        const bool in0 = x0 < nx, in1 = x0 + 1 < nx;
+        const int B = MASK ? P.block : 1;
+        const unsigned bc = P.bc;
+        const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+        const bool nzl = bc & 16u, nzh = bc & 32u;
+        // x selections of the two points
+        const int sxm0 = in0 ? sel_lo(x0, nx, MASK, B, nxl) : 0;
+        const int sxp0 = in0 ? sel_hi(x0, nx, MASK, B, nxh) : 0;
+        const int sxm1 = in1 ? sel_lo(x0 + 1, nx, MASK, B, nxl) : 0;
+        const int sxp1 = in1 ? sel_hi(x0 + 1, nx, MASK, B, nxh) : 0;
+        bool rin[RH];
+        int sym[RH], syp[RH];
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
+            const int j = jh + r;
+            rin[r] = j < ny;
+            sym[r] = rin[r] ? sel_lo(j, ny, MASK, B, nyl) : 0;
+            syp[r] = rin[r] ? sel_hi(j, ny, MASK, B, nyh) : 0;
+        }
+        const bool ymh = in0 && jh > 0 && jh - 1 < ny;
+        const bool yph = in0 && jh + RH < ny;
+        // x halo: lane q < RY holds the left neighbour of wave row q, lane 32+q the right one
+        const int hrow = lane & 31;
+        const bool hload = hrow < RY && jw + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+        size_t hidx = (size_t)(lane < 32 ? i0 - 1 : i0 + TX) +
+                      NXs * ((size_t)(jw + hrow) + (size_t)ny * (size_t)k0);
+        size_t base = (size_t)x0 + NXs * ((size_t)jh + (size_t)ny * (size_t)k0);
+
+        const TU *__restrict__ u = (const TU *)P.vec[A.in];
+        float *out = (float *)P.vec[A.out];
+        const float *vv = (const float *)P.vec[A.v];
+        const float *zz = (const float *)P.vec[A.z];
+        float *v32 = (float *)P.vec[V_V32];
+        const float ih2 = P.ih2f;
+        float cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
+        if constexpr (OP == S_CHEB1) {
+            cA = P.c1f;
+            cB = P.thetaf;
+        } else {
+            cA = P.rcf[A.step];
+            cB = P.rof[A.step];
+            cC = P.two_sigmaf;
+            cD = P.two_over_deltaf;
+            cE = P.thetaf;
+        }
+        Pair<float> c[RH], zm[RH];
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
+            const size_t idx = base + r * NXs;
+            c[r] = load_pair(u + idx, in0 && rin[r], in1 && rin[r], vec);
+            zm[r] = k0 > 0 ? load_pair(u + idx - S, in0 && rin[r], in1 && rin[r], vec)
+                           : Pair<float>{0.0f, 0.0f};
+        }
+        for (int k = k0; k < k1; ++k, base += S, hidx += S) {
+            const int szm = sel_lo(k, nz, MASK, B, nzl);
+            const int szp = sel_hi(k, nz, MASK, B, nzh);
+            Pair<float> zr[RH], o0[RH], o1[RH];
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                const size_t idx = base + r * NXs;
+                const bool a0 = in0 && rin[r], a1 = in1 && rin[r];
+                zr[r] = k + 1 < nz ? load_pair(u + idx + S, a0, a1, vec) : Pair<float>{0.0f, 0.0f};
+                if constexpr (OP == S_CHEB2) o0[r] = load_pair_nt(vv + idx, a0, a1, vec);
+                if constexpr (OP == S_CHEBK) {
+                    o0[r] = load_pair_nt(vv + idx, a0, a1, vec);
+                    o1[r] = load_pair_nt(zz + idx, a0, a1, vec);
+                }
+            }
+            const Pair<float> ymv = load_pair(u + base - (ymh ? NXs : 0), ymh, ymh && in1, vec);
+            const Pair<float> ypv = load_pair(u + base + (yph ? RH * NXs : 0), yph, yph && in1, vec);
+            const float he = hload ? (float)u[hidx] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                // neighbours across lanes, fixed up with the halo at half-wave edges
+                float xl = lane_prev(c[r].b); // x0 - 1
+                float xr = lane_next(c[r].a); // x0 + 2
+                const float elA = read_lane(he, r), elB = read_lane(he, RH + r);
+                const float erA = read_lane(he, 32 + r), erB = read_lane(he, 32 + RH + r);
+                if (hl == 0) xl = half ? elB : elA;
+                if (hl == 31) xr = half ? erB : erA;
+                const Pair<float> yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
+                const Pair<float> yr = r == RH - 1 ? ypv : c[r < RH - 1 ? r + 1 : 0];
+                // point 0 at x0: left xl, right c.b; point 1 at x0+1: left c.a, right xr
+                const float xm0 = sxm0 == 1 ? xl : sxm0 == 2 ? c[r].b : 0.0f;
+                const float xp0 = sxp0 == 1 ? c[r].b : sxp0 == 2 ? xl : 0.0f;
+                const float xm1 = sxm1 == 1 ? c[r].a : sxm1 == 2 ? xr : 0.0f;
+                const float xp1 = sxp1 == 1 ? xr : sxp1 == 2 ? c[r].a : 0.0f;
+                const float ym0 = sym[r] == 1 ? yl.a : sym[r] == 2 ? yr.a : 0.0f;
+                const float ym1 = sym[r] == 1 ? yl.b : sym[r] == 2 ? yr.b : 0.0f;
+                const float yp0 = syp[r] == 1 ? yr.a : syp[r] == 2 ? yl.a : 0.0f;
+                const float yp1 = syp[r] == 1 ? yr.b : syp[r] == 2 ? yl.b : 0.0f;
+                const float zm0 = szm == 1 ? zm[r].a : szm == 2 ? zr[r].a : 0.0f;
+                const float zm1 = szm == 1 ? zm[r].b : szm == 2 ? zr[r].b : 0.0f;
+                const float zp0 = szp == 1 ? zr[r].a : szp == 2 ? zm[r].a : 0.0f;
+                const float zp1 = szp == 1 ? zr[r].b : szp == 2 ? zm[r].b : 0.0f;
+                const float a0 = ((((((6.0f * c[r].a - xm0) - xp0) - ym0) - yp0) - zm0) - zp0) * ih2;
+                const float a1 = ((((((6.0f * c[r].b - xm1) - xp1) - ym1) - yp1) - zm1) - zp1) * ih2;
+                const size_t idx = base + r * NXs;
+                const bool ok0 = in0 && rin[r], ok1 = in1 && rin[r];
+                float w0, w1;
+                if constexpr (OP == S_CHEB1) {
+                    w0 = cA * (2.0f * c[r].a - a0 / cB);
+                    w1 = cA * (2.0f * c[r].b - a1 / cB);
+                    store_pair_nt(v32 + idx, c[r].a, c[r].b, ok0, ok1, vec);
+                } else if constexpr (OP == S_CHEB2) {
+                    const float z0 = o0[r].a / cE, z1 = o0[r].b / cE;
+                    w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * z0);
+                    w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * z1);
+                } else {
+                    w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * o1[r].a);
+                    w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * o1[r].b);
+                }
+                store_pair_nt(out + idx, w0, w1, ok0, ok1, vec);
+            }
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                zm[r] = c[r];
+                c[r] = zr[r];
             }
         }
     }
@@ -701,21 +949,30 @@ static void ls_mask(bool mask, const Work &w, int grid, hipStream_t s, const KAr
     else ls<OP, TU, TC, false>(w, grid, s, a);
 }
 
+template <int OP, typename TU>
+static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    if (mask)
+        hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    else
+        hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+}
+
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                     const KArgs &a)
 {
     switch (op) {
     case S_APPLY: ls<S_APPLY, double, double, false>(w, grid, s, a); break;
     case S_CHEB1:
-        if (mixed) ls_mask<S_CHEB1, double, float>(mask, w, grid, s, a);
+        if (mixed) lf2_mask<S_CHEB1, double>(mask, w, grid, s, a);
         else ls_mask<S_CHEB1, double, double>(mask, w, grid, s, a);
         break;
     case S_CHEB2:
-        if (mixed) ls_mask<S_CHEB2, float, float>(mask, w, grid, s, a);
+        if (mixed) lf2_mask<S_CHEB2, float>(mask, w, grid, s, a);
         else ls_mask<S_CHEB2, double, double>(mask, w, grid, s, a);
         break;
     case S_CHEBK:
-        if (mixed) ls_mask<S_CHEBK, float, float>(mask, w, grid, s, a);
+        if (mixed) lf2_mask<S_CHEBK, float>(mask, w, grid, s, a);
         else ls_mask<S_CHEBK, double, double>(mask, w, grid, s, a);
         break;
     case S_SDOT:

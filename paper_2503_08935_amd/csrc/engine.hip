@@ -117,8 +117,8 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 {
-    return fill_prob(p, c->nx, c->ny, c->nz, c->h, pc, deg, c->opt, tol, maxit, &c->plan_lo,
-                     &c->plan_hi);
+    return fill_prob(p, c->nx, c->ny, c->nz, c->h, c->bc, pc, deg, c->opt, tol, maxit,
+                     &c->plan_lo, &c->plan_hi);
 }
 
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
@@ -282,7 +282,8 @@ int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **
     if (nx < 1 || ny < 1 || nz < 1) return POISSON_ERR_ARG;
     if ((double)nx * ny * nz > 17179869184.0) return POISSON_ERR_ARG;
     if (!(h > 0) || !std::isfinite(h)) return POISSON_ERR_ARG;
-    if (bc != 0) return POISSON_ERR_UNSUPPORTED;
+    const int rcb = check_bc(nx, ny, nz, bc);
+    if (rcb != POISSON_OK) return rcb;
     poisson_ctx *c = new (std::nothrow) poisson_ctx;
     if (!c) return POISSON_ERR_NOMEM;
     c->nx = nx; c->ny = ny; c->nz = nz; c->h = h; c->bc = bc;
@@ -354,7 +355,8 @@ int poisson_solve(poisson_ctx *c, const double *rhs, double *x, int precond, int
     if (is_cheb(precond)) {
         // reject a degenerate interval before touching the device
         double lo, hi;
-        if (!cheb_interval(c->nx, c->ny, c->nz, c->h, precond, c->opt, lo, hi)) return POISSON_ERR_ARG;
+        if (!cheb_interval(c->nx, c->ny, c->nz, c->h, c->bc, precond, c->opt, lo, hi))
+            return POISSON_ERR_ARG;
     }
     try {
         c->have_stats = false;

@@ -37,11 +37,14 @@ struct PlanOpts {
 Tiling make_tiling(int nx, int ny, int nz);
 bool is_cheb(int pc);
 // interval handed to the Chebyshev iteration; false if degenerate
-bool cheb_interval(int nx, int ny, int nz, double h, int pc, const PlanOpts &o, double &lo,
-                   double &hi);
+bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
+                   double &lo, double &hi);
+// boundary-condition mask checks: Neumann faces need 2 points on their axis, and
+// Neumann on all six faces (a singular operator) is not supported
+int check_bc(int nx, int ny, int nz, unsigned bc);
 // geometry, tolerance and coefficients; vectors, scalars, partials are left null
-int fill_prob(Prob &p, int nx, int ny, int nz, double h, int pc, int deg, const PlanOpts &o,
-              double tol, int maxit, double *lo, double *hi);
+int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, int deg,
+              const PlanOpts &o, double tol, int maxit, double *lo, double *hi);
 // bytes of vector slot v for a plan (0 if unused)
 size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed);
 // total workspace of a plan, each slot 256-byte aligned

@@ -28,17 +28,68 @@ static double dirichlet_eig(int i, int n)
     return 4.0 * s * s;
 }
 
-// lambda_min, lambda_max of the Kronecker sum (eqs. lambdaMin, lambdaMax); with
-// block > 0 the spectrum of one block x block x block diagonal block
-static void grid_interval(int nx, int ny, int nz, double h, int block, double &lo, double &hi)
+// smallest and largest eigenvalue of the 1D operator of an axis of length n:
+// D (eq. matrix_dirichlet), or N (eq. matrix_neuman) with one or two Neumann
+// ends; the one-sided eigenvalues are 4 sin^2((2k-1) pi / (4n)), k = 1..n, the
+// two-sided ones 4 sin^2(k pi / (2(n-1))), k = 0..n-1 (cosine eigenvectors)
+static void axis_eigs(int n, int neu_lo, int neu_hi, double &mn, double &mx)
 {
-    int n[3] = {nx, ny, nz};
-    if (block > 0)
-        for (int &v : n) v = std::min(v, block);
+    if (!neu_lo && !neu_hi) {
+        mn = dirichlet_eig(1, n);
+        mx = dirichlet_eig(n, n);
+    } else if (neu_lo != neu_hi) {
+        const double a = sin(1.0 * M_PI / (4.0 * (double)n));
+        const double b = sin((double)(2 * n - 1) * M_PI / (4.0 * (double)n));
+        mn = 4.0 * a * a;
+        mx = 4.0 * b * b;
+    } else {
+        const double b = sin((double)(n - 1) * M_PI / (2.0 * (double)(n - 1)));
+        mn = 0.0;
+        mx = 4.0 * b * b;
+    }
+}
+
+// interval containing every diagonal block's spectrum along one axis: the first
+// block keeps the low face's condition, the last the high face's, interior
+// blocks are Dirichlet, and a shorter block lies inside its full-length type
+static void axis_interval(int n, int block, int neu_lo, int neu_hi, double &mn, double &mx)
+{
+    if (block <= 0 || n <= block) {
+        axis_eigs(n, neu_lo, neu_hi, mn, mx);
+        return;
+    }
+    double a, b;
+    axis_eigs(block, 0, 0, mn, mx);
+    axis_eigs(block, neu_lo, 0, a, b);
+    mn = std::min(mn, a);
+    mx = std::max(mx, b);
+    axis_eigs(block, 0, neu_hi, a, b);
+    mn = std::min(mn, a);
+    mx = std::max(mx, b);
+}
+
+// lambda_min, lambda_max of the Kronecker sum (eqs. lambdaMin, lambdaMax); with
+// block > 0 an interval containing every block x block x block diagonal block
+static void grid_interval(int nx, int ny, int nz, double h, unsigned bc, int block, double &lo,
+                          double &hi)
+{
+    const int n[3] = {nx, ny, nz};
+    double mn[3], mx[3];
+    for (int d = 0; d < 3; ++d)
+        axis_interval(n[d], block, (bc >> (2 * d)) & 1, (bc >> (2 * d + 1)) & 1, mn[d], mx[d]);
     const double h2 = h * h;
-    lo = dirichlet_eig(1, n[0]) / h2 + dirichlet_eig(1, n[1]) / h2 + dirichlet_eig(1, n[2]) / h2;
-    hi = dirichlet_eig(n[0], n[0]) / h2 + dirichlet_eig(n[1], n[1]) / h2 +
-         dirichlet_eig(n[2], n[2]) / h2;
+    lo = mn[0] / h2 + mn[1] / h2 + mn[2] / h2;
+    hi = mx[0] / h2 + mx[1] / h2 + mx[2] / h2;
+}
+
+int check_bc(int nx, int ny, int nz, unsigned bc)
+{
+    if (bc > 63) return POISSON_ERR_ARG;
+    const int n[3] = {nx, ny, nz};
+    for (int d = 0; d < 3; ++d)
+        if (((bc >> (2 * d)) & 3) && n[d] < 2) return POISSON_ERR_ARG;
+    if (bc == 63) return POISSON_ERR_UNSUPPORTED;
+    return POISSON_OK;
 }
 
 Tiling make_tiling(int nx, int ny, int nz)
@@ -59,24 +110,25 @@ Tiling make_tiling(int nx, int ny, int nz)
 
 bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI; }
 
-bool cheb_interval(int nx, int ny, int nz, double h, int pc, const PlanOpts &o, double &lo,
-                   double &hi)
+bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
+                   double &lo, double &hi)
 {
     const int local = (pc == POISSON_PC_BLOCK_JACOBI && !o.bj_global) ? o.block : 0;
-    grid_interval(nx, ny, nz, h, local, lo, hi);
+    grid_interval(nx, ny, nz, h, bc, local, lo, hi);
     lo = lo * o.lmin_scale;
     hi = hi * o.lmax_scale;
     return lo > 0 && hi > lo && std::isfinite(hi);
 }
 
-int fill_prob(Prob &p, int nx, int ny, int nz, double h, int pc, int deg, const PlanOpts &o,
-              double tol, int maxit, double *lo_out, double *hi_out)
+int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, int deg,
+              const PlanOpts &o, double tol, int maxit, double *lo_out, double *hi_out)
 {
     memset(&p, 0, sizeof(Prob));
     const Tiling t = make_tiling(nx, ny, nz);
     p.nx = nx; p.ny = ny; p.nz = nz; p.kz = t.kz;
     p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
     p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
+    p.bc = bc;
     p.maxit = maxit;
     p.debug_breakdown_at = o.debug_bd;
     p.degree = deg;
@@ -89,7 +141,7 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, int pc, int deg, const 
     if (hi_out) *hi_out = 0;
     if (is_cheb(pc)) {
         double lo, hi;
-        if (!cheb_interval(nx, ny, nz, h, pc, o, lo, hi)) return POISSON_ERR_ARG;
+        if (!cheb_interval(nx, ny, nz, h, bc, pc, o, lo, hi)) return POISSON_ERR_ARG;
         if (lo_out) *lo_out = lo;
         if (hi_out) *hi_out = hi;
         // Alg. 2 scalars: theta, delta, sigma (eq. chebyshevQuantities) and the

@@ -41,6 +41,7 @@ struct Request {
     uint64_t ticket;
     int nx, ny, nz;
     double h;
+    unsigned bc;
     const double *rhs;
     double *x;
     int pc, deg, prec;
@@ -322,8 +323,8 @@ int step_impl(poisson_server *s, int iters)
         // descriptor: workspace, partials, scalars in the arena block
         PlanOpts o;
         Prob &p = s->h_probs[id];
-        if ((rc = fill_prob(p, sl.req.nx, sl.req.ny, sl.req.nz, sl.req.h, sl.req.pc, sl.req.deg, o,
-                            sl.req.tol, sl.req.maxit, &sl.lo, &sl.hi)) != POISSON_OK)
+        if ((rc = fill_prob(p, sl.req.nx, sl.req.ny, sl.req.nz, sl.req.h, sl.req.bc, sl.req.pc,
+                            sl.req.deg, o, sl.req.tol, sl.req.maxit, &sl.lo, &sl.hi)) != POISSON_OK)
             return rc;
         sl.ntiles = p.ntiles;
         char *blk = s->arena_base + off;
@@ -449,7 +450,8 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
     if (!s || !ticket || !rhs || !x) return POISSON_ERR_ARG;
     if (nx < 1 || ny < 1 || nz < 1 || (double)nx * ny * nz > 17179869184.0) return POISSON_ERR_ARG;
     if (!(h > 0) || !std::isfinite(h)) return POISSON_ERR_ARG;
-    if (bc != 0) return POISSON_ERR_UNSUPPORTED;
+    const int rcb = check_bc(nx, ny, nz, bc);
+    if (rcb != POISSON_OK) return rcb;
     if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
     if (is_cheb(precond) && (degree < 0 || degree > MAXDEG)) return POISSON_ERR_ARG;
     if (!is_cheb(precond)) degree = 0;
@@ -458,7 +460,7 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
     if (is_cheb(precond)) {
         PlanOpts o;
         double lo, hi;
-        if (!cheb_interval(nx, ny, nz, h, precond, o, lo, hi)) return POISSON_ERR_ARG;
+        if (!cheb_interval(nx, ny, nz, h, bc, precond, o, lo, hi)) return POISSON_ERR_ARG;
     }
     size_t fp;
     poisson_server_footprint(nx, ny, nz, precond, degree, precision, &fp);
@@ -468,7 +470,7 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
     if ((rc = validate_ptr(x)) != POISSON_OK) return rc;
     Request r;
     r.ticket = s->next_ticket++;
-    r.nx = nx; r.ny = ny; r.nz = nz; r.h = h;
+    r.nx = nx; r.ny = ny; r.nz = nz; r.h = h; r.bc = bc;
     r.rhs = rhs; r.x = x;
     r.pc = precond; r.deg = degree; r.prec = precision;
     r.tol = tol; r.maxit = maxit;

@@ -42,7 +42,13 @@ def test_create_validation():
                  (4, 4, 4, float("nan")), (4, 4, 4, float("inf")), (1 << 13, 1 << 13, 1 << 13, 0.1)]:
         assert L.poisson_create(*args, 0, ctypes.byref(ctx)) == P.ERR_ARG
         assert not ctx.value
-    assert L.poisson_create(4, 4, 4, 0.1, 1, ctypes.byref(ctx)) == P.ERR_UNSUPPORTED
+    # Neumann on every face is singular; a mask above 6 bits or a Neumann face on a
+    # 1-point axis is invalid
+    assert L.poisson_create(4, 4, 4, 0.1, 63, ctypes.byref(ctx)) == P.ERR_UNSUPPORTED
+    assert L.poisson_create(4, 4, 4, 0.1, 64, ctypes.byref(ctx)) == P.ERR_ARG
+    assert L.poisson_create(1, 4, 4, 0.1, 2, ctypes.byref(ctx)) == P.ERR_ARG
+    assert L.poisson_create(4, 4, 4, 0.1, 22, ctypes.byref(ctx)) == P.OK and ctx.value
+    L.poisson_destroy(ctx)
     assert L.poisson_create(4, 4, 4, 0.1, 0, None) == P.ERR_ARG
     assert L.poisson_create(4, 4, 4, 0.1, 0, ctypes.byref(ctx)) == P.OK and ctx.value
     L.poisson_destroy(ctx)
@@ -114,7 +120,7 @@ def test_server_host_side_checks():
     # a request larger than the whole budget is rejected before any device access
     assert L.poisson_server_submit(srv, 64, 64, 64, 1 / 65, 0, fake, fake, 2, 4, 1, 1e-8, 100,
                                    ctypes.byref(t)) == P.ERR_NOMEM
-    assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 1, fake, fake, 2, 4, 1, 1e-8, 100,
+    assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 63, fake, fake, 2, 4, 1, 1e-8, 100,
                                    ctypes.byref(t)) == P.ERR_UNSUPPORTED
     assert L.poisson_server_submit(srv, 8, 8, 8, 1 / 9, 0, fake, fake, 2, 4, 5, 1e-8, 100,
                                    ctypes.byref(t)) == P.ERR_ARG
