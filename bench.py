@@ -44,11 +44,16 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--no-unfused", action="store_true",
+                    help="skip the comparison solve with one Chebyshev step per pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-iters", type=int, default=4,
                     help="iterations per server step (completion is observed per step)")
+    ap.add_argument("--table2", action="store_true",
+                    help="instead of the benchmark: the preconditioner comparison of the paper's "
+                         "Table 2 on its test problem (255^3 unknowns, mixed faces) on one GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference dispatch of known "
                          "size for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -100,8 +105,47 @@ def cpu_baseline(n, h, degree, seed):
             "seconds_maxit1": ts[0], "seconds_maxit2": ts[1]}
 
 
+def table2():
+    """The solver comparison of the paper's Table 2 (Results section) on its test
+    problem, one GPU: BiCGS, BJ(CI), G(CI) and GNoComm(CI) with 24 Chebyshev
+    iterations per apply, the G/GNoComm interval rescaled by 100 and (1 - 1e-4)
+    (Experimental Setup), 64^3 blocks, tolerance 1e-10, FP64."""
+    import torch
+
+    import paper_2503_08935_amd as P
+    from paper_2503_08935_amd import workloads
+    f, shape, h, bc = workloads.paper_problem()
+    b = torch.from_numpy(f.ravel()).to("cuda:0")
+    x = torch.zeros_like(b)
+    rows = []
+    cases = [("BiCGS", P.PC_NONE, 0, {}),
+             ("BiCGS-BJ(CI)", P.PC_BLOCK_JACOBI, 24, {}),
+             ("BiCGS-G(CI)", P.PC_CHEBYSHEV, 24, dict(lmin_scale=100.0, lmax_scale=1 - 1e-4)),
+             ("BiCGS-GNoComm(CI)", P.PC_BLOCK_JACOBI, 24,
+              dict(bj_global_interval=1, lmin_scale=100.0, lmax_scale=1 - 1e-4)),
+             ("BiCGS-G(CI), analytic interval", P.PC_CHEBYSHEV, 24, {}),
+             ("BiCGS-G(CI) degree 8", P.PC_CHEBYSHEV, 8, {})]
+    for name, pc, m, opts in cases:
+        with P.Solver(shape, h, bc=bc, **opts) as s:
+            best = None
+            for rep in range(2):
+                x.zero_()
+                st = s.solve(b, x, pc, m, 1e-10, 20000)
+                d = s.stats()
+                best = d if best is None or d["solve_ms"] < best["solve_ms"] else best
+            rows.append({"solver": name, "status": st, "outer_iterations": best["iterations"],
+                         "precond_iterations_per_outer": 2 * m,
+                         "tts_s": round(best["solve_ms"] / 1e3, 4),
+                         "relres_true": best["relres_true"],
+                         "hbm_gbps": round(best["model_gbps"], 1)})
+            log(json.dumps(rows[-1]))
+    print(json.dumps({"table2_one_gpu": rows, "grid": shape, "h": h, "bc_neumann_mask": bc}))
+
+
 def main():
     a = parse()
+    if a.table2:
+        return table2()
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the solver has no "
               "multi-GPU path in this build", file=sys.stderr)
@@ -164,25 +208,42 @@ def main():
         f"{last['relres_true']:.3e}")
     x64 = x.clone()
 
-    # dominant kernel: interior Chebyshev step, timed on the solver's stream
+    # dominant kernel (two fused interior Chebyshev steps, FP64), timed with HIP
+    # events on the solver's stream; the single interior step for reference
     reps = a.kernel_reps
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    s64.kernel_bench(P.KERNEL_CHEB_STEP, P.FP64, 2)  # warm
-    e0.record(stream)
-    s64.kernel_bench(P.KERNEL_CHEB_STEP, P.FP64, reps)
-    e1.record(stream)
-    e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    k_bytes = s64.kernel_bytes(P.KERNEL_CHEB_STEP, P.FP64)
-    k_gbps = k_bytes / (k_ms * 1e6)
-    log(f"cheb_step FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic")
-    workload = f"cheb_step_fp64_{n}^3"
+
+    def kernel_time(kernel):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        s64.kernel_bench(kernel, P.FP64, 2)  # warm
+        e0.record(stream)
+        s64.kernel_bench(kernel, P.FP64, reps)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = s64.kernel_bytes(kernel, P.FP64)
+        return ms, nbytes, nbytes / (ms * 1e6)
+
+    k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
+    s_ms, s_bytes, s_gbps = kernel_time(P.KERNEL_CHEB_STEP)
+    log(f"cheb pair FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic; "
+        f"single step {s_ms * 1e3:.1f} us, {s_gbps:.0f} GB/s")
+    workload = f"cheb_pair_fp64_{n}^3"
     roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": round(k_gbps / PEAK_HBM_GBPS, 4),
                 "traffic": traffic_record("device.hip", workload),
-                "kernel": "k_stencil<S_CHEBK,double,double,false>",
-                "kernel_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes}
+                "kernel": "k_cheb_pair<false,false>", "kernel_us": round(k_ms * 1e3, 2),
+                "bytes_per_launch": k_bytes,
+                "single_step": {"kernel": "k_stencil<S_CHEBK,double,double,false>",
+                                "kernel_us": round(s_ms * 1e3, 2), "bytes_per_launch": s_bytes,
+                                "achieved": round(s_gbps, 1)}}
+    if not a.no_unfused:
+        s64.set_option("fuse", 0)
+        st = solve64()
+        s64.set_option("fuse", 1)
+        unfused = {"iterations": st["iterations"], "solve_s": round(st["solve_ms"] / 1e3, 4),
+                   "hbm_gbps": round(st["model_gbps"], 1)}
+        log(f"unfused FP64: {st['iterations']} iterations, {st['solve_ms']:.1f} ms")
     s64.close()
 
     out = {"metric": METRIC, "value": round(iters / wall, 3), "unit": "iter/s", "n_gpus": 1,
@@ -199,6 +260,8 @@ def main():
            "hbm_frac": round(model_bytes / (loop_ms * 1e6) / PEAK_HBM_GBPS, 4),
            "tts_fp64_s": round(last["solve_ms"] / 1e3, 4),
            "relres_true_fp64": last["relres_true"]}
+    if not a.no_unfused:
+        out["fp64_one_step_per_pass"] = unfused
 
     if not a.no_mixed:
         sm = P.Solver(shape, h, stream=stream, precision=P.MIXED)
@@ -233,7 +296,8 @@ def main():
         log(f"serving: p50 {sv['p50_ms']:.0f} ms, p99 {sv['p99_ms']:.0f} ms, "
             f"{sv['solves_per_s']:.1f} solves/s, utilization {sv['utilization']:.2f}")
         out["p99_solve_ms"] = round(sv["p99_ms"], 1)
-        out["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sv.items()}
+        out["serving"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
+                          for k, v in sv.items()}
         torch.cuda.empty_cache()
     if not a.no_cpu:
         log("cpu oracle baseline (bounded sample) ...")

@@ -23,7 +23,7 @@ constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double
 
 // vector slots of a problem
 enum Vec {
-    V_X = 0, V_B, V_R, V_RT, V_P, V_W, V_T, V_PH, V_SH, V_RA, V_RB, V_V32, V_COUNT
+    V_X = 0, V_B, V_R, V_RT, V_P, V_W, V_T, V_PH, V_SH, V_RA, V_RB, V_V32, V_RC, V_RD, V_COUNT
 };
 
 // status codes mirrored from poisson.h
@@ -70,6 +70,7 @@ struct Work {
     const int *tile_local;
     const int *count_dev;        // null: use count
     int count;
+    int order;                   // single problem: 0 natural tile order, 1 x-grouped
 };
 
 // operations of the stencil kernel family
@@ -105,6 +106,10 @@ struct KArgs {
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                     const KArgs &a);
 void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a);
+// two fused Chebyshev steps i, i+1 (FP64): in = y_{i-1}, z = z_{i-2} (unless firstz:
+// i = 2, z = v/theta), v; out = w_i, x2 = w_{i+1}; step = i
+void launch_cheb_pair(bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
+                      const KArgs &a);
 void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
 
 } // namespace pz

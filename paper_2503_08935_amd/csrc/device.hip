@@ -36,8 +36,38 @@ namespace pz {
 // with the non-temporal hint, so they do not displace the stencil input (whose
 // neighbour rows and planes are re-read from L2) from the caches
 // ------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
-template <typename T> __device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+template <typename T> __device__ __forceinline__ T ld_nt(const T *p)
+{
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+template <typename T> __device__ __forceinline__ void st_nt(T *p, T v)
+{
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
+}
+// plain loads through the global address space (pointers read from a
+// descriptor are generic; these keep the compiler on global, not flat, loads)
+template <typename T> __device__ __forceinline__ T ld_g(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// ------------------------------------------------------------------------
+// Tile order of a single problem. Workgroup g runs on XCD g % 8 (round-robin
+// dispatch). Natural order puts neighbouring x-tiles on different XCDs, so the
+// cache lines of their shared x-halo are fetched into two L2s. The x-grouped
+// order takes 8 tile rows (a row = the tx tiles of one (y, z)) at a time and
+// gives each XCD one whole row: dispatch d of the group runs row d % 8, x-tile
+// d / 8. Rows left over at the end keep natural order.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int tile_order(const Work &W, const Prob &P, int g, int total)
+{
+    if (!W.order || W.tile_prob) return g;
+    const int tx = P.tx, grp = 8 * tx;
+    const int base = (g / grp) * grp;
+    if (base + grp > total) return g;
+    const int d = g - base;
+    return base + (d & 7) * tx + (d >> 3);
+}
 
 // ------------------------------------------------------------------------
 // double-double arithmetic
@@ -363,10 +393,9 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int t = g;
-        const int pid = W.tile_prob ? W.tile_prob[t] : 0;
-        const int local = W.tile_prob ? W.tile_local[t] : t;
+        const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
         if (OP != S_INIT && OP != S_TRUE && OP != S_APPLY) {
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -552,44 +581,48 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
 // scalar kernel.
 // ------------------------------------------------------------------------
 template <typename T> struct Pair { T a, b; };
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
+// Pair loads are branch-free: a lane that must not read uses the vector's
+// first element (always valid) and discards the value, so a plane's loads
+// issue together instead of each in its own exec-masked block.
 template <typename TU>
-__device__ __forceinline__ Pair<float> load_pair(const TU *p, bool ok0, bool ok1, bool vec)
+__device__ __forceinline__ Pair<float> load_pair(const TU *p, const TU *base, bool ok0, bool ok1,
+                                                 bool vec)
 {
-    Pair<float> r{0.0f, 0.0f};
+    Pair<float> r;
     if (vec) {
-        if (ok0) {
-            if constexpr (sizeof(TU) == 8) {
-                const double2 v = *(const double2 *)p;
-                r.a = (float)v.x;
-                r.b = (float)v.y;
-            } else {
-                const float2 v = *(const float2 *)p;
-                r.a = v.x;
-                r.b = v.y;
-            }
+        const TU *q = ok0 ? p : base;
+        if constexpr (sizeof(TU) == 8) {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            const d2 v = ld_g((const d2 *)q);
+            r.a = ok0 ? (float)v.x : 0.0f;
+            r.b = ok0 ? (float)v.y : 0.0f;
+        } else {
+            const f32x2 v = ld_g((const f32x2 *)q);
+            r.a = ok0 ? v.x : 0.0f;
+            r.b = ok0 ? v.y : 0.0f;
         }
     } else {
-        if (ok0) r.a = (float)p[0];
-        if (ok1) r.b = (float)p[1];
+        const TU a = ld_g(ok0 ? p : base), b = ld_g(ok1 ? p + 1 : base);
+        r.a = ok0 ? (float)a : 0.0f;
+        r.b = ok1 ? (float)b : 0.0f;
     }
     return r;
 }
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ Pair<float> load_pair_nt(const float *p, bool ok0, bool ok1, bool vec)
+__device__ __forceinline__ Pair<float> load_pair_nt(const float *p, const float *base, bool ok0,
+                                                    bool ok1, bool vec)
 {
-    Pair<float> r{0.0f, 0.0f};
+    Pair<float> r;
     if (vec) {
-        if (ok0) {
-            const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
-            r.a = v.x;
-            r.b = v.y;
-        }
+        const f32x2 v = ld_nt((const f32x2 *)(ok0 ? p : base));
+        r.a = ok0 ? v.x : 0.0f;
+        r.b = ok0 ? v.y : 0.0f;
     } else {
-        if (ok0) r.a = __builtin_nontemporal_load(p);
-        if (ok1) r.b = __builtin_nontemporal_load(p + 1);
+        const float a = ld_nt(ok0 ? p : base), b = ld_nt(ok1 ? p + 1 : base);
+        r.a = ok0 ? a : 0.0f;
+        r.b = ok1 ? b : 0.0f;
     }
     return r;
 }
@@ -600,11 +633,11 @@ __device__ __forceinline__ void store_pair_nt(float *p, float a, float b, bool o
     if (vec) {
         if (ok0) {
             const f32x2 v = {a, b};
-            __builtin_nontemporal_store(v, (f32x2 *)p);
+            st_nt((f32x2 *)p, v);
         }
     } else {
-        if (ok0) __builtin_nontemporal_store(a, p);
-        if (ok1) __builtin_nontemporal_store(b, p + 1);
+        if (ok0) st_nt(p, a);
+        if (ok1) st_nt(p + 1, b);
     }
 }
 
@@ -630,8 +663,8 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
-        const int local = W.tile_prob ? W.tile_local[g] : g;
         const Prob &P = W.probs[pid];
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
         {
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -696,9 +729,9 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 #pragma unroll
         for (int r = 0; r < RH; ++r) {
             const size_t idx = base + r * NXs;
-            c[r] = load_pair(u + idx, in0 && rin[r], in1 && rin[r], vec);
-            zm[r] = k0 > 0 ? load_pair(u + idx - S, in0 && rin[r], in1 && rin[r], vec)
-                           : Pair<float>{0.0f, 0.0f};
+            c[r] = load_pair(u + idx, u, in0 && rin[r], in1 && rin[r], vec);
+            zm[r] = load_pair(u + idx - (k0 > 0 ? S : 0), u, k0 > 0 && in0 && rin[r],
+                              k0 > 0 && in1 && rin[r], vec);
         }
         for (int k = k0; k < k1; ++k, base += S, hidx += S) {
             const int szm = sel_lo(k, nz, MASK, B, nzl);
@@ -708,16 +741,18 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
             for (int r = 0; r < RH; ++r) {
                 const size_t idx = base + r * NXs;
                 const bool a0 = in0 && rin[r], a1 = in1 && rin[r];
-                zr[r] = k + 1 < nz ? load_pair(u + idx + S, a0, a1, vec) : Pair<float>{0.0f, 0.0f};
-                if constexpr (OP == S_CHEB2) o0[r] = load_pair_nt(vv + idx, a0, a1, vec);
+                const bool zn = k + 1 < nz;
+                zr[r] = load_pair(u + idx + (zn ? S : 0), u, zn && a0, zn && a1, vec);
+                if constexpr (OP == S_CHEB2) o0[r] = load_pair_nt(vv + idx, vv, a0, a1, vec);
                 if constexpr (OP == S_CHEBK) {
-                    o0[r] = load_pair_nt(vv + idx, a0, a1, vec);
-                    o1[r] = load_pair_nt(zz + idx, a0, a1, vec);
+                    o0[r] = load_pair_nt(vv + idx, vv, a0, a1, vec);
+                    o1[r] = load_pair_nt(zz + idx, zz, a0, a1, vec);
                 }
             }
-            const Pair<float> ymv = load_pair(u + base - (ymh ? NXs : 0), ymh, ymh && in1, vec);
-            const Pair<float> ypv = load_pair(u + base + (yph ? RH * NXs : 0), yph, yph && in1, vec);
-            const float he = hload ? (float)u[hidx] : 0.0f;
+            const Pair<float> ymv = load_pair(u + base - (ymh ? NXs : 0), u, ymh, ymh && in1, vec);
+            const Pair<float> ypv = load_pair(u + base + (yph ? RH * NXs : 0), u, yph, yph && in1, vec);
+            const float hv = (float)ld_g(u + (hload ? hidx : 0));
+            const float he = hload ? hv : 0.0f;
 #pragma unroll
             for (int r = 0; r < RH; ++r) {
                 // neighbours across lanes, fixed up with the halo at half-wave edges
@@ -771,6 +806,219 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 }
 
 // ------------------------------------------------------------------------
+// Two consecutive Chebyshev steps in one pass (temporal blocking, FP64):
+//   w_i     = rc_i     ((2 sigma y + (2/delta)(v - A y))   - ro_i     z)
+//   w_{i+1} = rc_{i+1} ((2 sigma w_i + (2/delta)(v - A w_i)) - ro_{i+1} y)
+// with y = y_{i-1} read with the stencil, z = z_{i-2} (or v/theta when i = 2)
+// and v read pointwise. w_i is computed on the wave's rows plus one halo row
+// on each side and one plane ahead of w_{i+1}; its two halo columns are
+// computed by 8 lanes from direct loads. Reads y, z, v once and writes w_i and
+// w_{i+1}: 40 bytes per point instead of 64 for the two separate steps. The
+// arithmetic per point is exactly that of two k_stencil steps.
+// ------------------------------------------------------------------------
+template <bool MASK, bool FZ>
+__global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
+{
+    constexpr int RYY = RY + 4; // y rows j0-2 .. j0+RY+1
+    constexpr int RW = RY + 2;  // w_i rows j0-1 .. j0+RY
+    const int total = W.count_dev ? *W.count_dev : W.count;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int pid = W.tile_prob ? W.tile_prob[g] : 0;
+        const Prob &P = W.probs[pid];
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
+        {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+        const int i0 = tix * TX, i = i0 + lane;
+        const int j0 = tiy * (TY * RY) + wv * RY;
+        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+        if (j0 >= ny) continue; // uniform within the wave; no barriers below
+
+        const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+        const int B = MASK ? P.block : 1;
+        const unsigned bc = P.bc;
+        const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+        const bool nzl = bc & 16u, nzh = bc & 32u;
+        const bool xin = i < nx;
+        const int sxm = xin ? sel_lo(i, nx, MASK, B, nxl) : 0;
+        const int sxp = xin ? sel_hi(i, nx, MASK, B, nxh) : 0;
+        const double *__restrict__ Y = (const double *)P.vec[A.in];
+        const double *__restrict__ V = (const double *)P.vec[A.v];
+        const double *__restrict__ Z = (const double *)P.vec[A.z];
+        double *W1 = (double *)P.vec[A.out];
+        double *W2 = (double *)P.vec[A.x2];
+        const double ih2 = P.ih2, theta = P.theta, ts = P.two_sigma, tod = P.two_over_delta;
+        const double rc1 = P.rc[A.step], ro1 = P.ro[A.step];
+        const double rc2 = P.rc[A.step + 1], ro2 = P.ro[A.step + 1];
+
+        // rows: Y row q is j0-2+q, w row q is j0-1+q
+        bool yok[RYY], wok[RW];
+        int wsym[RW], wsyp[RW];
+#pragma unroll
+        for (int q = 0; q < RYY; ++q) {
+            const int j = j0 - 2 + q;
+            yok[q] = xin && j >= 0 && j < ny;
+        }
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int j = j0 - 1 + q;
+            wok[q] = xin && j >= 0 && j < ny;
+            wsym[q] = wok[q] ? sel_lo(j, ny, MASK, B, nyl) : 0;
+            wsyp[q] = wok[q] ? sel_hi(j, ny, MASK, B, nyh) : 0;
+        }
+        // x halo of y for the w_i rows: lane q < RW the left, lane 32+q the right
+        const int hq = lane & 31;
+        const int hj = j0 - 1 + hq;
+        const bool hload = hq < RW && hj >= 0 && hj < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+        const size_t hcol = (size_t)(lane < 32 ? i0 - 1 : i0 + TX);
+        // halo-column w_i (lanes 0..2RY-1): side = lane / RY, row j0 + lane % RY
+        const int cside = lane / RY, crow = j0 + (lane % RY);
+        const int cx = cside ? i0 + TX : i0 - 1;
+        const bool cact = lane < 2 * RY && cx >= 0 && cx < nx && crow < ny;
+
+        // Y at plane p for all RYY rows (zero outside the grid)
+        auto loadY = [&](int p, double (&dst)[RYY]) {
+#pragma unroll
+            for (int q = 0; q < RYY; ++q) {
+                const int j = j0 - 2 + q;
+                const bool ok = yok[q] && p >= 0 && p < nz;
+                const double v =
+                    ld_g(Y + (ok ? (size_t)i + NXs * ((size_t)j + (size_t)ny * (size_t)p) : 0));
+                dst[q] = ok ? v : 0.0;
+            }
+        };
+        // w_i at one point from its 7 y values, v and z (the k_stencil step)
+        auto step1 = [&](double yc, double xm, double xp, double ym, double yp, double zm,
+                         double zp, double v, double z) {
+            const double a = ((((((6.0 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+            return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
+        };
+        // w_i at plane p for the RW rows, from Y planes p-1 (ya), p (yb), p+1 (yc)
+        auto planeW = [&](int p, const double (&ya)[RYY], const double (&yb)[RYY],
+                          const double (&yc)[RYY], double (&dst)[RW], double (&vout)[RW]) {
+            const bool pin = p >= 0 && p < nz;
+            const int szm = pin ? sel_lo(p, nz, MASK, B, nzl) : 0;
+            const int szp = pin ? sel_hi(p, nz, MASK, B, nzh) : 0;
+            double vv[RW], zz[RW];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const bool ok = pin && wok[q];
+                const size_t idx =
+                    ok ? (size_t)i + NXs * ((size_t)(j0 - 1 + q) + (size_t)ny * (size_t)p) : 0;
+                const double v = ld_nt(V + idx);
+                vv[q] = ok ? v : 0.0;
+                if constexpr (!FZ) {
+                    const double zv = ld_nt(Z + idx);
+                    zz[q] = ok ? zv : 0.0;
+                }
+            }
+            const bool hok = hload && pin;
+            const double hv =
+                ld_g(Y + (hok ? hcol + NXs * ((size_t)hj + (size_t)ny * (size_t)p) : 0));
+            const double he = hok ? hv : 0.0;
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                double xl = lane_prev(yb[q + 1]), xr = lane_next(yb[q + 1]);
+                const double el = read_lane(he, q), er = read_lane(he, 32 + q);
+                if (lane == 0) xl = el;
+                if (lane == TX - 1) xr = er;
+                const double c = yb[q + 1];
+                const double xm = sxm == 1 ? xl : sxm == 2 ? xr : 0.0;
+                const double xp = sxp == 1 ? xr : sxp == 2 ? xl : 0.0;
+                const double ym = wsym[q] == 1 ? yb[q] : wsym[q] == 2 ? yb[q + 2] : 0.0;
+                const double yp = wsyp[q] == 1 ? yb[q + 2] : wsyp[q] == 2 ? yb[q] : 0.0;
+                const double zm = szm == 1 ? ya[q + 1] : szm == 2 ? yc[q + 1] : 0.0;
+                const double zp = szp == 1 ? yc[q + 1] : szp == 2 ? ya[q + 1] : 0.0;
+                const double z = FZ ? vv[q] / theta : zz[q];
+                dst[q] = (pin && wok[q]) ? step1(c, xm, xp, ym, yp, zm, zp, vv[q], z) : 0.0;
+                vout[q] = vv[q];
+            }
+        };
+        // Y value at (x, j, p) along the halo column, 0 outside the grid
+        auto yat = [&](int x, int j, int p) {
+            return (x >= 0 && x < nx && j >= 0 && j < ny && p >= 0 && p < nz)
+                       ? ld_g(Y + (size_t)x + NXs * ((size_t)j + (size_t)ny * (size_t)p))
+                       : 0.0;
+        };
+        // w_i at a halo-column point (x, j, p) from direct loads (same selections)
+        auto pointW = [&](int x, int j, int p) {
+            const int sxl = sel_lo(x, nx, MASK, B, nxl), sxh = sel_hi(x, nx, MASK, B, nxh);
+            const int syl = sel_lo(j, ny, MASK, B, nyl), syh = sel_hi(j, ny, MASK, B, nyh);
+            const int szl = sel_lo(p, nz, MASK, B, nzl), szh = sel_hi(p, nz, MASK, B, nzh);
+            const double c = yat(x, j, p);
+            const double l = yat(x - 1, j, p), r = yat(x + 1, j, p);
+            const double d = yat(x, j - 1, p), u = yat(x, j + 1, p);
+            const double b = yat(x, j, p - 1), f = yat(x, j, p + 1);
+            const double xm = sxl == 1 ? l : sxl == 2 ? r : 0.0;
+            const double xp = sxh == 1 ? r : sxh == 2 ? l : 0.0;
+            const double ym = syl == 1 ? d : syl == 2 ? u : 0.0;
+            const double yp = syh == 1 ? u : syh == 2 ? d : 0.0;
+            const double zm = szl == 1 ? b : szl == 2 ? f : 0.0;
+            const double zp = szh == 1 ? f : szh == 2 ? b : 0.0;
+            const size_t idx = (size_t)x + NXs * ((size_t)j + (size_t)ny * (size_t)p);
+            const double v = ld_g(V + idx);
+            const double z = FZ ? v / theta : ld_g(Z + idx);
+            return step1(c, xm, xp, ym, yp, zm, zp, v, z);
+        };
+
+        double ya[RYY], yb[RYY], yc[RYY];
+        double wa[RW], wb[RW], wc[RW], vb[RW], vc[RW];
+        loadY(k0 - 2, ya);
+        loadY(k0 - 1, yb);
+#pragma unroll
+        for (int q = 0; q < RW; ++q) wa[q] = wb[q] = vb[q] = 0.0;
+        for (int k = k0 - 2; k < k1; ++k) {
+            loadY(k + 2, yc);
+            planeW(k + 1, ya, yb, yc, wc, vc);
+            if (k >= k0) {
+                // w_{i+1} at plane k from w_i at planes k-1 (wa), k (wb), k+1 (wc)
+                const double hw = (cact) ? pointW(cx, crow, k) : 0.0;
+                const int szm = sel_lo(k, nz, MASK, B, nzl), szp = sel_hi(k, nz, MASK, B, nzh);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int q = r + 1; // w row of output row j0 + r
+                    double xl = lane_prev(wb[q]), xr = lane_next(wb[q]);
+                    const double el = read_lane(hw, r), er = read_lane(hw, RY + r);
+                    if (lane == 0) xl = el;
+                    if (lane == TX - 1) xr = er;
+                    const double c = wb[q];
+                    const double xm = sxm == 1 ? xl : sxm == 2 ? xr : 0.0;
+                    const double xp = sxp == 1 ? xr : sxp == 2 ? xl : 0.0;
+                    const double ym = wsym[q] == 1 ? wb[q - 1] : wsym[q] == 2 ? wb[q + 1] : 0.0;
+                    const double yp = wsyp[q] == 1 ? wb[q + 1] : wsyp[q] == 2 ? wb[q - 1] : 0.0;
+                    const double zm = szm == 1 ? wa[q] : szm == 2 ? wc[q] : 0.0;
+                    const double zp = szp == 1 ? wc[q] : szp == 2 ? wa[q] : 0.0;
+                    const double a = ((((((6.0 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                    const double w2 = rc2 * ((ts * c + tod * (vb[q] - a)) - ro2 * ya[q + 1]);
+                    if (wok[q]) {
+                        const size_t idx =
+                            (size_t)i + NXs * ((size_t)(j0 + r) + (size_t)ny * (size_t)k);
+                        st_nt(W1 + idx, c);
+                        st_nt(W2 + idx, w2);
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RYY; ++q) {
+                ya[q] = yb[q];
+                yb[q] = yc[q];
+            }
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                wa[q] = wb[q];
+                wb[q] = wc[q];
+                vb[q] = vc[q];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // elementwise family, same tiles; each thread streams its RY rows plane by
 // plane with all loads of a plane issued together.
 // TP: element type of p^ / s^ (E_UPD) or of the output (E_DIV).
@@ -786,10 +1034,9 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int t = g;
-        const int pid = W.tile_prob ? W.tile_prob[t] : 0;
-        const int local = W.tile_prob ? W.tile_local[t] : t;
+        const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
         const Scalars *sc = P.sc;
         if (OP != E_DOT) {
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -956,6 +1203,18 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
         hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
     else
         hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+}
+
+void launch_cheb_pair(bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
+                      const KArgs &a)
+{
+    if (mask) {
+        if (firstz) hipLaunchKernelGGL((k_cheb_pair<true, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        else hipLaunchKernelGGL((k_cheb_pair<true, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    } else {
+        if (firstz) hipLaunchKernelGGL((k_cheb_pair<false, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        else hipLaunchKernelGGL((k_cheb_pair<false, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    }
 }
 
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

@@ -24,10 +24,11 @@ using namespace pz;
 namespace {
 
 struct GraphKey {
-    int pc, deg, mixed, iters;
+    int pc, deg, mixed, iters, fuse, order;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(pc, deg, mixed, iters) < std::tie(o.pc, o.deg, o.mixed, o.iters);
+        return std::tie(pc, deg, mixed, iters, fuse, order) <
+               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order);
     }
 };
 
@@ -42,7 +43,7 @@ struct poisson_ctx {
     size_t N = 0;
     hipStream_t stream = nullptr;
     // options
-    int precision = POISSON_FP64, graph_iters = 8, use_graph = 1;
+    int precision = POISSON_FP64, graph_iters = 8, use_graph = 1, tile_order = 0;
     PlanOpts opt;
     // tiling
     int ntiles = 1;
@@ -63,7 +64,7 @@ struct poisson_ctx {
     std::vector<hipGraph_t> graph_src;
     // plan of the last solve
     bool plan_ok = false;
-    int plan_pc = -1, plan_deg = 0, plan_mixed = 0;
+    int plan_pc = -1, plan_deg = 0, plan_mixed = 0, plan_fuse = 0;
     void *vec[V_COUNT] = {};
     double plan_lo = 0, plan_hi = 0;
     // results
@@ -96,7 +97,7 @@ int ensure_device(poisson_ctx *c)
 // size the workspace for a plan; grows (never shrinks) the allocation
 int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 {
-    const size_t need = workspace_bytes(c->N, pc, deg, mixed);
+    const size_t need = workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse);
     if (need > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -110,7 +111,7 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
     }
     Prob tmp;
     memset(&tmp, 0, sizeof(tmp));
-    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed);
+    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, c->opt.fuse);
     for (int v = 0; v < V_COUNT; ++v) c->vec[v] = tmp.vec[v];
     return POISSON_OK;
 }
@@ -123,16 +124,17 @@ int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
 {
-    GraphKey k{pc, m, mixed ? 1 : 0, iters};
+    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order};
     auto it = c->graphs.find(k);
     if (it != c->graphs.end()) {
         *out = it->second;
         return POISSON_OK;
     }
-    Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles};
+    Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed);
+    for (int i = 0; i < iters; ++i)
+        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, c->opt.fuse);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipGraphExec_t e = nullptr;
     HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -190,9 +192,10 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     c->plan_pc = pc;
     c->plan_deg = deg;
     c->plan_mixed = mixed;
+    c->plan_fuse = fused(pc, deg, mixed, c->opt.fuse);
     if ((rc = upload_prob(c, 0)) != POISSON_OK) return rc;
 
-    const Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles};
+    const Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
     launch_stencil(S_INIT, false, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
     HIPCHK(hipGetLastError());
     if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -208,7 +211,8 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
             if (c->use_graph) {
                 HIPCHK(hipGraphLaunch(g, c->stream));
             } else {
-                for (int i = 0; i < K; ++i) enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed);
+                for (int i = 0; i < K; ++i)
+                    enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse);
                 HIPCHK(hipGetLastError());
             }
             if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -259,7 +263,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     st.lambda_min = c->plan_lo;
     st.lambda_max = c->plan_hi;
     st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed) * (double)c->N * sc.iter;
+    st.model_bytes = iteration_bytes(pc, deg, mixed, c->opt.fuse) * (double)c->N * sc.iter;
     st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
     st.history_len = (int)c->hist_rel.size();
     st.history = c->hist_rel.data();
@@ -328,6 +332,14 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
     case POISSON_OPT_DEBUG_BREAKDOWN_AT:
         if (v != std::floor(v)) return POISSON_ERR_ARG;
         c->opt.debug_bd = (int)v;
+        return POISSON_OK;
+    case POISSON_OPT_FUSE:
+        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        c->opt.fuse = (int)v;
+        return POISSON_OK;
+    case POISSON_OPT_TILE_ORDER:
+        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        c->tile_order = (int)v;
         return POISSON_OK;
     default:
         return POISSON_ERR_ARG;
@@ -445,7 +457,7 @@ int poisson_apply_operator(poisson_ctx *c, const double *u, double *out)
         c->h_prob[1].vec[V_B] = (void *)u;
         c->h_prob[1].vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles};
+        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
         launch_stencil(S_APPLY, false, false, w, c->ntiles, c->stream, KArgs{V_B, V_X, 0, 0, 0, 0, 0, 0});
         HIPCHK(hipGetLastError());
         return POISSON_OK;
@@ -472,8 +484,8 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
         p.vec[V_B] = (void *)v;
         p.vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles};
-        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, V_B, V_X, 0);
+        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, c->opt.fuse, V_B, V_X, 0);
         HIPCHK(hipGetLastError());
         return POISSON_OK;
     } catch (...) {
@@ -491,7 +503,7 @@ int poisson_dot(poisson_ctx *c, const double *x, const double *y, double *result
         c->h_prob[1].vec[V_X] = (void *)x;
         c->h_prob[1].vec[V_B] = (void *)y;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles};
+        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
         launch_elem(E_DOT, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, V_B});
         HIPCHK(hipGetLastError());
         if ((rc = read_scalars(c, 1)) != POISSON_OK) return rc;
@@ -511,6 +523,7 @@ double poisson_kernel_bytes(const poisson_ctx *c, int kernel, int precision)
     case POISSON_KERNEL_CHEB_STEP: return 4 * tc * N;          // y, v, z in; w out
     case POISSON_KERNEL_STENCIL_DOT: return (tc + 16) * N;     // p^, r~ in; w out
     case POISSON_KERNEL_UPDATE_XR: return (48 + 2 * tc) * N;   // x, p^, s^, r, t, r~ in; x, r out
+    case POISSON_KERNEL_CHEB_PAIR: return 5 * tc * N;          // y, z, v in; w_i, w_{i+1} out
     default: return 0.0;
     }
 }
@@ -526,7 +539,9 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
     if ((kernel == POISSON_KERNEL_STENCIL_DOT || kernel == POISSON_KERNEL_UPDATE_XR) &&
         c->plan_pc == POISSON_PC_NONE)
         return POISSON_ERR_ARG;
-    if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_UPDATE_XR) return POISSON_ERR_ARG;
+    if (kernel == POISSON_KERNEL_CHEB_PAIR && !(c->plan_fuse && c->plan_deg >= 5 && !mixed))
+        return POISSON_ERR_ARG;
+    if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_CHEB_PAIR) return POISSON_ERR_ARG;
     try {
         int rc;
         // same descriptor as the solve, but private scalars (never 'done') and
@@ -549,11 +564,14 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
         HIPCHK(hipMemcpyAsync(c->d_sc + 1, c->h_sc + 1, sizeof(Scalars), hipMemcpyHostToDevice,
                               c->stream));
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles};
+        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
         for (int r = 0; r < reps; ++r) {
             if (kernel == POISSON_KERNEL_CHEB_STEP)
                 launch_stencil(S_CHEBK, mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->ntiles,
                                c->stream, KArgs{V_RA, V_RB, mixed ? (int)V_V32 : (int)V_P, V_RB, 3, 0, 0, 0});
+            else if (kernel == POISSON_KERNEL_CHEB_PAIR)
+                launch_cheb_pair(c->plan_pc == POISSON_PC_BLOCK_JACOBI, false, w, c->ntiles, c->stream,
+                                 KArgs{V_RA, V_RC, V_P, V_RB, 3, 0, 0, V_RD});
             else if (kernel == POISSON_KERNEL_STENCIL_DOT)
                 launch_stencil(S_SDOT, mixed, false, w, c->ntiles, c->stream,
                                KArgs{V_PH, V_W, 0, 0, 0, 0, 0, 0});

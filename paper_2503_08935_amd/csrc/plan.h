@@ -32,6 +32,7 @@ struct PlanOpts {
     int bj_global = 0;       // 1: GNoComm(CI), global interval on the masked operator
     double lmin_scale = 1.0, lmax_scale = 1.0;
     int debug_bd = -1;
+    int fuse = 1;            // FP64 Chebyshev: two steps per pass where possible
 };
 
 Tiling make_tiling(int nx, int ny, int nz);
@@ -45,16 +46,19 @@ int check_bc(int nx, int ny, int nz, unsigned bc);
 // geometry, tolerance and coefficients; vectors, scalars, partials are left null
 int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, int deg,
               const PlanOpts &o, double tol, int maxit, double *lo, double *hi);
+// whether a plan runs fused Chebyshev step pairs
+bool fused(int pc, int deg, bool mixed, int fuse);
 // bytes of vector slot v for a plan (0 if unused)
-size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed);
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse);
 // total workspace of a plan, each slot 256-byte aligned
-size_t workspace_bytes(size_t N, int pc, int deg, bool mixed);
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse);
 // carve a workspace into the vector slots of p
-void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed);
-void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int vin,
-                int vout, int second);
-void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed);
-double iteration_bytes(int pc, int m, bool mixed);
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse);
+void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int fuse,
+                int vin, int vout, int second);
+void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed,
+                       int fuse);
+double iteration_bytes(int pc, int m, bool mixed, int fuse);
 int validate_ptr(const void *p);
 double now_ms();
 

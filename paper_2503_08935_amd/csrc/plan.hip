@@ -171,15 +171,22 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
     return POISSON_OK;
 }
 
-size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed)
+bool fused(int pc, int deg, bool mixed, int fuse)
+{
+    return fuse && !mixed && is_cheb(pc) && deg >= 3;
+}
+
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
 {
     const bool cheb = is_cheb(pc);
     const size_t tp = (mixed && pc != POISSON_PC_NONE) ? 4 : 8;
+    const bool fz = fused(pc, deg, mixed, fuse);
     switch (v) {
     case V_R: case V_RT: case V_P: case V_W: case V_T: return 8 * N;
     case V_PH: case V_SH: return pc != POISSON_PC_NONE ? tp * N : 0;
     case V_RA: return cheb && deg >= 2 ? tp * N : 0;
     case V_RB: return cheb && deg >= 3 ? tp * N : 0;
+    case V_RC: case V_RD: return fz ? 8 * N : 0;
     case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
     default: return 0;
     }
@@ -187,26 +194,26 @@ size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed)
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(size_t N, int pc, int deg, bool mixed)
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse)
 {
     size_t need = 0;
-    for (int v = 0; v < V_COUNT; ++v) need += align256(vec_bytes(N, v, pc, deg, mixed));
+    for (int v = 0; v < V_COUNT; ++v) need += align256(vec_bytes(N, v, pc, deg, mixed, fuse));
     return need;
 }
 
-void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed)
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse)
 {
     size_t off = 0;
     for (int v = 0; v < V_COUNT; ++v) {
-        const size_t b = vec_bytes(N, v, pc, deg, mixed);
+        const size_t b = vec_bytes(N, v, pc, deg, mixed, fuse);
         if (v != V_X && v != V_B) p.vec[v] = b ? ws + off : nullptr;
         off += align256(b);
     }
 }
 
 // preconditioner apply vout = M^-1 vin (Alg. 2; BJ(CI) with the masked operator)
-void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int vin,
-                int vout, int second)
+void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int fuse,
+                int vin, int vout, int second)
 {
     if (pc == POISSON_PC_NONE) return;
     if (pc == POISSON_PC_JACOBI || m == 0) {
@@ -218,6 +225,32 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
     KArgs a1{vin, m == 1 ? vout : (int)V_RA, 0, 0, 1, second, 0, 0};
     launch_stencil(S_CHEB1, mixed, mask, w, grid, s, a1);
     const int vsrc = mixed ? (int)V_V32 : vin;
+    if (fused(pc, m, mixed, fuse)) {
+        // steps 2..m: step 2 alone when m-1 is odd, the rest in fused pairs (i, i+1);
+        // a pair reads y_{i-1} and z_{i-2} and writes w_i, w_{i+1} to two other
+        // buffers of the ring {RA, RB, RC, RD} (nothing is written in place: every
+        // input is read by neighbouring tiles)
+        const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
+        int y = V_RA, z = -1; // z = -1: z_{i-2} = v/theta
+        int i = 2;
+        if ((m - 1) & 1) {
+            const int out = m == 2 ? vout : (int)V_RB;
+            launch_stencil(S_CHEB2, mixed, mask, w, grid, s, KArgs{y, out, vsrc, 0, 2, second, 0, 0});
+            z = y;
+            y = out;
+            i = 3;
+        }
+        for (; i + 1 <= m; i += 2) {
+            int o[2], n = 0;
+            for (int b : ring)
+                if (b != y && b != z && n < 2) o[n++] = b;
+            const int w2 = i + 1 == m ? vout : o[1];
+            launch_cheb_pair(mask, z < 0, w, grid, s, KArgs{y, o[0], vsrc, z < 0 ? 0 : z, i, second, 0, w2});
+            z = o[0];
+            y = w2;
+        }
+        return;
+    }
     for (int i = 2; i <= m; ++i) {
         // step i reads y = buf(i-1), z = buf(i-2), writes buf(i) (in place over z)
         // where buf(odd) = RA, buf(even) = RB, and the last step writes vout
@@ -230,22 +263,23 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
 }
 
 // one Bi-CGSTAB iteration in the kernel order of Alg. 3
-void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed)
+void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed,
+                       int fuse)
 {
     const bool pm = mixed && pc != POISSON_PC_NONE;
     const int ph = pc == POISSON_PC_NONE ? V_P : V_PH;
     const int sh = pc == POISSON_PC_NONE ? V_R : V_SH;
-    enqueue_pc(w, grid, s, pc, m, mixed, V_P, V_PH, 0);                            // M p^ = p
+    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_P, V_PH, 0);                      // M p^ = p
     launch_stencil(S_SDOT, pm, false, w, grid, s, KArgs{ph, V_W, 0, 0, 0, 0, 0, 0});  // w, alpha
     launch_elem(E_AXPY, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // s, half step
-    enqueue_pc(w, grid, s, pc, m, mixed, V_R, V_SH, 1);                            // M s^ = s
+    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_R, V_SH, 1);                      // M s^ = s
     launch_stencil(S_SDOT2, pm, false, w, grid, s, KArgs{sh, V_T, 0, 0, 0, 1, 0, 0}); // t, omega
     launch_elem(E_UPD, pm, w, grid, s, KArgs{ph, 0, 0, 0, 0, 0, 0, sh});            // x, r, beta
     launch_elem(E_PUPD, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // p
 }
 
 // algorithmic bytes per unknown of one iteration of a plan
-double iteration_bytes(int pc, int m, bool mixed)
+double iteration_bytes(int pc, int m, bool mixed, int fuse)
 {
     const bool pm = mixed && pc != POISSON_PC_NONE;
     const double tp = pm ? 4 : 8;
@@ -255,8 +289,14 @@ double iteration_bytes(int pc, int m, bool mixed)
     else if (is_cheb(pc)) {
         const double tc = mixed ? 4 : 8;
         pcb = 8 + tc + (mixed ? 4 : 0);                 // first step: v, y (+ v32)
-        if (m >= 2) pcb += 3 * tc;                      // step 2: y, v, w
-        if (m >= 3) pcb += (m - 2) * 4 * tc;            // steps 3..m: y, v, z, w
+        if (fused(pc, m, mixed, fuse)) {
+            int steps = m - 1;
+            if (steps & 1) { pcb += 3 * tc; --steps; }   // step 2 alone: y, v, w
+            pcb += (steps / 2) * 5 * tc;                // pairs: y, z, v in; w_i, w_{i+1} out
+        } else {
+            if (m >= 2) pcb += 3 * tc;                  // step 2: y, v, w
+            if (m >= 3) pcb += (m - 2) * 4 * tc;        // steps 3..m: y, v, z, w
+        }
     }
     double b = 2 * pcb;
     b += tp + 16;                                        // w = A p^, r~.w

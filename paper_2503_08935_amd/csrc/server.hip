@@ -217,7 +217,7 @@ void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids
 
 Work work_of(const poisson_server *s, const TileList &t)
 {
-    return Work{s->d_probs, t.d_prob, t.d_local, t.d_count, t.count};
+    return Work{s->d_probs, t.d_prob, t.d_local, t.d_count, t.count, 0};
 }
 
 int finish_requests(poisson_server *s, const std::vector<int> &ids)
@@ -263,7 +263,7 @@ int finish_requests(poisson_server *s, const std::vector<int> &ids)
         st.solve_ms = t - sl.req.t_submit;   // arrival to completion
         st.loop_ms = t - sl.t_admit;         // admission to completion
         const double N = (double)sl.req.nx * sl.req.ny * sl.req.nz;
-        st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED) * N *
+        st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED, 1) * N *
                          sc.iter;
         st.model_gbps = 0;
         s->results[sl.req.ticket] = r;
@@ -283,9 +283,9 @@ int capture_group(poisson_server *s, const PlanKey &k, Group &g)
         g.graph = nullptr;
         g.graph_src = nullptr;
     }
-    const Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, 0};
+    const Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, 0, 0};
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0);
+    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, 1);
     HIPCHK(hipStreamEndCapture(s->cap_stream, &g.graph_src));
     HIPCHK(hipGraphInstantiate(&g.graph, g.graph_src, nullptr, nullptr, 0));
     g.graph_cap = g.tiles.cap;
@@ -329,7 +329,7 @@ int step_impl(poisson_server *s, int iters)
         sl.ntiles = p.ntiles;
         char *blk = s->arena_base + off;
         const size_t N = (size_t)sl.req.nx * sl.req.ny * sl.req.nz;
-        carve_workspace(p, blk, N, sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED);
+        carve_workspace(p, blk, N, sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED, 1);
         p.vec[V_X] = sl.req.x;
         p.vec[V_B] = (void *)sl.req.rhs;
         p.partials = (double *)(blk + sl.req.ws_bytes);
@@ -376,7 +376,8 @@ int step_impl(poisson_server *s, int iters)
         } else {
             const Work w = work_of(s, g.tiles);
             for (int i = 0; i < iters; ++i)
-                enqueue_iteration(w, GRID, s->stream, kv.first.pc, kv.first.deg, kv.first.mixed != 0);
+                enqueue_iteration(w, GRID, s->stream, kv.first.pc, kv.first.deg, kv.first.mixed != 0,
+                                  1);
             HIPCHK(hipGetLastError());
         }
     }
@@ -438,7 +439,7 @@ int poisson_server_footprint(int nx, int ny, int nz, int precond, int degree, in
     if (precision != POISSON_FP64 && precision != POISSON_MIXED) return POISSON_ERR_ARG;
     const size_t N = (size_t)nx * ny * nz;
     const Tiling t = make_tiling(nx, ny, nz);
-    *bytes = workspace_bytes(N, precond, degree, precision == POISSON_MIXED) +
+    *bytes = workspace_bytes(N, precond, degree, precision == POISSON_MIXED, 1) +
              align256((size_t)t.ntiles * PARTIAL_STRIDE * sizeof(double));
     return POISSON_OK;
 }
@@ -474,7 +475,8 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
     r.rhs = rhs; r.x = x;
     r.pc = precond; r.deg = degree; r.prec = precision;
     r.tol = tol; r.maxit = maxit;
-    r.ws_bytes = workspace_bytes((size_t)nx * ny * nz, precond, degree, precision == POISSON_MIXED);
+    r.ws_bytes =
+        workspace_bytes((size_t)nx * ny * nz, precond, degree, precision == POISSON_MIXED, 1);
     r.footprint = fp;
     r.t_submit = now_ms();
     s->queue.push_back(r);

@@ -85,3 +85,24 @@ def manufactured_noisy(shape, seed, sigma=1e-3):
 def spacing(n):
     """Interior-unknown convention on the unit cube: h = 1/(n+1)."""
     return 1.0 / (n + 1)
+
+
+# The test problem of the paper's Experimental Setup: -lap(phi) = sin x + cos y +
+# 3 sin z - 2yz + 2 on [3, 28.5] x [2.5, 28] x [10, 35.5] with spacing 0.1 (256
+# nodes per axis including the boundary), Dirichlet on x-, y+, z+ and Neumann on
+# x+, y-, z-. The boundary values are not given in the paper; here they are
+# homogeneous. Unknowns: a Dirichlet boundary node is not an unknown, a Neumann
+# one is, so every axis has 255 unknowns.
+PAPER_BC = 2 | 4 | 16          # Neumann on x+, y-, z- (bit f = face x-, x+, y-, y+, z-, z+)
+PAPER_H = 0.1
+
+
+def paper_problem():
+    """(f, shape, h, bc) of the paper's test problem on 255^3 unknowns."""
+    n = 255
+    x = 3.0 + (np.arange(n) + 1) * PAPER_H      # x- Dirichlet node excluded, x+ included
+    y = 2.5 + np.arange(n) * PAPER_H            # y- Neumann node included, y+ excluded
+    z = 10.0 + np.arange(n) * PAPER_H           # z- Neumann node included, z+ excluded
+    f = (np.sin(x)[None, None, :] + np.cos(y)[None, :, None] + 3.0 * np.sin(z)[:, None, None]
+         - 2.0 * y[None, :, None] * z[:, None, None] + 2.0)
+    return np.ascontiguousarray(f), (n, n, n), PAPER_H, PAPER_BC

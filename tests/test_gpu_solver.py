@@ -18,8 +18,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def gpu_solve(shape, h, f, pc, m, tol, maxit=5000, x0=None, **opts):
-    with P.Solver(shape, h, **opts) as s:
+def gpu_solve(shape, h, f, pc, m, tol, maxit=5000, x0=None, bc=0, **opts):
+    with P.Solver(shape, h, bc=bc, **opts) as s:
         b = dev(f)
         x = dev(x0) if x0 is not None else torch.zeros_like(b)
         st = s.solve(b, x, pc, m, tol, maxit)
@@ -127,3 +127,42 @@ def test_special_cases(gpu):
     # forced omega = 0 at iteration 3 reports a breakdown there
     st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 4, 1e-12, debug_breakdown_at=3)
     assert st == P.ERR_BREAKDOWN and stats["iterations"] == 3 and np.all(np.isfinite(x))
+
+
+@pytest.mark.parametrize("pc,block,bc", [(P.PC_CHEBYSHEV, 64, 0), (P.PC_BLOCK_JACOBI, 16, 0),
+                                         (P.PC_CHEBYSHEV, 64, 2 | 4 | 16),
+                                         (P.PC_BLOCK_JACOBI, 10, 1 | 8)])
+def test_fused_step_pairs_change_no_bits(gpu, pc, block, bc):
+    """Two Chebyshev steps per pass (the default for FP64) against one per pass, and
+    against the oracle, for every degree pattern (odd/even step counts, step 2 fused)."""
+    shape = (61, 47, 35)
+    h = workloads.spacing(61)
+    f = workloads.uniform_grid(12, shape)
+    for m in (3, 4, 5, 6, 7, 9):
+        outs = []
+        for fuse in (0, 1):
+            st, stats, tr, x = gpu_solve(shape, h, f, pc, m, 1e-9, fuse=fuse, block=block, bc=bc)
+            outs.append((st, stats["iterations"], x))
+        assert outs[0][0] == outs[1][0] == P.OK
+        assert outs[0][1] == outs[1][1] and np.array_equal(outs[0][2], outs[1][2]), m
+    ref = oracle.bicgstab(f, h, pc=oracle_pc(pc), degree=9, tol=1e-9, block=block, bc=bc)
+    assert ref.iterations == outs[1][1] and np.array_equal(ref.x, outs[1][2])
+
+
+def test_kernel_bench_entry_points(gpu):
+    shape = (96, 80, 70)
+    h = workloads.spacing(96)
+    f = workloads.uniform_grid(1, shape)
+    with P.Solver(shape, h) as s:
+        b = dev(f)
+        x = torch.zeros_like(b)
+        assert s.solve(b, x, P.PC_CHEBYSHEV, 8, 1e-8, 500) == P.OK
+        x0 = x.clone()
+        for k in (P.KERNEL_CHEB_STEP, P.KERNEL_CHEB_PAIR, P.KERNEL_STENCIL_DOT,
+                  P.KERNEL_UPDATE_XR):
+            s.kernel_bench(k, P.FP64, 3)
+            assert s.kernel_bytes(k, P.FP64) > 0
+        torch.cuda.synchronize()
+        assert torch.equal(x, x0)  # the caller's solution is never touched
+        with pytest.raises(P.PoissonError):
+            s.kernel_bench(P.KERNEL_CHEB_STEP, P.MIXED, 1)  # plan is FP64
