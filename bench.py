@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--table2", action="store_true",
                     help="instead of the benchmark: the preconditioner comparison of the paper's "
                          "Table 2 on its test problem (255^3 unknowns, mixed faces) on one GPU")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the benchmark: the remaining measurement configurations "
+                         "(256^3 solver comparison, 512^3 Block-Jacobi vs Chebyshev to 1e-10, "
+                         "mixed vs FP64 at 1e-8 and 1e-10, a below-saturation serving point), one "
+                         "JSON line each")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference dispatch of known "
                          "size for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -65,20 +70,18 @@ def log(msg):
 
 
 def traffic_record(kernel_file, workload):
-    """HBM bytes per launch measured with rocprofv3 counters (profiles/), valid only
-    while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/hbm_traffic.txt:
+    FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the same counter's reading
+    for a copy of known size), valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
-        return None
-    try:
-        recs = json.load(open(path))
-    except Exception:
         return None
     src = open(os.path.join(ROOT, "paper_2503_08935_amd", "csrc", kernel_file), "rb").read()
     sha = hashlib.sha256(src).hexdigest()
-    for r in recs:
-        if r.get("workload") == workload and r.get("source_sha256") == sha:
-            return r.get("bytes_per_launch")
+    for line in open(path):
+        f = line.split()
+        if len(f) == 6 and not line.startswith("#") and f[0] == workload and f[2] == sha:
+            return float(f[5])
     return None
 
 
@@ -142,10 +145,85 @@ def table2():
     print(json.dumps({"table2_one_gpu": rows, "grid": shape, "h": h, "bc_neumann_mask": bc}))
 
 
+def suite():
+    """One JSON line per configuration; every solve is timed by the library (solve_ms
+    from entry to return, on the device stream) and its true residual reported."""
+    import torch
+
+    import paper_2503_08935_amd as P
+    from paper_2503_08935_amd import workloads
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+
+    def run(shape, h, b, pc, m, tol, reps=3, **opts):
+        x = torch.zeros_like(b)
+        with P.Solver(shape, h, stream=stream, **opts) as s:
+            ts = []
+            for _ in range(reps):
+                with torch.cuda.stream(stream):
+                    x.zero_()
+                st = s.solve(b, x, pc, m, tol, 20000)
+                d = s.stats()
+                ts.append(d["solve_ms"])
+        ts.sort()
+        return x, {"status": st, "iterations": d["iterations"], "half_step": d["half_step_exit"],
+                   "tts_median_s": round(ts[len(ts) // 2] / 1e3, 4),
+                   "relres_true": d["relres_true"], "hbm_gbps": round(d["model_gbps"], 1)}
+
+    names = {P.PC_NONE: "none", P.PC_JACOBI: "jacobi", P.PC_CHEBYSHEV: "chebyshev",
+             P.PC_BLOCK_JACOBI: "block_jacobi_64"}
+    # 256^3, f ~ U[-1,1) seed 2, FP64, tol 1e-8
+    n = 256
+    h = workloads.spacing(n)
+    b = torch.empty(n ** 3, dtype=torch.float64, device=dev)
+    P.fill_uniform(b, 2, stream)
+    stream.synchronize()
+    for pc, m in ((P.PC_NONE, 0), (P.PC_JACOBI, 0), (P.PC_BLOCK_JACOBI, 8), (P.PC_CHEBYSHEV, 4),
+                  (P.PC_CHEBYSHEV, 8)):
+        _, r = run((n, n, n), h, b, pc, m, 1e-8)
+        r.update({"config": "256^3 U[-1,1) seed 2, FP64, tol 1e-8", "precond": names[pc],
+                  "degree": m})
+        print(json.dumps(r), flush=True)
+    del b
+    # 512^3 noisy manufactured (seed 3), Block-Jacobi 64^3 vs Chebyshev-8, tol 1e-10
+    n = 512
+    h = workloads.spacing(n)
+    f = torch.from_numpy(workloads.manufactured_noisy((n, n, n), 3).ravel()).to(dev)
+    for pc in (P.PC_BLOCK_JACOBI, P.PC_CHEBYSHEV):
+        _, r = run((n, n, n), h, f, pc, 8, 1e-10)
+        r.update({"config": "512^3 3pi^2 sin sin sin + 1e-3 N(0,1) seed 3, FP64, tol 1e-10",
+                  "precond": names[pc], "degree": 8})
+        print(json.dumps(r), flush=True)
+    del f
+    # 512^3 f ~ U[-1,1) seed 4: mixed vs FP64 Chebyshev-8 at 1e-8 and 1e-10
+    b = torch.empty(n ** 3, dtype=torch.float64, device=dev)
+    P.fill_uniform(b, 4, stream)
+    stream.synchronize()
+    for tol in (1e-8, 1e-10):
+        x64, r64 = run((n, n, n), h, b, P.PC_CHEBYSHEV, 8, tol, precision=P.FP64)
+        xm, rm = run((n, n, n), h, b, P.PC_CHEBYSHEV, 8, tol, precision=P.MIXED)
+        rel = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
+        print(json.dumps({"config": f"512^3 U[-1,1) seed 4, Chebyshev-8, tol {tol}",
+                          "fp64": r64, "mixed": rm,
+                          "mixed_speedup": round(r64["tts_median_s"] / rm["tts_median_s"], 3),
+                          "mixed_vs_fp64_rel_diff": rel}), flush=True)
+        del x64, xm
+    del b
+    torch.cuda.empty_cache()
+    # serving below saturation: 400 requests at 10/s
+    from paper_2503_08935_amd import serving
+    sv = serving.run_stream(n_requests=400, rate=10.0, progress=log)
+    print(json.dumps({"config": "serving, 400 requests at 10/s (below saturation)",
+                      **{k: (float(f"{v:.6g}") if isinstance(v, float) else v)
+                         for k, v in sv.items()}}), flush=True)
+
+
 def main():
     a = parse()
     if a.table2:
         return table2()
+    if a.suite:
+        return suite()
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the solver has no "
               "multi-GPU path in this build", file=sys.stderr)

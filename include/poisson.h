@@ -104,8 +104,9 @@ typedef struct poisson_ctx poisson_ctx;
    non-symmetric. The Chebyshev interval uses the closed-form spectra of D and N
    (one Neumann end: 4 sin^2((2k-1) pi/(4n)); two: 4 sin^2(k pi/(2(n-1)))).
    Host-only: no device memory is touched until the first solve. Errors:
-   ERR_ARG if a size < 1, nx*ny*nz > 2^34, h not finite and > 0, bc > 63, a Neumann
-   face on an axis of length 1, or out == NULL; ERR_UNSUPPORTED for bc = 63 (all
+   ERR_ARG if a size < 1, nx*ny*nz > 2^34, nx*ny >= 2^28 (kernels address a plane
+   with 32-bit offsets), h not finite and > 0, bc > 63, a Neumann face on an axis of
+   length 1, or out == NULL; ERR_UNSUPPORTED for bc = 63 (all
    faces Neumann: singular). Chebyshev / Block-Jacobi need lambda_min > 0, so an
    axis with two Neumann ends must be paired with a Dirichlet face elsewhere. */
 int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **out);

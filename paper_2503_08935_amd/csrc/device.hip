@@ -370,6 +370,34 @@ __device__ __forceinline__ float read_lane(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// neighbour selection of one point along one axis: 0 zero, 1 neighbour, 2 mirror
+__device__ __forceinline__ int sel_lo(int a, int n, bool mask, int B, bool neu)
+{
+    return a > 0 ? ((!mask || a % B != 0) ? 1 : 0) : ((neu && n >= 2) ? 2 : 0);
+}
+__device__ __forceinline__ int sel_hi(int a, int n, bool mask, int B, bool neu)
+{
+    return a + 1 < n ? ((!mask || (a + 1) % B != 0) ? 1 : 0)
+                     : ((neu && n >= 2 && (!mask || a % B != 0)) ? 2 : 0);
+}
+
+// A selection code as two flags, so that picking a neighbour value is a pair
+// of selects (an integer code compared twice tends to become a branch).
+struct Sel {
+    bool nb, mi; // neighbour, mirror; neither: zero
+};
+__device__ __forceinline__ Sel to_sel(int code) { return Sel{code == 1, code == 2}; }
+__device__ __forceinline__ float pick(Sel s, float nbv, float miv)
+{
+    const float t = s.mi ? miv : 0.0f;
+    return s.nb ? nbv : t;
+}
+__device__ __forceinline__ double pick(Sel s, double nbv, double miv)
+{
+    const double t = s.mi ? miv : 0.0;
+    return s.nb ? nbv : t;
+}
+
 // ------------------------------------------------------------------------
 // stencil family
 // A tile is TX columns in x (one wave64 row) by TY*RY rows in y (wave w owns
@@ -381,6 +409,184 @@ __device__ __forceinline__ float read_lane(float v, int l)
 // registers and the two halo rows one load each.
 // TU: element type of the stencil input; TC: arithmetic type.
 // ------------------------------------------------------------------------
+
+// One tile of a stencil pass; its dot products accumulate into hi/lo.
+// FULL: the wave's RY rows and the tile's 64 columns are inside the grid, so
+// no row or column guard is needed. SIMPLE: no block mask and no Neumann face;
+// a neighbour outside the grid then reads as the +0.0 that the zero-filled
+// loads already hold, so no neighbour selection is needed either. Loads read
+// clamped (valid) addresses and a select keeps or zeroes the value, so the
+// loads of a plane issue together instead of each behind its own guard.
+template <int OP, typename TU, typename TC, bool MASK, bool FULL, bool SIMPLE>
+__device__ __forceinline__ void stencil_tile(const Prob &P, const KArgs &A, int local, int lane,
+                                             int wv, double (&hi)[2], double (&lo)[2])
+{
+    const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+    const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+    const int i0 = tix * TX, i = i0 + lane;
+    const int j0 = tiy * (TY * RY) + wv * RY;
+    const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+    if (j0 >= ny) return; // uniform within the wave
+
+    const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+    const TU *__restrict__ u = (const TU *)P.vec[A.in];
+    const int B = MASK ? P.block : 1;
+    const bool xin = FULL || i < nx;
+    const int ic = xin ? i : nx - 1;
+    // neighbour selection per face: zero (Dirichlet face or another block), the
+    // neighbour, or the mirror image across a Neumann face (u_{-1} = u_1, eq.
+    // matrix_neuman); mirrors also respect the block mask
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
+    const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
+    bool rin[RY];
+    size_t roff[RY]; // in-plane offset of the lane's point in row r (clamped)
+    Sel sym[RY], syp[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int j = j0 + r;
+        rin[r] = FULL || (xin && j < ny);
+        roff[r] = (size_t)ic + NXs * (size_t)(FULL ? j : min(j, ny - 1));
+        sym[r] = to_sel(rin[r] ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        syp[r] = to_sel(rin[r] ? sel_hi(j, ny, MASK, B, nyh) : 0);
+    }
+    const bool ymh = xin && j0 > 0;
+    const bool yph = xin && j0 + RY < ny;
+    const size_t ymoff = (size_t)ic + NXs * (size_t)(j0 > 0 ? j0 - 1 : 0);
+    const size_t ypoff = (size_t)ic + NXs * (size_t)min(j0 + RY, ny - 1);
+    const int hrow = lane & 31;
+    const bool hload = hrow < RY && j0 + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+    const size_t hoff =
+        hload ? (size_t)(lane < 32 ? i0 - 1 : i0 + TX) + NXs * (size_t)(j0 + hrow) : 0;
+    const TC ih2 = Coef<TC>::ih2(P);
+    TC cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
+    if constexpr (OP == S_CHEB1) {
+        cA = Coef<TC>::c1(P);
+        cB = Coef<TC>::theta(P);
+    } else if constexpr (OP == S_CHEB2 || OP == S_CHEBK) {
+        cA = Coef<TC>::rc(P, A.step);
+        cB = Coef<TC>::ro(P, A.step);
+        cC = Coef<TC>::two_sigma(P);
+        cD = Coef<TC>::two_over_delta(P);
+        cE = Coef<TC>::theta(P);
+    }
+    TC *out = (TC *)P.vec[A.out];
+    const TC *vv = (const TC *)P.vec[A.v];
+    const TC *zz = (const TC *)P.vec[A.z];
+    float *v32 = (float *)P.vec[V_V32];
+    const double *__restrict__ rt = (const double *)P.vec[V_RT];
+    const double *__restrict__ bv = (const double *)P.vec[V_B];
+    const double *sv = (const double *)P.vec[V_R];
+    double *rr = (double *)P.vec[V_R];
+    double *rtw = (double *)P.vec[V_RT];
+    double *pw = (double *)P.vec[V_P];
+
+    // type of the streamed operands: the arithmetic type for the Chebyshev steps
+    using TO = typename std::conditional<(OP == S_CHEB2 || OP == S_CHEBK), TC, double>::type;
+    const TO *o0p = nullptr;
+    if constexpr (OP == S_CHEB2 || OP == S_CHEBK) o0p = vv;
+    if constexpr (OP == S_SDOT) o0p = rt;
+    if constexpr (OP == S_SDOT2) o0p = sv;
+    if constexpr (OP == S_INIT || OP == S_TRUE) o0p = bv;
+
+    TC c[RY], zm[RY]; // planes k and k-1
+    {
+        const size_t pk = S * (size_t)k0, pm = k0 > 0 ? pk - S : pk;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const TC cv = (TC)ld_g(u + pk + roff[r]);
+            const TC mv = (TC)ld_g(u + pm + roff[r]);
+            c[r] = rin[r] ? cv : (TC)0;
+            zm[r] = (rin[r] && k0 > 0) ? mv : (TC)0;
+        }
+    }
+    for (int k = k0; k < k1; ++k) {
+        const size_t pk = S * (size_t)k;
+        const bool znext = k + 1 < nz;
+        const size_t pn = znext ? pk + S : pk;
+        const Sel szm = to_sel(sel_lo(k, nz, MASK, B, nzl));
+        const Sel szp = to_sel(sel_hi(k, nz, MASK, B, nzh));
+        TC zr[RY];
+        TO o0[RY], o1[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const TC nv = (TC)ld_g(u + pn + roff[r]);
+            zr[r] = (rin[r] && znext) ? nv : (TC)0;
+            o0[r] = o1[r] = (TO)0;
+            if constexpr (OP != S_APPLY && OP != S_CHEB1) {
+                const TO a0 = ld_nt(o0p + pk + roff[r]);
+                o0[r] = rin[r] ? a0 : (TO)0;
+            }
+            if constexpr (OP == S_CHEBK) {
+                const TO a1 = ld_nt(zz + pk + roff[r]);
+                o1[r] = rin[r] ? a1 : (TO)0;
+            }
+        }
+        const TC ymr = (TC)ld_g(u + pk + ymoff), ypr = (TC)ld_g(u + pk + ypoff);
+        const TC hr = (TC)ld_g(u + pk + hoff);
+        const TC ymv = ymh ? ymr : (TC)0, ypv = yph ? ypr : (TC)0, he = hload ? hr : (TC)0;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            // the DPP shifts run in every lane (a shift reads its source lane)
+            const TC pv = lane_prev(c[r]), nv = lane_next(c[r]);
+            const TC el = read_lane(he, r), er = read_lane(he, 32 + r);
+            const TC xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+            const TC yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
+            const TC yr = r == RY - 1 ? ypv : c[r < RY - 1 ? r + 1 : 0];
+            TC xm, xp, ym, yp, zmv, zpv;
+            if constexpr (SIMPLE) {
+                xm = xl, xp = xr, ym = yl, yp = yr, zmv = zm[r], zpv = zr[r];
+            } else {
+                xm = pick(sxm, xl, xr), xp = pick(sxp, xr, xl);
+                ym = pick(sym[r], yl, yr), yp = pick(syp[r], yr, yl);
+                zmv = pick(szm, zm[r], zr[r]), zpv = pick(szp, zr[r], zm[r]);
+            }
+            const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zmv) - zpv) * ih2;
+            if (rin[r]) {
+                const size_t idx = pk + roff[r];
+                if constexpr (OP == S_APPLY) {
+                    st_nt(out + idx, a);
+                } else if constexpr (OP == S_CHEB1) {
+                    st_nt(out + idx, cA * ((TC)2 * c[r] - a / cB));
+                    if constexpr (sizeof(TC) == 4) st_nt(v32 + idx, c[r]);
+                } else if constexpr (OP == S_CHEB2) {
+                    const TC v = (TC)o0[r];
+                    const TC z = v / cE;
+                    st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
+                } else if constexpr (OP == S_CHEBK) {
+                    const TC v = (TC)o0[r], z = (TC)o1[r];
+                    st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
+                } else if constexpr (OP == S_SDOT) {
+                    st_nt(out + idx, a);
+                    dd_acc(hi[0], lo[0], o0[r], a);
+                } else if constexpr (OP == S_SDOT2) {
+                    st_nt(out + idx, a);
+                    dd_acc(hi[0], lo[0], a, o0[r]);
+                    dd_acc(hi[1], lo[1], a, a);
+                } else if constexpr (OP == S_INIT) {
+                    const double b = o0[r];
+                    const double res = b - a;
+                    st_nt(rr + idx, res);
+                    st_nt(rtw + idx, res);
+                    st_nt(pw + idx, res);
+                    dd_acc(hi[0], lo[0], res, res);
+                    dd_acc(hi[1], lo[1], b, b);
+                } else if constexpr (OP == S_TRUE) {
+                    const double res = o0[r] - a;
+                    dd_acc(hi[0], lo[0], res, res);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            zm[r] = c[r];
+            c[r] = zr[r];
+        }
+    }
+}
+
 template <int OP, typename TU, typename TC, bool MASK>
 __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
 {
@@ -400,166 +606,29 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
-        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
-        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
-        const int i0 = tix * TX, i = i0 + lane;
+        double hi[2] = {0.0, 0.0}, lo[2] = {0.0, 0.0};
+        // one wave-uniform branch per tile
+        const int tix = local % P.tx, tiy = (local / P.tx) % P.ty;
         const int j0 = tiy * (TY * RY) + wv * RY;
-        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
-        double hi[NA], lo[NA];
-#pragma unroll
-        for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
-
-        if (j0 < ny) { // uniform within the wave
-            const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
-            size_t base = (size_t)i + NXs * ((size_t)j0 + (size_t)ny * (size_t)k0);
-            const TU *__restrict__ u = (const TU *)P.vec[A.in];
-            const int B = MASK ? P.block : 1;
-            const bool xin = i < nx;
-            // neighbour selection per face: 0 = reads zero (Dirichlet face or another
-            // block), 1 = the neighbour, 2 = the mirror image across a Neumann face
-            // (u_{-1} = u_1, eq. matrix_neuman); mirrors also respect the block mask
-            const unsigned bc = P.bc;
-            const int sxm = !xin ? 0
-                            : i > 0 ? ((!MASK || i % B != 0) ? 1 : 0)
-                                    : (((bc & 1u) && nx >= 2) ? 2 : 0);
-            const int sxp = !xin ? 0
-                            : i + 1 < nx ? ((!MASK || (i + 1) % B != 0) ? 1 : 0)
-                                         : (((bc & 2u) && nx >= 2 && (!MASK || i % B != 0)) ? 2 : 0);
-            bool rin[RY];
-            int sym[RY], syp[RY];
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const int j = j0 + r;
-                rin[r] = xin && j < ny;
-                sym[r] = !rin[r] ? 0
-                         : j > 0 ? ((!MASK || j % B != 0) ? 1 : 0)
-                                 : (((bc & 4u) && ny >= 2) ? 2 : 0);
-                syp[r] = !rin[r] ? 0
-                         : j + 1 < ny ? ((!MASK || (j + 1) % B != 0) ? 1 : 0)
-                                      : (((bc & 8u) && ny >= 2 && (!MASK || j % B != 0)) ? 2 : 0);
-            }
-            const bool ymh = xin && j0 > 0;
-            const bool yph = xin && j0 + RY < ny;
-            const int hrow = lane & 31;
-            const bool hload = hrow < RY && j0 + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
-            const size_t hbase = (size_t)(lane < 32 ? i0 - 1 : i0 + TX) +
-                                 NXs * ((size_t)(j0 + hrow) + (size_t)ny * (size_t)k0);
-            const TC ih2 = Coef<TC>::ih2(P);
-            TC cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
-            if constexpr (OP == S_CHEB1) {
-                cA = Coef<TC>::c1(P);
-                cB = Coef<TC>::theta(P);
-            } else if constexpr (OP == S_CHEB2 || OP == S_CHEBK) {
-                cA = Coef<TC>::rc(P, A.step);
-                cB = Coef<TC>::ro(P, A.step);
-                cC = Coef<TC>::two_sigma(P);
-                cD = Coef<TC>::two_over_delta(P);
-                cE = Coef<TC>::theta(P);
-            }
-            TC *out = (TC *)P.vec[A.out];
-            const TC *vv = (const TC *)P.vec[A.v];
-            const TC *zz = (const TC *)P.vec[A.z];
-            float *v32 = (float *)P.vec[V_V32];
-            const double *__restrict__ rt = (const double *)P.vec[V_RT];
-            const double *__restrict__ bv = (const double *)P.vec[V_B];
-            const double *sv = (const double *)P.vec[V_R];
-            double *rr = (double *)P.vec[V_R];
-            double *rtw = (double *)P.vec[V_RT];
-            double *pw = (double *)P.vec[V_P];
-
-            // type of the streamed operands: the arithmetic type for the Chebyshev steps
-            using TO = typename std::conditional<(OP == S_CHEB2 || OP == S_CHEBK), TC, double>::type;
-            TC c[RY], zm[RY]; // planes k and k-1 (unmasked values)
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                c[r] = rin[r] ? (TC)u[base + r * NXs] : (TC)0;
-                zm[r] = (rin[r] && k0 > 0) ? (TC)u[base + r * NXs - S] : (TC)0;
-            }
-            size_t hidx = hbase;
-            for (int k = k0; k < k1; ++k, base += S, hidx += S) {
-                const bool znext = k + 1 < nz;
-                const int szm = k > 0 ? ((!MASK || k % B != 0) ? 1 : 0)
-                                      : (((bc & 16u) && nz >= 2) ? 2 : 0);
-                const int szp = znext ? ((!MASK || (k + 1) % B != 0) ? 1 : 0)
-                                      : (((bc & 32u) && nz >= 2 && (!MASK || k % B != 0)) ? 2 : 0);
-                TC zr[RY];
-                TO o0[RY], o1[RY];
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    const size_t idx = base + r * NXs;
-                    zr[r] = (rin[r] && znext) ? (TC)u[idx + S] : (TC)0;
-                    o0[r] = o1[r] = (TO)0;
-                    if (rin[r]) {
-                        if constexpr (OP == S_CHEB2) o0[r] = ld_nt(vv + idx);
-                        if constexpr (OP == S_CHEBK) { o0[r] = ld_nt(vv + idx); o1[r] = ld_nt(zz + idx); }
-                        if constexpr (OP == S_SDOT) o0[r] = ld_nt(rt + idx);
-                        if constexpr (OP == S_SDOT2) o0[r] = ld_nt(sv + idx);
-                        if constexpr (OP == S_INIT || OP == S_TRUE) o0[r] = ld_nt(bv + idx);
-                    }
-                }
-                const TC ymv = ymh ? (TC)u[base - NXs] : (TC)0;
-                const TC ypv = yph ? (TC)u[base + RY * NXs] : (TC)0;
-                const TC he = hload ? (TC)u[hidx] : (TC)0;
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    TC xl = lane_prev(c[r]), xr = lane_next(c[r]);
-                    const TC el = read_lane(he, r), er = read_lane(he, 32 + r);
-                    if (lane == 0) xl = el;
-                    if (lane == TX - 1) xr = er;
-                    const TC yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
-                    const TC yr = r == RY - 1 ? ypv : c[r < RY - 1 ? r + 1 : 0];
-                    const TC xm = sxm == 1 ? xl : sxm == 2 ? xr : (TC)0;
-                    const TC xp = sxp == 1 ? xr : sxp == 2 ? xl : (TC)0;
-                    const TC ym = sym[r] == 1 ? yl : sym[r] == 2 ? yr : (TC)0;
-                    const TC yp = syp[r] == 1 ? yr : syp[r] == 2 ? yl : (TC)0;
-                    const TC zmv = szm == 1 ? zm[r] : szm == 2 ? zr[r] : (TC)0;
-                    const TC zpv = szp == 1 ? zr[r] : szp == 2 ? zm[r] : (TC)0;
-                    const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zmv) - zpv) * ih2;
-                    if (rin[r]) {
-                        const size_t idx = base + r * NXs;
-                        if constexpr (OP == S_APPLY) {
-                            st_nt(out + idx, a);
-                        } else if constexpr (OP == S_CHEB1) {
-                            st_nt(out + idx, cA * ((TC)2 * c[r] - a / cB));
-                            if constexpr (sizeof(TC) == 4) st_nt(v32 + idx, c[r]);
-                        } else if constexpr (OP == S_CHEB2) {
-                            const TC v = (TC)o0[r];
-                            const TC z = v / cE;
-                            st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
-                        } else if constexpr (OP == S_CHEBK) {
-                            const TC v = (TC)o0[r], z = (TC)o1[r];
-                            st_nt(out + idx, cA * ((cC * c[r] + cD * (v - a)) - cB * z));
-                        } else if constexpr (OP == S_SDOT) {
-                            st_nt(out + idx, a);
-                            dd_acc(hi[0], lo[0], o0[r], a);
-                        } else if constexpr (OP == S_SDOT2) {
-                            st_nt(out + idx, a);
-                            dd_acc(hi[0], lo[0], a, o0[r]);
-                            dd_acc(hi[1], lo[1], a, a);
-                        } else if constexpr (OP == S_INIT) {
-                            const double b = o0[r];
-                            const double res = b - a;
-                            st_nt(rr + idx, res);
-                            st_nt(rtw + idx, res);
-                            st_nt(pw + idx, res);
-                            dd_acc(hi[0], lo[0], res, res);
-                            dd_acc(hi[1], lo[1], b, b);
-                        } else if constexpr (OP == S_TRUE) {
-                            const double res = o0[r] - a;
-                            dd_acc(hi[0], lo[0], res, res);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    zm[r] = c[r];
-                    c[r] = zr[r];
-                }
+        const bool full = tix * TX + TX <= P.nx && j0 + RY <= P.ny;
+        if constexpr (MASK) {
+            if (full) stencil_tile<OP, TU, TC, true, true, false>(P, A, local, lane, wv, hi, lo);
+            else stencil_tile<OP, TU, TC, true, false, false>(P, A, local, lane, wv, hi, lo);
+        } else {
+            if (P.bc == 0) {
+                if (full) stencil_tile<OP, TU, TC, false, true, true>(P, A, local, lane, wv, hi, lo);
+                else stencil_tile<OP, TU, TC, false, false, true>(P, A, local, lane, wv, hi, lo);
+            } else {
+                if (full) stencil_tile<OP, TU, TC, false, true, false>(P, A, local, lane, wv, hi, lo);
+                else stencil_tile<OP, TU, TC, false, false, false>(P, A, local, lane, wv, hi, lo);
             }
         }
         if constexpr (ND > 0) {
             double res[NA];
-            if (tile_commit<NA>(P, local, hi, lo, lds, &flag, res) && threadIdx.x == 0) {
+            double h2[NA], l2[NA];
+#pragma unroll
+            for (int d = 0; d < NA; ++d) h2[d] = hi[d], l2[d] = lo[d];
+            if (tile_commit<NA>(P, local, h2, l2, lds, &flag, res) && threadIdx.x == 0) {
                 if constexpr (OP == S_SDOT) fin_sdot(P, res[0]);
                 else if constexpr (OP == S_SDOT2) fin_sdot2(P, res[0], res[1]);
                 else if constexpr (OP == S_INIT) fin_init(P, res[0], res[1]);
@@ -584,14 +653,15 @@ template <typename T> struct Pair { T a, b; };
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Pair loads are branch-free: a lane that must not read uses the vector's
-// first element (always valid) and discards the value, so a plane's loads
-// issue together instead of each in its own exec-masked block.
-template <typename TU>
-__device__ __forceinline__ Pair<float> load_pair(const TU *p, const TU *base, bool ok0, bool ok1,
-                                                 bool vec)
+// first element (always valid) and discards the value. VEC (nx even, so every
+// pair is 8-/16-byte aligned) is a compile-time choice: a run-time test here
+// would put every load in its own basic block, each closed by a full wait, and
+// serialise a plane's loads.
+template <bool VEC, typename TU>
+__device__ __forceinline__ Pair<float> load_pair(const TU *p, const TU *base, bool ok0, bool ok1)
 {
     Pair<float> r;
-    if (vec) {
+    if constexpr (VEC) {
         const TU *q = ok0 ? p : base;
         if constexpr (sizeof(TU) == 8) {
             typedef double d2 __attribute__((ext_vector_type(2)));
@@ -611,11 +681,12 @@ __device__ __forceinline__ Pair<float> load_pair(const TU *p, const TU *base, bo
     return r;
 }
 
+template <bool VEC>
 __device__ __forceinline__ Pair<float> load_pair_nt(const float *p, const float *base, bool ok0,
-                                                    bool ok1, bool vec)
+                                                    bool ok1)
 {
     Pair<float> r;
-    if (vec) {
+    if constexpr (VEC) {
         const f32x2 v = ld_nt((const f32x2 *)(ok0 ? p : base));
         r.a = ok0 ? v.x : 0.0f;
         r.b = ok0 ? v.y : 0.0f;
@@ -627,10 +698,10 @@ __device__ __forceinline__ Pair<float> load_pair_nt(const float *p, const float 
     return r;
 }
 
-__device__ __forceinline__ void store_pair_nt(float *p, float a, float b, bool ok0, bool ok1,
-                                              bool vec)
+template <bool VEC>
+__device__ __forceinline__ void store_pair_nt(float *p, float a, float b, bool ok0, bool ok1)
 {
-    if (vec) {
+    if constexpr (VEC) {
         if (ok0) {
             const f32x2 v = {a, b};
             st_nt((f32x2 *)p, v);
@@ -641,26 +712,157 @@ __device__ __forceinline__ void store_pair_nt(float *p, float a, float b, bool o
     }
 }
 
-// neighbour selection of one point along one axis: 0 zero, 1 neighbour, 2 mirror
-__device__ __forceinline__ int sel_lo(int a, int n, bool mask, int B, bool neu)
+// One tile of an FP32 Chebyshev step. VEC: nx even. FULL: the wave's RY rows
+// and the tile's 64 columns are all inside the grid, so no access needs a
+// guard (guarded stores let the compiler sink loads into their branches).
+template <int OP, typename TU, bool MASK, bool VEC, bool FULL, bool SIMPLE>
+__device__ __forceinline__ void cheb_f32x2_tile(const Prob &P, const KArgs &A, int local, int lane,
+                                                int wv)
 {
-    return a > 0 ? ((!mask || a % B != 0) ? 1 : 0) : ((neu && n >= 2) ? 2 : 0);
-}
-__device__ __forceinline__ int sel_hi(int a, int n, bool mask, int B, bool neu)
-{
-    return a + 1 < n ? ((!mask || (a + 1) % B != 0) ? 1 : 0)
-                     : ((neu && n >= 2 && (!mask || a % B != 0)) ? 2 : 0);
+    constexpr int RH = RY / 2;
+    const int half = lane >> 5, hl = lane & 31;
+    const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+    const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+    const int i0 = tix * TX;
+    const int x0 = i0 + 2 * hl;
+    const int jw = tiy * (TY * RY) + wv * RY; // the wave's first row
+    const int jh = jw + half * RH;            // this half-wave's first row
+    const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+    if (jw >= ny) return; // uniform within the wave (no barriers below)
+
+    const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+    const bool in0 = FULL || x0 < nx, in1 = FULL || x0 + 1 < nx;
+    const int B = MASK ? P.block : 1;
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    // x selections of the two points
+    const Sel sxm0 = to_sel(in0 ? sel_lo(x0, nx, MASK, B, nxl) : 0);
+    const Sel sxp0 = to_sel(in0 ? sel_hi(x0, nx, MASK, B, nxh) : 0);
+    const Sel sxm1 = to_sel(in1 ? sel_lo(x0 + 1, nx, MASK, B, nxl) : 0);
+    const Sel sxp1 = to_sel(in1 ? sel_hi(x0 + 1, nx, MASK, B, nxh) : 0);
+    bool rin[RH];
+    Sel sym[RH], syp[RH];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const int j = jh + r;
+        rin[r] = FULL || j < ny;
+        sym[r] = to_sel(rin[r] ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        syp[r] = to_sel(rin[r] ? sel_hi(j, ny, MASK, B, nyh) : 0);
+    }
+    const bool ymh = in0 && jh > 0 && jh - 1 < ny;
+    const bool yph = in0 && jh + RH < ny;
+    // x halo: lane q < RY holds the left neighbour of wave row q, lane 32+q the right one
+    const int hrow = lane & 31;
+    const bool hload = hrow < RY && jw + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+    size_t hidx = (size_t)(lane < 32 ? i0 - 1 : i0 + TX) +
+                  NXs * ((size_t)(jw + hrow) + (size_t)ny * (size_t)k0);
+    size_t base = (size_t)x0 + NXs * ((size_t)jh + (size_t)ny * (size_t)k0);
+
+    const TU *__restrict__ u = (const TU *)P.vec[A.in];
+    float *out = (float *)P.vec[A.out];
+    const float *vv = (const float *)P.vec[A.v];
+    const float *zz = (const float *)P.vec[A.z];
+    float *v32 = (float *)P.vec[V_V32];
+    const float ih2 = P.ih2f;
+    float cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
+    if constexpr (OP == S_CHEB1) {
+        cA = P.c1f;
+        cB = P.thetaf;
+    } else {
+        cA = P.rcf[A.step];
+        cB = P.rof[A.step];
+        cC = P.two_sigmaf;
+        cD = P.two_over_deltaf;
+        cE = P.thetaf;
+    }
+    Pair<float> c[RH], zm[RH];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const size_t idx = base + r * NXs;
+        c[r] = load_pair<VEC>(u + idx, u, in0 && rin[r], in1 && rin[r]);
+        zm[r] = load_pair<VEC>(u + idx - (k0 > 0 ? S : 0), u, k0 > 0 && in0 && rin[r],
+                               k0 > 0 && in1 && rin[r]);
+    }
+    for (int k = k0; k < k1; ++k, base += S, hidx += S) {
+        const Sel szm = to_sel(sel_lo(k, nz, MASK, B, nzl));
+        const Sel szp = to_sel(sel_hi(k, nz, MASK, B, nzh));
+        Pair<float> zr[RH], o0[RH], o1[RH];
+        const bool zn = k + 1 < nz;
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
+            const size_t idx = base + r * NXs;
+            const bool a0 = in0 && rin[r], a1 = in1 && rin[r];
+            zr[r] = load_pair<VEC>(u + idx + (zn ? S : 0), u, zn && a0, zn && a1);
+            if constexpr (OP == S_CHEB2) o0[r] = load_pair_nt<VEC>(vv + idx, vv, a0, a1);
+            if constexpr (OP == S_CHEBK) {
+                o0[r] = load_pair_nt<VEC>(vv + idx, vv, a0, a1);
+                o1[r] = load_pair_nt<VEC>(zz + idx, zz, a0, a1);
+            }
+        }
+        const Pair<float> ymv = load_pair<VEC>(u + base - (ymh ? NXs : 0), u, ymh, ymh && in1);
+        const Pair<float> ypv = load_pair<VEC>(u + base + (yph ? RH * NXs : 0), u, yph, yph && in1);
+        const float hv = (float)ld_g(u + (hload ? hidx : 0));
+        const float he = hload ? hv : 0.0f;
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
+            // neighbours across lanes, fixed up with the halo at half-wave edges
+            const float elA = read_lane(he, r), elB = read_lane(he, RH + r);
+            const float erA = read_lane(he, 32 + r), erB = read_lane(he, 32 + RH + r);
+            const float el = half ? elB : elA, er = half ? erB : erA;
+            // the DPP shifts run in every lane (a shift reads its source lane)
+            const float pv = lane_prev(c[r].b), nv = lane_next(c[r].a);
+            const float xl = hl == 0 ? el : pv;  // x0 - 1
+            const float xr = hl == 31 ? er : nv; // x0 + 2
+            const Pair<float> yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
+            const Pair<float> yr = r == RH - 1 ? ypv : c[r < RH - 1 ? r + 1 : 0];
+            // point 0 at x0: left xl, right c.b; point 1 at x0+1: left c.a, right xr
+            float xm0, xp0, xm1, xp1, ym0, ym1, yp0, yp1, zm0, zm1, zp0, zp1;
+            if constexpr (SIMPLE) {
+                xm0 = xl, xp0 = c[r].b, xm1 = c[r].a, xp1 = xr;
+                ym0 = yl.a, ym1 = yl.b, yp0 = yr.a, yp1 = yr.b;
+                zm0 = zm[r].a, zm1 = zm[r].b, zp0 = zr[r].a, zp1 = zr[r].b;
+            } else {
+                xm0 = pick(sxm0, xl, c[r].b), xp0 = pick(sxp0, c[r].b, xl);
+                xm1 = pick(sxm1, c[r].a, xr), xp1 = pick(sxp1, xr, c[r].a);
+                ym0 = pick(sym[r], yl.a, yr.a), ym1 = pick(sym[r], yl.b, yr.b);
+                yp0 = pick(syp[r], yr.a, yl.a), yp1 = pick(syp[r], yr.b, yl.b);
+                zm0 = pick(szm, zm[r].a, zr[r].a), zm1 = pick(szm, zm[r].b, zr[r].b);
+                zp0 = pick(szp, zr[r].a, zm[r].a), zp1 = pick(szp, zr[r].b, zm[r].b);
+            }
+            const float a0 = ((((((6.0f * c[r].a - xm0) - xp0) - ym0) - yp0) - zm0) - zp0) * ih2;
+            const float a1 = ((((((6.0f * c[r].b - xm1) - xp1) - ym1) - yp1) - zm1) - zp1) * ih2;
+            const size_t idx = base + r * NXs;
+            const bool ok0 = in0 && rin[r], ok1 = in1 && rin[r];
+            float w0, w1;
+            if constexpr (OP == S_CHEB1) {
+                w0 = cA * (2.0f * c[r].a - a0 / cB);
+                w1 = cA * (2.0f * c[r].b - a1 / cB);
+                store_pair_nt<VEC>(v32 + idx, c[r].a, c[r].b, ok0, ok1);
+            } else if constexpr (OP == S_CHEB2) {
+                const float z0 = o0[r].a / cE, z1 = o0[r].b / cE;
+                w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * z0);
+                w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * z1);
+            } else {
+                w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * o1[r].a);
+                w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * o1[r].b);
+            }
+            store_pair_nt<VEC>(out + idx, w0, w1, ok0, ok1);
+        }
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
+            zm[r] = c[r];
+            c[r] = zr[r];
+        }
+    }
 }
 
 template <int OP, typename TU, bool MASK>
 __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 {
     static_assert(OP == S_CHEB1 || OP == S_CHEB2 || OP == S_CHEBK, "Chebyshev steps only");
-    constexpr int RH = RY / 2;
     const int total = W.count_dev ? *W.count_dev : W.count;
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
-    const int half = lane >> 5, hl = lane & 31;
-
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
@@ -669,139 +871,14 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
-        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
-        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
-        const int i0 = tix * TX;
-        const int x0 = i0 + 2 * hl;
-        const int jw = tiy * (TY * RY) + wv * RY; // the wave's first row
-        const int jh = jw + half * RH;            // this half-wave's first row
-        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
-        if (jw >= ny) continue; // uniform within the wave (no barriers below)
-
-        const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
-        const bool vec = (nx & 1) == 0;
-        const bool in0 = x0 < nx, in1 = x0 + 1 < nx;
-        const int B = MASK ? P.block : 1;
-        const unsigned bc = P.bc;
-        const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
-        const bool nzl = bc & 16u, nzh = bc & 32u;
-        // x selections of the two points
-        const int sxm0 = in0 ? sel_lo(x0, nx, MASK, B, nxl) : 0;
-        const int sxp0 = in0 ? sel_hi(x0, nx, MASK, B, nxh) : 0;
-        const int sxm1 = in1 ? sel_lo(x0 + 1, nx, MASK, B, nxl) : 0;
-        const int sxp1 = in1 ? sel_hi(x0 + 1, nx, MASK, B, nxh) : 0;
-        bool rin[RH];
-        int sym[RH], syp[RH];
-#pragma unroll
-        for (int r = 0; r < RH; ++r) {
-            const int j = jh + r;
-            rin[r] = j < ny;
-            sym[r] = rin[r] ? sel_lo(j, ny, MASK, B, nyl) : 0;
-            syp[r] = rin[r] ? sel_hi(j, ny, MASK, B, nyh) : 0;
-        }
-        const bool ymh = in0 && jh > 0 && jh - 1 < ny;
-        const bool yph = in0 && jh + RH < ny;
-        // x halo: lane q < RY holds the left neighbour of wave row q, lane 32+q the right one
-        const int hrow = lane & 31;
-        const bool hload = hrow < RY && jw + hrow < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
-        size_t hidx = (size_t)(lane < 32 ? i0 - 1 : i0 + TX) +
-                      NXs * ((size_t)(jw + hrow) + (size_t)ny * (size_t)k0);
-        size_t base = (size_t)x0 + NXs * ((size_t)jh + (size_t)ny * (size_t)k0);
-
-        const TU *__restrict__ u = (const TU *)P.vec[A.in];
-        float *out = (float *)P.vec[A.out];
-        const float *vv = (const float *)P.vec[A.v];
-        const float *zz = (const float *)P.vec[A.z];
-        float *v32 = (float *)P.vec[V_V32];
-        const float ih2 = P.ih2f;
-        float cA = 0, cB = 0, cC = 0, cD = 0, cE = 0;
-        if constexpr (OP == S_CHEB1) {
-            cA = P.c1f;
-            cB = P.thetaf;
-        } else {
-            cA = P.rcf[A.step];
-            cB = P.rof[A.step];
-            cC = P.two_sigmaf;
-            cD = P.two_over_deltaf;
-            cE = P.thetaf;
-        }
-        Pair<float> c[RH], zm[RH];
-#pragma unroll
-        for (int r = 0; r < RH; ++r) {
-            const size_t idx = base + r * NXs;
-            c[r] = load_pair(u + idx, u, in0 && rin[r], in1 && rin[r], vec);
-            zm[r] = load_pair(u + idx - (k0 > 0 ? S : 0), u, k0 > 0 && in0 && rin[r],
-                              k0 > 0 && in1 && rin[r], vec);
-        }
-        for (int k = k0; k < k1; ++k, base += S, hidx += S) {
-            const int szm = sel_lo(k, nz, MASK, B, nzl);
-            const int szp = sel_hi(k, nz, MASK, B, nzh);
-            Pair<float> zr[RH], o0[RH], o1[RH];
-#pragma unroll
-            for (int r = 0; r < RH; ++r) {
-                const size_t idx = base + r * NXs;
-                const bool a0 = in0 && rin[r], a1 = in1 && rin[r];
-                const bool zn = k + 1 < nz;
-                zr[r] = load_pair(u + idx + (zn ? S : 0), u, zn && a0, zn && a1, vec);
-                if constexpr (OP == S_CHEB2) o0[r] = load_pair_nt(vv + idx, vv, a0, a1, vec);
-                if constexpr (OP == S_CHEBK) {
-                    o0[r] = load_pair_nt(vv + idx, vv, a0, a1, vec);
-                    o1[r] = load_pair_nt(zz + idx, zz, a0, a1, vec);
-                }
-            }
-            const Pair<float> ymv = load_pair(u + base - (ymh ? NXs : 0), u, ymh, ymh && in1, vec);
-            const Pair<float> ypv = load_pair(u + base + (yph ? RH * NXs : 0), u, yph, yph && in1, vec);
-            const float hv = (float)ld_g(u + (hload ? hidx : 0));
-            const float he = hload ? hv : 0.0f;
-#pragma unroll
-            for (int r = 0; r < RH; ++r) {
-                // neighbours across lanes, fixed up with the halo at half-wave edges
-                float xl = lane_prev(c[r].b); // x0 - 1
-                float xr = lane_next(c[r].a); // x0 + 2
-                const float elA = read_lane(he, r), elB = read_lane(he, RH + r);
-                const float erA = read_lane(he, 32 + r), erB = read_lane(he, 32 + RH + r);
-                if (hl == 0) xl = half ? elB : elA;
-                if (hl == 31) xr = half ? erB : erA;
-                const Pair<float> yl = r == 0 ? ymv : c[r > 0 ? r - 1 : 0];
-                const Pair<float> yr = r == RH - 1 ? ypv : c[r < RH - 1 ? r + 1 : 0];
-                // point 0 at x0: left xl, right c.b; point 1 at x0+1: left c.a, right xr
-                const float xm0 = sxm0 == 1 ? xl : sxm0 == 2 ? c[r].b : 0.0f;
-                const float xp0 = sxp0 == 1 ? c[r].b : sxp0 == 2 ? xl : 0.0f;
-                const float xm1 = sxm1 == 1 ? c[r].a : sxm1 == 2 ? xr : 0.0f;
-                const float xp1 = sxp1 == 1 ? xr : sxp1 == 2 ? c[r].a : 0.0f;
-                const float ym0 = sym[r] == 1 ? yl.a : sym[r] == 2 ? yr.a : 0.0f;
-                const float ym1 = sym[r] == 1 ? yl.b : sym[r] == 2 ? yr.b : 0.0f;
-                const float yp0 = syp[r] == 1 ? yr.a : syp[r] == 2 ? yl.a : 0.0f;
-                const float yp1 = syp[r] == 1 ? yr.b : syp[r] == 2 ? yl.b : 0.0f;
-                const float zm0 = szm == 1 ? zm[r].a : szm == 2 ? zr[r].a : 0.0f;
-                const float zm1 = szm == 1 ? zm[r].b : szm == 2 ? zr[r].b : 0.0f;
-                const float zp0 = szp == 1 ? zr[r].a : szp == 2 ? zm[r].a : 0.0f;
-                const float zp1 = szp == 1 ? zr[r].b : szp == 2 ? zm[r].b : 0.0f;
-                const float a0 = ((((((6.0f * c[r].a - xm0) - xp0) - ym0) - yp0) - zm0) - zp0) * ih2;
-                const float a1 = ((((((6.0f * c[r].b - xm1) - xp1) - ym1) - yp1) - zm1) - zp1) * ih2;
-                const size_t idx = base + r * NXs;
-                const bool ok0 = in0 && rin[r], ok1 = in1 && rin[r];
-                float w0, w1;
-                if constexpr (OP == S_CHEB1) {
-                    w0 = cA * (2.0f * c[r].a - a0 / cB);
-                    w1 = cA * (2.0f * c[r].b - a1 / cB);
-                    store_pair_nt(v32 + idx, c[r].a, c[r].b, ok0, ok1, vec);
-                } else if constexpr (OP == S_CHEB2) {
-                    const float z0 = o0[r].a / cE, z1 = o0[r].b / cE;
-                    w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * z0);
-                    w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * z1);
-                } else {
-                    w0 = cA * ((cC * c[r].a + cD * (o0[r].a - a0)) - cB * o1[r].a);
-                    w1 = cA * ((cC * c[r].b + cD * (o0[r].b - a1)) - cB * o1[r].b);
-                }
-                store_pair_nt(out + idx, w0, w1, ok0, ok1, vec);
-            }
-#pragma unroll
-            for (int r = 0; r < RH; ++r) {
-                zm[r] = c[r];
-                c[r] = zr[r];
-            }
-        }
+        // one wave-uniform branch per tile; each body is straight-line in its plane loop
+        const int tix = local % P.tx, tiy = (local / P.tx) % P.ty;
+        const bool full = tix * TX + TX <= P.nx && tiy * (TY * RY) + wv * RY + RY <= P.ny;
+        const bool simple = !MASK && P.bc == 0;
+        if (P.nx & 1) cheb_f32x2_tile<OP, TU, MASK, false, false, false>(P, A, local, lane, wv);
+        else if (!full) cheb_f32x2_tile<OP, TU, MASK, true, false, false>(P, A, local, lane, wv);
+        else if (simple) cheb_f32x2_tile<OP, TU, MASK, true, true, !MASK>(P, A, local, lane, wv);
+        else cheb_f32x2_tile<OP, TU, MASK, true, true, false>(P, A, local, lane, wv);
     }
 }
 
@@ -816,14 +893,245 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 // w_{i+1}: 40 bytes per point instead of 64 for the two separate steps. The
 // arithmetic per point is exactly that of two k_stencil steps.
 // ------------------------------------------------------------------------
-template <bool MASK, bool FZ>
-__global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
+// One tile of the fused pair. FULL: the tile's 64 columns and the wave's rows
+// j0-2 .. j0+RY+1 are inside the grid, so the row and column guards are
+// compile-time true; plane validity is wave-uniform and every load reads a
+// clamped (valid) address whose value a select then keeps or zeroes, so no
+// load sits in a branch of its own.
+template <bool MASK, bool FZ, bool FULL, bool SIMPLE>
+__device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, int local, int lane,
+                                               int wv)
 {
     constexpr int RYY = RY + 4; // y rows j0-2 .. j0+RY+1
     constexpr int RW = RY + 2;  // w_i rows j0-1 .. j0+RY
+    const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
+    const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
+    const int i0 = tix * TX, i = i0 + lane;
+    const int j0 = tiy * (TY * RY) + wv * RY;
+    const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
+    if (j0 >= ny) return; // uniform within the wave; no barriers below
+
+    // Addresses: a wave-uniform plane base plus a per-lane 32-bit byte offset
+    // inside the plane (the host uses this kernel only for planes below 2 GiB).
+    const size_t PB = (size_t)nx * (size_t)ny * sizeof(double);
+    const int B = MASK ? P.block : 1;
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    const bool xin = FULL || i < nx;
+    const int ic = xin ? i : nx - 1; // clamped column
+    const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
+    const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
+    const char *Yb = (const char *)P.vec[A.in];
+    const char *Vb = (const char *)P.vec[A.v];
+    const char *Zb = (const char *)P.vec[A.z];
+    char *W1b = (char *)P.vec[A.out];
+    char *W2b = (char *)P.vec[A.x2];
+    const double ih2 = P.ih2, theta = P.theta, ts = P.two_sigma, tod = P.two_over_delta;
+    const double rc1 = P.rc[A.step], ro1 = P.ro[A.step];
+    const double rc2 = P.rc[A.step + 1], ro2 = P.ro[A.step + 1];
+    auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
+    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(double); };
+    auto ld = [](const char *plane, unsigned o) { return ld_g((const double *)(plane + o)); };
+    auto ldn = [](const char *plane, unsigned o) { return ld_nt((const double *)(plane + o)); };
+
+    // rows: Y row q is j0-2+q, w row q is j0-1+q
+    bool yok[RYY], wok[RW];
+    unsigned yoff[RYY], woff[RW];
+    Sel wsym[RW], wsyp[RW];
+#pragma unroll
+    for (int q = 0; q < RYY; ++q) {
+        const int j = j0 - 2 + q;
+        yok[q] = FULL || (xin && j >= 0 && j < ny);
+        yoff[q] = off(ic, FULL ? j : clampi(j, ny));
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        const int j = j0 - 1 + q;
+        wok[q] = FULL || (xin && j >= 0 && j < ny);
+        woff[q] = off(ic, FULL ? j : clampi(j, ny));
+        wsym[q] = to_sel(wok[q] ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        wsyp[q] = to_sel(wok[q] ? sel_hi(j, ny, MASK, B, nyh) : 0);
+    }
+    // x halo of y for the w_i rows: lane q < RW the left, lane 32+q the right
+    const int hq = lane & 31;
+    const int hj = j0 - 1 + hq;
+    const bool hload = hq < RW && hj >= 0 && hj < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
+    const unsigned hoff = hload ? off(lane < 32 ? i0 - 1 : i0 + TX, hj) : 0u;
+    // halo-column w_i (lanes 0..2RY-1): side = lane / RY, row j0 + lane % RY
+    const int cside = (lane / RY) & 1, crow = j0 + (lane % RY);
+    const int cx = cside ? i0 + TX : i0 - 1;
+    const bool cact = lane < 2 * RY && cx >= 0 && cx < nx && crow < ny;
+    // its neighbour coordinates, clamped, with validity (zero outside the grid)
+    const int cx0 = clampi(cx - 1, nx), cx1 = clampi(cx, nx), cx2 = clampi(cx + 1, nx);
+    const int cj0 = clampi(crow - 1, ny), cj1 = clampi(crow, ny), cj2 = clampi(crow + 1, ny);
+    const bool xv0 = cx - 1 >= 0 && cx - 1 < nx, xv1 = cx >= 0 && cx < nx;
+    const bool xv2 = cx + 1 >= 0 && cx + 1 < nx;
+    const bool jv0 = crow - 1 >= 0 && crow - 1 < ny, jv1 = crow < ny, jv2 = crow + 1 < ny;
+    const unsigned oc = off(cx1, cj1), ol = off(cx0, cj1), orr = off(cx2, cj1);
+    const unsigned od = off(cx1, cj0), ou = off(cx1, cj2);
+    const Sel csxl = to_sel(sel_lo(cx1, nx, MASK, B, nxl));
+    const Sel csxh = to_sel(sel_hi(cx1, nx, MASK, B, nxh));
+    const Sel csyl = to_sel(sel_lo(cj1, ny, MASK, B, nyl));
+    const Sel csyh = to_sel(sel_hi(cj1, ny, MASK, B, nyh));
+
+    // Y at plane p for all RYY rows (zero outside the grid)
+    auto loadY = [&](int p, double (&dst)[RYY]) {
+        const bool pin = p >= 0 && p < nz;
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
+#pragma unroll
+        for (int q = 0; q < RYY; ++q) {
+            const double v = ld(Yp, yoff[q]);
+            dst[q] = (pin && yok[q]) ? v : 0.0;
+        }
+    };
+    // w_i at one point from its 7 y values, v and z (the k_stencil step)
+    auto step1 = [&](double yc, double xm, double xp, double ym, double yp, double zm,
+                     double zp, double v, double z) {
+        const double a = ((((((6.0 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
+    };
+    // w_i at plane p for the RW rows, from Y planes p-1 (ya), p (yb), p+1 (yc);
+    // vout gets v on the RY output rows (w rows 1..RY)
+    auto planeW = [&](int p, const double (&ya)[RYY], const double (&yb)[RYY],
+                      const double (&yc)[RYY], double (&dst)[RW], double (&vout)[RY]) {
+        const bool pin = p >= 0 && p < nz;
+        const size_t po = (size_t)clampi(p, nz) * PB;
+        const Sel szm = to_sel(pin ? sel_lo(p, nz, MASK, B, nzl) : 0);
+        const Sel szp = to_sel(pin ? sel_hi(p, nz, MASK, B, nzh) : 0);
+        double vv[RW], zz[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const bool ok = pin && wok[q];
+            const double v = ldn(Vb + po, woff[q]);
+            vv[q] = ok ? v : 0.0;
+            if constexpr (!FZ) {
+                const double zv = ldn(Zb + po, woff[q]);
+                zz[q] = ok ? zv : 0.0;
+            }
+        }
+        const double hv = ld(Yb + po, hoff);
+        const double he = (hload && pin) ? hv : 0.0;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            // the DPP shifts run in every lane (a shift reads its source lane)
+            const double pv = lane_prev(yb[q + 1]), nv = lane_next(yb[q + 1]);
+            const double el = read_lane(he, q), er = read_lane(he, 32 + q);
+            const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+            const double c = yb[q + 1];
+            double xm, xp, ym, yp, zm, zp;
+            if constexpr (SIMPLE) {
+                xm = xl, xp = xr, ym = yb[q], yp = yb[q + 2], zm = ya[q + 1], zp = yc[q + 1];
+            } else {
+                xm = pick(sxm, xl, xr), xp = pick(sxp, xr, xl);
+                ym = pick(wsym[q], yb[q], yb[q + 2]), yp = pick(wsyp[q], yb[q + 2], yb[q]);
+                zm = pick(szm, ya[q + 1], yc[q + 1]), zp = pick(szp, yc[q + 1], ya[q + 1]);
+            }
+            const double z = FZ ? vv[q] / theta : zz[q];
+            const double w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
+            dst[q] = (pin && wok[q]) ? w : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) vout[r] = vv[r + 1];
+    };
+    // w_i at the lane's halo-column point (cx, crow, p) from direct loads
+    auto pointW = [&](int p) {
+        const bool pv0 = p - 1 >= 0 && p - 1 < nz, pv1 = p >= 0 && p < nz;
+        const bool pv2 = p + 1 >= 0 && p + 1 < nz;
+        const int p1 = clampi(p, nz);
+        const char *Y0 = Yb + (size_t)clampi(p - 1, nz) * PB, *Y1 = Yb + (size_t)p1 * PB;
+        const char *Y2 = Yb + (size_t)clampi(p + 1, nz) * PB;
+        const double c0 = ld(Y1, oc), l0 = ld(Y1, ol), r0 = ld(Y1, orr);
+        const double d0 = ld(Y1, od), u0 = ld(Y1, ou);
+        const double b0 = ld(Y0, oc), f0 = ld(Y2, oc);
+        const double v0 = ld(Vb + (size_t)p1 * PB, oc);
+        double z0 = 0.0;
+        if constexpr (!FZ) z0 = ld(Zb + (size_t)p1 * PB, oc);
+        const bool cen = xv1 && jv1;
+        const double c = (cen && pv1) ? c0 : 0.0;
+        const double l = (xv0 && jv1 && pv1) ? l0 : 0.0;
+        const double r = (xv2 && jv1 && pv1) ? r0 : 0.0;
+        const double d = (xv1 && jv0 && pv1) ? d0 : 0.0;
+        const double u = (xv1 && jv2 && pv1) ? u0 : 0.0;
+        const double b = (cen && pv0) ? b0 : 0.0;
+        const double f = (cen && pv2) ? f0 : 0.0;
+        const Sel szl = to_sel(sel_lo(p1, nz, MASK, B, nzl));
+        const Sel szh = to_sel(sel_hi(p1, nz, MASK, B, nzh));
+        double xm, xp, ym, yp, zm, zp;
+        if constexpr (SIMPLE) {
+            xm = l, xp = r, ym = d, yp = u, zm = b, zp = f;
+        } else {
+            xm = pick(csxl, l, r), xp = pick(csxh, r, l);
+            ym = pick(csyl, d, u), yp = pick(csyh, u, d);
+            zm = pick(szl, b, f), zp = pick(szh, f, b);
+        }
+        const double z = FZ ? v0 / theta : z0;
+        const double w = step1(c, xm, xp, ym, yp, zm, zp, v0, z);
+        return (cact && pv1) ? w : 0.0;
+    };
+
+    // ya keeps the rows planeW and the second step read (1 .. RW), wa the
+    // output rows' w_i (1 .. RY); yb, yc, wb, wc are full
+    double ya[RYY], yb[RYY], yc[RYY];
+    double wa[RW], wb[RW], wc[RW], vb[RY], vc[RY];
+    loadY(k0 - 2, ya);
+    loadY(k0 - 1, yb);
+#pragma unroll
+    for (int q = 0; q < RW; ++q) wa[q] = wb[q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) vb[r] = 0.0;
+    for (int k = k0 - 2; k < k1; ++k) {
+        loadY(k + 2, yc);
+        planeW(k + 1, ya, yb, yc, wc, vc);
+        if (k >= k0) {
+            // w_{i+1} at plane k from w_i at planes k-1 (wa), k (wb), k+1 (wc)
+            const double hw = pointW(k);
+            const Sel szm = to_sel(sel_lo(k, nz, MASK, B, nzl));
+            const Sel szp = to_sel(sel_hi(k, nz, MASK, B, nzh));
+            const size_t po = (size_t)k * PB;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int q = r + 1; // w row of output row j0 + r
+                const double pv = lane_prev(wb[q]), nv = lane_next(wb[q]);
+                const double el = read_lane(hw, r), er = read_lane(hw, RY + r);
+                const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+                const double c = wb[q];
+                double xm, xp, ym, yp, zm, zp;
+                if constexpr (SIMPLE) {
+                    xm = xl, xp = xr, ym = wb[q - 1], yp = wb[q + 1], zm = wa[q], zp = wc[q];
+                } else {
+                    xm = pick(sxm, xl, xr), xp = pick(sxp, xr, xl);
+                    ym = pick(wsym[q], wb[q - 1], wb[q + 1]), yp = pick(wsyp[q], wb[q + 1], wb[q - 1]);
+                    zm = pick(szm, wa[q], wc[q]), zp = pick(szp, wc[q], wa[q]);
+                }
+                const double a = ((((((6.0 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                const double w2 = rc2 * ((ts * c + tod * (vb[r] - a)) - ro2 * ya[q + 1]);
+                if (wok[q]) {
+                    st_nt((double *)(W1b + po + woff[q]), c);
+                    st_nt((double *)(W2b + po + woff[q]), w2);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RYY; ++q) {
+            ya[q] = yb[q];
+            yb[q] = yc[q];
+        }
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            wa[q] = wb[q];
+            wb[q] = wc[q];
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) vb[r] = vc[r];
+    }
+}
+
+template <bool MASK, bool FZ>
+__global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
+{
     const int total = W.count_dev ? *W.count_dev : W.count;
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
-
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
@@ -832,188 +1140,127 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
-        const int nx = P.nx, ny = P.ny, nz = P.nz, tx = P.tx, ty = P.ty;
-        const int tix = local % tx, tiy = (local / tx) % ty, tiz = local / (tx * ty);
-        const int i0 = tix * TX, i = i0 + lane;
+        // one wave-uniform branch per tile
+        const int tix = local % P.tx, tiy = (local / P.tx) % P.ty;
         const int j0 = tiy * (TY * RY) + wv * RY;
-        const int k0 = tiz * P.kz, k1 = min(k0 + P.kz, nz);
-        if (j0 >= ny) continue; // uniform within the wave; no barriers below
-
-        const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
-        const int B = MASK ? P.block : 1;
-        const unsigned bc = P.bc;
-        const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
-        const bool nzl = bc & 16u, nzh = bc & 32u;
-        const bool xin = i < nx;
-        const int sxm = xin ? sel_lo(i, nx, MASK, B, nxl) : 0;
-        const int sxp = xin ? sel_hi(i, nx, MASK, B, nxh) : 0;
-        const double *__restrict__ Y = (const double *)P.vec[A.in];
-        const double *__restrict__ V = (const double *)P.vec[A.v];
-        const double *__restrict__ Z = (const double *)P.vec[A.z];
-        double *W1 = (double *)P.vec[A.out];
-        double *W2 = (double *)P.vec[A.x2];
-        const double ih2 = P.ih2, theta = P.theta, ts = P.two_sigma, tod = P.two_over_delta;
-        const double rc1 = P.rc[A.step], ro1 = P.ro[A.step];
-        const double rc2 = P.rc[A.step + 1], ro2 = P.ro[A.step + 1];
-
-        // rows: Y row q is j0-2+q, w row q is j0-1+q
-        bool yok[RYY], wok[RW];
-        int wsym[RW], wsyp[RW];
-#pragma unroll
-        for (int q = 0; q < RYY; ++q) {
-            const int j = j0 - 2 + q;
-            yok[q] = xin && j >= 0 && j < ny;
+        const bool full = tix * TX + TX <= P.nx && j0 - 2 >= 0 && j0 + RY + 1 < P.ny;
+        if constexpr (MASK) {
+            if (full) cheb_pair_tile<true, FZ, true, false>(P, A, local, lane, wv);
+            else cheb_pair_tile<true, FZ, false, false>(P, A, local, lane, wv);
+        } else if (P.bc == 0) {
+            if (full) cheb_pair_tile<false, FZ, true, true>(P, A, local, lane, wv);
+            else cheb_pair_tile<false, FZ, false, true>(P, A, local, lane, wv);
+        } else {
+            if (full) cheb_pair_tile<false, FZ, true, false>(P, A, local, lane, wv);
+            else cheb_pair_tile<false, FZ, false, false>(P, A, local, lane, wv);
         }
-#pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            const int j = j0 - 1 + q;
-            wok[q] = xin && j >= 0 && j < ny;
-            wsym[q] = wok[q] ? sel_lo(j, ny, MASK, B, nyl) : 0;
-            wsyp[q] = wok[q] ? sel_hi(j, ny, MASK, B, nyh) : 0;
-        }
-        // x halo of y for the w_i rows: lane q < RW the left, lane 32+q the right
-        const int hq = lane & 31;
-        const int hj = j0 - 1 + hq;
-        const bool hload = hq < RW && hj >= 0 && hj < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
-        const size_t hcol = (size_t)(lane < 32 ? i0 - 1 : i0 + TX);
-        // halo-column w_i (lanes 0..2RY-1): side = lane / RY, row j0 + lane % RY
-        const int cside = lane / RY, crow = j0 + (lane % RY);
-        const int cx = cside ? i0 + TX : i0 - 1;
-        const bool cact = lane < 2 * RY && cx >= 0 && cx < nx && crow < ny;
+    }
+}
 
-        // Y at plane p for all RYY rows (zero outside the grid)
-        auto loadY = [&](int p, double (&dst)[RYY]) {
+// One tile of an elementwise pass for the lanes inside the grid (i < nx);
+// FULL: all RY rows of the wave are inside, so no row guard remains and the
+// loads of a plane issue together.
+template <int OP, typename TP, bool FULL>
+__device__ __forceinline__ void elem_tile(const Prob &P, const KArgs &A, const Scalars *sc,
+                                          bool half, int i, int j0, int k0, int k1,
+                                          double (&hi)[2], double (&lo)[2])
+{
+    const int nx = P.nx, ny = P.ny;
+    const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
+    size_t base = (size_t)i + NXs * ((size_t)j0 + (size_t)ny * (size_t)k0);
+    bool rin[RY];
 #pragma unroll
-            for (int q = 0; q < RYY; ++q) {
-                const int j = j0 - 2 + q;
-                const bool ok = yok[q] && p >= 0 && p < nz;
-                const double v =
-                    ld_g(Y + (ok ? (size_t)i + NXs * ((size_t)j + (size_t)ny * (size_t)p) : 0));
-                dst[q] = ok ? v : 0.0;
-            }
-        };
-        // w_i at one point from its 7 y values, v and z (the k_stencil step)
-        auto step1 = [&](double yc, double xm, double xp, double ym, double yp, double zm,
-                         double zp, double v, double z) {
-            const double a = ((((((6.0 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-            return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
-        };
-        // w_i at plane p for the RW rows, from Y planes p-1 (ya), p (yb), p+1 (yc)
-        auto planeW = [&](int p, const double (&ya)[RYY], const double (&yb)[RYY],
-                          const double (&yc)[RYY], double (&dst)[RW], double (&vout)[RW]) {
-            const bool pin = p >= 0 && p < nz;
-            const int szm = pin ? sel_lo(p, nz, MASK, B, nzl) : 0;
-            const int szp = pin ? sel_hi(p, nz, MASK, B, nzh) : 0;
-            double vv[RW], zz[RW];
+    for (int r = 0; r < RY; ++r) rin[r] = FULL || j0 + r < ny;
+    const double alpha = sc->alpha, omega = sc->omega, beta = sc->beta;
+    for (int k = k0; k < k1; ++k, base += S) {
+        if constexpr (OP == E_AXPY) {
+            double *r_ = (double *)P.vec[V_R];
+            const double *__restrict__ w = (const double *)P.vec[V_W];
+            double a[RY], b[RY];
 #pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const bool ok = pin && wok[q];
-                const size_t idx =
-                    ok ? (size_t)i + NXs * ((size_t)(j0 - 1 + q) + (size_t)ny * (size_t)p) : 0;
-                const double v = ld_nt(V + idx);
-                vv[q] = ok ? v : 0.0;
-                if constexpr (!FZ) {
-                    const double zv = ld_nt(Z + idx);
-                    zz[q] = ok ? zv : 0.0;
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) { a[r] = ld_nt(r_ + base + r * NXs); b[r] = ld_nt(w + base + r * NXs); }
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) {
+                    const double s = a[r] - alpha * b[r];
+                    st_nt(r_ + base + r * NXs, s);
+                    dd_acc(hi[0], lo[0], s, s);
                 }
-            }
-            const bool hok = hload && pin;
-            const double hv =
-                ld_g(Y + (hok ? hcol + NXs * ((size_t)hj + (size_t)ny * (size_t)p) : 0));
-            const double he = hok ? hv : 0.0;
+        } else if constexpr (OP == E_UPD) {
+            double *x = (double *)P.vec[V_X];
+            const TP *ph = (const TP *)P.vec[A.in];
+            const TP *sh = (const TP *)P.vec[A.x2];
+            double *r_ = (double *)P.vec[V_R];
+            const double *__restrict__ tv = (const double *)P.vec[V_T];
+            const double *__restrict__ rt = (const double *)P.vec[V_RT];
+            double xv[RY], pv[RY];
 #pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                double xl = lane_prev(yb[q + 1]), xr = lane_next(yb[q + 1]);
-                const double el = read_lane(he, q), er = read_lane(he, 32 + q);
-                if (lane == 0) xl = el;
-                if (lane == TX - 1) xr = er;
-                const double c = yb[q + 1];
-                const double xm = sxm == 1 ? xl : sxm == 2 ? xr : 0.0;
-                const double xp = sxp == 1 ? xr : sxp == 2 ? xl : 0.0;
-                const double ym = wsym[q] == 1 ? yb[q] : wsym[q] == 2 ? yb[q + 2] : 0.0;
-                const double yp = wsyp[q] == 1 ? yb[q + 2] : wsyp[q] == 2 ? yb[q] : 0.0;
-                const double zm = szm == 1 ? ya[q + 1] : szm == 2 ? yc[q + 1] : 0.0;
-                const double zp = szp == 1 ? yc[q + 1] : szp == 2 ? ya[q + 1] : 0.0;
-                const double z = FZ ? vv[q] / theta : zz[q];
-                dst[q] = (pin && wok[q]) ? step1(c, xm, xp, ym, yp, zm, zp, vv[q], z) : 0.0;
-                vout[q] = vv[q];
-            }
-        };
-        // Y value at (x, j, p) along the halo column, 0 outside the grid
-        auto yat = [&](int x, int j, int p) {
-            return (x >= 0 && x < nx && j >= 0 && j < ny && p >= 0 && p < nz)
-                       ? ld_g(Y + (size_t)x + NXs * ((size_t)j + (size_t)ny * (size_t)p))
-                       : 0.0;
-        };
-        // w_i at a halo-column point (x, j, p) from direct loads (same selections)
-        auto pointW = [&](int x, int j, int p) {
-            const int sxl = sel_lo(x, nx, MASK, B, nxl), sxh = sel_hi(x, nx, MASK, B, nxh);
-            const int syl = sel_lo(j, ny, MASK, B, nyl), syh = sel_hi(j, ny, MASK, B, nyh);
-            const int szl = sel_lo(p, nz, MASK, B, nzl), szh = sel_hi(p, nz, MASK, B, nzh);
-            const double c = yat(x, j, p);
-            const double l = yat(x - 1, j, p), r = yat(x + 1, j, p);
-            const double d = yat(x, j - 1, p), u = yat(x, j + 1, p);
-            const double b = yat(x, j, p - 1), f = yat(x, j, p + 1);
-            const double xm = sxl == 1 ? l : sxl == 2 ? r : 0.0;
-            const double xp = sxh == 1 ? r : sxh == 2 ? l : 0.0;
-            const double ym = syl == 1 ? d : syl == 2 ? u : 0.0;
-            const double yp = syh == 1 ? u : syh == 2 ? d : 0.0;
-            const double zm = szl == 1 ? b : szl == 2 ? f : 0.0;
-            const double zp = szh == 1 ? f : szh == 2 ? b : 0.0;
-            const size_t idx = (size_t)x + NXs * ((size_t)j + (size_t)ny * (size_t)p);
-            const double v = ld_g(V + idx);
-            const double z = FZ ? v / theta : ld_g(Z + idx);
-            return step1(c, xm, xp, ym, yp, zm, zp, v, z);
-        };
-
-        double ya[RYY], yb[RYY], yc[RYY];
-        double wa[RW], wb[RW], wc[RW], vb[RW], vc[RW];
-        loadY(k0 - 2, ya);
-        loadY(k0 - 1, yb);
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) { xv[r] = ld_nt(x + base + r * NXs); pv[r] = (double)ld_nt(ph + base + r * NXs); }
+            if (half) {
 #pragma unroll
-        for (int q = 0; q < RW; ++q) wa[q] = wb[q] = vb[q] = 0.0;
-        for (int k = k0 - 2; k < k1; ++k) {
-            loadY(k + 2, yc);
-            planeW(k + 1, ya, yb, yc, wc, vc);
-            if (k >= k0) {
-                // w_{i+1} at plane k from w_i at planes k-1 (wa), k (wb), k+1 (wc)
-                const double hw = (cact) ? pointW(cx, crow, k) : 0.0;
-                const int szm = sel_lo(k, nz, MASK, B, nzl), szp = sel_hi(k, nz, MASK, B, nzh);
+                for (int r = 0; r < RY; ++r)
+                    if (rin[r]) st_nt(x + base + r * NXs, xv[r] + alpha * pv[r]);
+            } else {
+                double sv[RY], shv[RY], tt[RY], rtv[RY];
 #pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    const int q = r + 1; // w row of output row j0 + r
-                    double xl = lane_prev(wb[q]), xr = lane_next(wb[q]);
-                    const double el = read_lane(hw, r), er = read_lane(hw, RY + r);
-                    if (lane == 0) xl = el;
-                    if (lane == TX - 1) xr = er;
-                    const double c = wb[q];
-                    const double xm = sxm == 1 ? xl : sxm == 2 ? xr : 0.0;
-                    const double xp = sxp == 1 ? xr : sxp == 2 ? xl : 0.0;
-                    const double ym = wsym[q] == 1 ? wb[q - 1] : wsym[q] == 2 ? wb[q + 1] : 0.0;
-                    const double yp = wsyp[q] == 1 ? wb[q + 1] : wsyp[q] == 2 ? wb[q - 1] : 0.0;
-                    const double zm = szm == 1 ? wa[q] : szm == 2 ? wc[q] : 0.0;
-                    const double zp = szp == 1 ? wc[q] : szp == 2 ? wa[q] : 0.0;
-                    const double a = ((((((6.0 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-                    const double w2 = rc2 * ((ts * c + tod * (vb[q] - a)) - ro2 * ya[q + 1]);
-                    if (wok[q]) {
-                        const size_t idx =
-                            (size_t)i + NXs * ((size_t)(j0 + r) + (size_t)ny * (size_t)k);
-                        st_nt(W1 + idx, c);
-                        st_nt(W2 + idx, w2);
+                for (int r = 0; r < RY; ++r)
+                    if (rin[r]) {
+                        const size_t idx = base + r * NXs;
+                        sv[r] = ld_nt(r_ + idx);
+                        shv[r] = (double)ld_nt(sh + idx);
+                        tt[r] = ld_nt(tv + idx);
+                        rtv[r] = ld_nt(rt + idx);
                     }
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+                    if (rin[r]) {
+                        const size_t idx = base + r * NXs;
+                        st_nt(x + idx, (xv[r] + alpha * pv[r]) + omega * shv[r]);
+                        const double rn = sv[r] - omega * tt[r];
+                        st_nt(r_ + idx, rn);
+                        dd_acc(hi[0], lo[0], rtv[r], rn);
+                        dd_acc(hi[1], lo[1], rn, rn);
+                    }
+            }
+        } else if constexpr (OP == E_PUPD) {
+            double *p = (double *)P.vec[V_P];
+            const double *__restrict__ r_ = (const double *)P.vec[V_R];
+            const double *__restrict__ w = (const double *)P.vec[V_W];
+            double a[RY], b[RY], c[RY];
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) {
+                    const size_t idx = base + r * NXs;
+                    a[r] = ld_nt(r_ + idx);
+                    b[r] = ld_nt(p + idx);
+                    c[r] = ld_nt(w + idx);
                 }
-            }
 #pragma unroll
-            for (int q = 0; q < RYY; ++q) {
-                ya[q] = yb[q];
-                yb[q] = yc[q];
-            }
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) st_nt(p + base + r * NXs, a[r] + beta * (b[r] - omega * c[r]));
+        } else if constexpr (OP == E_DIV) {
+            const double *__restrict__ v = (const double *)P.vec[A.in];
+            TP *out = (TP *)P.vec[A.out];
+            const TP d = A.divisor ? Coef<TP>::theta(P) : Coef<TP>::jac(P);
+            double a[RY];
 #pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                wa[q] = wb[q];
-                wb[q] = wc[q];
-                vb[q] = vc[q];
-            }
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) a[r] = ld_nt(v + base + r * NXs);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) st_nt(out + base + r * NXs, (TP)a[r] / d);
+        } else if constexpr (OP == E_DOT) {
+            const double *__restrict__ xv = (const double *)P.vec[A.in];
+            const double *__restrict__ yv = (const double *)P.vec[A.x2];
+            double a[RY], b[RY];
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) { a[r] = ld_nt(xv + base + r * NXs); b[r] = ld_nt(yv + base + r * NXs); }
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (rin[r]) dd_acc(hi[0], lo[0], a[r], b[r]);
         }
     }
 }
@@ -1052,103 +1299,11 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
         for (int d = 0; d < NA; ++d) hi[d] = lo[d] = 0.0;
 
         if (j0 < ny && i < nx) {
-            const size_t S = (size_t)nx * (size_t)ny, NXs = (size_t)nx;
-            size_t base = (size_t)i + NXs * ((size_t)j0 + (size_t)ny * (size_t)k0);
-            bool rin[RY];
+            double h2[2] = {0.0, 0.0}, l2[2] = {0.0, 0.0};
+            if (j0 + RY <= ny) elem_tile<OP, TP, true>(P, A, sc, half, i, j0, k0, k1, h2, l2);
+            else elem_tile<OP, TP, false>(P, A, sc, half, i, j0, k0, k1, h2, l2);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) rin[r] = j0 + r < ny;
-            const double alpha = sc->alpha, omega = sc->omega, beta = sc->beta;
-            for (int k = k0; k < k1; ++k, base += S) {
-                if constexpr (OP == E_AXPY) {
-                    double *r_ = (double *)P.vec[V_R];
-                    const double *__restrict__ w = (const double *)P.vec[V_W];
-                    double a[RY], b[RY];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) { a[r] = ld_nt(r_ + base + r * NXs); b[r] = ld_nt(w + base + r * NXs); }
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) {
-                            const double s = a[r] - alpha * b[r];
-                            st_nt(r_ + base + r * NXs, s);
-                            dd_acc(hi[0], lo[0], s, s);
-                        }
-                } else if constexpr (OP == E_UPD) {
-                    double *x = (double *)P.vec[V_X];
-                    const TP *ph = (const TP *)P.vec[A.in];
-                    const TP *sh = (const TP *)P.vec[A.x2];
-                    double *r_ = (double *)P.vec[V_R];
-                    const double *__restrict__ tv = (const double *)P.vec[V_T];
-                    const double *__restrict__ rt = (const double *)P.vec[V_RT];
-                    double xv[RY], pv[RY];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) { xv[r] = ld_nt(x + base + r * NXs); pv[r] = (double)ld_nt(ph + base + r * NXs); }
-                    if (half) {
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-                            if (rin[r]) st_nt(x + base + r * NXs, xv[r] + alpha * pv[r]);
-                    } else {
-                        double sv[RY], shv[RY], tt[RY], rtv[RY];
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-                            if (rin[r]) {
-                                const size_t idx = base + r * NXs;
-                                sv[r] = ld_nt(r_ + idx);
-                                shv[r] = (double)ld_nt(sh + idx);
-                                tt[r] = ld_nt(tv + idx);
-                                rtv[r] = ld_nt(rt + idx);
-                            }
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-                            if (rin[r]) {
-                                const size_t idx = base + r * NXs;
-                                st_nt(x + idx, (xv[r] + alpha * pv[r]) + omega * shv[r]);
-                                const double rn = sv[r] - omega * tt[r];
-                                st_nt(r_ + idx, rn);
-                                dd_acc(hi[0], lo[0], rtv[r], rn);
-                                dd_acc(hi[1], lo[1], rn, rn);
-                            }
-                    }
-                } else if constexpr (OP == E_PUPD) {
-                    double *p = (double *)P.vec[V_P];
-                    const double *__restrict__ r_ = (const double *)P.vec[V_R];
-                    const double *__restrict__ w = (const double *)P.vec[V_W];
-                    double a[RY], b[RY], c[RY];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) {
-                            const size_t idx = base + r * NXs;
-                            a[r] = ld_nt(r_ + idx);
-                            b[r] = ld_nt(p + idx);
-                            c[r] = ld_nt(w + idx);
-                        }
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) st_nt(p + base + r * NXs, a[r] + beta * (b[r] - omega * c[r]));
-                } else if constexpr (OP == E_DIV) {
-                    const double *__restrict__ v = (const double *)P.vec[A.in];
-                    TP *out = (TP *)P.vec[A.out];
-                    const TP d = A.divisor ? Coef<TP>::theta(P) : Coef<TP>::jac(P);
-                    double a[RY];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) a[r] = ld_nt(v + base + r * NXs);
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) st_nt(out + base + r * NXs, (TP)a[r] / d);
-                } else if constexpr (OP == E_DOT) {
-                    const double *__restrict__ xv = (const double *)P.vec[A.in];
-                    const double *__restrict__ yv = (const double *)P.vec[A.x2];
-                    double a[RY], b[RY];
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) { a[r] = ld_nt(xv + base + r * NXs); b[r] = ld_nt(yv + base + r * NXs); }
-#pragma unroll
-                    for (int r = 0; r < RY; ++r)
-                        if (rin[r]) dd_acc(hi[0], lo[0], a[r], b[r]);
-                }
-            }
+            for (int d = 0; d < NA; ++d) hi[d] = h2[d], lo[d] = l2[d];
         }
         if constexpr (ND > 0) {
             double res[NA];

@@ -450,6 +450,7 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
 {
     if (!s || !ticket || !rhs || !x) return POISSON_ERR_ARG;
     if (nx < 1 || ny < 1 || nz < 1 || (double)nx * ny * nz > 17179869184.0) return POISSON_ERR_ARG;
+    if ((double)nx * ny >= 268435456.0) return POISSON_ERR_ARG; // plane offsets are 32-bit
     if (!(h > 0) || !std::isfinite(h)) return POISSON_ERR_ARG;
     const int rcb = check_bc(nx, ny, nz, bc);
     if (rcb != POISSON_OK) return rcb;

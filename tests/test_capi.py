@@ -39,7 +39,8 @@ def test_create_validation():
     L = P.lib()
     ctx = ctypes.c_void_p()
     for args in [(0, 4, 4, 0.1), (4, -1, 4, 0.1), (4, 4, 4, 0.0), (4, 4, 4, -1.0),
-                 (4, 4, 4, float("nan")), (4, 4, 4, float("inf")), (1 << 13, 1 << 13, 1 << 13, 0.1)]:
+                 (4, 4, 4, float("nan")), (4, 4, 4, float("inf")), (1 << 13, 1 << 13, 1 << 13, 0.1),
+                 (1 << 14, 1 << 14, 2, 0.1)]:
         assert L.poisson_create(*args, 0, ctypes.byref(ctx)) == P.ERR_ARG
         assert not ctx.value
     # Neumann on every face is singular; a mask above 6 bits or a Neumann face on a

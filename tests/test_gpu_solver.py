@@ -166,3 +166,35 @@ def test_kernel_bench_entry_points(gpu):
         assert torch.equal(x, x0)  # the caller's solution is never touched
         with pytest.raises(P.PoissonError):
             s.kernel_bench(P.KERNEL_CHEB_STEP, P.MIXED, 1)  # plan is FP64
+
+
+INTERIOR = [
+    dict(pc=P.PC_CHEBYSHEV, m=8, bc=0),                   # fused pairs, no selects
+    dict(pc=P.PC_CHEBYSHEV, m=7, bc=0, mixed=True),       # FP32 pairs of points
+    dict(pc=P.PC_BLOCK_JACOBI, m=6, bc=0, block=16),      # block-face mask
+    dict(pc=P.PC_CHEBYSHEV, m=5, bc=2 | 4 | 16),          # Neumann faces: selects kept
+    dict(pc=P.PC_CHEBYSHEV, m=6, bc=1 | 32, mixed=True),
+    dict(pc=P.PC_NONE, m=0, bc=0),
+]
+
+
+@pytest.mark.parametrize("nx", [128, 127])
+@pytest.mark.parametrize("case", INTERIOR, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_interior_tile_paths_parity(gpu, nx, case):
+    """Grids with whole 64-column tiles and interior wave rows, so the kernels'
+    interior bodies (no guards, and without neighbour selects when every face is
+    Dirichlet and there is no block mask) run next to the guarded edge bodies;
+    nx odd takes the unpaired FP32 accesses. Bitwise against the oracle."""
+    shape = (nx, 40, 24)
+    h = 1.0 / 41
+    f = workloads.uniform_grid(21, shape)
+    mixed = case.get("mixed", False)
+    block = case.get("block", 64)
+    st, stats, tr, x = gpu_solve(shape, h, f, case["pc"], case["m"], 1e-9, bc=case["bc"],
+                                 precision=P.MIXED if mixed else P.FP64, block=block)
+    ref = oracle.bicgstab(f, h, pc=oracle_pc(case["pc"]), degree=case["m"], mixed=mixed,
+                          tol=1e-9, block=block, bc=case["bc"])
+    assert st == ref.status == P.OK
+    assert stats["iterations"] == ref.iterations
+    assert np.array_equal(tr[:, 0], ref.alpha) and np.array_equal(tr[:, 2], ref.rho)
+    assert np.array_equal(x, ref.x)
