@@ -888,10 +888,11 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 //   w_{i+1} = rc_{i+1} ((2 sigma w_i + (2/delta)(v - A w_i)) - ro_{i+1} y)
 // with y = y_{i-1} read with the stencil, z = z_{i-2} (or v/theta when i = 2)
 // and v read pointwise. w_i is computed on the wave's rows plus one halo row
-// on each side and one plane ahead of w_{i+1}; its two halo columns are
-// computed by 8 lanes from direct loads. Reads y, z, v once and writes w_i and
-// w_{i+1}: 40 bytes per point instead of 64 for the two separate steps. The
-// arithmetic per point is exactly that of two k_stencil steps.
+// on each side and one plane ahead of w_{i+1}; at its two halo columns it is
+// computed by the halo lanes from the halo values they load anyway plus y one
+// column further out, v and z. Reads y, z, v once and writes w_i and w_{i+1}:
+// 40 bytes per point instead of 64 for the two separate steps. The arithmetic
+// per point is exactly that of two k_stencil steps.
 // ------------------------------------------------------------------------
 // One tile of the fused pair. FULL: the tile's 64 columns and the wave's rows
 // j0-2 .. j0+RY+1 are inside the grid, so the row and column guards are
@@ -933,7 +934,6 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
     auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(double); };
     auto ld = [](const char *plane, unsigned o) { return ld_g((const double *)(plane + o)); };
-    auto ldn = [](const char *plane, unsigned o) { return ld_nt((const double *)(plane + o)); };
 
     // rows: Y row q is j0-2+q, w row q is j0-1+q
     bool yok[RYY], wok[RW];
@@ -958,134 +958,160 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const int hj = j0 - 1 + hq;
     const bool hload = hq < RW && hj >= 0 && hj < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
     const unsigned hoff = hload ? off(lane < 32 ? i0 - 1 : i0 + TX, hj) : 0u;
-    // halo-column w_i (lanes 0..2RY-1): side = lane / RY, row j0 + lane % RY
-    const int cside = (lane / RY) & 1, crow = j0 + (lane % RY);
-    const int cx = cside ? i0 + TX : i0 - 1;
-    const bool cact = lane < 2 * RY && cx >= 0 && cx < nx && crow < ny;
-    // its neighbour coordinates, clamped, with validity (zero outside the grid)
-    const int cx0 = clampi(cx - 1, nx), cx1 = clampi(cx, nx), cx2 = clampi(cx + 1, nx);
-    const int cj0 = clampi(crow - 1, ny), cj1 = clampi(crow, ny), cj2 = clampi(crow + 1, ny);
-    const bool xv0 = cx - 1 >= 0 && cx - 1 < nx, xv1 = cx >= 0 && cx < nx;
-    const bool xv2 = cx + 1 >= 0 && cx + 1 < nx;
-    const bool jv0 = crow - 1 >= 0 && crow - 1 < ny, jv1 = crow < ny, jv2 = crow + 1 < ny;
-    const unsigned oc = off(cx1, cj1), ol = off(cx0, cj1), orr = off(cx2, cj1);
-    const unsigned od = off(cx1, cj0), ou = off(cx1, cj2);
-    const Sel csxl = to_sel(sel_lo(cx1, nx, MASK, B, nxl));
-    const Sel csxh = to_sel(sel_hi(cx1, nx, MASK, B, nxh));
-    const Sel csyl = to_sel(sel_lo(cj1, ny, MASK, B, nyl));
-    const Sel csyh = to_sel(sel_hi(cj1, ny, MASK, B, nyh));
+    // The halo lanes also evaluate w_i at the two halo columns i0-1 and i0+TX:
+    // lane q (1..RY) the left point of row j0+q-1, lane 32+q the right one. For
+    // that the x-halo load above is joined by three more per plane: y one
+    // column further out, v and z, all at the halo column of the lane's row.
+    const bool hside = lane >= 32;
+    const int hcx = hside ? i0 + TX : i0 - 1;       // halo column
+    const int hfx = hside ? i0 + TX + 1 : i0 - 2;   // one further out
+    const bool hrow_ok = hq < RW && hj >= 0 && hj < ny;
+    const bool fload = hrow_ok && hfx >= 0 && hfx < nx;
+    const unsigned foff = fload ? off(hfx, hj) : 0u;
+    const bool cact = hq >= 1 && hq <= RY && hrow_ok && hcx >= 0 && hcx < nx;
+    const unsigned coff = cact ? off(hcx, hj) : 0u;
+    const Sel csxl = to_sel(cact ? sel_lo(hcx, nx, MASK, B, nxl) : 0);
+    const Sel csxh = to_sel(cact ? sel_hi(hcx, nx, MASK, B, nxh) : 0);
+    const Sel csyl = to_sel(cact ? sel_lo(hj, ny, MASK, B, nyl) : 0);
+    const Sel csyh = to_sel(cact ? sel_hi(hj, ny, MASK, B, nyh) : 0);
 
-    // Y at plane p for all RYY rows (zero outside the grid)
-    auto loadY = [&](int p, double (&dst)[RYY]) {
-        const bool pin = p >= 0 && p < nz;
-        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
-#pragma unroll
-        for (int q = 0; q < RYY; ++q) {
-            const double v = ld(Yp, yoff[q]);
-            dst[q] = (pin && yok[q]) ? v : 0.0;
-        }
-    };
     // w_i at one point from its 7 y values, v and z (the k_stencil step)
     auto step1 = [&](double yc, double xm, double xp, double ym, double yp, double zm,
                      double zp, double v, double z) {
         const double a = ((((((6.0 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
         return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
     };
-    // w_i at plane p for the RW rows, from Y planes p-1 (ya), p (yb), p+1 (yc);
-    // vout gets v on the RY output rows (w rows 1..RY)
-    auto planeW = [&](int p, const double (&ya)[RYY], const double (&yb)[RYY],
-                      const double (&yc)[RYY], double (&dst)[RW], double (&vout)[RY]) {
-        const bool pin = p >= 0 && p < nz;
-        const size_t po = (size_t)clampi(p, nz) * PB;
-        const Sel szm = to_sel(pin ? sel_lo(p, nz, MASK, B, nzl) : 0);
-        const Sel szp = to_sel(pin ? sel_hi(p, nz, MASK, B, nzh) : 0);
-        double vv[RW], zz[RW];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            const bool ok = pin && wok[q];
-            const double v = ldn(Vb + po, woff[q]);
-            vv[q] = ok ? v : 0.0;
-            if constexpr (!FZ) {
-                const double zv = ldn(Zb + po, woff[q]);
-                zz[q] = ok ? zv : 0.0;
-            }
-        }
-        const double hv = ld(Yb + po, hoff);
-        const double he = (hload && pin) ? hv : 0.0;
-#pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            // the DPP shifts run in every lane (a shift reads its source lane)
-            const double pv = lane_prev(yb[q + 1]), nv = lane_next(yb[q + 1]);
-            const double el = read_lane(he, q), er = read_lane(he, 32 + q);
-            const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
-            const double c = yb[q + 1];
-            double xm, xp, ym, yp, zm, zp;
-            if constexpr (SIMPLE) {
-                xm = xl, xp = xr, ym = yb[q], yp = yb[q + 2], zm = ya[q + 1], zp = yc[q + 1];
-            } else {
-                xm = pick(sxm, xl, xr), xp = pick(sxp, xr, xl);
-                ym = pick(wsym[q], yb[q], yb[q + 2]), yp = pick(wsyp[q], yb[q + 2], yb[q]);
-                zm = pick(szm, ya[q + 1], yc[q + 1]), zp = pick(szp, yc[q + 1], ya[q + 1]);
-            }
-            const double z = FZ ? vv[q] / theta : zz[q];
-            const double w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
-            dst[q] = (pin && wok[q]) ? w : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < RY; ++r) vout[r] = vv[r + 1];
+    // The plane loop is software-pipelined: iteration k issues the loads of y
+    // at plane k+3 and of v, z and the halo values at plane k+2, and consumes
+    // what iteration k-1 issued. Raw loaded values are kept until their use;
+    // only there are they zeroed outside the grid, so no wait sits between a
+    // load and the next iteration.
+    struct Raw {
+        double y[RYY], v[RW], z[RW], he, hf, hv, hz;
     };
-    // w_i at the lane's halo-column point (cx, crow, p) from direct loads
-    auto pointW = [&](int p) {
-        const bool pv0 = p - 1 >= 0 && p - 1 < nz, pv1 = p >= 0 && p < nz;
-        const bool pv2 = p + 1 >= 0 && p + 1 < nz;
-        const int p1 = clampi(p, nz);
-        const char *Y0 = Yb + (size_t)clampi(p - 1, nz) * PB, *Y1 = Yb + (size_t)p1 * PB;
-        const char *Y2 = Yb + (size_t)clampi(p + 1, nz) * PB;
-        const double c0 = ld(Y1, oc), l0 = ld(Y1, ol), r0 = ld(Y1, orr);
-        const double d0 = ld(Y1, od), u0 = ld(Y1, ou);
-        const double b0 = ld(Y0, oc), f0 = ld(Y2, oc);
-        const double v0 = ld(Vb + (size_t)p1 * PB, oc);
-        double z0 = 0.0;
-        if constexpr (!FZ) z0 = ld(Zb + (size_t)p1 * PB, oc);
-        const bool cen = xv1 && jv1;
-        const double c = (cen && pv1) ? c0 : 0.0;
-        const double l = (xv0 && jv1 && pv1) ? l0 : 0.0;
-        const double r = (xv2 && jv1 && pv1) ? r0 : 0.0;
-        const double d = (xv1 && jv0 && pv1) ? d0 : 0.0;
-        const double u = (xv1 && jv2 && pv1) ? u0 : 0.0;
-        const double b = (cen && pv0) ? b0 : 0.0;
-        const double f = (cen && pv2) ? f0 : 0.0;
-        const Sel szl = to_sel(sel_lo(p1, nz, MASK, B, nzl));
-        const Sel szh = to_sel(sel_hi(p1, nz, MASK, B, nzh));
-        double xm, xp, ym, yp, zm, zp;
-        if constexpr (SIMPLE) {
-            xm = l, xp = r, ym = d, yp = u, zm = b, zp = f;
-        } else {
-            xm = pick(csxl, l, r), xp = pick(csxh, r, l);
-            ym = pick(csyl, d, u), yp = pick(csyh, u, d);
-            zm = pick(szl, b, f), zp = pick(szh, f, b);
+    auto issueY = [&](int p, double (&dst)[RYY]) {
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
+#pragma unroll
+        for (int q = 0; q < RYY; ++q) dst[q] = ld(Yp, yoff[q]);
+    };
+    auto issueP = [&](int p, Raw &R) {
+        const size_t po = (size_t)clampi(p, nz) * PB;
+        // v and z rows are read by three waves (as own and as halo rows), so
+        // they are loaded through the caches, not as a read-once stream
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            R.v[q] = ld(Vb + po, woff[q]);
+            if constexpr (!FZ) R.z[q] = ld(Zb + po, woff[q]);
         }
-        const double z = FZ ? v0 / theta : z0;
-        const double w = step1(c, xm, xp, ym, yp, zm, zp, v0, z);
-        return (cact && pv1) ? w : 0.0;
+        R.he = ld(Yb + po, hoff);
+        R.hf = ld(Yb + po, foff);
+        R.hv = ld(Vb + po, coff);
+        if constexpr (!FZ) R.hz = ld(Zb + po, coff);
+    };
+    auto takeY = [&](int p, const double (&raw)[RYY], double (&dst)[RYY]) {
+        const bool pin = p >= 0 && p < nz;
+#pragma unroll
+        for (int q = 0; q < RYY; ++q) dst[q] = (pin && yok[q]) ? raw[q] : 0.0;
     };
 
-    // ya keeps the rows planeW and the second step read (1 .. RW), wa the
-    // output rows' w_i (1 .. RY); yb, yc, wb, wc are full
     double ya[RYY], yb[RYY], yc[RYY];
     double wa[RW], wb[RW], wc[RW], vb[RY], vc[RY];
-    loadY(k0 - 2, ya);
-    loadY(k0 - 1, yb);
+    // halo values: y at the halo column on planes k-1, k, k+1 (ha, hb, hc), and
+    // at plane k the further column, v and z (hfb, hvb, hzb)
+    double ha = 0.0, hb = 0.0, hc = 0.0, hfb = 0.0, hvb = 0.0, hzb = 0.0;
+    Raw R;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) R.z[q] = 0.0;
+    R.hz = 0.0;
+    {
+        double t[RYY];
+        issueY(k0 - 2, t);
+        takeY(k0 - 2, t, ya);
+        issueY(k0 - 1, t);
+        takeY(k0 - 1, t, yb);
+    }
+    issueY(k0, R.y);
+    issueP(k0 - 1, R);
 #pragma unroll
     for (int q = 0; q < RW; ++q) wa[q] = wb[q] = 0.0;
 #pragma unroll
     for (int r = 0; r < RY; ++r) vb[r] = 0.0;
     for (int k = k0 - 2; k < k1; ++k) {
-        loadY(k + 2, yc);
-        planeW(k + 1, ya, yb, yc, wc, vc);
+        // consume the loads of plane k+2 (y) and k+1 (v, z, halo)
+        const int p = k + 1;
+        const bool pin = p >= 0 && p < nz;
+        takeY(k + 2, R.y, yc);
+        double vv[RW], zz[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const bool ok = pin && wok[q];
+            vv[q] = ok ? R.v[q] : 0.0;
+            zz[q] = (!FZ && ok) ? R.z[q] : 0.0;
+        }
+        const double he = (hload && pin) ? R.he : 0.0;
+        const double hfc = (fload && pin) ? R.hf : 0.0;
+        const double hvc = (cact && pin) ? R.hv : 0.0;
+        const double hzc = (!FZ && cact && pin) ? R.hz : 0.0;
+        hc = he;
+        // issue the next plane's loads before computing this one
+        issueY(k + 3, R.y);
+        issueP(k + 2, R);
+
+        // w_i at plane p = k+1 on the RW rows, from y planes k (ya), k+1 (yb), k+2 (yc)
+        {
+            const Sel szm = to_sel(pin ? sel_lo(p, nz, MASK, B, nzl) : 0);
+            const Sel szp = to_sel(pin ? sel_hi(p, nz, MASK, B, nzh) : 0);
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                // the DPP shifts run in every lane (a shift reads its source lane)
+                const double pv = lane_prev(yb[q + 1]), nv = lane_next(yb[q + 1]);
+                const double el = read_lane(he, q), er = read_lane(he, 32 + q);
+                const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+                const double c = yb[q + 1];
+                double xm, xp, ym, yp, zm, zp;
+                if constexpr (SIMPLE) {
+                    xm = xl, xp = xr, ym = yb[q], yp = yb[q + 2], zm = ya[q + 1], zp = yc[q + 1];
+                } else {
+                    xm = pick(sxm, xl, xr), xp = pick(sxp, xr, xl);
+                    ym = pick(wsym[q], yb[q], yb[q + 2]), yp = pick(wsyp[q], yb[q + 2], yb[q]);
+                    zm = pick(szm, ya[q + 1], yc[q + 1]), zp = pick(szp, yc[q + 1], ya[q + 1]);
+                }
+                const double z = FZ ? vv[q] / theta : zz[q];
+                const double w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
+                wc[q] = (pin && wok[q]) ? w : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < RY; ++r) vc[r] = vv[r + 1];
+        }
         if (k >= k0) {
+            // w_i at the halo lanes' points (hcx, hj, k): row neighbours from the
+            // adjacent halo lanes, the tile-edge neighbour from lane 0 or TX-1
+            double edge = 0.0;
+#pragma unroll
+            for (int q = 1; q <= RY; ++q) {
+                const double eL = read_lane(ya[q + 1], 0), eR = read_lane(ya[q + 1], TX - 1);
+                const double e = hside ? eR : eL;
+                edge = hq == q ? e : edge;
+            }
+            double hw;
+            {
+                const double d = lane_prev(hb), u = lane_next(hb);
+                const double l = hside ? edge : hfb, r = hside ? hfb : edge;
+                double xm, xp, ym, yp, zm, zp;
+                if constexpr (SIMPLE) {
+                    xm = l, xp = r, ym = d, yp = u, zm = ha, zp = hc;
+                } else {
+                    const Sel szl = to_sel(sel_lo(k, nz, MASK, B, nzl));
+                    const Sel szh = to_sel(sel_hi(k, nz, MASK, B, nzh));
+                    xm = pick(csxl, l, r), xp = pick(csxh, r, l);
+                    ym = pick(csyl, d, u), yp = pick(csyh, u, d);
+                    zm = pick(szl, ha, hc), zp = pick(szh, hc, ha);
+                }
+                const double z = FZ ? hvb / theta : hzb;
+                const double w = step1(hb, xm, xp, ym, yp, zm, zp, hvb, z);
+                hw = cact ? w : 0.0;
+            }
             // w_{i+1} at plane k from w_i at planes k-1 (wa), k (wb), k+1 (wc)
-            const double hw = pointW(k);
             const Sel szm = to_sel(sel_lo(k, nz, MASK, B, nzl));
             const Sel szp = to_sel(sel_hi(k, nz, MASK, B, nzh));
             const size_t po = (size_t)k * PB;
@@ -1093,7 +1119,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
             for (int r = 0; r < RY; ++r) {
                 const int q = r + 1; // w row of output row j0 + r
                 const double pv = lane_prev(wb[q]), nv = lane_next(wb[q]);
-                const double el = read_lane(hw, r), er = read_lane(hw, RY + r);
+                const double el = read_lane(hw, 1 + r), er = read_lane(hw, 33 + r);
                 const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
                 const double c = wb[q];
                 double xm, xp, ym, yp, zm, zp;
@@ -1124,6 +1150,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) vb[r] = vc[r];
+        ha = hb, hb = hc, hfb = hfc, hvb = hvc, hzb = hzc;
     }
 }
 
