@@ -85,9 +85,10 @@ enum {
                                            (default 8, 1..256) */
     POISSON_OPT_USE_GRAPH = 7,          /* 1 = replay captured HIP graphs (default), 0 = launch */
     POISSON_OPT_DEBUG_BREAKDOWN_AT = 8, /* testing: force omega = 0 at this iteration (-1 off) */
-    POISSON_OPT_FUSE = 9,               /* FP64 Chebyshev / Block-Jacobi with degree >= 3: run
-                                           Chebyshev steps two per pass (1, default) or one
-                                           per pass (0); same arithmetic, same results */
+    POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
+                                           mixed): run Chebyshev steps two per pass (1,
+                                           default) or one per pass (0); same arithmetic,
+                                           same results */
     POISSON_OPT_TILE_ORDER = 10         /* order in which workgroups take tiles: 0 natural
                                            (default), 1 x-grouped (the x-tiles of a tile row
                                            on one XCD); same results */
@@ -187,14 +188,14 @@ enum {
     POISSON_KERNEL_CHEB_STEP = 0,       /* one interior Chebyshev step (Alg. 2 loop body) */
     POISSON_KERNEL_STENCIL_DOT = 1,     /* w = A p^ fused with r~.w */
     POISSON_KERNEL_UPDATE_XR = 2,       /* x and r updates fused with r~.r, r.r */
-    POISSON_KERNEL_CHEB_PAIR = 3        /* two interior Chebyshev steps in one pass (FP64) */
+    POISSON_KERNEL_CHEB_PAIR = 3        /* two interior Chebyshev steps in one pass */
 };
 
 /* Launch one kernel `reps` times back to back on the context stream over the
    workspace of the last solve (its values are overwritten), for timing with
    events on that stream. precision selects the FP64 or FP32 variant.
    Requires a previous successful poisson_solve with a plan that has the buffers
-   (Chebyshev degree >= 3 for CHEB_STEP; an FP64 fused plan of degree >= 5 for
+   (Chebyshev degree >= 3 for CHEB_STEP; a fused plan of degree >= 5 for
    CHEB_PAIR). Asynchronous. */
 int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps);
 

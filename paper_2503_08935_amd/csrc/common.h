@@ -106,9 +106,9 @@ struct KArgs {
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                     const KArgs &a);
 void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a);
-// two fused Chebyshev steps i, i+1 (FP64): in = y_{i-1}, z = z_{i-2} (unless firstz:
+// two fused Chebyshev steps i, i+1 (FP64, or FP32 when mixed): in = y_{i-1}, z = z_{i-2} (unless firstz:
 // i = 2, z = v/theta), v; out = w_i, x2 = w_{i+1}; step = i
-void launch_cheb_pair(bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
+void launch_cheb_pair(bool mixed, bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
                       const KArgs &a);
 void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
 

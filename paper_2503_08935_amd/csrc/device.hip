@@ -899,7 +899,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 // compile-time true; plane validity is wave-uniform and every load reads a
 // clamped (valid) address whose value a select then keeps or zeroes, so no
 // load sits in a branch of its own.
-template <bool MASK, bool FZ, bool FULL, bool SIMPLE>
+template <typename T, bool MASK, bool FZ, bool FULL, bool SIMPLE>
 __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, int local, int lane,
                                                int wv)
 {
@@ -914,7 +914,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 
     // Addresses: a wave-uniform plane base plus a per-lane 32-bit byte offset
     // inside the plane (the host uses this kernel only for planes below 2 GiB).
-    const size_t PB = (size_t)nx * (size_t)ny * sizeof(double);
+    const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
     const int B = MASK ? P.block : 1;
     const unsigned bc = P.bc;
     const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
@@ -928,12 +928,13 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
-    const double ih2 = P.ih2, theta = P.theta, ts = P.two_sigma, tod = P.two_over_delta;
-    const double rc1 = P.rc[A.step], ro1 = P.ro[A.step];
-    const double rc2 = P.rc[A.step + 1], ro2 = P.ro[A.step + 1];
+    const T ih2 = Coef<T>::ih2(P), theta = Coef<T>::theta(P);
+    const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
+    const T rc1 = Coef<T>::rc(P, A.step), ro1 = Coef<T>::ro(P, A.step);
+    const T rc2 = Coef<T>::rc(P, A.step + 1), ro2 = Coef<T>::ro(P, A.step + 1);
     auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
-    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(double); };
-    auto ld = [](const char *plane, unsigned o) { return ld_g((const double *)(plane + o)); };
+    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
 
     // rows: Y row q is j0-2+q, w row q is j0-1+q
     bool yok[RYY], wok[RW];
@@ -976,9 +977,9 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const Sel csyh = to_sel(cact ? sel_hi(hj, ny, MASK, B, nyh) : 0);
 
     // w_i at one point from its 7 y values, v and z (the k_stencil step)
-    auto step1 = [&](double yc, double xm, double xp, double ym, double yp, double zm,
-                     double zp, double v, double z) {
-        const double a = ((((((6.0 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+    auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm,
+                     T zp, T v, T z) {
+        const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
         return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
     };
     // The plane loop is software-pipelined: iteration k issues the loads of y
@@ -987,9 +988,9 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     // only there are they zeroed outside the grid, so no wait sits between a
     // load and the next iteration.
     struct Raw {
-        double y[RYY], v[RW], z[RW], he, hf, hv, hz;
+        T y[RYY], v[RW], z[RW], he, hf, hv, hz;
     };
-    auto issueY = [&](int p, double (&dst)[RYY]) {
+    auto issueY = [&](int p, T (&dst)[RYY]) {
         const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
 #pragma unroll
         for (int q = 0; q < RYY; ++q) dst[q] = ld(Yp, yoff[q]);
@@ -1008,23 +1009,23 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         R.hv = ld(Vb + po, coff);
         if constexpr (!FZ) R.hz = ld(Zb + po, coff);
     };
-    auto takeY = [&](int p, const double (&raw)[RYY], double (&dst)[RYY]) {
+    auto takeY = [&](int p, const T (&raw)[RYY], T (&dst)[RYY]) {
         const bool pin = p >= 0 && p < nz;
 #pragma unroll
-        for (int q = 0; q < RYY; ++q) dst[q] = (pin && yok[q]) ? raw[q] : 0.0;
+        for (int q = 0; q < RYY; ++q) dst[q] = (pin && yok[q]) ? raw[q] : (T)0;
     };
 
-    double ya[RYY], yb[RYY], yc[RYY];
-    double wa[RW], wb[RW], wc[RW], vb[RY], vc[RY];
+    T ya[RYY], yb[RYY], yc[RYY];
+    T wa[RW], wb[RW], wc[RW], vb[RY], vc[RY];
     // halo values: y at the halo column on planes k-1, k, k+1 (ha, hb, hc), and
     // at plane k the further column, v and z (hfb, hvb, hzb)
-    double ha = 0.0, hb = 0.0, hc = 0.0, hfb = 0.0, hvb = 0.0, hzb = 0.0;
+    T ha = (T)0, hb = (T)0, hc = (T)0, hfb = (T)0, hvb = (T)0, hzb = (T)0;
     Raw R;
 #pragma unroll
-    for (int q = 0; q < RW; ++q) R.z[q] = 0.0;
-    R.hz = 0.0;
+    for (int q = 0; q < RW; ++q) R.z[q] = (T)0;
+    R.hz = (T)0;
     {
-        double t[RYY];
+        T t[RYY];
         issueY(k0 - 2, t);
         takeY(k0 - 2, t, ya);
         issueY(k0 - 1, t);
@@ -1033,25 +1034,25 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     issueY(k0, R.y);
     issueP(k0 - 1, R);
 #pragma unroll
-    for (int q = 0; q < RW; ++q) wa[q] = wb[q] = 0.0;
+    for (int q = 0; q < RW; ++q) wa[q] = wb[q] = (T)0;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) vb[r] = 0.0;
+    for (int r = 0; r < RY; ++r) vb[r] = (T)0;
     for (int k = k0 - 2; k < k1; ++k) {
         // consume the loads of plane k+2 (y) and k+1 (v, z, halo)
         const int p = k + 1;
         const bool pin = p >= 0 && p < nz;
         takeY(k + 2, R.y, yc);
-        double vv[RW], zz[RW];
+        T vv[RW], zz[RW];
 #pragma unroll
         for (int q = 0; q < RW; ++q) {
             const bool ok = pin && wok[q];
-            vv[q] = ok ? R.v[q] : 0.0;
-            zz[q] = (!FZ && ok) ? R.z[q] : 0.0;
+            vv[q] = ok ? R.v[q] : (T)0;
+            zz[q] = (!FZ && ok) ? R.z[q] : (T)0;
         }
-        const double he = (hload && pin) ? R.he : 0.0;
-        const double hfc = (fload && pin) ? R.hf : 0.0;
-        const double hvc = (cact && pin) ? R.hv : 0.0;
-        const double hzc = (!FZ && cact && pin) ? R.hz : 0.0;
+        const T he = (hload && pin) ? R.he : (T)0;
+        const T hfc = (fload && pin) ? R.hf : (T)0;
+        const T hvc = (cact && pin) ? R.hv : (T)0;
+        const T hzc = (!FZ && cact && pin) ? R.hz : (T)0;
         hc = he;
         // issue the next plane's loads before computing this one
         issueY(k + 3, R.y);
@@ -1064,11 +1065,11 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 #pragma unroll
             for (int q = 0; q < RW; ++q) {
                 // the DPP shifts run in every lane (a shift reads its source lane)
-                const double pv = lane_prev(yb[q + 1]), nv = lane_next(yb[q + 1]);
-                const double el = read_lane(he, q), er = read_lane(he, 32 + q);
-                const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
-                const double c = yb[q + 1];
-                double xm, xp, ym, yp, zm, zp;
+                const T pv = lane_prev(yb[q + 1]), nv = lane_next(yb[q + 1]);
+                const T el = read_lane(he, q), er = read_lane(he, 32 + q);
+                const T xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+                const T c = yb[q + 1];
+                T xm, xp, ym, yp, zm, zp;
                 if constexpr (SIMPLE) {
                     xm = xl, xp = xr, ym = yb[q], yp = yb[q + 2], zm = ya[q + 1], zp = yc[q + 1];
                 } else {
@@ -1076,9 +1077,9 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(wsym[q], yb[q], yb[q + 2]), yp = pick(wsyp[q], yb[q + 2], yb[q]);
                     zm = pick(szm, ya[q + 1], yc[q + 1]), zp = pick(szp, yc[q + 1], ya[q + 1]);
                 }
-                const double z = FZ ? vv[q] / theta : zz[q];
-                const double w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
-                wc[q] = (pin && wok[q]) ? w : 0.0;
+                const T z = FZ ? vv[q] / theta : zz[q];
+                const T w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
+                wc[q] = (pin && wok[q]) ? w : (T)0;
             }
 #pragma unroll
             for (int r = 0; r < RY; ++r) vc[r] = vv[r + 1];
@@ -1086,18 +1087,18 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         if (k >= k0) {
             // w_i at the halo lanes' points (hcx, hj, k): row neighbours from the
             // adjacent halo lanes, the tile-edge neighbour from lane 0 or TX-1
-            double edge = 0.0;
+            T edge = (T)0;
 #pragma unroll
             for (int q = 1; q <= RY; ++q) {
-                const double eL = read_lane(ya[q + 1], 0), eR = read_lane(ya[q + 1], TX - 1);
-                const double e = hside ? eR : eL;
+                const T eL = read_lane(ya[q + 1], 0), eR = read_lane(ya[q + 1], TX - 1);
+                const T e = hside ? eR : eL;
                 edge = hq == q ? e : edge;
             }
-            double hw;
+            T hw;
             {
-                const double d = lane_prev(hb), u = lane_next(hb);
-                const double l = hside ? edge : hfb, r = hside ? hfb : edge;
-                double xm, xp, ym, yp, zm, zp;
+                const T d = lane_prev(hb), u = lane_next(hb);
+                const T l = hside ? edge : hfb, r = hside ? hfb : edge;
+                T xm, xp, ym, yp, zm, zp;
                 if constexpr (SIMPLE) {
                     xm = l, xp = r, ym = d, yp = u, zm = ha, zp = hc;
                 } else {
@@ -1107,9 +1108,9 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(csyl, d, u), yp = pick(csyh, u, d);
                     zm = pick(szl, ha, hc), zp = pick(szh, hc, ha);
                 }
-                const double z = FZ ? hvb / theta : hzb;
-                const double w = step1(hb, xm, xp, ym, yp, zm, zp, hvb, z);
-                hw = cact ? w : 0.0;
+                const T z = FZ ? hvb / theta : hzb;
+                const T w = step1(hb, xm, xp, ym, yp, zm, zp, hvb, z);
+                hw = cact ? w : (T)0;
             }
             // w_{i+1} at plane k from w_i at planes k-1 (wa), k (wb), k+1 (wc)
             const Sel szm = to_sel(sel_lo(k, nz, MASK, B, nzl));
@@ -1118,11 +1119,11 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const int q = r + 1; // w row of output row j0 + r
-                const double pv = lane_prev(wb[q]), nv = lane_next(wb[q]);
-                const double el = read_lane(hw, 1 + r), er = read_lane(hw, 33 + r);
-                const double xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
-                const double c = wb[q];
-                double xm, xp, ym, yp, zm, zp;
+                const T pv = lane_prev(wb[q]), nv = lane_next(wb[q]);
+                const T el = read_lane(hw, 1 + r), er = read_lane(hw, 33 + r);
+                const T xl = lane == 0 ? el : pv, xr = lane == TX - 1 ? er : nv;
+                const T c = wb[q];
+                T xm, xp, ym, yp, zm, zp;
                 if constexpr (SIMPLE) {
                     xm = xl, xp = xr, ym = wb[q - 1], yp = wb[q + 1], zm = wa[q], zp = wc[q];
                 } else {
@@ -1130,11 +1131,11 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(wsym[q], wb[q - 1], wb[q + 1]), yp = pick(wsyp[q], wb[q + 1], wb[q - 1]);
                     zm = pick(szm, wa[q], wc[q]), zp = pick(szp, wc[q], wa[q]);
                 }
-                const double a = ((((((6.0 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-                const double w2 = rc2 * ((ts * c + tod * (vb[r] - a)) - ro2 * ya[q + 1]);
+                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                const T w2 = rc2 * ((ts * c + tod * (vb[r] - a)) - ro2 * ya[q + 1]);
                 if (wok[q]) {
-                    st_nt((double *)(W1b + po + woff[q]), c);
-                    st_nt((double *)(W2b + po + woff[q]), w2);
+                    st_nt((T *)(W1b + po + woff[q]), c);
+                    st_nt((T *)(W2b + po + woff[q]), w2);
                 }
             }
         }
@@ -1154,7 +1155,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     }
 }
 
-template <bool MASK, bool FZ>
+template <typename T, bool MASK, bool FZ>
 __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
 {
     const int total = W.count_dev ? *W.count_dev : W.count;
@@ -1172,14 +1173,14 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
         const int j0 = tiy * (TY * RY) + wv * RY;
         const bool full = tix * TX + TX <= P.nx && j0 - 2 >= 0 && j0 + RY + 1 < P.ny;
         if constexpr (MASK) {
-            if (full) cheb_pair_tile<true, FZ, true, false>(P, A, local, lane, wv);
-            else cheb_pair_tile<true, FZ, false, false>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, true, FZ, true, false>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, true, FZ, false, false>(P, A, local, lane, wv);
         } else if (P.bc == 0) {
-            if (full) cheb_pair_tile<false, FZ, true, true>(P, A, local, lane, wv);
-            else cheb_pair_tile<false, FZ, false, true>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, false, FZ, true, true>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, false, FZ, false, true>(P, A, local, lane, wv);
         } else {
-            if (full) cheb_pair_tile<false, FZ, true, false>(P, A, local, lane, wv);
-            else cheb_pair_tile<false, FZ, false, false>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, false, FZ, true, false>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, false, FZ, false, false>(P, A, local, lane, wv);
         }
     }
 }
@@ -1387,16 +1388,23 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
         hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }
 
-void launch_cheb_pair(bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
-                      const KArgs &a)
+template <typename T>
+static void lp(bool mask, bool firstz, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
     if (mask) {
-        if (firstz) hipLaunchKernelGGL((k_cheb_pair<true, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-        else hipLaunchKernelGGL((k_cheb_pair<true, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        if (firstz) hipLaunchKernelGGL((k_cheb_pair<T, true, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        else hipLaunchKernelGGL((k_cheb_pair<T, true, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
     } else {
-        if (firstz) hipLaunchKernelGGL((k_cheb_pair<false, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-        else hipLaunchKernelGGL((k_cheb_pair<false, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        if (firstz) hipLaunchKernelGGL((k_cheb_pair<T, false, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+        else hipLaunchKernelGGL((k_cheb_pair<T, false, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
     }
+}
+
+void launch_cheb_pair(bool mixed, bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
+                      const KArgs &a)
+{
+    if (mixed) lp<float>(mask, firstz, w, grid, s, a);
+    else lp<double>(mask, firstz, w, grid, s, a);
 }
 
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

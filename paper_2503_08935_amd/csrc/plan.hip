@@ -173,7 +173,8 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
 
 bool fused(int pc, int deg, bool mixed, int fuse)
 {
-    return fuse && !mixed && is_cheb(pc) && deg >= 3;
+    (void)mixed;
+    return fuse && is_cheb(pc) && deg >= 3;
 }
 
 size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
@@ -186,7 +187,7 @@ size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
     case V_PH: case V_SH: return pc != POISSON_PC_NONE ? tp * N : 0;
     case V_RA: return cheb && deg >= 2 ? tp * N : 0;
     case V_RB: return cheb && deg >= 3 ? tp * N : 0;
-    case V_RC: case V_RD: return fz ? 8 * N : 0;
+    case V_RC: case V_RD: return fz ? tp * N : 0;
     case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
     default: return 0;
     }
@@ -245,7 +246,8 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
             for (int b : ring)
                 if (b != y && b != z && n < 2) o[n++] = b;
             const int w2 = i + 1 == m ? vout : o[1];
-            launch_cheb_pair(mask, z < 0, w, grid, s, KArgs{y, o[0], vsrc, z < 0 ? 0 : z, i, second, 0, w2});
+            launch_cheb_pair(mixed, mask, z < 0, w, grid, s,
+                             KArgs{y, o[0], vsrc, z < 0 ? 0 : z, i, second, 0, w2});
             z = o[0];
             y = w2;
         }
