@@ -89,9 +89,11 @@ enum {
                                            mixed): run Chebyshev steps two per pass (1,
                                            default) or one per pass (0); same arithmetic,
                                            same results */
-    POISSON_OPT_TILE_ORDER = 10         /* order in which workgroups take tiles: 0 natural
-                                           (default), 1 x-grouped (the x-tiles of a tile row
-                                           on one XCD); same results */
+    POISSON_OPT_TILE_ORDER = 10         /* order in which workgroups take tiles: 0 default
+                                           (natural; x-grouped for the fused Chebyshev
+                                           pairs), 1 x-grouped everywhere (the x-tiles of a
+                                           tile row on one XCD), 2 slabs (each XCD one
+                                           contiguous eighth of the tiles); same results */
 };
 
 /* ---- solver context ----------------------------------------------------- */

@@ -57,11 +57,20 @@ template <typename T> __device__ __forceinline__ T ld_g(const T *p)
 // cache lines of their shared x-halo are fetched into two L2s. The x-grouped
 // order takes 8 tile rows (a row = the tx tiles of one (y, z)) at a time and
 // gives each XCD one whole row: dispatch d of the group runs row d % 8, x-tile
-// d / 8. Rows left over at the end keep natural order.
+// d / 8. Rows left over at the end keep natural order. The slab order gives
+// XCD x the x-th eighth of all tiles, a contiguous range of whole tile rows,
+// when the tile count is a multiple of 8.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int tile_order(const Work &W, const Prob &P, int g, int total)
+__device__ __forceinline__ int tile_order(int order, const Work &W, const Prob &P, int g,
+                                          int total)
 {
-    if (!W.order || W.tile_prob) return g;
+    if (!order || W.tile_prob) return g;
+    if (order == 2) {
+        // workgroup g runs on XCD g % 8: XCD x takes the x-th eighth of the tiles
+        // (whole tile rows and z-slabs), so x and y neighbours share its L2
+        if (total % 8) return g;
+        return (g % 8) * (total / 8) + g / 8;
+    }
     const int tx = P.tx, grp = 8 * tx;
     const int base = (g / grp) * grp;
     if (base + grp > total) return g;
@@ -601,7 +610,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
-        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W.order, W, P, g, total);
         if (OP != S_INIT && OP != S_TRUE && OP != S_APPLY) {
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -866,7 +875,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
-        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W.order, W, P, g, total);
         {
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -1163,7 +1172,10 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
-        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
+        // the default order for this kernel is x-grouped: its x-halo columns (y, v
+        // and z) then come from the same L2 as the neighbouring tile's data
+        const int local =
+            W.tile_prob ? W.tile_local[g] : tile_order(W.order ? W.order : 1, W, P, g, total);
         {
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
@@ -1311,7 +1323,7 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int pid = W.tile_prob ? W.tile_prob[g] : 0;
         const Prob &P = W.probs[pid];
-        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W, P, g, total);
+        const int local = W.tile_prob ? W.tile_local[g] : tile_order(W.order, W, P, g, total);
         const Scalars *sc = P.sc;
         if (OP != E_DOT) {
             if (sc->done || (A.second && sc->half_pending)) continue;

@@ -339,7 +339,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         c->opt.fuse = (int)v;
         return POISSON_OK;
     case POISSON_OPT_TILE_ORDER:
-        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        if (v != 0 && v != 1 && v != 2) return POISSON_ERR_ARG;
         c->tile_order = (int)v;
         return POISSON_OK;
     default:

@@ -97,11 +97,13 @@ Tiling make_tiling(int nx, int ny, int nz)
     Tiling t;
     t.tx = (nx + TX - 1) / TX;
     t.ty = (ny + TY * RY - 1) / (TY * RY);
-    // z-chunk per tile: long chunks amortise the two halo planes, but keep at
-    // least ~2048 tiles so 256 CUs have several workgroups each
+    // z-chunk per tile: long chunks amortise the halo planes (one on each side for
+    // a stencil pass, three for the fused Chebyshev pair), but keep at least 1024
+    // tiles (4096 waves) so that 256 CUs are busy; at 256^3 kz = 16 measured
+    // 11-21% faster solves than kz = 8 with 2048 tiles
     int kz = 64;
     const long base = (long)t.tx * t.ty;
-    while (kz > 8 && base * ((nz + kz - 1) / kz) < 2048) kz /= 2;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < 1024) kz /= 2;
     t.kz = std::min(kz, std::max(nz, 1));
     t.tz = (nz + t.kz - 1) / t.kz;
     t.ntiles = t.tx * t.ty * t.tz;

@@ -198,3 +198,20 @@ def test_interior_tile_paths_parity(gpu, nx, case):
     assert stats["iterations"] == ref.iterations
     assert np.array_equal(tr[:, 0], ref.alpha) and np.array_equal(tr[:, 2], ref.rho)
     assert np.array_equal(x, ref.x)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_tile_orders_change_no_bits(gpu, mixed):
+    """The three tile orders (natural, x-grouped, slabs per XCD) only permute which
+    workgroup takes which tile; the reductions commit per tile in tile order."""
+    shape = (128, 64, 32)  # 32 tiles: every order is a full permutation
+    h = 1.0 / 129
+    f = workloads.uniform_grid(31, shape)
+    outs = []
+    for order in (0, 1, 2):
+        st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 7, 1e-9, tile_order=order,
+                                     precision=P.MIXED if mixed else P.FP64)
+        outs.append((st, stats["iterations"], x))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] == P.OK and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2])
