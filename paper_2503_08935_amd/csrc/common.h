@@ -106,10 +106,13 @@ struct KArgs {
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                     const KArgs &a);
 void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a);
-// two fused Chebyshev steps i, i+1 (FP64, or FP32 when mixed): in = y_{i-1}, z = z_{i-2} (unless firstz:
-// i = 2, z = v/theta), v; out = w_i, x2 = w_{i+1}; step = i
-void launch_cheb_pair(bool mixed, bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
-                      const KArgs &a);
+// two fused Chebyshev steps i, i+1 (i >= 3; FP64, or FP32 when mixed): in = y_{i-1},
+// z = z_{i-2}, v; out = w_i, x2 = w_{i+1}; step = i
+void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
+// Chebyshev steps 1 and 2 in one pass: in = v (FP64), out = y_1, x2 = w_2, step = 1;
+// in mixed mode the FP32 copy of v is written to V_V32 as well
+void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                            const KArgs &a);
 void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
 
 } // namespace pz

@@ -908,7 +908,11 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 // compile-time true; plane validity is wave-uniform and every load reads a
 // clamped (valid) address whose value a select then keeps or zeroes, so no
 // load sits in a branch of its own.
-template <typename T, bool MASK, bool FZ, bool FULL, bool SIMPLE>
+// FIRST: steps 1 and 2 (the first step's own formula, y_0 := v, z = v/theta at
+// step 2). The stencil input is then v itself, read as TU (FP64 also when the
+// arithmetic is FP32: it is rounded once on load, and the FP32 copy of v that
+// the later steps read is written out).
+template <typename T, typename TU, bool MASK, bool FZ, bool FULL, bool SIMPLE, bool FIRST>
 __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, int local, int lane,
                                                int wv)
 {
@@ -924,6 +928,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     // Addresses: a wave-uniform plane base plus a per-lane 32-bit byte offset
     // inside the plane (the host uses this kernel only for planes below 2 GiB).
     const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
+    const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU); // the stencil input's planes
     const int B = MASK ? P.block : 1;
     const unsigned bc = P.bc;
     const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
@@ -937,13 +942,17 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
+    char *V32b = (char *)P.vec[V_V32];
     const T ih2 = Coef<T>::ih2(P), theta = Coef<T>::theta(P);
     const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
     const T rc1 = Coef<T>::rc(P, A.step), ro1 = Coef<T>::ro(P, A.step);
     const T rc2 = Coef<T>::rc(P, A.step + 1), ro2 = Coef<T>::ro(P, A.step + 1);
+    const T c1 = Coef<T>::c1(P);
     auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
     auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto offy = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(TU); };
     auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
+    auto ldy = [](const char *plane, unsigned o) { return ld_g((const TU *)(plane + o)); };
 
     // rows: Y row q is j0-2+q, w row q is j0-1+q
     bool yok[RYY], wok[RW];
@@ -953,7 +962,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     for (int q = 0; q < RYY; ++q) {
         const int j = j0 - 2 + q;
         yok[q] = FULL || (xin && j >= 0 && j < ny);
-        yoff[q] = off(ic, FULL ? j : clampi(j, ny));
+        yoff[q] = offy(ic, FULL ? j : clampi(j, ny));
     }
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
@@ -967,7 +976,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const int hq = lane & 31;
     const int hj = j0 - 1 + hq;
     const bool hload = hq < RW && hj >= 0 && hj < ny && (lane < 32 ? i0 > 0 : i0 + TX < nx);
-    const unsigned hoff = hload ? off(lane < 32 ? i0 - 1 : i0 + TX, hj) : 0u;
+    const unsigned hoff = hload ? offy(lane < 32 ? i0 - 1 : i0 + TX, hj) : 0u;
     // The halo lanes also evaluate w_i at the two halo columns i0-1 and i0+TX:
     // lane q (1..RY) the left point of row j0+q-1, lane 32+q the right one. For
     // that the x-halo load above is joined by three more per plane: y one
@@ -977,7 +986,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const int hfx = hside ? i0 + TX + 1 : i0 - 2;   // one further out
     const bool hrow_ok = hq < RW && hj >= 0 && hj < ny;
     const bool fload = hrow_ok && hfx >= 0 && hfx < nx;
-    const unsigned foff = fload ? off(hfx, hj) : 0u;
+    const unsigned foff = fload ? offy(hfx, hj) : 0u;
     const bool cact = hq >= 1 && hq <= RY && hrow_ok && hcx >= 0 && hcx < nx;
     const unsigned coff = cact ? off(hcx, hj) : 0u;
     const Sel csxl = to_sel(cact ? sel_lo(hcx, nx, MASK, B, nxl) : 0);
@@ -989,7 +998,8 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm,
                      T zp, T v, T z) {
         const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-        return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
+        if constexpr (FIRST) return c1 * ((T)2 * yc - a / theta);
+        else return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
     };
     // The plane loop is software-pipelined: iteration k issues the loads of y
     // at plane k+3 and of v, z and the halo values at plane k+2, and consumes
@@ -997,31 +1007,35 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     // only there are they zeroed outside the grid, so no wait sits between a
     // load and the next iteration.
     struct Raw {
-        T y[RYY], v[RW], z[RW], he, hf, hv, hz;
+        TU y[RYY], he, hf;
+        T v[RW], z[RW], hv, hz;
     };
-    auto issueY = [&](int p, T (&dst)[RYY]) {
-        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
+    auto issueY = [&](int p, TU (&dst)[RYY]) {
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PBY;
 #pragma unroll
-        for (int q = 0; q < RYY; ++q) dst[q] = ld(Yp, yoff[q]);
+        for (int q = 0; q < RYY; ++q) dst[q] = ldy(Yp, yoff[q]);
     };
     auto issueP = [&](int p, Raw &R) {
         const size_t po = (size_t)clampi(p, nz) * PB;
         // v and z rows are read by three waves (as own and as halo rows), so
         // they are loaded through the caches, not as a read-once stream
+        const size_t pyo = (size_t)clampi(p, nz) * PBY;
+        if constexpr (!FIRST) {
 #pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            R.v[q] = ld(Vb + po, woff[q]);
-            if constexpr (!FZ) R.z[q] = ld(Zb + po, woff[q]);
+            for (int q = 0; q < RW; ++q) {
+                R.v[q] = ld(Vb + po, woff[q]);
+                if constexpr (!FZ) R.z[q] = ld(Zb + po, woff[q]);
+            }
+            R.hv = ld(Vb + po, coff);
+            if constexpr (!FZ) R.hz = ld(Zb + po, coff);
         }
-        R.he = ld(Yb + po, hoff);
-        R.hf = ld(Yb + po, foff);
-        R.hv = ld(Vb + po, coff);
-        if constexpr (!FZ) R.hz = ld(Zb + po, coff);
+        R.he = ldy(Yb + pyo, hoff);
+        R.hf = ldy(Yb + pyo, foff);
     };
-    auto takeY = [&](int p, const T (&raw)[RYY], T (&dst)[RYY]) {
+    auto takeY = [&](int p, const TU (&raw)[RYY], T (&dst)[RYY]) {
         const bool pin = p >= 0 && p < nz;
 #pragma unroll
-        for (int q = 0; q < RYY; ++q) dst[q] = (pin && yok[q]) ? raw[q] : (T)0;
+        for (int q = 0; q < RYY; ++q) dst[q] = (pin && yok[q]) ? (T)raw[q] : (T)0;
     };
 
     T ya[RYY], yb[RYY], yc[RYY];
@@ -1031,10 +1045,10 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     T ha = (T)0, hb = (T)0, hc = (T)0, hfb = (T)0, hvb = (T)0, hzb = (T)0;
     Raw R;
 #pragma unroll
-    for (int q = 0; q < RW; ++q) R.z[q] = (T)0;
-    R.hz = (T)0;
+    for (int q = 0; q < RW; ++q) R.v[q] = R.z[q] = (T)0;
+    R.hv = R.hz = (T)0;
     {
-        T t[RYY];
+        TU t[RYY];
         issueY(k0 - 2, t);
         takeY(k0 - 2, t, ya);
         issueY(k0 - 1, t);
@@ -1055,11 +1069,11 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 #pragma unroll
         for (int q = 0; q < RW; ++q) {
             const bool ok = pin && wok[q];
-            vv[q] = ok ? R.v[q] : (T)0;
-            zz[q] = (!FZ && ok) ? R.z[q] : (T)0;
+            vv[q] = FIRST ? yb[q + 1] : (ok ? R.v[q] : (T)0);
+            zz[q] = (!FZ && !FIRST && ok) ? R.z[q] : (T)0;
         }
-        const T he = (hload && pin) ? R.he : (T)0;
-        const T hfc = (fload && pin) ? R.hf : (T)0;
+        const T he = (hload && pin) ? (T)R.he : (T)0;
+        const T hfc = (fload && pin) ? (T)R.hf : (T)0;
         const T hvc = (cact && pin) ? R.hv : (T)0;
         const T hzc = (!FZ && cact && pin) ? R.hz : (T)0;
         hc = he;
@@ -1141,10 +1155,15 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     zm = pick(szm, wa[q], wc[q]), zp = pick(szp, wc[q], wa[q]);
                 }
                 const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
-                const T w2 = rc2 * ((ts * c + tod * (vb[r] - a)) - ro2 * ya[q + 1]);
+                // step i+1 reads z = y_{i-1}, the pair's stencil input at plane k
+                // (for the first pair, z = v/theta with v = that input)
+                const T v = FIRST ? ya[q + 1] : vb[r];
+                const T z = FIRST ? v / theta : ya[q + 1];
+                const T w2 = rc2 * ((ts * c + tod * (v - a)) - ro2 * z);
                 if (wok[q]) {
                     st_nt((T *)(W1b + po + woff[q]), c);
                     st_nt((T *)(W2b + po + woff[q]), w2);
+                    if constexpr (FIRST && sizeof(T) == 4) st_nt((T *)(V32b + po + woff[q]), v);
                 }
             }
         }
@@ -1164,7 +1183,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     }
 }
 
-template <typename T, bool MASK, bool FZ>
+template <typename T, typename TU, bool MASK, bool FZ, bool FIRST>
 __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
 {
     const int total = W.count_dev ? *W.count_dev : W.count;
@@ -1185,14 +1204,14 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
         const int j0 = tiy * (TY * RY) + wv * RY;
         const bool full = tix * TX + TX <= P.nx && j0 - 2 >= 0 && j0 + RY + 1 < P.ny;
         if constexpr (MASK) {
-            if (full) cheb_pair_tile<T, true, FZ, true, false>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, true, FZ, false, false>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, true, FZ, true, false, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, true, FZ, false, false, FIRST>(P, A, local, lane, wv);
         } else if (P.bc == 0) {
-            if (full) cheb_pair_tile<T, false, FZ, true, true>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, false, FZ, false, true>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, false, FZ, true, true, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, false, FZ, false, true, FIRST>(P, A, local, lane, wv);
         } else {
-            if (full) cheb_pair_tile<T, false, FZ, true, false>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, false, FZ, false, false>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, false, FZ, true, false, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, false, FZ, false, false, FIRST>(P, A, local, lane, wv);
         }
     }
 }
@@ -1400,23 +1419,27 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
         hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }
 
-template <typename T>
+template <typename T, typename TU, bool FIRST>
 static void lp(bool mask, bool firstz, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (mask) {
-        if (firstz) hipLaunchKernelGGL((k_cheb_pair<T, true, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-        else hipLaunchKernelGGL((k_cheb_pair<T, true, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-    } else {
-        if (firstz) hipLaunchKernelGGL((k_cheb_pair<T, false, true>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-        else hipLaunchKernelGGL((k_cheb_pair<T, false, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-    }
+    // FZ (z = v/theta, no z input) only for the first pair, whose z is not read
+    (void)firstz;
+    if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    else hipLaunchKernelGGL((k_cheb_pair<T, TU, false, FIRST, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }
 
-void launch_cheb_pair(bool mixed, bool mask, bool firstz, const Work &w, int grid, hipStream_t s,
-                      const KArgs &a)
+void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (mixed) lp<float>(mask, firstz, w, grid, s, a);
-    else lp<double>(mask, firstz, w, grid, s, a);
+    if (mixed) lp<float, float, false>(mask, false, w, grid, s, a);
+    else lp<double, double, false>(mask, false, w, grid, s, a);
+}
+
+void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                            const KArgs &a)
+{
+    // the first pair has no z input; FZ is irrelevant and fixed
+    if (mixed) lp<float, double, true>(mask, true, w, grid, s, a);
+    else lp<double, double, true>(mask, true, w, grid, s, a);
 }
 
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

@@ -571,8 +571,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
                 launch_stencil(S_CHEBK, mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->ntiles,
                                c->stream, KArgs{V_RA, V_RB, mixed ? (int)V_V32 : (int)V_P, V_RB, 3, 0, 0, 0});
             else if (kernel == POISSON_KERNEL_CHEB_PAIR)
-                launch_cheb_pair(mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, false, w, c->ntiles,
-                                 c->stream,
+                launch_cheb_pair(mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->ntiles, c->stream,
                                  KArgs{V_RA, V_RC, mixed ? (int)V_V32 : (int)V_P, V_RB, 3, 0, 0, V_RD});
             else if (kernel == POISSON_KERNEL_STENCIL_DOT)
                 launch_stencil(S_SDOT, mixed, false, w, c->ntiles, c->stream,

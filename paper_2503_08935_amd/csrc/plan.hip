@@ -189,7 +189,9 @@ size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
     case V_PH: case V_SH: return pc != POISSON_PC_NONE ? tp * N : 0;
     case V_RA: return cheb && deg >= 2 ? tp * N : 0;
     case V_RB: return cheb && deg >= 3 ? tp * N : 0;
-    case V_RC: case V_RD: return fz ? tp * N : 0;
+    // the ring's third and fourth buffers: the pairs after the first one
+    case V_RC: return fz && deg >= 4 ? tp * N : 0;
+    case V_RD: return fz && deg >= 5 ? tp * N : 0;
     case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
     default: return 0;
     }
@@ -225,36 +227,32 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         return;
     }
     const bool mask = pc == POISSON_PC_BLOCK_JACOBI;
-    KArgs a1{vin, m == 1 ? vout : (int)V_RA, 0, 0, 1, second, 0, 0};
-    launch_stencil(S_CHEB1, mixed, mask, w, grid, s, a1);
     const int vsrc = mixed ? (int)V_V32 : vin;
     if (fused(pc, m, mixed, fuse)) {
-        // steps 2..m: step 2 alone when m-1 is odd, the rest in fused pairs (i, i+1);
-        // a pair reads y_{i-1} and z_{i-2} and writes w_i, w_{i+1} to two other
-        // buffers of the ring {RA, RB, RC, RD} (nothing is written in place: every
-        // input is read by neighbouring tiles)
+        // steps 1 and 2 in one pass: reads v, writes y_1 (RA) and w_2 (RB), and in
+        // mixed mode the FP32 copy of v; then steps (i, i+1) in fused pairs, each
+        // reading y_{i-1} and z_{i-2} and writing w_i, w_{i+1} to two other buffers
+        // of the ring {RA, RB, RC, RD} (nothing is written in place: every input is
+        // read by neighbouring tiles); an odd last step runs alone
+        launch_cheb_first_pair(mixed, mask, w, grid, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
-        int y = V_RA, z = -1; // z = -1: z_{i-2} = v/theta
-        int i = 2;
-        if ((m - 1) & 1) {
-            const int out = m == 2 ? vout : (int)V_RB;
-            launch_stencil(S_CHEB2, mixed, mask, w, grid, s, KArgs{y, out, vsrc, 0, 2, second, 0, 0});
-            z = y;
-            y = out;
-            i = 3;
-        }
+        int y = V_RB, z = V_RA;
+        int i = 3;
         for (; i + 1 <= m; i += 2) {
             int o[2], n = 0;
             for (int b : ring)
                 if (b != y && b != z && n < 2) o[n++] = b;
             const int w2 = i + 1 == m ? vout : o[1];
-            launch_cheb_pair(mixed, mask, z < 0, w, grid, s,
-                             KArgs{y, o[0], vsrc, z < 0 ? 0 : z, i, second, 0, w2});
+            launch_cheb_pair(mixed, mask, w, grid, s, KArgs{y, o[0], vsrc, z, i, second, 0, w2});
             z = o[0];
             y = w2;
         }
+        if (i == m)
+            launch_stencil(S_CHEBK, mixed, mask, w, grid, s, KArgs{y, vout, vsrc, z, m, second, 0, 0});
         return;
     }
+    KArgs a1{vin, m == 1 ? vout : (int)V_RA, 0, 0, 1, second, 0, 0};
+    launch_stencil(S_CHEB1, mixed, mask, w, grid, s, a1);
     for (int i = 2; i <= m; ++i) {
         // step i reads y = buf(i-1), z = buf(i-2), writes buf(i) (in place over z)
         // where buf(odd) = RA, buf(even) = RB, and the last step writes vout
@@ -292,12 +290,13 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse)
         pcb = 8 + tp;
     else if (is_cheb(pc)) {
         const double tc = mixed ? 4 : 8;
-        pcb = 8 + tc + (mixed ? 4 : 0);                 // first step: v, y (+ v32)
         if (fused(pc, m, mixed, fuse)) {
-            int steps = m - 1;
-            if (steps & 1) { pcb += 3 * tc; --steps; }   // step 2 alone: y, v, w
+            pcb = 8 + 2 * tc + (mixed ? 4 : 0);          // steps 1, 2: v in; y_1, w_2 (+ v32) out
+            int steps = m - 2;
             pcb += (steps / 2) * 5 * tc;                // pairs: y, z, v in; w_i, w_{i+1} out
+            if (steps & 1) pcb += 4 * tc;               // last step alone: y, v, z, w
         } else {
+            pcb = 8 + tc + (mixed ? 4 : 0);             // first step: v, y (+ v32)
             if (m >= 2) pcb += 3 * tc;                  // step 2: y, v, w
             if (m >= 3) pcb += (m - 2) * 4 * tc;        // steps 3..m: y, v, z, w
         }

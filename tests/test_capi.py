@@ -141,12 +141,12 @@ def test_server_host_side_checks():
 
 
 def test_footprint_model():
-    # mixed Chebyshev-4: r, r~, p, w, t in FP64 and p^, s^, the ring of four Chebyshev
-    # buffers for the fused step pairs and the FP32 copy of the input: 5*8 + 7*4 = 68
-    # bytes per unknown, plus tile partials
+    # mixed Chebyshev-4: r, r~, p, w, t in FP64 and p^, s^, three Chebyshev buffers (the
+    # first pair writes y_1, w_2; the pair (3, 4) one more) and the FP32 copy of the
+    # input: 5*8 + 6*4 = 64 bytes per unknown, plus tile partials
     n = 128
     fp = P.footprint((n, n, n), P.PC_CHEBYSHEV, 4, P.MIXED)
-    assert 68 * n ** 3 <= fp <= 68 * n ** 3 + 64 * 1024 + 13 * 256
+    assert 64 * n ** 3 <= fp <= 64 * n ** 3 + 64 * 1024 + 13 * 256
     # FP64 Chebyshev-8: 7 FP64 vectors plus a ring of 4 for the fused step pairs
     fp64 = P.footprint((n, n, n), P.PC_CHEBYSHEV, 8, P.FP64)
     assert 88 * n ** 3 <= fp64 <= 88 * n ** 3 + 64 * 1024 + 14 * 256
