@@ -4,8 +4,8 @@
 // an array of Prob descriptors in device memory plus a tile list. Every kernel
 // walks tiles of TX x TY columns by kz planes; each tile belongs to one
 // problem. Reductions are per problem and deterministic: every tile writes a
-// double-double partial into its own slot and the last tile of the problem to
-// finish (atomic ticket) sums the slots in index order and updates that
+// double-double partial into its own slot, and a small finalize kernel launched
+// right after sums each problem's slots in index order and updates that
 // problem's scalars. A problem's arithmetic therefore depends only on the
 // problem itself, never on which other problems share the launch.
 #pragma once
@@ -39,7 +39,7 @@ struct Scalars {
     double rr_true, dot, pad_d[2];
     int iter, done, status, half_pending;
     int half, zero_x, pad_i[2];
-    unsigned ticket, pad_u[3];
+    unsigned pad_u[4];
 };
 
 struct Prob {

@@ -160,11 +160,14 @@ __device__ __forceinline__ void block_reduce_dd(double (&hi)[ND], double (&lo)[N
     __syncthreads();
 }
 
-// Publish this tile's partial sums; if this is the problem's last tile, sum
-// all partials in tile order and return true (res valid in thread 0).
+// Publish this tile's partial sums in its slot. The sums over all tiles are
+// formed by k_finalize, launched right after the reduction kernel: the kernel
+// boundary makes every slot visible, so no device-scope fence is needed here
+// (on this chip such a fence writes back and invalidates the XCD's L2, which at
+// one per tile cost ~15% of the reduction kernels' time).
 template <int ND>
-__device__ bool tile_commit(const Prob &P, int local, double (&hi)[ND], double (&lo)[ND],
-                            double *lds, int *flag, double (&res)[ND])
+__device__ void tile_publish(const Prob &P, int local, double (&hi)[ND], double (&lo)[ND],
+                             double *lds)
 {
     block_reduce_dd<ND>(hi, lo, lds);
     if (threadIdx.x == 0) {
@@ -174,15 +177,13 @@ __device__ bool tile_commit(const Prob &P, int local, double (&hi)[ND], double (
             pp[2 * d] = hi[d];
             pp[2 * d + 1] = lo[d];
         }
-        __threadfence();
-        const unsigned prev = atomicAdd(&P.sc->ticket, 1u);
-        *flag = prev == (unsigned)(P.ntiles - 1);
     }
-    __syncthreads();
-    const bool last = *flag != 0;
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Sum a problem's tile partials in tile order (res valid in thread 0).
+template <int ND>
+__device__ void sum_partials(const Prob &P, double *lds, double (&res)[ND])
+{
     const int nt = P.ntiles;
     const int chunk = (nt + NTHREADS - 1) / NTHREADS;
     const int b0 = threadIdx.x * chunk, b1 = min(b0 + chunk, nt);
@@ -200,9 +201,7 @@ __device__ bool tile_commit(const Prob &P, int local, double (&hi)[ND], double (
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int d = 0; d < ND; ++d) res[d] = h2[d] + l2[d];
-        P.sc->ticket = 0;
     }
-    return true;
 }
 
 // ------------------------------------------------------------------------
@@ -603,7 +602,6 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
                        : (OP == S_SDOT || OP == S_TRUE) ? 1 : 0;
     constexpr int NA = ND > 0 ? ND : 1;
     __shared__ double lds[TY * 2 * 2];
-    __shared__ int flag;
     const int total = W.count_dev ? *W.count_dev : W.count;
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
@@ -633,16 +631,10 @@ __global__ void __launch_bounds__(NTHREADS) k_stencil(Work W, KArgs A)
             }
         }
         if constexpr (ND > 0) {
-            double res[NA];
             double h2[NA], l2[NA];
 #pragma unroll
             for (int d = 0; d < NA; ++d) h2[d] = hi[d], l2[d] = lo[d];
-            if (tile_commit<NA>(P, local, h2, l2, lds, &flag, res) && threadIdx.x == 0) {
-                if constexpr (OP == S_SDOT) fin_sdot(P, res[0]);
-                else if constexpr (OP == S_SDOT2) fin_sdot2(P, res[0], res[1]);
-                else if constexpr (OP == S_INIT) fin_init(P, res[0], res[1]);
-                else if constexpr (OP == S_TRUE) P.sc->rr_true = res[0];
-            }
+            tile_publish<NA>(P, local, h2, l2, lds);
         }
     }
 }
@@ -1335,7 +1327,6 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
     constexpr int ND = OP == E_UPD ? 2 : (OP == E_AXPY || OP == E_DOT) ? 1 : 0;
     constexpr int NA = ND > 0 ? ND : 1;
     __shared__ double lds[TY * 2 * 2];
-    __shared__ int flag;
     const int total = W.count_dev ? *W.count_dev : W.count;
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
 
@@ -1364,14 +1355,7 @@ __global__ void __launch_bounds__(NTHREADS) k_elem(Work W, KArgs A)
 #pragma unroll
             for (int d = 0; d < NA; ++d) hi[d] = h2[d], lo[d] = l2[d];
         }
-        if constexpr (ND > 0) {
-            double res[NA];
-            if (tile_commit<NA>(P, local, hi, lo, lds, &flag, res) && threadIdx.x == 0) {
-                if constexpr (OP == E_AXPY) fin_axpy(P, res[0]);
-                else if constexpr (OP == E_UPD) fin_upd(P, res[0], res[1]);
-                else if constexpr (OP == E_DOT) P.sc->dot = res[0];
-            }
-        }
+        if constexpr (ND > 0) tile_publish<NA>(P, local, hi, lo, lds);
     }
 }
 // ------------------------------------------------------------------------
@@ -1392,6 +1376,55 @@ __global__ void k_fill_uniform(double *out, int64_t n, uint64_t key)
         const double u = (double)(v >> 11) * 0x1.0p-53;
         out[i] = 2.0 * u - 1.0;
     }
+}
+
+// ------------------------------------------------------------------------
+// Scalar epilogue of a reduction: one workgroup per problem sums the problem's
+// tile partials in tile order and updates its scalars (alpha, omega, beta, rho,
+// the stopping tests). Launched right after the reduction kernel, with the same
+// arguments, so it sees the same flags and skips the same problems.
+// ------------------------------------------------------------------------
+enum Fin { F_SDOT, F_SDOT2, F_INIT, F_TRUE, F_AXPY, F_UPD, F_DOT };
+
+template <int F>
+__global__ void __launch_bounds__(NTHREADS) k_finalize(Work W, KArgs A)
+{
+    constexpr int ND = (F == F_SDOT2 || F == F_INIT || F == F_UPD) ? 2 : 1;
+    constexpr bool SKIPS = F == F_SDOT || F == F_SDOT2 || F == F_AXPY || F == F_UPD;
+    __shared__ double lds[TY * 2 * 2];
+    const bool single = W.tile_prob == nullptr;
+    const int total = single ? 1 : (W.count_dev ? *W.count_dev : W.count);
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int pid = 0;
+        if (!single) {
+            if (W.tile_local[g] != 0) continue; // one entry per problem: its first tile
+            pid = W.tile_prob[g];
+        }
+        const Prob &P = W.probs[pid];
+        if constexpr (SKIPS) {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        double res[ND];
+        sum_partials<ND>(P, lds, res);
+        if (threadIdx.x == 0) {
+            if constexpr (F == F_SDOT) fin_sdot(P, res[0]);
+            else if constexpr (F == F_SDOT2) fin_sdot2(P, res[0], res[1]);
+            else if constexpr (F == F_INIT) fin_init(P, res[0], res[1]);
+            else if constexpr (F == F_TRUE) P.sc->rr_true = res[0];
+            else if constexpr (F == F_AXPY) fin_axpy(P, res[0]);
+            else if constexpr (F == F_UPD) fin_upd(P, res[0], res[1]);
+            else if constexpr (F == F_DOT) P.sc->dot = res[0];
+        }
+        __syncthreads(); // lds is reused by the next problem
+    }
+}
+
+template <int F>
+static void lfin(const Work &w, int grid, hipStream_t s, const KArgs &a)
+{
+    const int g = w.tile_prob ? grid : 1;
+    hipLaunchKernelGGL((k_finalize<F>), dim3(g), dim3(NTHREADS), 0, s, w, a);
 }
 
 // ------------------------------------------------------------------------
@@ -1462,13 +1495,21 @@ void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipS
     case S_SDOT:
         if (mixed) ls<S_SDOT, float, double, false>(w, grid, s, a);
         else ls<S_SDOT, double, double, false>(w, grid, s, a);
+        lfin<F_SDOT>(w, grid, s, a);
         break;
     case S_SDOT2:
         if (mixed) ls<S_SDOT2, float, double, false>(w, grid, s, a);
         else ls<S_SDOT2, double, double, false>(w, grid, s, a);
+        lfin<F_SDOT2>(w, grid, s, a);
         break;
-    case S_INIT: ls<S_INIT, double, double, false>(w, grid, s, a); break;
-    case S_TRUE: ls<S_TRUE, double, double, false>(w, grid, s, a); break;
+    case S_INIT:
+        ls<S_INIT, double, double, false>(w, grid, s, a);
+        lfin<F_INIT>(w, grid, s, a);
+        break;
+    case S_TRUE:
+        ls<S_TRUE, double, double, false>(w, grid, s, a);
+        lfin<F_TRUE>(w, grid, s, a);
+        break;
     default: break;
     }
 }
@@ -1482,17 +1523,24 @@ static void le(const Work &w, int grid, hipStream_t s, const KArgs &a)
 void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
     switch (op) {
-    case E_AXPY: le<E_AXPY, double>(w, grid, s, a); break;
+    case E_AXPY:
+        le<E_AXPY, double>(w, grid, s, a);
+        lfin<F_AXPY>(w, grid, s, a);
+        break;
     case E_UPD:
         if (mixed) le<E_UPD, float>(w, grid, s, a);
         else le<E_UPD, double>(w, grid, s, a);
+        lfin<F_UPD>(w, grid, s, a);
         break;
     case E_PUPD: le<E_PUPD, double>(w, grid, s, a); break;
     case E_DIV:
         if (mixed) le<E_DIV, float>(w, grid, s, a);
         else le<E_DIV, double>(w, grid, s, a);
         break;
-    case E_DOT: le<E_DOT, double>(w, grid, s, a); break;
+    case E_DOT:
+        le<E_DOT, double>(w, grid, s, a);
+        lfin<F_DOT>(w, grid, s, a);
+        break;
     default: break;
     }
 }
