@@ -31,8 +31,8 @@ enum {
     ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = -5, ST_NONFINITE = -6
 };
 
-// Per-problem scalar block (device). Written only by the last tile of a
-// reduction kernel, read by every tile at the start of later kernels.
+// Per-problem scalar block (device). Written only by the finalize kernel of a
+// reduction, read by every tile at the start of later kernels.
 struct Scalars {
     double rho, alpha, omega, beta;
     double bb, tol2bb, rr, ss;

@@ -205,7 +205,7 @@ __device__ void sum_partials(const Prob &P, double *lds, double (&res)[ND])
 }
 
 // ------------------------------------------------------------------------
-// scalar epilogues of the reductions (last tile, thread 0)
+// scalar epilogues of the reductions (finalize kernel, thread 0)
 // ------------------------------------------------------------------------
 __device__ __forceinline__ void hist_put(const Prob &P, int it, int slot, double v)
 {
@@ -884,11 +884,11 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 }
 
 // ------------------------------------------------------------------------
-// Two consecutive Chebyshev steps in one pass (temporal blocking, FP64):
+// Two consecutive Chebyshev steps in one pass (temporal blocking; FP64, or
+// FP32 in the mixed mode), for i >= 3:
 //   w_i     = rc_i     ((2 sigma y + (2/delta)(v - A y))   - ro_i     z)
 //   w_{i+1} = rc_{i+1} ((2 sigma w_i + (2/delta)(v - A w_i)) - ro_{i+1} y)
-// with y = y_{i-1} read with the stencil, z = z_{i-2} (or v/theta when i = 2)
-// and v read pointwise. w_i is computed on the wave's rows plus one halo row
+// with y = y_{i-1} read with the stencil, z = z_{i-2} and v read pointwise. w_i is computed on the wave's rows plus one halo row
 // on each side and one plane ahead of w_{i+1}; at its two halo columns it is
 // computed by the halo lanes from the halo values they load anyway plus y one
 // column further out, v and z. Reads y, z, v once and writes w_i and w_{i+1}:
@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_f32x2(Work W, KArgs A)
 // step 2). The stencil input is then v itself, read as TU (FP64 also when the
 // arithmetic is FP32: it is rounded once on load, and the FP32 copy of v that
 // the later steps read is written out).
-template <typename T, typename TU, bool MASK, bool FZ, bool FULL, bool SIMPLE, bool FIRST>
+template <typename T, typename TU, bool MASK, bool FULL, bool SIMPLE, bool FIRST>
 __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, int local, int lane,
                                                int wv)
 {
@@ -1016,10 +1016,10 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 #pragma unroll
             for (int q = 0; q < RW; ++q) {
                 R.v[q] = ld(Vb + po, woff[q]);
-                if constexpr (!FZ) R.z[q] = ld(Zb + po, woff[q]);
+                if constexpr (!FIRST) R.z[q] = ld(Zb + po, woff[q]);
             }
             R.hv = ld(Vb + po, coff);
-            if constexpr (!FZ) R.hz = ld(Zb + po, coff);
+            if constexpr (!FIRST) R.hz = ld(Zb + po, coff);
         }
         R.he = ldy(Yb + pyo, hoff);
         R.hf = ldy(Yb + pyo, foff);
@@ -1062,12 +1062,12 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         for (int q = 0; q < RW; ++q) {
             const bool ok = pin && wok[q];
             vv[q] = FIRST ? yb[q + 1] : (ok ? R.v[q] : (T)0);
-            zz[q] = (!FZ && !FIRST && ok) ? R.z[q] : (T)0;
+            zz[q] = (!FIRST && ok) ? R.z[q] : (T)0;
         }
         const T he = (hload && pin) ? (T)R.he : (T)0;
         const T hfc = (fload && pin) ? (T)R.hf : (T)0;
         const T hvc = (cact && pin) ? R.hv : (T)0;
-        const T hzc = (!FZ && cact && pin) ? R.hz : (T)0;
+        const T hzc = (!FIRST && cact && pin) ? R.hz : (T)0;
         hc = he;
         // issue the next plane's loads before computing this one
         issueY(k + 3, R.y);
@@ -1092,7 +1092,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(wsym[q], yb[q], yb[q + 2]), yp = pick(wsyp[q], yb[q + 2], yb[q]);
                     zm = pick(szm, ya[q + 1], yc[q + 1]), zp = pick(szp, yc[q + 1], ya[q + 1]);
                 }
-                const T z = FZ ? vv[q] / theta : zz[q];
+                const T z = zz[q]; // not read by the first pair's step 1
                 const T w = step1(c, xm, xp, ym, yp, zm, zp, vv[q], z);
                 wc[q] = (pin && wok[q]) ? w : (T)0;
             }
@@ -1123,7 +1123,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(csyl, d, u), yp = pick(csyh, u, d);
                     zm = pick(szl, ha, hc), zp = pick(szh, hc, ha);
                 }
-                const T z = FZ ? hvb / theta : hzb;
+                const T z = hzb;
                 const T w = step1(hb, xm, xp, ym, yp, zm, zp, hvb, z);
                 hw = cact ? w : (T)0;
             }
@@ -1175,7 +1175,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     }
 }
 
-template <typename T, typename TU, bool MASK, bool FZ, bool FIRST>
+template <typename T, typename TU, bool MASK, bool FIRST>
 __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
 {
     const int total = W.count_dev ? *W.count_dev : W.count;
@@ -1196,14 +1196,14 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
         const int j0 = tiy * (TY * RY) + wv * RY;
         const bool full = tix * TX + TX <= P.nx && j0 - 2 >= 0 && j0 + RY + 1 < P.ny;
         if constexpr (MASK) {
-            if (full) cheb_pair_tile<T, TU, true, FZ, true, false, FIRST>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, TU, true, FZ, false, false, FIRST>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, true, true, false, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, true, false, false, FIRST>(P, A, local, lane, wv);
         } else if (P.bc == 0) {
-            if (full) cheb_pair_tile<T, TU, false, FZ, true, true, FIRST>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, TU, false, FZ, false, true, FIRST>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, false, true, true, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, false, false, true, FIRST>(P, A, local, lane, wv);
         } else {
-            if (full) cheb_pair_tile<T, TU, false, FZ, true, false, FIRST>(P, A, local, lane, wv);
-            else cheb_pair_tile<T, TU, false, FZ, false, false, FIRST>(P, A, local, lane, wv);
+            if (full) cheb_pair_tile<T, TU, false, true, false, FIRST>(P, A, local, lane, wv);
+            else cheb_pair_tile<T, TU, false, false, false, FIRST>(P, A, local, lane, wv);
         }
     }
 }
@@ -1453,26 +1453,23 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 }
 
 template <typename T, typename TU, bool FIRST>
-static void lp(bool mask, bool firstz, const Work &w, int grid, hipStream_t s, const KArgs &a)
+static void lp(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    // FZ (z = v/theta, no z input) only for the first pair, whose z is not read
-    (void)firstz;
-    if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
-    else hipLaunchKernelGGL((k_cheb_pair<T, TU, false, FIRST, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
+    else hipLaunchKernelGGL((k_cheb_pair<T, TU, false, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }
 
 void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (mixed) lp<float, float, false>(mask, false, w, grid, s, a);
-    else lp<double, double, false>(mask, false, w, grid, s, a);
+    if (mixed) lp<float, float, false>(mask, w, grid, s, a);
+    else lp<double, double, false>(mask, w, grid, s, a);
 }
 
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                             const KArgs &a)
 {
-    // the first pair has no z input; FZ is irrelevant and fixed
-    if (mixed) lp<float, double, true>(mask, true, w, grid, s, a);
-    else lp<double, double, true>(mask, true, w, grid, s, a);
+    if (mixed) lp<float, double, true>(mask, w, grid, s, a);
+    else lp<double, double, true>(mask, w, grid, s, a);
 }
 
 void launch_stencil(int op, bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

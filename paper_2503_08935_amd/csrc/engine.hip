@@ -2,9 +2,9 @@
 //
 // A solve keeps every Krylov vector resident in HBM and never returns control
 // to the host inside an iteration: the scalars alpha, omega, rho, beta and the
-// stopping tests are computed by the last tile of each fused reduction kernel
-// (the paper computes them on the host after each MPI_Allreduce, Alg. 3 and the
-// alpaka implementation section). The host replays a captured HIP graph of
+// stopping tests are computed on the device by the finalize kernel that follows
+// each fused reduction kernel (the paper computes them on the host after each
+// MPI_Allreduce, Alg. 3 and the alpaka implementation section). The host replays a captured HIP graph of
 // several iterations and reads the convergence flag once per graph.
 #include <algorithm>
 #include <chrono>
