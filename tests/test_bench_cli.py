@@ -1,0 +1,51 @@
+"""bench.py's host-side contract: more than one GPU is refused with a message
+and exit status 2 (this build measures one GPU), and the HBM traffic record of
+profiles/ is well formed and used only while the kernel source is unchanged."""
+import hashlib
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_traffic_record_format_and_source_binding(tmp_path, monkeypatch):
+    b = load_bench()
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2503_08935_amd", "csrc", "device.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    lines = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert lines and all(len(f) == 6 for f in lines)
+    for f in lines:
+        fetch, write, total = float(f[3]), float(f[4]), float(f[5])
+        assert fetch > 0 and write > 0 and abs(fetch + write - total) <= 1.0
+    got = b.traffic_record("device.hip", "cheb_pair_fp64_512^3")
+    recorded = [f for f in lines if f[0] == "cheb_pair_fp64_512^3"]
+    if recorded and recorded[0][2] == sha:
+        assert got == float(recorded[0][5])
+    else:
+        assert got is None  # counters taken on another version of the kernels
+    # a record for another source never matches
+    fake = tmp_path / "profiles"
+    fake.mkdir()
+    (fake / "hbm_traffic.txt").write_text("cheb_pair_fp64_512^3 k 00ff 1 2 3\n")
+    csrc = tmp_path / "paper_2503_08935_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "device.hip").write_text("// not the kernels\n")
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.traffic_record("device.hip", "cheb_pair_fp64_512^3") is None
