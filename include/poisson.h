@@ -89,11 +89,15 @@ enum {
                                            mixed): run Chebyshev steps two per pass (1,
                                            default) or one per pass (0); same arithmetic,
                                            same results */
-    POISSON_OPT_TILE_ORDER = 10         /* order in which workgroups take tiles: 0 default
+    POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the fused Chebyshev
                                            pairs), 1 x-grouped everywhere (the x-tiles of a
                                            tile row on one XCD), 2 slabs (each XCD one
                                            contiguous eighth of the tiles); same results */
+    POISSON_OPT_PAIR_LDS = 11           /* fused Chebyshev pairs on grids whose faces are all
+                                           Dirichlet, without a Block-Jacobi mask: 1 (default)
+                                           stage 128 x 16 tiles in LDS, 0 use the 64 x 16
+                                           register tiles; same arithmetic, same results */
 };
 
 /* ---- solver context ----------------------------------------------------- */

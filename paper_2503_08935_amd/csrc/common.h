@@ -20,6 +20,10 @@ constexpr int RY = 4;           // y rows per wave (a tile is TY*RY rows)
 constexpr int NTHREADS = TX * TY;
 constexpr int MAXDEG = 64;      // largest Chebyshev degree
 constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double sums
+// tiles of the LDS-staged Chebyshev pair: 2*LNXW waves, each 64 columns x LPR rows
+constexpr int LNXW = 2;
+constexpr int LPR = 8;
+constexpr int LX = 64 * LNXW, LY = 2 * LPR;
 
 // vector slots of a problem
 enum Vec {
@@ -49,7 +53,8 @@ struct Prob {
     int maxit, debug_breakdown_at, degree;
     int hist_iters;              // iterations recorded in hist
     unsigned bc;                 // bit f (x-, x+, y-, y+, z-, z+) = Neumann on face f
-    int pad_i[2];
+    int pkz;                     // z-chunk of the LDS-staged pair's LX x LY tiles
+    int pad_i;
     double ih2;                  // 1/(h*h)
     double tol2;                 // tol*tol
     double jac_d;                // diagonal of A = 6*ih2
@@ -71,6 +76,8 @@ struct Work {
     const int *count_dev;        // null: use count
     int count;
     int order;                   // single problem: 0 natural tile order, 1 x-grouped
+    int pair_tiles;              // single problem: > 0 runs the Chebyshev pairs LDS-staged
+                                 // over this many LX x LY x pkz tiles; 0 = register tiles
 };
 
 // operations of the stencil kernel family
@@ -100,6 +107,8 @@ struct KArgs {
     int second;                  // 1: belongs to the second half of the iteration
     int divisor;                 // E_DIV: 0 = jac_d, 1 = theta
     int x2;                      // E_DOT second operand slot / E_UPD s^ slot
+    int drop1;                   // fused pair: 1 = w_i is not stored (the last pair of an
+                                 // apply, whose w_i no later step reads)
 };
 
 // host-side launchers (device.hip)

@@ -1035,10 +1035,14 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     // halo values: y at the halo column on planes k-1, k, k+1 (ha, hb, hc), and
     // at plane k the further column, v and z (hfb, hvb, hzb)
     T ha = (T)0, hb = (T)0, hc = (T)0, hfb = (T)0, hvb = (T)0, hzb = (T)0;
-    Raw R;
+    // D planes of loads in flight: the first pair issues only y and its halo
+    // values, so in FP64 it keeps two planes in flight (measured 769 -> 732 us
+    // at 512^3); in FP32 the extra registers would cost a wave per SIMD
+    constexpr int D = (FIRST && sizeof(T) == 8) ? 2 : 1;
+    Raw R0, R1;
 #pragma unroll
-    for (int q = 0; q < RW; ++q) R.v[q] = R.z[q] = (T)0;
-    R.hv = R.hz = (T)0;
+    for (int q = 0; q < RW; ++q) R0.v[q] = R0.z[q] = R1.v[q] = R1.z[q] = (T)0;
+    R0.hv = R0.hz = R1.hv = R1.hz = (T)0;
     {
         TU t[RYY];
         issueY(k0 - 2, t);
@@ -1046,14 +1050,19 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         issueY(k0 - 1, t);
         takeY(k0 - 1, t, yb);
     }
-    issueY(k0, R.y);
-    issueP(k0 - 1, R);
+    issueY(k0, R0.y);
+    issueP(k0 - 1, R0);
+    if constexpr (D == 2) {
+        issueY(k0 + 1, R1.y);
+        issueP(k0, R1);
+    }
 #pragma unroll
     for (int q = 0; q < RW; ++q) wa[q] = wb[q] = (T)0;
 #pragma unroll
     for (int r = 0; r < RY; ++r) vb[r] = (T)0;
-    for (int k = k0 - 2; k < k1; ++k) {
-        // consume the loads of plane k+2 (y) and k+1 (v, z, halo)
+    // iteration k consumes the loads of plane k+2 (y) and k+1 (v, z, halo)
+    // held in R and refills R with those of planes k+2+D and k+1+D
+    auto iter = [&](int k, Raw &R) {
         const int p = k + 1;
         const bool pin = p >= 0 && p < nz;
         takeY(k + 2, R.y, yc);
@@ -1070,8 +1079,8 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
         const T hzc = (!FIRST && cact && pin) ? R.hz : (T)0;
         hc = he;
         // issue the next plane's loads before computing this one
-        issueY(k + 3, R.y);
-        issueP(k + 2, R);
+        issueY(k + 2 + D, R.y);
+        issueP(k + 1 + D, R);
 
         // w_i at plane p = k+1 on the RW rows, from y planes k (ya), k+1 (yb), k+2 (yc)
         {
@@ -1153,7 +1162,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                 const T z = FIRST ? v / theta : ya[q + 1];
                 const T w2 = rc2 * ((ts * c + tod * (v - a)) - ro2 * z);
                 if (wok[q]) {
-                    st_nt((T *)(W1b + po + woff[q]), c);
+                    if (!A.drop1) st_nt((T *)(W1b + po + woff[q]), c);
                     st_nt((T *)(W2b + po + woff[q]), w2);
                     if constexpr (FIRST && sizeof(T) == 4) st_nt((T *)(V32b + po + woff[q]), v);
                 }
@@ -1172,6 +1181,15 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
 #pragma unroll
         for (int r = 0; r < RY; ++r) vb[r] = vc[r];
         ha = hb, hb = hc, hfb = hfc, hvb = hvc, hzb = hzc;
+    };
+    if constexpr (D == 1) {
+        for (int k = k0 - 2; k < k1; ++k) iter(k, R0);
+    } else {
+        // two iterations per trip, so each raw buffer stays in registers
+        for (int k = k0 - 2; k < k1; k += 2) {
+            iter(k, R0);
+            if (k + 1 < k1) iter(k + 1, R1);
+        }
     }
 }
 
@@ -1205,6 +1223,322 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
             if (full) cheb_pair_tile<T, TU, false, true, false, FIRST>(P, A, local, lane, wv);
             else cheb_pair_tile<T, TU, false, false, false, FIRST>(P, A, local, lane, wv);
         }
+    }
+}
+
+// ------------------------------------------------------------------------
+// The fused pair over wide tiles staged in LDS, for grids whose faces are all
+// Dirichlet and without a block mask. A workgroup of 2*NXW waves covers
+// 64*NXW columns x 2*PR rows x kz planes. Wave (xw, yw) owns 64 columns x PR
+// rows; a top wave (yw = 0) also holds the tile's halo row above, a bottom
+// wave the halo row below, so w_i is computed on the tile plus its halo ring.
+// Per plane every wave writes its rows of y and of w_i to LDS, and the lanes
+// at the two halo columns write theirs. A wave then takes the values other
+// waves own (the row across the wave boundary, the column beyond its first
+// and last lane) from LDS instead of loading them again, and the tile's halo
+// lines are fetched once for a perimeter of a 64*NXW x 2*PR tile. Two LDS
+// buffers per field, alternating by plane, take one barrier per plane. The
+// plane loop is pipelined as in cheb_pair_tile, and the arithmetic per point
+// is exactly that of two k_stencil steps.
+// ------------------------------------------------------------------------
+template <int NXW, int PR> struct LPair {
+    static constexpr int X = 64 * NXW, Y = 2 * PR;
+    static constexpr int PW = X + 2, PH = Y + 2; // LDS plane: rows -1..Y, columns -1..X
+    static constexpr int PLANE = PW * PH;
+    static constexpr int NT = 128 * NXW;
+};
+
+template <typename T, typename TU, bool FIRST, int NXW, int PR, bool TOP>
+__device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A, int tile,
+                                                   int lane, int xw, T *lds)
+{
+    using L = LPair<NXW, PR>;
+    constexpr int E = PR + 1;           // rows held: PR own rows and the halo row outside them
+    constexpr int EOWN = TOP ? 1 : 0;   // first own row among the held rows
+    constexpr int ERING = TOP ? 0 : PR; // the halo row among them
+    constexpr int TRO = TOP ? -2 : 2 * PR + 1; // tile row of the outer row (y only)
+    auto trow = [](int e) { return TOP ? e - 1 : PR + e; };
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int ltx = (nx + L::X - 1) / L::X, lty = (ny + L::Y - 1) / L::Y;
+    const int tix = tile % ltx, tiy = (tile / ltx) % lty, tiz = tile / (ltx * lty);
+    const int x0 = tix * L::X, y0 = tiy * L::Y;
+    const int k0 = tiz * P.pkz, k1 = min(k0 + P.pkz, nz);
+    const int cx = xw * 64 + lane; // tile column of the lane
+    const int i = x0 + cx;
+    const bool xin = i < nx;
+    const int ic = xin ? i : nx - 1;
+    const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
+    const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU);
+    const char *Yb = (const char *)P.vec[A.in];
+    const char *Vb = (const char *)P.vec[A.v];
+    const char *Zb = (const char *)P.vec[A.z];
+    char *W1b = (char *)P.vec[A.out];
+    char *W2b = (char *)P.vec[A.x2];
+    char *V32b = (char *)P.vec[V_V32];
+    const T ih2 = Coef<T>::ih2(P), theta = Coef<T>::theta(P);
+    const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
+    const T rc1 = Coef<T>::rc(P, A.step), ro1 = Coef<T>::ro(P, A.step);
+    const T rc2 = Coef<T>::rc(P, A.step + 1), ro2 = Coef<T>::ro(P, A.step + 1);
+    const T c1 = Coef<T>::c1(P);
+    auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
+    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto offy = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(TU); };
+    auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
+    auto ldy = [](const char *plane, unsigned o) { return ld_g((const TU *)(plane + o)); };
+    // LDS element of tile row r (-1..Y) and tile column c (-1..X)
+    auto lidx = [](int r, int c) { return (r + 1) * L::PW + (c + 1); };
+
+    bool rok[E];
+    unsigned roff[E], ryoff[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = y0 + trow(e);
+        rok[e] = xin && j >= 0 && j < ny;
+        roff[e] = off(ic, clampi(j, ny));
+        ryoff[e] = offy(ic, clampi(j, ny));
+    }
+    const int jo = y0 + TRO;
+    const bool ook = xin && jo >= 0 && jo < ny;
+    const unsigned ooff = offy(ic, clampi(jo, ny));
+    // own position in LDS (held row 0); row e adds e*PW. The lane's x
+    // neighbour across the wave edge: column cx-1 for lane 0, cx+1 for lane 63.
+    const int lown = lidx(trow(0), cx);
+    const int lpatch = lown + (lane == 0 ? -1 : (lane == 63 ? 1 : 0));
+    // the row across the wave's inner boundary, at the lane's column
+    const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
+
+    // Halo lanes: lane e (< E) of the leftmost waves holds tile column -1 of
+    // held row e, lane 32+e of the rightmost waves column X. Both write their y
+    // value to LDS; on own rows they also compute w_i there, for which they
+    // load y one column further out, v and z.
+    const bool hside = lane >= 32;
+    const int eh = min(lane & 31, PR);
+    const bool hwave = hside ? xw == NXW - 1 : xw == 0;
+    const bool hact = hwave && (lane & 31) < E;
+    const int hcol = hside ? L::X : -1;
+    const int hi = x0 + hcol, hfi = hside ? hi + 1 : hi - 1;
+    const int hj = y0 + trow(eh);
+    const bool hrow = hj >= 0 && hj < ny;
+    const bool hload = hact && hrow && hi >= 0 && hi < nx;
+    const bool hown = hact && eh != ERING;
+    const bool cact = hown && hload;
+    const bool fload = hown && hrow && hfi >= 0 && hfi < nx;
+    const unsigned hoff = offy(clampi(hi, nx), clampi(hj, ny));
+    const unsigned foff = offy(clampi(hfi, nx), clampi(hj, ny));
+    const unsigned coff = off(clampi(hi, nx), clampi(hj, ny));
+    const int lhself = lidx(trow(eh), hcol);
+    const int lhin = lidx(trow(eh), hside ? L::X - 1 : 0);
+    const int lhup = lidx(max(trow(eh) - 1, -1), hcol), lhdn = lidx(min(trow(eh) + 1, L::Y), hcol);
+
+    auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z) {
+        const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        if constexpr (FIRST) return c1 * ((T)2 * yc - a / theta);
+        else return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
+    };
+    // Loads in flight: y (held rows, outer row, halo column) one plane ahead,
+    // issued as soon as the previous plane is taken; v, z (held rows and halo
+    // column points) and y one column further out, issued after step i of
+    // the plane before their own and consumed straight from these registers.
+    struct RawY {
+        TU y[E], yo, he;
+    };
+    struct RawV {
+        T v[E], z[E], hv, hz;
+        TU hf;
+    };
+    auto issueY = [&](int p, RawY &R) {
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PBY;
+#pragma unroll
+        for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
+        R.yo = ldy(Yp, ooff);
+        R.he = ldy(Yp, hoff);
+    };
+    auto issueV = [&](int p, RawV &R) {
+        const size_t po = (size_t)clampi(p, nz) * PB;
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                R.v[e] = ld(Vb + po, roff[e]);
+                R.z[e] = ld(Zb + po, roff[e]);
+            }
+            R.hv = ld(Vb + po, coff);
+            R.hz = ld(Zb + po, coff);
+        }
+        R.hf = ldy(Yb + (size_t)clampi(p, nz) * PBY, foff);
+    };
+    auto bufy = [&](int k) { return lds + (k & 1) * L::PLANE; };
+    auto bufw = [&](int k) { return lds + (2 + (k & 1)) * L::PLANE; };
+
+    // registers across planes: y at plane k-1 (ya), w_i at plane k-2 (wa) and
+    // v at plane k-1 (vb) on the held rows; y at plane k and w_i at plane k-1
+    // are read back from LDS where they are needed
+    T ya[E], wa[E], vb[E];
+    T yob, ha;
+    RawY RY;
+    RawV RV;
+#pragma unroll
+    for (int e = 0; e < E; ++e) RV.v[e] = RV.z[e] = (T)0;
+    RV.hv = RV.hz = (T)0;
+    {
+        // planes k0-2 and k0-1 of y; plane k0-1 into LDS
+        RawY t;
+        issueY(k0 - 2, t);
+        {
+            const bool pin = k0 - 2 >= 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
+            ha = (pin && hload) ? (T)t.he : (T)0;
+        }
+        issueY(k0 - 1, t);
+        {
+            const bool pin = k0 - 1 >= 0;
+            T *yd = bufy(k0 - 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
+            yob = (pin && ook) ? (T)t.yo : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? (T)t.he : (T)0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) wa[e] = vb[e] = (T)0;
+    issueY(k0, RY);
+    issueV(k0 - 1, RV);
+    __syncthreads();
+
+    for (int k = k0 - 1; k <= k1; ++k) {
+        const bool pin1 = k + 1 >= 0 && k + 1 < nz, pin0 = k >= 0 && k < nz;
+        // take y at plane k+1, publish it for the next plane, issue plane k+2
+        T yc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? (T)RY.y[e] : (T)0;
+        const T yoc = (pin1 && ook) ? (T)RY.yo : (T)0;
+        const T hc = (pin1 && hload) ? (T)RY.he : (T)0;
+        {
+            T *yd = bufy(k + 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = yc[e];
+            if (hact) yd[lhself] = hc;
+        }
+        issueY(k + 2, RY);
+
+        // w_i at plane k on the held rows, from y planes k-1 (ya), k (LDS), k+1 (yc)
+        const T *ys = bufy(k);
+        T wc[E], vc[E];
+        {
+            const T inner = ys[linner];
+            T cen[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) cen[e] = ys[lown + e * L::PW];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T c = cen[e];
+                const T pv = lane_prev(c), nv = lane_next(c);
+                const T patch = ys[lpatch + e * L::PW];
+                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T ym, yp;
+                if constexpr (TOP) {
+                    ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
+                    yp = e == E - 1 ? inner : cen[e < E - 1 ? e + 1 : e];
+                } else {
+                    ym = e == 0 ? inner : cen[e > 0 ? e - 1 : 0];
+                    yp = e == E - 1 ? yob : cen[e < E - 1 ? e + 1 : e];
+                }
+                const bool ok = pin0 && rok[e];
+                const T v = FIRST ? c : (ok ? RV.v[e] : (T)0);
+                const T z = (!FIRST && ok) ? RV.z[e] : (T)0;
+                vc[e] = v;
+                const T w = step1(c, xm, xp, ym, yp, ya[e], yc[e], v, z);
+                wc[e] = ok ? w : (T)0;
+            }
+        }
+        // w_i at the halo-column points of the own rows
+        T hb, hw;
+        {
+            hb = ys[lhself];
+            const T xn = ys[lhin], d = ys[lhup], u = ys[lhdn];
+            const T hf = (fload && pin0) ? (T)RV.hf : (T)0;
+            const T hv = (!FIRST && cact && pin0) ? RV.hv : (T)0;
+            const T hz = (!FIRST && cact && pin0) ? RV.hz : (T)0;
+            const T l = hside ? xn : hf, r = hside ? hf : xn;
+            const T w = step1(hb, l, r, d, u, ha, hc, hv, hz);
+            hw = (cact && pin0) ? w : (T)0;
+        }
+        {
+            T *wd = bufw(k);
+#pragma unroll
+            for (int e = 0; e < E; ++e) wd[lown + e * L::PW] = wc[e];
+            if (hown) wd[lhself] = hw;
+        }
+        issueV(k + 1, RV);
+
+        // w_{i+1} at plane k-1 from w_i at planes k-2 (wa), k-1 (LDS), k (wc)
+        const T *ws = bufw(k - 1);
+        T wcen[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) wcen[e] = ws[lown + e * L::PW];
+        if (k - 1 >= k0) {
+            const T inner = ws[linner];
+            const size_t po = (size_t)(k - 1) * PB;
+#pragma unroll
+            for (int e = EOWN; e < EOWN + PR; ++e) {
+                const T c = wcen[e];
+                const T pv = lane_prev(c), nv = lane_next(c);
+                const T patch = ws[lpatch + e * L::PW];
+                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T ym, yp;
+                if constexpr (TOP) {
+                    ym = wcen[e - 1];
+                    yp = e == E - 1 ? inner : wcen[e < E - 1 ? e + 1 : e];
+                } else {
+                    ym = e == 0 ? inner : wcen[e > 0 ? e - 1 : 0];
+                    yp = wcen[e + 1];
+                }
+                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - wa[e]) - wc[e]) * ih2;
+                // step i+1 reads z = y_{i-1}, the pair's stencil input at plane k-1
+                // (for the first pair, z = v/theta with v = that input)
+                const T v = FIRST ? ya[e] : vb[e];
+                const T z = FIRST ? v / theta : ya[e];
+                const T w2 = rc2 * ((ts * c + tod * (v - a)) - ro2 * z);
+                if (rok[e]) {
+                    if (!A.drop1) st_nt((T *)(W1b + po + roff[e]), c);
+                    st_nt((T *)(W2b + po + roff[e]), w2);
+                    if constexpr (FIRST && sizeof(T) == 4) st_nt((T *)(V32b + po + roff[e]), v);
+                }
+            }
+        }
+        // y at plane k for the next plane's z neighbour
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            ya[e] = ys[lown + e * L::PW];
+            wa[e] = wcen[e];
+            vb[e] = vc[e];
+        }
+        yob = yoc;
+        ha = hb;
+        __syncthreads();
+    }
+}
+
+template <typename T, typename TU, bool FIRST, int NXW, int PR>
+__global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
+{
+    using L = LPair<NXW, PR>;
+    __shared__ T lds[4 * L::PLANE];
+    const Prob &P = W.probs[0];
+    if (P.pkz < 1) return;
+    {
+        const Scalars *sc = P.sc;
+        if (sc->done || (A.second && sc->half_pending)) return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int xw = wv % NXW, yw = wv / NXW;
+    const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
+    const int total = ltx * lty * ((P.nz + P.pkz - 1) / P.pkz);
+    // every wave runs the same number of barriers: the tile loop and the plane
+    // loop depend only on the workgroup's tiles
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        if (yw == 0) cheb_pair_lds_tile<T, TU, FIRST, NXW, PR, true>(P, A, g, lane, xw, lds);
+        else cheb_pair_lds_tile<T, TU, FIRST, NXW, PR, false>(P, A, g, lane, xw, lds);
     }
 }
 
@@ -1455,6 +1789,11 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 template <typename T, typename TU, bool FIRST>
 static void lp(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
+    if (!mask && !w.tile_prob && w.pair_tiles > 0) {
+        hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, LNXW, LPR>), dim3(w.pair_tiles),
+                           dim3(LPair<LNXW, LPR>::NT), 0, s, w, a);
+        return;
+    }
     if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
     else hipLaunchKernelGGL((k_cheb_pair<T, TU, false, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }

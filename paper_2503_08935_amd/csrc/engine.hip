@@ -24,11 +24,11 @@ using namespace pz;
 namespace {
 
 struct GraphKey {
-    int pc, deg, mixed, iters, fuse, order;
+    int pc, deg, mixed, iters, fuse, order, pair_tiles;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(pc, deg, mixed, iters, fuse, order) <
-               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order);
+        return std::tie(pc, deg, mixed, iters, fuse, order, pair_tiles) <
+               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order, o.pair_tiles);
     }
 };
 
@@ -44,6 +44,7 @@ struct poisson_ctx {
     hipStream_t stream = nullptr;
     // options
     int precision = POISSON_FP64, graph_iters = 8, use_graph = 1, tile_order = 0;
+    int pair_lds = 1;
     PlanOpts opt;
     // tiling
     int ntiles = 1;
@@ -116,6 +117,15 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
     return POISSON_OK;
 }
 
+// the work list of a single problem (prob = d_prob or d_prob + 1): all tiles in
+// the chosen order; the Chebyshev pairs LDS-staged where the grid allows it
+// (all faces Dirichlet; the launcher also requires no block mask)
+Work single_work(const poisson_ctx *c, const Prob *prob)
+{
+    const int pt = (c->pair_lds && c->bc == 0) ? make_pair_tiling(c->nx, c->ny, c->nz).ntiles : 0;
+    return Work{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, pt};
+}
+
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 {
     return fill_prob(p, c->nx, c->ny, c->nz, c->h, c->bc, pc, deg, c->opt, tol, maxit,
@@ -124,13 +134,13 @@ int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
 {
-    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order};
+    const Work w = single_work(c, c->d_prob);
+    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order, w.pair_tiles};
     auto it = c->graphs.find(k);
     if (it != c->graphs.end()) {
         *out = it->second;
         return POISSON_OK;
     }
-    Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i)
@@ -195,7 +205,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     c->plan_fuse = fused(pc, deg, mixed, c->opt.fuse);
     if ((rc = upload_prob(c, 0)) != POISSON_OK) return rc;
 
-    const Work w{c->d_prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+    const Work w = single_work(c, c->d_prob);
     launch_stencil(S_INIT, false, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
     HIPCHK(hipGetLastError());
     if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -342,6 +352,10 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         if (v != 0 && v != 1 && v != 2) return POISSON_ERR_ARG;
         c->tile_order = (int)v;
         return POISSON_OK;
+    case POISSON_OPT_PAIR_LDS:
+        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        c->pair_lds = (int)v;
+        return POISSON_OK;
     default:
         return POISSON_ERR_ARG;
     }
@@ -458,7 +472,7 @@ int poisson_apply_operator(poisson_ctx *c, const double *u, double *out)
         c->h_prob[1].vec[V_B] = (void *)u;
         c->h_prob[1].vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+        const Work w = single_work(c, c->d_prob + 1);
         launch_stencil(S_APPLY, false, false, w, c->ntiles, c->stream, KArgs{V_B, V_X, 0, 0, 0, 0, 0, 0});
         HIPCHK(hipGetLastError());
         return POISSON_OK;
@@ -485,7 +499,7 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
         p.vec[V_B] = (void *)v;
         p.vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+        const Work w = single_work(c, c->d_prob + 1);
         enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, c->opt.fuse, V_B, V_X, 0);
         HIPCHK(hipGetLastError());
         return POISSON_OK;
@@ -504,7 +518,7 @@ int poisson_dot(poisson_ctx *c, const double *x, const double *y, double *result
         c->h_prob[1].vec[V_X] = (void *)x;
         c->h_prob[1].vec[V_B] = (void *)y;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+        const Work w = single_work(c, c->d_prob + 1);
         launch_elem(E_DOT, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, V_B});
         HIPCHK(hipGetLastError());
         if ((rc = read_scalars(c, 1)) != POISSON_OK) return rc;
@@ -565,7 +579,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
         HIPCHK(hipMemcpyAsync(c->d_sc + 1, c->h_sc + 1, sizeof(Scalars), hipMemcpyHostToDevice,
                               c->stream));
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
-        const Work w{c->d_prob + 1, nullptr, nullptr, nullptr, c->ntiles, c->tile_order};
+        const Work w = single_work(c, c->d_prob + 1);
         for (int r = 0; r < reps; ++r) {
             if (kernel == POISSON_KERNEL_CHEB_STEP)
                 launch_stencil(S_CHEBK, mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->ntiles,

@@ -110,6 +110,21 @@ Tiling make_tiling(int nx, int ny, int nz)
     return t;
 }
 
+Tiling make_pair_tiling(int nx, int ny, int nz)
+{
+    Tiling t;
+    t.tx = (nx + LX - 1) / LX;
+    t.ty = (ny + LY - 1) / LY;
+    // same rule as the register tiles: the longest chunk that leaves >= 1024 tiles
+    int kz = 64;
+    const long base = (long)t.tx * t.ty;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < 1024) kz /= 2;
+    t.kz = std::min(kz, std::max(nz, 1));
+    t.tz = (nz + t.kz - 1) / t.kz;
+    t.ntiles = t.tx * t.ty * t.tz;
+    return t;
+}
+
 bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI; }
 
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
@@ -129,6 +144,7 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
     const Tiling t = make_tiling(nx, ny, nz);
     p.nx = nx; p.ny = ny; p.nz = nz; p.kz = t.kz;
     p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
+    p.pkz = make_pair_tiling(nx, ny, nz).kz;
     p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
     p.bc = bc;
     p.maxit = maxit;
@@ -242,8 +258,10 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
             int o[2], n = 0;
             for (int b : ring)
                 if (b != y && b != z && n < 2) o[n++] = b;
-            const int w2 = i + 1 == m ? vout : o[1];
-            launch_cheb_pair(mixed, mask, w, grid, s, KArgs{y, o[0], vsrc, z, i, second, 0, w2});
+            const bool last = i + 1 == m;
+            const int w2 = last ? vout : o[1];
+            launch_cheb_pair(mixed, mask, w, grid, s,
+                             KArgs{y, o[0], vsrc, z, i, second, 0, w2, last ? 1 : 0});
             z = o[0];
             y = w2;
         }
@@ -295,6 +313,7 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse)
             int steps = m - 2;
             pcb += (steps / 2) * 5 * tc;                // pairs: y, z, v in; w_i, w_{i+1} out
             if (steps & 1) pcb += 4 * tc;               // last step alone: y, v, z, w
+            else if (steps >= 2) pcb -= tc;             // the last pair stores w_m only
         } else {
             pcb = 8 + tc + (mixed ? 4 : 0);             // first step: v, y (+ v32)
             if (m >= 2) pcb += 3 * tc;                  // step 2: y, v, w

@@ -76,3 +76,27 @@ def test_preconditioner_bitwise(gpu, pc, m, block, mixed, shape):
         got = host(out).astype(np.float64)
     ref = oracle.precond(v, h, pc, degree=m, mixed=mixed, block=block or 64)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("shape", [(200, 37, 21), (128, 16, 8), (64, 16, 70), (3, 50, 2),
+                                   (2, 1, 7), (257, 33, 9)])
+def test_lds_pairs_match_register_pairs(gpu, mixed, shape):
+    """The fused Chebyshev pairs staged in LDS over 128 x 16 tiles (the default on
+    all-Dirichlet grids) against the 64 x 16 register tiles and the oracle, bitwise:
+    ragged x, y and z tails, a tile whose second wave column lies outside the grid,
+    two-plane and single-row grids; odd and even degrees (an odd degree ends with a
+    single step, an even one with a pair that stores w_m only)."""
+    nx, ny, nz = shape
+    h = 1.0 / (nx + 1)
+    v = workloads.uniform_grid(9, shape)
+    dt = torch.float32 if mixed else torch.float64
+    for m in (3, 4, 8, 9):
+        got = []
+        for lds in (1, 0):
+            with P.Solver(shape, h, precision=P.MIXED if mixed else P.FP64, pair_lds=lds) as s:
+                out = torch.empty(v.shape, dtype=dt, device=gpu)
+                s.apply_precond(P.PC_CHEBYSHEV, m, dev(v), out)
+                got.append(host(out).astype(np.float64))
+        assert np.array_equal(got[0], got[1]), m
+        assert np.array_equal(got[0], oracle.precond(v, h, P.PC_CHEBYSHEV, degree=m, mixed=mixed))
