@@ -20,10 +20,11 @@ constexpr int RY = 4;           // y rows per wave (a tile is TY*RY rows)
 constexpr int NTHREADS = TX * TY;
 constexpr int MAXDEG = 64;      // largest Chebyshev degree
 constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double sums
-// tiles of the LDS-staged Chebyshev pair: 2*LNXW waves, each 64 columns x LPR rows
-constexpr int LNXW = 2;
+// tiles of the LDS-staged Chebyshev pair: 2*nxw waves, each 64 columns x LPR rows;
+// 128 columns in FP64, 256 in FP32 (measured fastest at 512^3 for each)
 constexpr int LPR = 8;
-constexpr int LX = 64 * LNXW, LY = 2 * LPR;
+constexpr int LY = 2 * LPR;
+constexpr int pair_nxw(bool fp32) { return fp32 ? 4 : 2; }
 
 // vector slots of a problem
 enum Vec {
@@ -53,8 +54,7 @@ struct Prob {
     int maxit, debug_breakdown_at, degree;
     int hist_iters;              // iterations recorded in hist
     unsigned bc;                 // bit f (x-, x+, y-, y+, z-, z+) = Neumann on face f
-    int pkz;                     // z-chunk of the LDS-staged pair's LX x LY tiles
-    int pad_i;
+    int pkz[2];                  // z-chunk of the LDS-staged pair's tiles: [0] FP64, [1] FP32
     double ih2;                  // 1/(h*h)
     double tol2;                 // tol*tol
     double jac_d;                // diagonal of A = 6*ih2
@@ -76,8 +76,8 @@ struct Work {
     const int *count_dev;        // null: use count
     int count;
     int order;                   // single problem: 0 natural tile order, 1 x-grouped
-    int pair_tiles;              // single problem: > 0 runs the Chebyshev pairs LDS-staged
-                                 // over this many LX x LY x pkz tiles; 0 = register tiles
+    int pair_tiles[2];           // single problem: > 0 runs the Chebyshev pairs LDS-staged
+                                 // over this many tiles ([0] FP64, [1] FP32); 0 = register tiles
 };
 
 // operations of the stencil kernel family

@@ -61,21 +61,27 @@ template <typename T> __device__ __forceinline__ T ld_g(const T *p)
 // XCD x the x-th eighth of all tiles, a contiguous range of whole tile rows,
 // when the tile count is a multiple of 8.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int tile_order(int order, const Work &W, const Prob &P, int g,
-                                          int total)
+__device__ __forceinline__ int tile_order_tx(int order, int tx, int g, int total)
 {
-    if (!order || W.tile_prob) return g;
     if (order == 2) {
         // workgroup g runs on XCD g % 8: XCD x takes the x-th eighth of the tiles
         // (whole tile rows and z-slabs), so x and y neighbours share its L2
         if (total % 8) return g;
         return (g % 8) * (total / 8) + g / 8;
     }
-    const int tx = P.tx, grp = 8 * tx;
+    if (order != 1) return g;
+    const int grp = 8 * tx;
     const int base = (g / grp) * grp;
     if (base + grp > total) return g;
     const int d = g - base;
     return base + (d & 7) * tx + (d >> 3);
+}
+
+__device__ __forceinline__ int tile_order(int order, const Work &W, const Prob &P, int g,
+                                          int total)
+{
+    if (!order || W.tile_prob) return g;
+    return tile_order_tx(order, P.tx, g, total);
 }
 
 // ------------------------------------------------------------------------
@@ -1248,7 +1254,7 @@ template <int NXW, int PR> struct LPair {
     static constexpr int NT = 128 * NXW;
 };
 
-template <typename T, typename TU, bool FIRST, int NXW, int PR, bool TOP>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP>
 __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A, int tile,
                                                    int lane, int xw, T *lds)
 {
@@ -1262,7 +1268,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     const int ltx = (nx + L::X - 1) / L::X, lty = (ny + L::Y - 1) / L::Y;
     const int tix = tile % ltx, tiy = (tile / ltx) % lty, tiz = tile / (ltx * lty);
     const int x0 = tix * L::X, y0 = tiy * L::Y;
-    const int k0 = tiz * P.pkz, k1 = min(k0 + P.pkz, nz);
+    const int pkz = P.pkz[sizeof(T) == 4];
+    const int k0 = tiz * pkz, k1 = min(k0 + pkz, nz);
     const int cx = xw * 64 + lane; // tile column of the lane
     const int i = x0 + cx;
     const bool xin = i < nx;
@@ -1500,7 +1507,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
                 const T z = FIRST ? v / theta : ya[e];
                 const T w2 = rc2 * ((ts * c + tod * (v - a)) - ro2 * z);
                 if (rok[e]) {
-                    if (!A.drop1) st_nt((T *)(W1b + po + roff[e]), c);
+                    if constexpr (!DROP) st_nt((T *)(W1b + po + roff[e]), c);
                     st_nt((T *)(W2b + po + roff[e]), w2);
                     if constexpr (FIRST && sizeof(T) == 4) st_nt((T *)(V32b + po + roff[e]), v);
                 }
@@ -1519,13 +1526,16 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     }
 }
 
-template <typename T, typename TU, bool FIRST, int NXW, int PR>
+// DROP: the last pair of an apply, which stores w_{i+1} only (a kernel of its
+// own, so that profiles report the two traffic figures apart)
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR>
 __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
 {
     using L = LPair<NXW, PR>;
     __shared__ T lds[4 * L::PLANE];
     const Prob &P = W.probs[0];
-    if (P.pkz < 1) return;
+    const int pkz = P.pkz[sizeof(T) == 4];
+    if (pkz < 1) return;
     {
         const Scalars *sc = P.sc;
         if (sc->done || (A.second && sc->half_pending)) return;
@@ -1533,12 +1543,15 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int xw = wv % NXW, yw = wv / NXW;
     const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
-    const int total = ltx * lty * ((P.nz + P.pkz - 1) / P.pkz);
+    const int total = ltx * lty * ((P.nz + pkz - 1) / pkz);
     // every wave runs the same number of barriers: the tile loop and the plane
     // loop depend only on the workgroup's tiles
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        if (yw == 0) cheb_pair_lds_tile<T, TU, FIRST, NXW, PR, true>(P, A, g, lane, xw, lds);
-        else cheb_pair_lds_tile<T, TU, FIRST, NXW, PR, false>(P, A, g, lane, xw, lds);
+        // x-grouped unless another order is asked for: the tiles of a tile row
+        // share the L2 that holds their common halo columns
+        const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        if (yw == 0) cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true>(P, A, t, lane, xw, lds);
+        else cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false>(P, A, t, lane, xw, lds);
     }
 }
 
@@ -1789,9 +1802,19 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 template <typename T, typename TU, bool FIRST>
 static void lp(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (!mask && !w.tile_prob && w.pair_tiles > 0) {
-        hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, LNXW, LPR>), dim3(w.pair_tiles),
-                           dim3(LPair<LNXW, LPR>::NT), 0, s, w, a);
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int NXW = pair_nxw(F32);
+    if (!mask && !w.tile_prob && w.pair_tiles[F32] > 0) {
+        const dim3 grid_l(w.pair_tiles[F32]), block_l(LPair<NXW, LPR>::NT);
+        if constexpr (!FIRST) {
+            if (a.drop1) {
+                hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, false, true, NXW, LPR>), grid_l,
+                                   block_l, 0, s, w, a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, false, NXW, LPR>), grid_l, block_l, 0, s,
+                           w, a);
         return;
     }
     if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);

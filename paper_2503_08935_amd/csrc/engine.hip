@@ -24,11 +24,11 @@ using namespace pz;
 namespace {
 
 struct GraphKey {
-    int pc, deg, mixed, iters, fuse, order, pair_tiles;
+    int pc, deg, mixed, iters, fuse, order, pair_lds;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(pc, deg, mixed, iters, fuse, order, pair_tiles) <
-               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order, o.pair_tiles);
+        return std::tie(pc, deg, mixed, iters, fuse, order, pair_lds) <
+               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order, o.pair_lds);
     }
 };
 
@@ -122,8 +122,10 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 // (all faces Dirichlet; the launcher also requires no block mask)
 Work single_work(const poisson_ctx *c, const Prob *prob)
 {
-    const int pt = (c->pair_lds && c->bc == 0) ? make_pair_tiling(c->nx, c->ny, c->nz).ntiles : 0;
-    return Work{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, pt};
+    Work w{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, {0, 0}};
+    if (c->pair_lds && c->bc == 0)
+        for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
+    return w;
 }
 
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
@@ -135,7 +137,7 @@ int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
 {
     const Work w = single_work(c, c->d_prob);
-    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order, w.pair_tiles};
+    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order, w.pair_tiles[0] > 0};
     auto it = c->graphs.find(k);
     if (it != c->graphs.end()) {
         *out = it->second;

@@ -110,10 +110,11 @@ Tiling make_tiling(int nx, int ny, int nz)
     return t;
 }
 
-Tiling make_pair_tiling(int nx, int ny, int nz)
+Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32)
 {
     Tiling t;
-    t.tx = (nx + LX - 1) / LX;
+    const int lx = 64 * pair_nxw(fp32);
+    t.tx = (nx + lx - 1) / lx;
     t.ty = (ny + LY - 1) / LY;
     // same rule as the register tiles: the longest chunk that leaves >= 1024 tiles
     int kz = 64;
@@ -144,7 +145,8 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
     const Tiling t = make_tiling(nx, ny, nz);
     p.nx = nx; p.ny = ny; p.nz = nz; p.kz = t.kz;
     p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
-    p.pkz = make_pair_tiling(nx, ny, nz).kz;
+    p.pkz[0] = make_pair_tiling(nx, ny, nz, false).kz;
+    p.pkz[1] = make_pair_tiling(nx, ny, nz, true).kz;
     p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
     p.bc = bc;
     p.maxit = maxit;

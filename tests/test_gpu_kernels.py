@@ -82,8 +82,9 @@ def test_preconditioner_bitwise(gpu, pc, m, block, mixed, shape):
 @pytest.mark.parametrize("shape", [(200, 37, 21), (128, 16, 8), (64, 16, 70), (3, 50, 2),
                                    (2, 1, 7), (257, 33, 9)])
 def test_lds_pairs_match_register_pairs(gpu, mixed, shape):
-    """The fused Chebyshev pairs staged in LDS over 128 x 16 tiles (the default on
-    all-Dirichlet grids) against the 64 x 16 register tiles and the oracle, bitwise:
+    """The fused Chebyshev pairs staged in LDS over 128 x 16 (FP64) and 256 x 16 (FP32)
+    tiles (the default on all-Dirichlet grids) against the 64 x 16 register tiles and
+    the oracle, bitwise:
     ragged x, y and z tails, a tile whose second wave column lies outside the grid,
     two-plane and single-row grids; odd and even degrees (an odd degree ends with a
     single step, an even one with a pair that stores w_m only)."""
