@@ -310,7 +310,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": round(k_gbps / PEAK_HBM_GBPS, 4),
                 "traffic": traffic_record("device.hip", workload),
-                "kernel": "k_cheb_pair_lds<double,double,false,false,2,8>", "kernel_us": round(k_ms * 1e3, 2),
+                "kernel": "k_cheb_pair_lds<double,double,false,false,2,8,false,true>", "kernel_us": round(k_ms * 1e3, 2),
                 "bytes_per_launch": k_bytes,
                 "single_step": {"kernel": "k_stencil<S_CHEBK,double,double,false>",
                                 "kernel_us": round(s_ms * 1e3, 2), "bytes_per_launch": s_bytes,

@@ -94,8 +94,7 @@ enum {
                                            pairs), 1 x-grouped everywhere (the x-tiles of a
                                            tile row on one XCD), 2 slabs (each XCD one
                                            contiguous eighth of the tiles); same results */
-    POISSON_OPT_PAIR_LDS = 11           /* fused Chebyshev pairs on grids whose faces are all
-                                           Dirichlet, without a Block-Jacobi mask: 1 (default)
+    POISSON_OPT_PAIR_LDS = 11           /* fused Chebyshev pairs of single solves: 1 (default)
                                            stage 128 x 16 (FP64) or 256 x 16 (FP32) tiles in
                                            LDS, 0 use the 64 x 16 register tiles; same
                                            arithmetic, same results */

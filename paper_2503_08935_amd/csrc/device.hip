@@ -1254,7 +1254,12 @@ template <int NXW, int PR> struct LPair {
     static constexpr int NT = 128 * NXW;
 };
 
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP>
+// MASK: Block-Jacobi block faces; SIMPLE: no mask and no Neumann face, so every
+// neighbour outside the grid is the +0.0 that the zeroed loads already hold and
+// no neighbour select is needed. Otherwise each neighbour goes through the same
+// selection (neighbour, zero or mirror) as in k_stencil.
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
+          bool SIMPLE>
 __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A, int tile,
                                                    int lane, int xw, T *lds)
 {
@@ -1295,14 +1300,26 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     // LDS element of tile row r (-1..Y) and tile column c (-1..X)
     auto lidx = [](int r, int c) { return (r + 1) * L::PW + (c + 1); };
 
+    // neighbour selection (used unless SIMPLE): per lane along x, per held row
+    // along y, per plane along z
+    const int B = MASK ? P.block : 1;
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
+    const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
     bool rok[E];
     unsigned roff[E], ryoff[E];
+    Sel sym[E], syp[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = y0 + trow(e);
-        rok[e] = xin && j >= 0 && j < ny;
+        const bool jin = j >= 0 && j < ny;
+        rok[e] = xin && jin;
         roff[e] = off(ic, clampi(j, ny));
         ryoff[e] = offy(ic, clampi(j, ny));
+        sym[e] = to_sel(jin ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
     }
     const int jo = y0 + TRO;
     const bool ook = xin && jo >= 0 && jo < ny;
@@ -1336,6 +1353,10 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     const int lhself = lidx(trow(eh), hcol);
     const int lhin = lidx(trow(eh), hside ? L::X - 1 : 0);
     const int lhup = lidx(max(trow(eh) - 1, -1), hcol), lhdn = lidx(min(trow(eh) + 1, L::Y), hcol);
+    const Sel csxl = to_sel(cact ? sel_lo(hi, nx, MASK, B, nxl) : 0);
+    const Sel csxh = to_sel(cact ? sel_hi(hi, nx, MASK, B, nxh) : 0);
+    const Sel csyl = to_sel(cact ? sel_lo(hj, ny, MASK, B, nyl) : 0);
+    const Sel csyh = to_sel(cact ? sel_hi(hj, ny, MASK, B, nyh) : 0);
 
     auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z) {
         const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
@@ -1431,6 +1452,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         // w_i at plane k on the held rows, from y planes k-1 (ya), k (LDS), k+1 (yc)
         const T *ys = bufy(k);
         T wc[E], vc[E];
+        const Sel sz1m = to_sel(pin0 ? sel_lo(k, nz, MASK, B, nzl) : 0);
+        const Sel sz1p = to_sel(pin0 ? sel_hi(k, nz, MASK, B, nzh) : 0);
         {
             const T inner = ys[linner];
             T cen[E];
@@ -1454,7 +1477,14 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
                 const T v = FIRST ? c : (ok ? RV.v[e] : (T)0);
                 const T z = (!FIRST && ok) ? RV.z[e] : (T)0;
                 vc[e] = v;
-                const T w = step1(c, xm, xp, ym, yp, ya[e], yc[e], v, z);
+                T w;
+                if constexpr (SIMPLE) {
+                    w = step1(c, xm, xp, ym, yp, ya[e], yc[e], v, z);
+                } else {
+                    w = step1(c, pick(sxm, xm, xp), pick(sxp, xp, xm), pick(sym[e], ym, yp),
+                              pick(syp[e], yp, ym), pick(sz1m, ya[e], yc[e]),
+                              pick(sz1p, yc[e], ya[e]), v, z);
+                }
                 wc[e] = ok ? w : (T)0;
             }
         }
@@ -1467,7 +1497,13 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
             const T hv = (!FIRST && cact && pin0) ? RV.hv : (T)0;
             const T hz = (!FIRST && cact && pin0) ? RV.hz : (T)0;
             const T l = hside ? xn : hf, r = hside ? hf : xn;
-            const T w = step1(hb, l, r, d, u, ha, hc, hv, hz);
+            T w;
+            if constexpr (SIMPLE) {
+                w = step1(hb, l, r, d, u, ha, hc, hv, hz);
+            } else {
+                w = step1(hb, pick(csxl, l, r), pick(csxh, r, l), pick(csyl, d, u), pick(csyh, u, d),
+                          pick(sz1m, ha, hc), pick(sz1p, hc, ha), hv, hz);
+            }
             hw = (cact && pin0) ? w : (T)0;
         }
         {
@@ -1486,12 +1522,14 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         if (k - 1 >= k0) {
             const T inner = ws[linner];
             const size_t po = (size_t)(k - 1) * PB;
+            const Sel sz2m = to_sel(sel_lo(k - 1, nz, MASK, B, nzl));
+            const Sel sz2p = to_sel(sel_hi(k - 1, nz, MASK, B, nzh));
 #pragma unroll
             for (int e = EOWN; e < EOWN + PR; ++e) {
                 const T c = wcen[e];
                 const T pv = lane_prev(c), nv = lane_next(c);
                 const T patch = ws[lpatch + e * L::PW];
-                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = wcen[e - 1];
@@ -1500,7 +1538,14 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
                     ym = e == 0 ? inner : wcen[e > 0 ? e - 1 : 0];
                     yp = wcen[e + 1];
                 }
-                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - wa[e]) - wc[e]) * ih2;
+                T zm = wa[e], zp = wc[e];
+                if constexpr (!SIMPLE) {
+                    const T xm0 = xm, ym0 = ym, zm0 = zm;
+                    xm = pick(sxm, xm0, xp), xp = pick(sxp, xp, xm0);
+                    ym = pick(sym[e], ym0, yp), yp = pick(syp[e], yp, ym0);
+                    zm = pick(sz2m, zm0, zp), zp = pick(sz2p, zp, zm0);
+                }
+                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
                 // step i+1 reads z = y_{i-1}, the pair's stencil input at plane k-1
                 // (for the first pair, z = v/theta with v = that input)
                 const T v = FIRST ? ya[e] : vb[e];
@@ -1528,7 +1573,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 
 // DROP: the last pair of an apply, which stores w_{i+1} only (a kernel of its
 // own, so that profiles report the two traffic figures apart)
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
 __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
 {
     using L = LPair<NXW, PR>;
@@ -1550,8 +1595,10 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
         // x-grouped unless another order is asked for: the tiles of a tile row
         // share the L2 that holds their common halo columns
         const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
-        if (yw == 0) cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true>(P, A, t, lane, xw, lds);
-        else cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false>(P, A, t, lane, xw, lds);
+        if (yw == 0)
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+        else
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
     }
 }
 
@@ -1799,22 +1846,42 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
         hipLaunchKernelGGL((k_cheb_f32x2<OP, TU, false>), dim3(grid), dim3(NTHREADS), 0, s, w, a);
 }
 
+// the LDS-staged pair: the last pair of an apply (drop1) and the block mask are
+// kernels of their own, and so is the select-free body of all-Dirichlet grids
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, bool MASK, bool SIMPLE>
+static void lpl_launch(const Work &w, hipStream_t s, const KArgs &a)
+{
+    hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, LPR, MASK, SIMPLE>),
+                       dim3(w.pair_tiles[sizeof(T) == 4]), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+}
+
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW>
+static void lpl_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (mask) lpl_launch<T, TU, FIRST, DROP, NXW, true, false>(w, s, a);
+    else if (w.neumann) lpl_launch<T, TU, FIRST, DROP, NXW, false, false>(w, s, a);
+    else lpl_launch<T, TU, FIRST, DROP, NXW, false, true>(w, s, a);
+}
+
+template <typename T, typename TU, bool FIRST, int NXW>
+static void lpl(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if constexpr (!FIRST) {
+        if (a.drop1) {
+            lpl_drop<T, TU, false, true, NXW>(mask, w, s, a);
+            return;
+        }
+    }
+    lpl_drop<T, TU, FIRST, false, NXW>(mask, w, s, a);
+}
+
 template <typename T, typename TU, bool FIRST>
 static void lp(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NXW = pair_nxw(F32);
-    if (!mask && !w.tile_prob && w.pair_tiles[F32] > 0) {
-        const dim3 grid_l(w.pair_tiles[F32]), block_l(LPair<NXW, LPR>::NT);
-        if constexpr (!FIRST) {
-            if (a.drop1) {
-                hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, false, true, NXW, LPR>), grid_l,
-                                   block_l, 0, s, w, a);
-                return;
-            }
-        }
-        hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, false, NXW, LPR>), grid_l, block_l, 0, s,
-                           w, a);
+    if (!w.tile_prob && w.pair_tiles[F32] > 0) {
+        lpl<T, TU, FIRST, NXW>(mask, w, s, a);
         return;
     }
     if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);

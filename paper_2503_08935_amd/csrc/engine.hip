@@ -118,12 +118,11 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 }
 
 // the work list of a single problem (prob = d_prob or d_prob + 1): all tiles in
-// the chosen order; the Chebyshev pairs LDS-staged where the grid allows it
-// (all faces Dirichlet; the launcher also requires no block mask)
+// the chosen order; the Chebyshev pairs LDS-staged unless that is switched off
 Work single_work(const poisson_ctx *c, const Prob *prob)
 {
-    Work w{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, {0, 0}};
-    if (c->pair_lds && c->bc == 0)
+    Work w{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, {0, 0}, c->bc != 0};
+    if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
 }

@@ -78,26 +78,43 @@ def test_preconditioner_bitwise(gpu, pc, m, block, mixed, shape):
     assert np.array_equal(got, ref)
 
 
+LDS_CONFIGS = [
+    dict(bc=0, pc=P.PC_CHEBYSHEV, block=64),            # select-free body
+    dict(bc=2 | 4 | 16, pc=P.PC_CHEBYSHEV, block=64),   # the paper's faces: mirror selects
+    dict(bc=1 | 32, pc=P.PC_CHEBYSHEV, block=64),
+    dict(bc=1 | 2 | 4 | 8 | 16, pc=P.PC_CHEBYSHEV, block=64),
+    dict(bc=0, pc=P.PC_BLOCK_JACOBI, block=16),         # block faces inside and at tile edges
+    dict(bc=2 | 8 | 16, pc=P.PC_BLOCK_JACOBI, block=7),  # mask and mirror together
+]
+
+
+@pytest.mark.parametrize("cfg", LDS_CONFIGS, ids=lambda c: f"bc{c['bc']}-pc{c['pc']}-b{c['block']}")
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("shape", [(200, 37, 21), (128, 16, 8), (64, 16, 70), (3, 50, 2),
                                    (2, 1, 7), (257, 33, 9)])
-def test_lds_pairs_match_register_pairs(gpu, mixed, shape):
+def test_lds_pairs_match_register_pairs(gpu, cfg, mixed, shape):
     """The fused Chebyshev pairs staged in LDS over 128 x 16 (FP64) and 256 x 16 (FP32)
-    tiles (the default on all-Dirichlet grids) against the 64 x 16 register tiles and
-    the oracle, bitwise:
+    tiles (the default) against the 64 x 16 register tiles and the oracle, bitwise:
     ragged x, y and z tails, a tile whose second wave column lies outside the grid,
-    two-plane and single-row grids; odd and even degrees (an odd degree ends with a
-    single step, an even one with a pair that stores w_m only)."""
+    two-plane and single-row grids; Dirichlet, Neumann and mixed faces, Block-Jacobi
+    masks; odd and even degrees (an odd degree ends with a single step, an even one
+    with a pair that stores w_m only)."""
     nx, ny, nz = shape
+    bc, pc, block = cfg["bc"], cfg["pc"], cfg["block"]
+    for axis, n in enumerate(shape):
+        if bc >> (2 * axis) & 3 and n < 2:
+            pytest.skip("a Neumann face needs two points on its axis")
     h = 1.0 / (nx + 1)
     v = workloads.uniform_grid(9, shape)
     dt = torch.float32 if mixed else torch.float64
     for m in (3, 4, 8, 9):
         got = []
         for lds in (1, 0):
-            with P.Solver(shape, h, precision=P.MIXED if mixed else P.FP64, pair_lds=lds) as s:
+            with P.Solver(shape, h, bc=bc, block=block, pair_lds=lds,
+                          precision=P.MIXED if mixed else P.FP64) as s:
                 out = torch.empty(v.shape, dtype=dt, device=gpu)
-                s.apply_precond(P.PC_CHEBYSHEV, m, dev(v), out)
+                s.apply_precond(pc, m, dev(v), out)
                 got.append(host(out).astype(np.float64))
         assert np.array_equal(got[0], got[1]), m
-        assert np.array_equal(got[0], oracle.precond(v, h, P.PC_CHEBYSHEV, degree=m, mixed=mixed))
+        ref = oracle.precond(v, h, pc, degree=m, mixed=mixed, block=block, bc=bc)
+        assert np.array_equal(got[0], ref), m
