@@ -78,8 +78,12 @@ struct Work {
     int order;                   // single problem: 0 natural tile order, 1 x-grouped
     int pair_tiles[2];           // single problem: > 0 runs the Chebyshev pairs LDS-staged
                                  // over this many tiles ([0] FP64, [1] FP32); 0 = register tiles
-    int neumann;                 // single problem: it has a Neumann face (the LDS-staged
-                                 // pairs then select neighbours)
+    int neumann;                 // it has (some problem has) a Neumann face: the LDS-staged
+                                 // pairs then select neighbours
+    // batched problems: the LDS-staged pairs' own tile list (null: single problem)
+    const int *pair_prob;
+    const int *pair_local;
+    const int *pair_count_dev;
 };
 
 // operations of the stencil kernel family

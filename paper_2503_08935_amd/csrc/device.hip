@@ -1578,23 +1578,35 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
 {
     using L = LPair<NXW, PR>;
     __shared__ T lds[4 * L::PLANE];
-    const Prob &P = W.probs[0];
-    const int pkz = P.pkz[sizeof(T) == 4];
-    if (pkz < 1) return;
-    {
-        const Scalars *sc = P.sc;
-        if (sc->done || (A.second && sc->half_pending)) return;
-    }
+    constexpr int F32 = sizeof(T) == 4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int xw = wv % NXW, yw = wv / NXW;
-    const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
-    const int total = ltx * lty * ((P.nz + pkz - 1) / pkz);
+    // batched problems walk the pair tile list; a single problem all its tiles
+    int total;
+    if (W.pair_prob) {
+        total = *W.pair_count_dev;
+    } else {
+        const Prob &P = W.probs[0];
+        const int pkz = P.pkz[F32];
+        if (pkz < 1) return;
+        const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
+        total = ltx * lty * ((P.nz + pkz - 1) / pkz);
+    }
     // every wave runs the same number of barriers: the tile loop and the plane
-    // loop depend only on the workgroup's tiles
+    // loop depend only on the workgroup's tiles, and a skipped tile is skipped
+    // by the whole workgroup
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        // x-grouped unless another order is asked for: the tiles of a tile row
-        // share the L2 that holds their common halo columns
-        const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        const int pid = W.pair_prob ? W.pair_prob[g] : 0;
+        const Prob &P = W.probs[pid];
+        if (P.pkz[F32] < 1) continue;
+        {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        // single problem: x-grouped unless another order is asked for, so that
+        // the tiles of a tile row share the L2 that holds their halo columns
+        const int ltx = (P.nx + L::X - 1) / L::X;
+        const int t = W.pair_prob ? W.pair_local[g] : tile_order_tx(W.order ? W.order : 1, ltx, g, total);
         if (yw == 0)
             cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
         else
@@ -1849,30 +1861,32 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 // the LDS-staged pair: the last pair of an apply (drop1) and the block mask are
 // kernels of their own, and so is the select-free body of all-Dirichlet grids
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW, bool MASK, bool SIMPLE>
-static void lpl_launch(const Work &w, hipStream_t s, const KArgs &a)
+static void lpl_launch(const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, LPR, MASK, SIMPLE>),
-                       dim3(w.pair_tiles[sizeof(T) == 4]), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+    hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, LPR, MASK, SIMPLE>), dim3(grid),
+                       dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
 }
 
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW>
-static void lpl_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+static void lpl_drop(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (mask) lpl_launch<T, TU, FIRST, DROP, NXW, true, false>(w, s, a);
-    else if (w.neumann) lpl_launch<T, TU, FIRST, DROP, NXW, false, false>(w, s, a);
-    else lpl_launch<T, TU, FIRST, DROP, NXW, false, true>(w, s, a);
+    if (mask) lpl_launch<T, TU, FIRST, DROP, NXW, true, false>(w, grid, s, a);
+    else if (w.neumann) lpl_launch<T, TU, FIRST, DROP, NXW, false, false>(w, grid, s, a);
+    else lpl_launch<T, TU, FIRST, DROP, NXW, false, true>(w, grid, s, a);
 }
 
+// grid: one workgroup per tile for a single problem; for batched problems the
+// caller's persistent grid over the pair tile list
 template <typename T, typename TU, bool FIRST, int NXW>
-static void lpl(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+static void lpl(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
     if constexpr (!FIRST) {
         if (a.drop1) {
-            lpl_drop<T, TU, false, true, NXW>(mask, w, s, a);
+            lpl_drop<T, TU, false, true, NXW>(mask, w, grid, s, a);
             return;
         }
     }
-    lpl_drop<T, TU, FIRST, false, NXW>(mask, w, s, a);
+    lpl_drop<T, TU, FIRST, false, NXW>(mask, w, grid, s, a);
 }
 
 template <typename T, typename TU, bool FIRST>
@@ -1880,8 +1894,12 @@ static void lp(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NXW = pair_nxw(F32);
+    if (w.pair_prob) {
+        lpl<T, TU, FIRST, NXW>(mask, w, grid, s, a);
+        return;
+    }
     if (!w.tile_prob && w.pair_tiles[F32] > 0) {
-        lpl<T, TU, FIRST, NXW>(mask, w, s, a);
+        lpl<T, TU, FIRST, NXW>(mask, w, w.pair_tiles[F32], s, a);
         return;
     }
     if (mask) hipLaunchKernelGGL((k_cheb_pair<T, TU, true, FIRST>), dim3(grid), dim3(NTHREADS), 0, s, w, a);

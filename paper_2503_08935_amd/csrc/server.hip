@@ -30,10 +30,10 @@ namespace {
 constexpr int GRID = 2048;   // persistent workgroups of the batched kernels (multiple of 8)
 
 struct PlanKey {
-    int pc, deg, mixed;
+    int pc, deg, mixed, neu; // neu: the requests have a Neumann face
     bool operator<(const PlanKey &o) const
     {
-        return std::tie(pc, deg, mixed) < std::tie(o.pc, o.deg, o.mixed);
+        return std::tie(pc, deg, mixed, neu) < std::tie(o.pc, o.deg, o.mixed, o.neu);
     }
 };
 
@@ -116,9 +116,11 @@ struct TileList {
 
 struct Group {
     TileList tiles;
+    TileList ptiles;          // tiles of the LDS-staged Chebyshev pairs
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
-    int graph_cap = -1;       // capacity the graph was captured with
+    int graph_cap = -1;       // capacities the graph was captured with
+    int pgraph_cap = -1;
     bool dirty = true;        // tile list must be rebuilt
 };
 
@@ -215,9 +217,36 @@ void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids
         }
 }
 
+// the LDS-staged pairs' tiles of the requests in ids (64 * pair_nxw x LY columns)
+void list_pair_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids, bool fp32)
+{
+    t.h_prob.clear();
+    t.h_local.clear();
+    for (int id : slot_ids) {
+        const Request &rq = s->slots[id].req;
+        const int n = make_pair_tiling(rq.nx, rq.ny, rq.nz, fp32).ntiles;
+        for (int l = 0; l < n; ++l) {
+            t.h_prob.push_back(id);
+            t.h_local.push_back(l);
+        }
+    }
+}
+
 Work work_of(const poisson_server *s, const TileList &t)
 {
     return Work{s->d_probs, t.d_prob, t.d_local, t.d_count, t.count, 0};
+}
+
+// the work of a plan group: its tile list, and the pair tile list for the
+// LDS-staged Chebyshev pairs
+Work group_work(const poisson_server *s, const PlanKey &k, const Group &g, int count)
+{
+    Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, count, 0};
+    w.neumann = k.neu;
+    w.pair_prob = g.ptiles.d_prob;
+    w.pair_local = g.ptiles.d_local;
+    w.pair_count_dev = g.ptiles.d_count;
+    return w;
 }
 
 int finish_requests(poisson_server *s, const std::vector<int> &ids)
@@ -283,12 +312,13 @@ int capture_group(poisson_server *s, const PlanKey &k, Group &g)
         g.graph = nullptr;
         g.graph_src = nullptr;
     }
-    const Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, 0, 0};
+    const Work w = group_work(s, k, g, 0);
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, 1);
     HIPCHK(hipStreamEndCapture(s->cap_stream, &g.graph_src));
     HIPCHK(hipGraphInstantiate(&g.graph, g.graph_src, nullptr, nullptr, 0));
     g.graph_cap = g.tiles.cap;
+    g.pgraph_cap = g.ptiles.cap;
     return POISSON_OK;
 }
 
@@ -339,7 +369,7 @@ int step_impl(poisson_server *s, int iters)
         HIPCHK(hipMemcpyAsync(s->d_probs + id, s->h_probs + id, sizeof(Prob), hipMemcpyHostToDevice,
                               s->stream));
         admitted.push_back(id);
-        s->groups[PlanKey{sl.req.pc, sl.req.deg, sl.req.prec}].dirty = true;
+        s->groups[PlanKey{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0}].dirty = true;
     }
     HIPCHK(hipEventRecord(s->ev_a, s->stream));
     // 3. initial residuals of the new requests, one launch
@@ -359,22 +389,25 @@ int step_impl(poisson_server *s, int iters)
             std::vector<int> ids;
             for (int i = 0; i < s->max_slots; ++i) {
                 const Slot &sl = s->slots[i];
-                const PlanKey k{sl.req.pc, sl.req.deg, sl.req.prec};
+                const PlanKey k{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0};
                 if (sl.active && !(k < kv.first) && !(kv.first < k)) ids.push_back(i);
             }
             list_tiles(s, g.tiles, ids);
-            bool moved;
+            list_pair_tiles(s, g.ptiles, ids, kv.first.mixed == POISSON_MIXED);
+            bool moved, pmoved;
             if ((rc = upload_tiles(s, g.tiles, moved)) != POISSON_OK) return rc;
-            if (moved && g.graph) g.graph_cap = -1;
+            if ((rc = upload_tiles(s, g.ptiles, pmoved)) != POISSON_OK) return rc;
+            if ((moved || pmoved) && g.graph) g.graph_cap = -1;
             g.dirty = false;
         }
         if (g.tiles.count == 0) continue;
         if (s->use_graph) {
-            if (g.graph_cap != g.tiles.cap && (rc = capture_group(s, kv.first, g)) != POISSON_OK)
+            if ((g.graph_cap != g.tiles.cap || g.pgraph_cap != g.ptiles.cap) &&
+                (rc = capture_group(s, kv.first, g)) != POISSON_OK)
                 return rc;
             for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(g.graph, s->stream));
         } else {
-            const Work w = work_of(s, g.tiles);
+            const Work w = group_work(s, kv.first, g, g.tiles.count);
             for (int i = 0; i < iters; ++i)
                 enqueue_iteration(w, GRID, s->stream, kv.first.pc, kv.first.deg, kv.first.mixed != 0,
                                   1);
