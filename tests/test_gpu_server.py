@@ -152,3 +152,46 @@ def test_fifo_admission_and_budget(gpu):
             b = torch.zeros(64 ** 3, dtype=torch.float64, device="cuda:0")
             srv.submit(b, b.clone(), shape, h, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
     assert e.value.code == P.ERR_NOMEM
+
+
+def test_neumann_and_dirichlet_requests_in_one_batch(gpu):
+    """Requests with Neumann faces share the server with all-Dirichlet requests of
+    the same plan (they run as groups of their own, whose fused pairs select
+    neighbours); each result equals the same solve done alone, and the oracle's."""
+    reqs = [  # shape, seed, precond, degree, precision, tol, bc
+        ((40, 36, 30), 21, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 2 | 4 | 16),
+        ((48, 48, 48), 22, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 0),
+        ((33, 40, 28), 23, P.PC_CHEBYSHEV, 8, P.FP64, 1e-9, 1 | 32),
+        ((70, 30, 20), 24, P.PC_BLOCK_JACOBI, 6, P.FP64, 1e-8, 4 | 8),
+        ((50, 41, 37), 25, P.PC_CHEBYSHEV, 8, P.FP64, 1e-9, 0),
+    ]
+    out = {}
+    with P.Server(1 << 30, 8) as srv:
+        bufs, tickets = {}, {}
+        for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
+            b = torch.from_numpy(workloads.uniform_grid(seed, shape)).to("cuda:0")
+            x = torch.zeros_like(b)
+            bufs[i] = (b, x)  # the caller keeps rhs and x alive until the final poll
+            tickets[i] = srv.submit(b, x, shape, workloads.spacing(shape[0]), pc, deg, prec, tol,
+                                    5000, bc=bc)
+        for _ in range(10000):
+            if srv.step(4) == 0:
+                break
+        for i, t in tickets.items():
+            st, stats = srv.poll(t)
+            out[i] = (st, stats["iterations"], bufs[i][1].cpu().numpy())
+    for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
+        h = workloads.spacing(shape[0])
+        f = workloads.uniform_grid(seed, shape)
+        with P.Solver(shape, h, bc=bc, precision=prec) as s:
+            b = torch.from_numpy(f).to("cuda:0")
+            x = torch.zeros_like(b)
+            st1 = s.solve(b, x, pc, deg, tol, 5000)
+            torch.cuda.synchronize()
+            it1, x1 = s.stats()["iterations"], x.cpu().numpy()
+        st, it, xs = out[i]
+        assert st == st1 == P.OK and it == it1, (i, st, st1, it, it1)
+        assert np.array_equal(xs, x1), i
+        ref = oracle.bicgstab(f, h, pc=OPC[pc], degree=deg, mixed=prec == P.MIXED, tol=tol,
+                              maxit=5000, bc=bc)
+        assert ref.iterations == it1 and np.array_equal(xs, ref.x), i
