@@ -226,7 +226,7 @@ def main():
         return suite()
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the solver has no "
-              "multi-GPU path in this build", file=sys.stderr)
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -1,5 +1,5 @@
 """bench.py's host-side contract: more than one GPU is refused with a message
-and exit status 2 (this build measures one GPU), and the HBM traffic record of
+and exit status 2 (the solver runs on one GPU), and the HBM traffic record of
 profiles/ is well formed and used only while the kernel source is unchanged."""
 import hashlib
 import importlib.util
