@@ -87,7 +87,9 @@ enum {
     POISSON_OPT_DEBUG_BREAKDOWN_AT = 8, /* testing: force omega = 0 at this iteration (-1 off) */
     POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
                                            mixed): run Chebyshev steps two per pass (1,
-                                           default) or one per pass (0); same arithmetic,
+                                           default), one per pass (0), or three per pass
+                                           where the pairs are LDS-staged (2; the steps left
+                                           over run as a pair or alone); same arithmetic,
                                            same results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the fused Chebyshev

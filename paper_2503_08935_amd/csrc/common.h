@@ -25,6 +25,10 @@ constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double
 constexpr int LPR = 8;
 constexpr int LY = 2 * LPR;
 constexpr int pair_nxw(bool fp32) { return fp32 ? 4 : 2; }
+// tiles of the LDS-staged Chebyshev triple: 2*triple_nxw waves of 64 columns x
+// triple_pr rows
+constexpr int triple_nxw(bool fp32) { return fp32 ? 2 : 2; }
+constexpr int triple_pr(bool fp32) { return fp32 ? 8 : 4; }
 
 // vector slots of a problem
 enum Vec {
@@ -55,6 +59,7 @@ struct Prob {
     int hist_iters;              // iterations recorded in hist
     unsigned bc;                 // bit f (x-, x+, y-, y+, z-, z+) = Neumann on face f
     int pkz[2];                  // z-chunk of the LDS-staged pair's tiles: [0] FP64, [1] FP32
+    int tkz[2];                  // and of the LDS-staged triple's tiles
     double ih2;                  // 1/(h*h)
     double tol2;                 // tol*tol
     double jac_d;                // diagonal of A = 6*ih2
@@ -80,6 +85,8 @@ struct Work {
                                  // over this many tiles ([0] FP64, [1] FP32); 0 = register tiles
     int neumann;                 // it has (some problem has) a Neumann face: the LDS-staged
                                  // pairs then select neighbours
+    int triple_tiles[2];         // single problem: > 0 runs three Chebyshev steps per pass
+                                 // (LDS-staged) over this many tiles ([0] FP64, [1] FP32)
     // batched problems: the LDS-staged pairs' own tile list (null: single problem)
     const int *pair_prob;
     const int *pair_local;
@@ -128,6 +135,10 @@ void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_
 // in mixed mode the FP32 copy of v is written to V_V32 as well
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                             const KArgs &a);
+// three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
+// in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
+// w_{i+1} is not stored
+void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, const KArgs &a);
 void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
 
 } // namespace pz

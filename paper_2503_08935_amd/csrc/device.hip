@@ -1614,6 +1614,388 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
     }
 }
 
+// ------------------------------------------------------------------------
+// Three consecutive Chebyshev steps i, i+1, i+2 (i >= 3) in one pass, staged
+// in LDS like k_cheb_pair_lds. One pass reads y = y_{i-1}, z = y_{i-2} and v
+// and writes w_{i+1}, w_{i+2}: the bytes of one pair for three steps.
+//   w_i     = rc_i     ((2 sigma y       + (2/delta)(v - A y))       - ro_i     z)
+//   w_{i+1} = rc_{i+1} ((2 sigma w_i     + (2/delta)(v - A w_i))     - ro_{i+1} y)
+//   w_{i+2} = rc_{i+2} ((2 sigma w_{i+1} + (2/delta)(v - A w_{i+1})) - ro_{i+2} w_i)
+// Plane k of the march computes w_i at plane k, w_{i+1} at k-1 and w_{i+2}
+// at k-2. w_i is computed on the tile plus a halo ring of two, w_{i+1} on the
+// tile plus one. A wave owns 64 columns x PR rows and holds PR + 2 rows: a top
+// wave also the two halo rows above, a bottom wave the two below. At each side
+// 2 x 16 halo lanes hold the columns one and two out; they load y, v and z
+// there, the lanes two out also y three out, and they compute w_i (and w_{i+1}
+// one out) at those points. y, w_i and w_{i+1} each have two LDS planes
+// alternating by plane, with one barrier per plane. The arithmetic per point
+// is that of k_stencil's step.
+// ------------------------------------------------------------------------
+template <int NXW, int PR> struct LTriple {
+    static constexpr int X = 64 * NXW, Y = 2 * PR;
+    static constexpr int PW = X + 4, PH = Y + 4; // LDS plane: rows -2..Y+1, columns -2..X+1
+    static constexpr int PLANE = PW * PH;
+    static constexpr int NT = 128 * NXW;
+};
+
+template <typename T, bool DROP, int NXW, int PR, bool TOP, bool MASK, bool SIMPLE>
+__device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs &A, int tile,
+                                                     int lane, int xw, T *lds)
+{
+    using L = LTriple<NXW, PR>;
+    constexpr int E = PR + 2;                      // held rows: own PR and two halo rows
+    constexpr int L2LO = TOP ? 1 : 0, L2HI = TOP ? E : E - 1;   // rows of w_{i+1}
+    constexpr int OWNLO = TOP ? 2 : 0, OWNHI = TOP ? E : PR;    // own rows (w_{i+2})
+    constexpr int TRO = TOP ? -3 : 2 * PR + 2;     // tile row of the outer row (y only)
+    auto trow = [](int e) { return TOP ? e - 2 : PR + e; };
+    auto in2 = [](int e) { return e >= L2LO && e < L2HI; };
+    auto own = [](int e) { return e >= OWNLO && e < OWNHI; };
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int ltx = (nx + L::X - 1) / L::X, lty = (ny + L::Y - 1) / L::Y;
+    const int tix = tile % ltx, tiy = (tile / ltx) % lty, tiz = tile / (ltx * lty);
+    const int x0 = tix * L::X, y0 = tiy * L::Y;
+    const int pkz = P.tkz[sizeof(T) == 4];
+    const int k0 = tiz * pkz, k1 = min(k0 + pkz, nz);
+    const int cx = xw * 64 + lane;
+    const int i = x0 + cx;
+    const bool xin = i < nx;
+    const int ic = xin ? i : nx - 1;
+    const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
+    const char *Yb = (const char *)P.vec[A.in];
+    const char *Vb = (const char *)P.vec[A.v];
+    const char *Zb = (const char *)P.vec[A.z];
+    char *W1b = (char *)P.vec[A.out];
+    char *W2b = (char *)P.vec[A.x2];
+    const T ih2 = Coef<T>::ih2(P);
+    const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
+    const T rc1 = Coef<T>::rc(P, A.step), ro1 = Coef<T>::ro(P, A.step);
+    const T rc2 = Coef<T>::rc(P, A.step + 1), ro2 = Coef<T>::ro(P, A.step + 1);
+    const T rc3 = Coef<T>::rc(P, A.step + 2), ro3 = Coef<T>::ro(P, A.step + 2);
+    auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
+    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
+    // LDS element of tile row r (-2..Y+1) and tile column c (-2..X+1)
+    auto lidx = [](int r, int c) { return (r + 2) * L::PW + (c + 2); };
+
+    const int B = MASK ? P.block : 1;
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
+    const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
+    bool rok[E];
+    unsigned roff[E];
+    Sel sym[E], syp[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = y0 + trow(e);
+        const bool jin = j >= 0 && j < ny;
+        rok[e] = xin && jin;
+        roff[e] = off(ic, clampi(j, ny));
+        sym[e] = to_sel(jin ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
+    }
+    const int jo = y0 + TRO;
+    const bool ook = xin && jo >= 0 && jo < ny;
+    const unsigned ooff = off(ic, clampi(jo, ny));
+    const int lown = lidx(trow(0), cx);
+    const int lpatch = lown + (lane == 0 ? -1 : (lane == 63 ? 1 : 0));
+    const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
+
+    // Halo lanes. Lanes 0-15 (left) and 32-47 (right) hold the column one out
+    // (A), lanes 16-31 and 48-63 the column two out (B); lane e of a group
+    // holds held row e. All of them load and publish y there. A computes w_i
+    // on the rows of w_{i+1} and w_{i+1} on the own rows; B computes w_i on the
+    // own rows and also loads y three columns out.
+    const bool hside = lane >= 32, grpb = (lane & 16) != 0;
+    const int eh = min(lane & 15, E - 1);
+    const bool hwave = hside ? xw == NXW - 1 : xw == 0;
+    const bool hact = hwave && (lane & 15) < E;
+    const int hcol = hside ? (grpb ? L::X + 1 : L::X) : (grpb ? -2 : -1);
+    const int hnear = hside ? hcol - 1 : hcol + 1;      // towards the tile
+    const int hfarc = hside ? hcol + 1 : hcol - 1;      // away from it (B: column three out)
+    const int hi = x0 + hcol, hfi = x0 + hfarc;
+    const int hj = y0 + trow(eh);
+    const bool hrow = hj >= 0 && hj < ny;
+    const bool hload = hact && hrow && hi >= 0 && hi < nx;
+    const bool h1 = hact && (grpb ? own(eh) : in2(eh));  // computes w_i here
+    const bool h2 = hact && !grpb && own(eh);            // computes w_{i+1} here
+    const bool c1act = h1 && hload, c2act = h2 && hload;
+    const bool fload = hact && grpb && hrow && hfi >= 0 && hfi < nx;
+    const unsigned hoff = off(clampi(hi, nx), clampi(hj, ny));
+    const unsigned foff = off(clampi(hfi, nx), clampi(hj, ny));
+    const int lhself = lidx(trow(eh), hcol);
+    const int lhnear = lidx(trow(eh), hnear);
+    const int lhfar = grpb ? lhself : lidx(trow(eh), hfarc);
+    const int lhup = lidx(max(trow(eh) - 1, -2), hcol), lhdn = lidx(min(trow(eh) + 1, L::Y + 1), hcol);
+    const Sel csxl = to_sel(hload ? sel_lo(hi, nx, MASK, B, nxl) : 0);
+    const Sel csxh = to_sel(hload ? sel_hi(hi, nx, MASK, B, nxh) : 0);
+    const Sel csyl = to_sel(hload ? sel_lo(hj, ny, MASK, B, nyl) : 0);
+    const Sel csyh = to_sel(hload ? sel_hi(hj, ny, MASK, B, nyh) : 0);
+
+    // one step at one point: A u from the centre and its six neighbours (in
+    // the order x-, x+, y-, y+, z-, z+), then the Chebyshev update
+    auto step = [&](T rc, T ro, T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl,
+                    Sel szh, Sel sxl, Sel sxh, Sel syl, Sel syh) {
+        if constexpr (!SIMPLE) {
+            const T xm0 = xm, ym0 = ym, zm0 = zm;
+            xm = pick(sxl, xm0, xp), xp = pick(sxh, xp, xm0);
+            ym = pick(syl, ym0, yp), yp = pick(syh, yp, ym0);
+            zm = pick(szl, zm0, zp), zp = pick(szh, zp, zm0);
+        }
+        const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        return rc * ((ts * c + tod * (v - a)) - ro * z);
+    };
+
+    struct RawY {
+        T y[E], yo, he;
+    };
+    struct RawV {
+        T v[E], z[E], hv, hz, hf;
+    };
+    auto issueY = [&](int p, RawY &R) {
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
+#pragma unroll
+        for (int e = 0; e < E; ++e) R.y[e] = ld(Yp, roff[e]);
+        R.yo = ld(Yp, ooff);
+        R.he = ld(Yp, hoff);
+    };
+    auto issueV = [&](int p, RawV &R) {
+        const size_t po = (size_t)clampi(p, nz) * PB;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            R.v[e] = ld(Vb + po, roff[e]);
+            R.z[e] = ld(Zb + po, roff[e]);
+        }
+        R.hv = ld(Vb + po, hoff);
+        R.hz = ld(Zb + po, hoff);
+        R.hf = ld(Yb + po, foff);
+    };
+    auto buf = [&](int f, int k) { return lds + (2 * f + (k & 1)) * L::PLANE; }; // f: 0 y, 1 w_i, 2 w_{i+1}
+
+    // registers across planes (k = the plane of w_i): y at k-1 (ya), w_i at
+    // k-2 (w1a), w_{i+1} at k-3 (w2a), v at k-1 (vb) and k-2 (vbb); at the halo
+    // points y at k-1 (ha), w_i at k-2 (h1a) and v at k-1 (hvb)
+    T ya[E], w1a[E], w2a[E], vb[E], vbb[E];
+    T yob, ha, h1a, hvb;
+    RawY RY;
+    RawV RV;
+    {
+        RawY t;
+        issueY(k0 - 3, t);
+        {
+            const bool pin = k0 - 3 >= 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? t.y[e] : (T)0;
+            ha = (pin && hload) ? t.he : (T)0;
+        }
+        issueY(k0 - 2, t);
+        {
+            const bool pin = k0 - 2 >= 0;
+            T *yd = buf(0, k0 - 2);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? t.y[e] : (T)0;
+            yob = (pin && ook) ? t.yo : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? t.he : (T)0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) w1a[e] = w2a[e] = vb[e] = vbb[e] = (T)0;
+    h1a = hvb = (T)0;
+    issueY(k0 - 1, RY);
+    issueV(k0 - 2, RV);
+    __syncthreads();
+
+    for (int k = k0 - 2; k <= k1 + 1; ++k) {
+        const bool pin1 = k + 1 >= 0 && k + 1 < nz, pin0 = k >= 0 && k < nz;
+        const bool pinm = k - 1 >= 0 && k - 1 < nz;
+        // take y at plane k+1, publish it, issue plane k+2
+        T yc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? RY.y[e] : (T)0;
+        const T yoc = (pin1 && ook) ? RY.yo : (T)0;
+        const T hc = (pin1 && hload) ? RY.he : (T)0;
+        {
+            T *yd = buf(0, k + 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = yc[e];
+            if (hact) yd[lhself] = hc;
+        }
+        issueY(k + 2, RY);
+
+        // w_i at plane k on the held rows
+        const T *ys = buf(0, k);
+        const Sel s1m = to_sel(pin0 ? sel_lo(k, nz, MASK, B, nzl) : 0);
+        const Sel s1p = to_sel(pin0 ? sel_hi(k, nz, MASK, B, nzh) : 0);
+        T w1c[E], vc[E];
+        {
+            const T inner = ys[linner];
+            T cen[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) cen[e] = ys[lown + e * L::PW];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T c = cen[e];
+                const T pv = lane_prev(c), nv = lane_next(c);
+                const T patch = ys[lpatch + e * L::PW];
+                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T ym, yp;
+                if constexpr (TOP) {
+                    ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
+                    yp = e == E - 1 ? inner : cen[e < E - 1 ? e + 1 : e];
+                } else {
+                    ym = e == 0 ? inner : cen[e > 0 ? e - 1 : 0];
+                    yp = e == E - 1 ? yob : cen[e < E - 1 ? e + 1 : e];
+                }
+                const bool ok = pin0 && rok[e];
+                const T v = ok ? RV.v[e] : (T)0, z = ok ? RV.z[e] : (T)0;
+                vc[e] = v;
+                const T w = step(rc1, ro1, c, xm, xp, ym, yp, ya[e], yc[e], v, z, s1m, s1p, sxm, sxp,
+                                 sym[e], syp[e]);
+                w1c[e] = ok ? w : (T)0;
+            }
+        }
+        // w_i at the halo points (A: rows of w_{i+1}; B: own rows)
+        T hb, h1c, hvc;
+        {
+            hb = ys[lhself];
+            const T xn = ys[lhnear], d = ys[lhup], u = ys[lhdn];
+            const T xf = grpb ? ((fload && pin0) ? RV.hf : (T)0) : ys[lhfar];
+            const bool ok = c1act && pin0;
+            hvc = (hload && pin0) ? RV.hv : (T)0;
+            const T hz = ok ? RV.hz : (T)0;
+            const T l = hside ? xn : xf, r = hside ? xf : xn;
+            const T w = step(rc1, ro1, hb, l, r, d, u, ha, hc, hvc, hz, s1m, s1p, csxl, csxh, csyl,
+                             csyh);
+            h1c = ok ? w : (T)0;
+        }
+        {
+            T *wd = buf(1, k);
+#pragma unroll
+            for (int e = 0; e < E; ++e) wd[lown + e * L::PW] = w1c[e];
+            if (h1) wd[lhself] = h1c;
+        }
+        issueV(k + 1, RV);
+
+        // w_{i+1} at plane k-1 on its rows, from w_i at k-2 (w1a), k-1 (LDS), k (w1c)
+        const T *w1s = buf(1, k - 1);
+        const Sel s2m = to_sel(pinm ? sel_lo(k - 1, nz, MASK, B, nzl) : 0);
+        const Sel s2p = to_sel(pinm ? sel_hi(k - 1, nz, MASK, B, nzh) : 0);
+        T w2c[E], cen1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) cen1[e] = w1s[lown + e * L::PW];
+        T h2c = (T)0;
+        if (k >= k0) {
+            const T inner = w1s[linner];
+#pragma unroll
+            for (int e = L2LO; e < L2HI; ++e) {
+                const T c = cen1[e];
+                const T pv = lane_prev(c), nv = lane_next(c);
+                const T patch = w1s[lpatch + e * L::PW];
+                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T ym, yp;
+                if constexpr (TOP) {
+                    ym = cen1[e - 1];
+                    yp = e == E - 1 ? inner : cen1[e < E - 1 ? e + 1 : e];
+                } else {
+                    ym = e == 0 ? inner : cen1[e > 0 ? e - 1 : 0];
+                    yp = cen1[e + 1];
+                }
+                const T w = step(rc2, ro2, c, xm, xp, ym, yp, w1a[e], w1c[e], vb[e], ya[e], s2m, s2p,
+                                 sxm, sxp, sym[e], syp[e]);
+                w2c[e] = (pinm && rok[e]) ? w : (T)0;
+            }
+            // w_{i+1} at the halo points one out, own rows (lanes A)
+            {
+                const T c = w1s[lhself];
+                const T xn = w1s[lhnear], xf = w1s[lhfar], d = w1s[lhup], u = w1s[lhdn];
+                const T l = hside ? xn : xf, r = hside ? xf : xn;
+                const T w = step(rc2, ro2, c, l, r, d, u, h1a, h1c, hvb, ha, s2m, s2p, csxl, csxh,
+                                 csyl, csyh);
+                h2c = (c2act && pinm) ? w : (T)0;
+            }
+            T *wd = buf(2, k - 1);
+#pragma unroll
+            for (int e = L2LO; e < L2HI; ++e) wd[lown + e * L::PW] = w2c[e];
+            if (h2) wd[lhself] = h2c;
+        }
+
+        // w_{i+2} at plane k-2 on the own rows, from w_{i+1} at k-3 (w2a), k-2 (LDS), k-1 (w2c)
+        const T *w2s = buf(2, k - 2);
+        T cen2[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) cen2[e] = w2s[lown + e * L::PW];
+        if (k >= k0 + 2) {
+            const T inner = w2s[linner];
+            const Sel s3m = to_sel(sel_lo(k - 2, nz, MASK, B, nzl));
+            const Sel s3p = to_sel(sel_hi(k - 2, nz, MASK, B, nzh));
+            const size_t po = (size_t)(k - 2) * PB;
+#pragma unroll
+            for (int e = OWNLO; e < OWNHI; ++e) {
+                const T c = cen2[e];
+                const T pv = lane_prev(c), nv = lane_next(c);
+                const T patch = w2s[lpatch + e * L::PW];
+                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T ym, yp;
+                if constexpr (TOP) {
+                    ym = cen2[e - 1];
+                    yp = e == E - 1 ? inner : cen2[e < E - 1 ? e + 1 : e];
+                } else {
+                    ym = e == 0 ? inner : cen2[e > 0 ? e - 1 : 0];
+                    yp = cen2[e + 1];
+                }
+                // step i+2 reads z = w_i at plane k-2, held in w1a
+                const T w3 = step(rc3, ro3, c, xm, xp, ym, yp, w2a[e], w2c[e], vbb[e], w1a[e], s3m,
+                                  s3p, sxm, sxp, sym[e], syp[e]);
+                if (rok[e]) {
+                    if constexpr (!DROP) st_nt((T *)(W1b + po + roff[e]), c);
+                    st_nt((T *)(W2b + po + roff[e]), w3);
+                }
+            }
+        }
+        // rotate: y at plane k, w_i at k-1, w_{i+1} at k-2 for the next plane
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            ya[e] = ys[lown + e * L::PW];
+            w1a[e] = cen1[e];
+            w2a[e] = cen2[e];
+            vbb[e] = vb[e];
+            vb[e] = vc[e];
+        }
+        yob = yoc;
+        h1a = w1s[lhself];
+        ha = hb;
+        hvb = hvc;
+        __syncthreads();
+    }
+}
+
+template <typename T, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
+__global__ void __launch_bounds__(128 * NXW) k_cheb_triple_lds(Work W, KArgs A)
+{
+    using L = LTriple<NXW, PR>;
+    __shared__ T lds[6 * L::PLANE];
+    constexpr int F32 = sizeof(T) == 4;
+    const Prob &P = W.probs[0];
+    const int tkz = P.tkz[F32];
+    if (tkz < 1) return;
+    {
+        const Scalars *sc = P.sc;
+        if (sc->done || (A.second && sc->half_pending)) return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int xw = wv % NXW, yw = wv / NXW;
+    const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
+    const int total = ltx * lty * ((P.nz + tkz - 1) / tkz);
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        if (yw == 0)
+            cheb_triple_lds_tile<T, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+        else
+            cheb_triple_lds_tile<T, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+    }
+}
+
 // One tile of an elementwise pass for the lanes inside the grid (i < nx);
 // FULL: all RY rows of the wave are inside, so no row guard remains and the
 // loads of a plane issue together.
@@ -1910,6 +2292,36 @@ void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_
 {
     if (mixed) lp<float, float, false>(mask, w, grid, s, a);
     else lp<double, double, false>(mask, w, grid, s, a);
+}
+
+template <typename T, bool DROP, bool MASK, bool SIMPLE>
+static void ltr_launch(const Work &w, hipStream_t s, const KArgs &a)
+{
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int NXW = triple_nxw(F32), PR = triple_pr(F32);
+    hipLaunchKernelGGL((k_cheb_triple_lds<T, DROP, NXW, PR, MASK, SIMPLE>), dim3(w.triple_tiles[F32]),
+                       dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+}
+
+template <typename T, bool DROP>
+static void ltr_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (mask) ltr_launch<T, DROP, true, false>(w, s, a);
+    else if (w.neumann) ltr_launch<T, DROP, false, false>(w, s, a);
+    else ltr_launch<T, DROP, false, true>(w, s, a);
+}
+
+template <typename T>
+static void ltr(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (a.drop1) ltr_drop<T, true>(mask, w, s, a);
+    else ltr_drop<T, false>(mask, w, s, a);
+}
+
+void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (mixed) ltr<float>(mask, w, s, a);
+    else ltr<double>(mask, w, s, a);
 }
 
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

@@ -122,9 +122,17 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
 Work single_work(const poisson_ctx *c, const Prob *prob)
 {
     Work w{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, {0, 0}, c->bc != 0};
+    if (c->pair_lds && c->opt.fuse >= 2)
+        for (int f = 0; f < 2; ++f) w.triple_tiles[f] = make_triple_tiling(c->nx, c->ny, c->nz, f).ntiles;
     if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
+}
+
+// steps per pass the plan runs: three only with the LDS-staged tiles
+int plan_fuse_level(const poisson_ctx *c)
+{
+    return (c->opt.fuse >= 2 && !c->pair_lds) ? 1 : c->opt.fuse;
 }
 
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
@@ -274,7 +282,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     st.lambda_min = c->plan_lo;
     st.lambda_max = c->plan_hi;
     st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed, c->opt.fuse) * (double)c->N * sc.iter;
+    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c)) * (double)c->N * sc.iter;
     st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
     st.history_len = (int)c->hist_rel.size();
     st.history = c->hist_rel.data();
@@ -346,7 +354,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         c->opt.debug_bd = (int)v;
         return POISSON_OK;
     case POISSON_OPT_FUSE:
-        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        if (v != 0 && v != 1 && v != 2) return POISSON_ERR_ARG;
         c->opt.fuse = (int)v;
         return POISSON_OK;
     case POISSON_OPT_TILE_ORDER:

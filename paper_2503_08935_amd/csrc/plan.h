@@ -38,6 +38,8 @@ struct PlanOpts {
 Tiling make_tiling(int nx, int ny, int nz);
 // tiles of the LDS-staged Chebyshev pair (64 * pair_nxw(fp32) x LY columns, kz planes)
 Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32);
+// tiles of the LDS-staged Chebyshev triple (64 * triple_nxw x 2 * triple_pr columns)
+Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32);
 bool is_cheb(int pc);
 // interval handed to the Chebyshev iteration; false if degenerate
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,

@@ -126,6 +126,21 @@ Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32)
     return t;
 }
 
+Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32)
+{
+    Tiling t;
+    const int lx = 64 * triple_nxw(fp32), ly = 2 * triple_pr(fp32);
+    t.tx = (nx + lx - 1) / lx;
+    t.ty = (ny + ly - 1) / ly;
+    int kz = 64;
+    const long base = (long)t.tx * t.ty;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < 1024) kz /= 2;
+    t.kz = std::min(kz, std::max(nz, 1));
+    t.tz = (nz + t.kz - 1) / t.kz;
+    t.ntiles = t.tx * t.ty * t.tz;
+    return t;
+}
+
 bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI; }
 
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
@@ -147,6 +162,8 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
     p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
     p.pkz[0] = make_pair_tiling(nx, ny, nz, false).kz;
     p.pkz[1] = make_pair_tiling(nx, ny, nz, true).kz;
+    p.tkz[0] = make_triple_tiling(nx, ny, nz, false).kz;
+    p.tkz[1] = make_triple_tiling(nx, ny, nz, true).kz;
     p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
     p.bc = bc;
     p.maxit = maxit;
@@ -256,6 +273,22 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
         int y = V_RB, z = V_RA;
         int i = 3;
+        // three steps per pass where that is on (LDS-staged single problems):
+        // steps (i, i+1, i+2) read y_{i-1}, z_{i-2} and write w_{i+1}, w_{i+2};
+        // the steps left over run as a pair or alone
+        if (fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0) {
+            for (; i + 2 <= m; i += 3) {
+                int o[2], n = 0;
+                for (int b : ring)
+                    if (b != y && b != z && n < 2) o[n++] = b;
+                const bool last = i + 2 == m;
+                const int w3 = last ? vout : o[1];
+                launch_cheb_triple(mixed, mask, w, s,
+                                   KArgs{y, o[0], vsrc, z, i, second, 0, w3, last ? 1 : 0});
+                z = o[0];
+                y = w3;
+            }
+        }
         for (; i + 1 <= m; i += 2) {
             int o[2], n = 0;
             for (int b : ring)
@@ -313,9 +346,16 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse)
         if (fused(pc, m, mixed, fuse)) {
             pcb = 8 + 2 * tc + (mixed ? 4 : 0);          // steps 1, 2: v in; y_1, w_2 (+ v32) out
             int steps = m - 2;
+            int passes = 0;                             // passes of two or three steps
+            if (fuse >= 2) {                            // triples: y, z, v in; w_{i+1}, w_{i+2} out
+                pcb += (steps / 3) * 5 * tc;
+                passes += steps / 3;
+                steps %= 3;
+            }
             pcb += (steps / 2) * 5 * tc;                // pairs: y, z, v in; w_i, w_{i+1} out
+            passes += steps / 2;
             if (steps & 1) pcb += 4 * tc;               // last step alone: y, v, z, w
-            else if (steps >= 2) pcb -= tc;             // the last pair stores w_m only
+            else if (passes > 0) pcb -= tc;             // the last pass stores w_m only
         } else {
             pcb = 8 + tc + (mixed ? 4 : 0);             // first step: v, y (+ v32)
             if (m >= 2) pcb += 3 * tc;                  // step 2: y, v, w

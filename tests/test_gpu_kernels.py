@@ -118,3 +118,34 @@ def test_lds_pairs_match_register_pairs(gpu, cfg, mixed, shape):
         assert np.array_equal(got[0], got[1]), m
         ref = oracle.precond(v, h, pc, degree=m, mixed=mixed, block=block, bc=bc)
         assert np.array_equal(got[0], ref), m
+
+
+@pytest.mark.parametrize("cfg", LDS_CONFIGS, ids=lambda c: f"bc{c['bc']}-pc{c['pc']}-b{c['block']}")
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("shape", [(200, 37, 21), (128, 16, 8), (64, 8, 70), (3, 50, 2),
+                                   (257, 33, 9)])
+def test_triples_match_pairs(gpu, cfg, mixed, shape):
+    """Three Chebyshev steps per pass (LDS-staged, 128 x 8 tiles in FP64 and 128 x 16
+    in FP32) against two per pass and the oracle, bitwise, on ragged shapes, for
+    every face type and block mask; degrees whose steps after the first pair split
+    into triples only (5, 8), triples and a single step (6, 9) or triples and a pair
+    (7, 10)."""
+    nx, ny, nz = shape
+    bc, pc, block = cfg["bc"], cfg["pc"], cfg["block"]
+    for axis, n in enumerate(shape):
+        if bc >> (2 * axis) & 3 and n < 2:
+            pytest.skip("a Neumann face needs two points on its axis")
+    h = 1.0 / (nx + 1)
+    v = workloads.uniform_grid(10, shape)
+    dt = torch.float32 if mixed else torch.float64
+    for m in (5, 6, 7, 8, 9, 10):
+        got = []
+        for fuse in (2, 1):
+            with P.Solver(shape, h, bc=bc, block=block, fuse=fuse,
+                          precision=P.MIXED if mixed else P.FP64) as s:
+                out = torch.empty(v.shape, dtype=dt, device=gpu)
+                s.apply_precond(pc, m, dev(v), out)
+                got.append(host(out).astype(np.float64))
+        assert np.array_equal(got[0], got[1]), m
+        ref = oracle.precond(v, h, pc, degree=m, mixed=mixed, block=block, bc=bc)
+        assert np.array_equal(got[0], ref), m

@@ -215,3 +215,18 @@ def test_tile_orders_change_no_bits(gpu, mixed):
     for o in outs[1:]:
         assert o[0] == outs[0][0] == P.OK and o[1] == outs[0][1]
         assert np.array_equal(o[2], outs[0][2])
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_three_steps_per_pass_solve(gpu, mixed):
+    """Full solves with three Chebyshev steps per pass: the same iterations and bits
+    as the oracle."""
+    shape = (130, 45, 33)
+    h = 1.0 / 131
+    f = workloads.uniform_grid(41, shape)
+    st, stats, tr, x = gpu_solve(shape, h, f, P.PC_CHEBYSHEV, 8, 1e-9, fuse=2,
+                                 precision=P.MIXED if mixed else P.FP64)
+    ref = oracle.bicgstab(f, h, pc=oracle.PC_CHEBYSHEV, degree=8, mixed=mixed, tol=1e-9)
+    assert st == ref.status == P.OK
+    assert stats["iterations"] == ref.iterations
+    assert np.array_equal(x, ref.x)
