@@ -302,26 +302,39 @@ def main():
         nbytes = s64.kernel_bytes(kernel, P.FP64)
         return ms, nbytes, nbytes / (ms * 1e6)
 
-    k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
+    # the dominant kernel of the default plan: three fused Chebyshev steps per
+    # pass (two per pass where three are not available)
+    try:
+        k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_TRIPLE)
+        dom, dom_name, dom_work = "triple", "k_cheb_triple_lds<double,false,2,4,false,true>", "cheb_triple"
+    except P.PoissonError:
+        k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
+        dom, dom_name, dom_work = "pair", "k_cheb_pair_lds<double,double,false,false,2,8,false,true>", "cheb_pair"
+    p_ms, p_bytes, p_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
     s_ms, s_bytes, s_gbps = kernel_time(P.KERNEL_CHEB_STEP)
-    log(f"cheb pair FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic; "
-        f"single step {s_ms * 1e3:.1f} us, {s_gbps:.0f} GB/s")
-    workload = f"cheb_pair_fp64_{n}^3"
+    log(f"cheb {dom} FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic; pair "
+        f"{p_ms * 1e3:.1f} us, {p_gbps:.0f} GB/s; single step {s_ms * 1e3:.1f} us, {s_gbps:.0f} GB/s")
+    workload = f"{dom_work}_fp64_{n}^3"
     roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": round(k_gbps / PEAK_HBM_GBPS, 4),
                 "traffic": traffic_record("device.hip", workload),
-                "kernel": "k_cheb_pair_lds<double,double,false,false,2,8,false,true>", "kernel_us": round(k_ms * 1e3, 2),
+                "kernel": dom_name, "kernel_us": round(k_ms * 1e3, 2),
                 "bytes_per_launch": k_bytes,
+                "pair": {"kernel": "k_cheb_pair_lds<double,double,false,false,2,8,false,true>",
+                         "kernel_us": round(p_ms * 1e3, 2), "bytes_per_launch": p_bytes,
+                         "achieved": round(p_gbps, 1), "frac": round(p_gbps / PEAK_HBM_GBPS, 4),
+                         "traffic": traffic_record("device.hip", f"cheb_pair_fp64_{n}^3")},
                 "single_step": {"kernel": "k_stencil<S_CHEBK,double,double,false>",
                                 "kernel_us": round(s_ms * 1e3, 2), "bytes_per_launch": s_bytes,
                                 "achieved": round(s_gbps, 1)}}
+    others = {}
     if not a.no_unfused:
-        s64.set_option("fuse", 0)
-        st = solve64()
-        s64.set_option("fuse", 1)
-        unfused = {"iterations": st["iterations"], "solve_s": round(st["solve_ms"] / 1e3, 4),
-                   "hbm_gbps": round(st["model_gbps"], 1)}
-        log(f"unfused FP64: {st['iterations']} iterations, {st['solve_ms']:.1f} ms")
+        for fuse, key in ((1, "fp64_two_steps_per_pass"), (0, "fp64_one_step_per_pass")):
+            s64.set_option("fuse", fuse)
+            st = solve64()
+            others[key] = {"iterations": st["iterations"], "solve_s": round(st["solve_ms"] / 1e3, 4),
+                           "hbm_gbps": round(st["model_gbps"], 1)}
+            log(f"FP64 with fuse={fuse}: {st['iterations']} iterations, {st['solve_ms']:.1f} ms")
     s64.close()
 
     out = {"metric": METRIC, "value": round(iters / wall, 3), "unit": "iter/s", "n_gpus": 1,
@@ -338,8 +351,7 @@ def main():
            "hbm_frac": round(model_bytes / (loop_ms * 1e6) / PEAK_HBM_GBPS, 4),
            "tts_fp64_s": round(last["solve_ms"] / 1e3, 4),
            "relres_true_fp64": last["relres_true"]}
-    if not a.no_unfused:
-        out["fp64_one_step_per_pass"] = unfused
+    out.update(others)
 
     if not a.no_mixed:
         sm = P.Solver(shape, h, stream=stream, precision=P.MIXED)

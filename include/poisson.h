@@ -86,11 +86,11 @@ enum {
     POISSON_OPT_USE_GRAPH = 7,          /* 1 = replay captured HIP graphs (default), 0 = launch */
     POISSON_OPT_DEBUG_BREAKDOWN_AT = 8, /* testing: force omega = 0 at this iteration (-1 off) */
     POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
-                                           mixed): run Chebyshev steps two per pass (1,
-                                           default), one per pass (0), or three per pass
-                                           where the pairs are LDS-staged (2; the steps left
-                                           over run as a pair or alone); same arithmetic,
-                                           same results */
+                                           mixed): run Chebyshev steps three per pass where
+                                           the passes are LDS-staged (2, default; the steps
+                                           left over, and the first two, run as pairs or
+                                           alone), two per pass (1) or one per pass (0);
+                                           same arithmetic, same results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the fused Chebyshev
                                            pairs), 1 x-grouped everywhere (the x-tiles of a
@@ -196,7 +196,8 @@ enum {
     POISSON_KERNEL_CHEB_STEP = 0,       /* one interior Chebyshev step (Alg. 2 loop body) */
     POISSON_KERNEL_STENCIL_DOT = 1,     /* w = A p^ fused with r~.w */
     POISSON_KERNEL_UPDATE_XR = 2,       /* x and r updates fused with r~.r, r.r */
-    POISSON_KERNEL_CHEB_PAIR = 3        /* two interior Chebyshev steps in one pass */
+    POISSON_KERNEL_CHEB_PAIR = 3,       /* two interior Chebyshev steps in one pass */
+    POISSON_KERNEL_CHEB_TRIPLE = 4      /* three interior Chebyshev steps in one pass */
 };
 
 /* Launch one kernel `reps` times back to back on the context stream over the
@@ -204,7 +205,8 @@ enum {
    events on that stream. precision selects the FP64 or FP32 variant.
    Requires a previous successful poisson_solve with a plan that has the buffers
    (Chebyshev degree >= 3 for CHEB_STEP; a fused plan of degree >= 5 for
-   CHEB_PAIR). Asynchronous. */
+   CHEB_PAIR; for CHEB_TRIPLE also three steps per pass, POISSON_OPT_FUSE = 2
+   with LDS-staged pairs). Asynchronous. */
 int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps);
 
 /* Algorithmic HBM bytes of one launch of that kernel on this grid. */

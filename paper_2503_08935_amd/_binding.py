@@ -16,6 +16,7 @@ OPT_PRECISION, OPT_BLOCK, OPT_LMIN_SCALE, OPT_LMAX_SCALE = 1, 2, 3, 4
 OPT_BJ_GLOBAL_INTERVAL, OPT_GRAPH_ITERS, OPT_USE_GRAPH, OPT_DEBUG_BREAKDOWN_AT = 5, 6, 7, 8
 OPT_FUSE, OPT_TILE_ORDER, OPT_PAIR_LDS = 9, 10, 11
 KERNEL_CHEB_STEP, KERNEL_STENCIL_DOT, KERNEL_UPDATE_XR, KERNEL_CHEB_PAIR = 0, 1, 2, 3
+KERNEL_CHEB_TRIPLE = 4
 
 # every symbol declared in include/poisson.h
 EXPORTS = [

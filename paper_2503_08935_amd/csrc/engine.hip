@@ -548,6 +548,7 @@ double poisson_kernel_bytes(const poisson_ctx *c, int kernel, int precision)
     case POISSON_KERNEL_STENCIL_DOT: return (tc + 16) * N;     // p^, r~ in; w out
     case POISSON_KERNEL_UPDATE_XR: return (48 + 2 * tc) * N;   // x, p^, s^, r, t, r~ in; x, r out
     case POISSON_KERNEL_CHEB_PAIR: return 5 * tc * N;          // y, z, v in; w_i, w_{i+1} out
+    case POISSON_KERNEL_CHEB_TRIPLE: return 5 * tc * N;        // y, z, v in; w_{i+1}, w_{i+2} out
     default: return 0.0;
     }
 }
@@ -565,7 +566,11 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
         return POISSON_ERR_ARG;
     if (kernel == POISSON_KERNEL_CHEB_PAIR && !(c->plan_fuse && c->plan_deg >= 5))
         return POISSON_ERR_ARG;
-    if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_CHEB_PAIR) return POISSON_ERR_ARG;
+    if (kernel == POISSON_KERNEL_CHEB_TRIPLE &&
+        !(c->plan_fuse && c->plan_deg >= 5 && plan_fuse_level(c) >= 2))
+        return POISSON_ERR_ARG;
+    if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_CHEB_TRIPLE)
+        return POISSON_ERR_ARG;
     try {
         int rc;
         // same descriptor as the solve, but private scalars (never 'done') and
@@ -596,6 +601,9 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
             else if (kernel == POISSON_KERNEL_CHEB_PAIR)
                 launch_cheb_pair(mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->ntiles, c->stream,
                                  KArgs{V_RA, V_RC, mixed ? (int)V_V32 : (int)V_P, V_RB, 3, 0, 0, V_RD});
+            else if (kernel == POISSON_KERNEL_CHEB_TRIPLE)
+                launch_cheb_triple(mixed, c->plan_pc == POISSON_PC_BLOCK_JACOBI, w, c->stream,
+                                   KArgs{V_RA, V_RC, mixed ? (int)V_V32 : (int)V_P, V_RB, 3, 0, 0, V_RD});
             else if (kernel == POISSON_KERNEL_STENCIL_DOT)
                 launch_stencil(S_SDOT, mixed, false, w, c->ntiles, c->stream,
                                KArgs{V_PH, V_W, 0, 0, 0, 0, 0, 0});
