@@ -1970,8 +1970,11 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     }
 }
 
+// At most 256 VGPRs (two waves per SIMD): the bodies with neighbour selects
+// need a few more and spill them (measured faster than one wave per SIMD)
 template <typename T, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
-__global__ void __launch_bounds__(128 * NXW) k_cheb_triple_lds(Work W, KArgs A)
+__global__ void __launch_bounds__(128 * NXW) __attribute__((amdgpu_waves_per_eu(2)))
+k_cheb_triple_lds(Work W, KArgs A)
 {
     using L = LTriple<NXW, PR>;
     __shared__ T lds[6 * L::PLANE];
