@@ -139,6 +139,10 @@ void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipS
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored
 void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, const KArgs &a);
+// Chebyshev steps 1, 2 and 3 in one pass in the mixed mode (FP32 arithmetic,
+// LDS-staged, single problem): in = v (FP64, rounded once), out = y_2,
+// x2 = y_3, step = 1; the FP32 copy of v is written to V_V32 as well
+void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KArgs &a);
 void launch_fill_uniform(double *out, int64_t n, uint64_t seed, hipStream_t s);
 
 } // namespace pz

@@ -1638,7 +1638,12 @@ template <int NXW, int PR> struct LTriple {
     static constexpr int NT = 128 * NXW;
 };
 
-template <typename T, bool DROP, int NXW, int PR, bool TOP, bool MASK, bool SIMPLE>
+// FIRST: steps 1, 2 and 3 (the first step's own formula, y_0 := v, z = v/theta
+// at step 2; step 3 reads v = the input and z = w_1). The input is then v
+// itself, read as TU (FP64 also in the mixed mode, rounded once on load, with
+// the FP32 copy of v written out).
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
+          bool SIMPLE>
 __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs &A, int tile,
                                                      int lane, int xw, T *lds)
 {
@@ -1661,19 +1666,23 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     const bool xin = i < nx;
     const int ic = xin ? i : nx - 1;
     const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
+    const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU); // the input's planes
     const char *Yb = (const char *)P.vec[A.in];
     const char *Vb = (const char *)P.vec[A.v];
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
-    const T ih2 = Coef<T>::ih2(P);
+    char *V32b = (char *)P.vec[V_V32];
+    const T ih2 = Coef<T>::ih2(P), theta = Coef<T>::theta(P), c1 = Coef<T>::c1(P);
     const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
     const T rc1 = Coef<T>::rc(P, A.step), ro1 = Coef<T>::ro(P, A.step);
     const T rc2 = Coef<T>::rc(P, A.step + 1), ro2 = Coef<T>::ro(P, A.step + 1);
     const T rc3 = Coef<T>::rc(P, A.step + 2), ro3 = Coef<T>::ro(P, A.step + 2);
     auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
     auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto offy = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(TU); };
     auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
+    auto ldy = [](const char *plane, unsigned o) { return ld_g((const TU *)(plane + o)); };
     // LDS element of tile row r (-2..Y+1) and tile column c (-2..X+1)
     auto lidx = [](int r, int c) { return (r + 2) * L::PW + (c + 2); };
 
@@ -1684,7 +1693,7 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
     const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
     bool rok[E];
-    unsigned roff[E];
+    unsigned roff[E], ryoff[E];
     Sel sym[E], syp[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1692,12 +1701,13 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         const bool jin = j >= 0 && j < ny;
         rok[e] = xin && jin;
         roff[e] = off(ic, clampi(j, ny));
+        ryoff[e] = offy(ic, clampi(j, ny));
         sym[e] = to_sel(jin ? sel_lo(j, ny, MASK, B, nyl) : 0);
         syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
     }
     const int jo = y0 + TRO;
     const bool ook = xin && jo >= 0 && jo < ny;
-    const unsigned ooff = off(ic, clampi(jo, ny));
+    const unsigned ooff = offy(ic, clampi(jo, ny));
     const int lown = lidx(trow(0), cx);
     const int lpatch = lown + (lane == 0 ? -1 : (lane == 63 ? 1 : 0));
     const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
@@ -1723,7 +1733,8 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     const bool c1act = h1 && hload, c2act = h2 && hload;
     const bool fload = hact && grpb && hrow && hfi >= 0 && hfi < nx;
     const unsigned hoff = off(clampi(hi, nx), clampi(hj, ny));
-    const unsigned foff = off(clampi(hfi, nx), clampi(hj, ny));
+    const unsigned hoffy = offy(clampi(hi, nx), clampi(hj, ny));
+    const unsigned foff = offy(clampi(hfi, nx), clampi(hj, ny));
     const int lhself = lidx(trow(eh), hcol);
     const int lhnear = lidx(trow(eh), hnear);
     const int lhfar = grpb ? lhself : lidx(trow(eh), hfarc);
@@ -1735,68 +1746,88 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 
     // one step at one point: A u from the centre and its six neighbours (in
     // the order x-, x+, y-, y+, z-, z+), then the Chebyshev update
-    auto step = [&](T rc, T ro, T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl,
-                    Sel szh, Sel sxl, Sel sxh, Sel syl, Sel syh) {
+    // A u at one point from the centre and its six neighbours (in the order x-,
+    // x+, y-, y+, z-, z+), then the Chebyshev update of a step after the first
+    auto lap = [&](T c, T xm, T xp, T ym, T yp, T zm, T zp, Sel szl, Sel szh, Sel sxl, Sel sxh,
+                   Sel syl, Sel syh) {
         if constexpr (!SIMPLE) {
             const T xm0 = xm, ym0 = ym, zm0 = zm;
             xm = pick(sxl, xm0, xp), xp = pick(sxh, xp, xm0);
             ym = pick(syl, ym0, yp), yp = pick(syh, yp, ym0);
             zm = pick(szl, zm0, zp), zp = pick(szh, zp, zm0);
         }
-        const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        return (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+    };
+    auto step = [&](T rc, T ro, T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl,
+                    Sel szh, Sel sxl, Sel sxh, Sel syl, Sel syh) {
+        const T a = lap(c, xm, xp, ym, yp, zm, zp, szl, szh, sxl, sxh, syl, syh);
         return rc * ((ts * c + tod * (v - a)) - ro * z);
+    };
+    // step i (the first step's formula when FIRST)
+    auto step1 = [&](T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl, Sel szh, Sel sxl,
+                     Sel sxh, Sel syl, Sel syh) {
+        const T a = lap(c, xm, xp, ym, yp, zm, zp, szl, szh, sxl, sxh, syl, syh);
+        if constexpr (FIRST) return c1 * ((T)2 * c - a / theta);
+        else return rc1 * ((ts * c + tod * (v - a)) - ro1 * z);
     };
 
     struct RawY {
-        T y[E], yo, he;
+        TU y[E], yo, he;
     };
     struct RawV {
-        T v[E], z[E], hv, hz, hf;
+        T v[E], z[E], hv, hz;
+        TU hf;
     };
     auto issueY = [&](int p, RawY &R) {
-        const char *Yp = Yb + (size_t)clampi(p, nz) * PB;
+        const char *Yp = Yb + (size_t)clampi(p, nz) * PBY;
 #pragma unroll
-        for (int e = 0; e < E; ++e) R.y[e] = ld(Yp, roff[e]);
-        R.yo = ld(Yp, ooff);
-        R.he = ld(Yp, hoff);
+        for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
+        R.yo = ldy(Yp, ooff);
+        R.he = ldy(Yp, hoffy);
     };
     auto issueV = [&](int p, RawV &R) {
         const size_t po = (size_t)clampi(p, nz) * PB;
+        if constexpr (!FIRST) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            R.v[e] = ld(Vb + po, roff[e]);
-            R.z[e] = ld(Zb + po, roff[e]);
+            for (int e = 0; e < E; ++e) {
+                R.v[e] = ld(Vb + po, roff[e]);
+                R.z[e] = ld(Zb + po, roff[e]);
+            }
+            R.hv = ld(Vb + po, hoff);
+            R.hz = ld(Zb + po, hoff);
         }
-        R.hv = ld(Vb + po, hoff);
-        R.hz = ld(Zb + po, hoff);
-        R.hf = ld(Yb + po, foff);
+        R.hf = ldy(Yb + (size_t)clampi(p, nz) * PBY, foff);
     };
     auto buf = [&](int f, int k) { return lds + (2 * f + (k & 1)) * L::PLANE; }; // f: 0 y, 1 w_i, 2 w_{i+1}
 
     // registers across planes (k = the plane of w_i): y at k-1 (ya), w_i at
     // k-2 (w1a), w_{i+1} at k-3 (w2a), v at k-1 (vb) and k-2 (vbb); at the halo
     // points y at k-1 (ha), w_i at k-2 (h1a) and v at k-1 (hvb)
-    T ya[E], w1a[E], w2a[E], vb[E], vbb[E];
+    // FIRST: yaa = y (= v) at k-2, the v of step i+2
+    T ya[E], w1a[E], w2a[E], vb[E], vbb[E], yaa[E];
     T yob, ha, h1a, hvb;
     RawY RY;
     RawV RV;
+#pragma unroll
+    for (int e = 0; e < E; ++e) RV.v[e] = RV.z[e] = yaa[e] = (T)0;
+    RV.hv = RV.hz = (T)0;
     {
         RawY t;
         issueY(k0 - 3, t);
         {
             const bool pin = k0 - 3 >= 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? t.y[e] : (T)0;
-            ha = (pin && hload) ? t.he : (T)0;
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
+            ha = (pin && hload) ? (T)t.he : (T)0;
         }
         issueY(k0 - 2, t);
         {
             const bool pin = k0 - 2 >= 0;
             T *yd = buf(0, k0 - 2);
 #pragma unroll
-            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? t.y[e] : (T)0;
-            yob = (pin && ook) ? t.yo : (T)0;
-            if (hact) yd[lhself] = (pin && hload) ? t.he : (T)0;
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
+            yob = (pin && ook) ? (T)t.yo : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? (T)t.he : (T)0;
         }
     }
 #pragma unroll
@@ -1812,9 +1843,9 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         // take y at plane k+1, publish it, issue plane k+2
         T yc[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? RY.y[e] : (T)0;
-        const T yoc = (pin1 && ook) ? RY.yo : (T)0;
-        const T hc = (pin1 && hload) ? RY.he : (T)0;
+        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? (T)RY.y[e] : (T)0;
+        const T yoc = (pin1 && ook) ? (T)RY.yo : (T)0;
+        const T hc = (pin1 && hload) ? (T)RY.he : (T)0;
         {
             T *yd = buf(0, k + 1);
 #pragma unroll
@@ -1848,10 +1879,10 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                     yp = e == E - 1 ? yob : cen[e < E - 1 ? e + 1 : e];
                 }
                 const bool ok = pin0 && rok[e];
-                const T v = ok ? RV.v[e] : (T)0, z = ok ? RV.z[e] : (T)0;
+                const T v = (!FIRST && ok) ? RV.v[e] : (T)0, z = (!FIRST && ok) ? RV.z[e] : (T)0;
                 vc[e] = v;
-                const T w = step(rc1, ro1, c, xm, xp, ym, yp, ya[e], yc[e], v, z, s1m, s1p, sxm, sxp,
-                                 sym[e], syp[e]);
+                const T w = step1(c, xm, xp, ym, yp, ya[e], yc[e], v, z, s1m, s1p, sxm, sxp, sym[e],
+                                  syp[e]);
                 w1c[e] = ok ? w : (T)0;
             }
         }
@@ -1860,13 +1891,12 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         {
             hb = ys[lhself];
             const T xn = ys[lhnear], d = ys[lhup], u = ys[lhdn];
-            const T xf = grpb ? ((fload && pin0) ? RV.hf : (T)0) : ys[lhfar];
+            const T xf = grpb ? ((fload && pin0) ? (T)RV.hf : (T)0) : ys[lhfar];
             const bool ok = c1act && pin0;
-            hvc = (hload && pin0) ? RV.hv : (T)0;
-            const T hz = ok ? RV.hz : (T)0;
+            hvc = (!FIRST && hload && pin0) ? RV.hv : (T)0;
+            const T hz = (!FIRST && ok) ? RV.hz : (T)0;
             const T l = hside ? xn : xf, r = hside ? xf : xn;
-            const T w = step(rc1, ro1, hb, l, r, d, u, ha, hc, hvc, hz, s1m, s1p, csxl, csxh, csyl,
-                             csyh);
+            const T w = step1(hb, l, r, d, u, ha, hc, hvc, hz, s1m, s1p, csxl, csxh, csyl, csyh);
             h1c = ok ? w : (T)0;
         }
         {
@@ -1901,8 +1931,12 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                     ym = e == 0 ? inner : cen1[e > 0 ? e - 1 : 0];
                     yp = cen1[e + 1];
                 }
-                const T w = step(rc2, ro2, c, xm, xp, ym, yp, w1a[e], w1c[e], vb[e], ya[e], s2m, s2p,
-                                 sxm, sxp, sym[e], syp[e]);
+                // step i+1 reads z = y_{i-1}, the stencil input at plane k-1 (for the
+                // first triple v = that input and z = v/theta)
+                const T v = FIRST ? ya[e] : vb[e];
+                const T z = FIRST ? v / theta : ya[e];
+                const T w = step(rc2, ro2, c, xm, xp, ym, yp, w1a[e], w1c[e], v, z, s2m, s2p, sxm, sxp,
+                                 sym[e], syp[e]);
                 w2c[e] = (pinm && rok[e]) ? w : (T)0;
             }
             // w_{i+1} at the halo points one out, own rows (lanes A)
@@ -1910,8 +1944,10 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                 const T c = w1s[lhself];
                 const T xn = w1s[lhnear], xf = w1s[lhfar], d = w1s[lhup], u = w1s[lhdn];
                 const T l = hside ? xn : xf, r = hside ? xf : xn;
-                const T w = step(rc2, ro2, c, l, r, d, u, h1a, h1c, hvb, ha, s2m, s2p, csxl, csxh,
-                                 csyl, csyh);
+                const T v = FIRST ? ha : hvb;
+                const T z = FIRST ? v / theta : ha;
+                const T w = step(rc2, ro2, c, l, r, d, u, h1a, h1c, v, z, s2m, s2p, csxl, csxh, csyl,
+                                 csyh);
                 h2c = (c2act && pinm) ? w : (T)0;
             }
             T *wd = buf(2, k - 1);
@@ -1945,17 +1981,20 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                     yp = cen2[e + 1];
                 }
                 // step i+2 reads z = w_i at plane k-2, held in w1a
-                const T w3 = step(rc3, ro3, c, xm, xp, ym, yp, w2a[e], w2c[e], vbb[e], w1a[e], s3m,
-                                  s3p, sxm, sxp, sym[e], syp[e]);
+                const T v = FIRST ? yaa[e] : vbb[e];
+                const T w3 = step(rc3, ro3, c, xm, xp, ym, yp, w2a[e], w2c[e], v, w1a[e], s3m, s3p,
+                                  sxm, sxp, sym[e], syp[e]);
                 if (rok[e]) {
                     if constexpr (!DROP) st_nt((T *)(W1b + po + roff[e]), c);
                     st_nt((T *)(W2b + po + roff[e]), w3);
+                    if constexpr (FIRST && sizeof(T) == 4) st_nt((T *)(V32b + po + roff[e]), v);
                 }
             }
         }
         // rotate: y at plane k, w_i at k-1, w_{i+1} at k-2 for the next plane
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            if constexpr (FIRST) yaa[e] = ya[e];
             ya[e] = ys[lown + e * L::PW];
             w1a[e] = cen1[e];
             w2a[e] = cen2[e];
@@ -1972,7 +2011,7 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 
 // At most 256 VGPRs (two waves per SIMD): the bodies with neighbour selects
 // need a few more and spill them (measured faster than one wave per SIMD)
-template <typename T, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
 __global__ void __launch_bounds__(128 * NXW) __attribute__((amdgpu_waves_per_eu(2)))
 k_cheb_triple_lds(Work W, KArgs A)
 {
@@ -1993,9 +2032,9 @@ k_cheb_triple_lds(Work W, KArgs A)
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
         if (yw == 0)
-            cheb_triple_lds_tile<T, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
         else
-            cheb_triple_lds_tile<T, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
     }
 }
 
@@ -2297,34 +2336,39 @@ void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_
     else lp<double, double, false>(mask, w, grid, s, a);
 }
 
-template <typename T, bool DROP, bool MASK, bool SIMPLE>
+template <typename T, typename TU, bool FIRST, bool DROP, bool MASK, bool SIMPLE>
 static void ltr_launch(const Work &w, hipStream_t s, const KArgs &a)
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NXW = triple_nxw(F32), PR = triple_pr(F32);
-    hipLaunchKernelGGL((k_cheb_triple_lds<T, DROP, NXW, PR, MASK, SIMPLE>), dim3(w.triple_tiles[F32]),
-                       dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+    hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, FIRST, DROP, NXW, PR, MASK, SIMPLE>),
+                       dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
 }
 
-template <typename T, bool DROP>
+template <typename T, typename TU, bool FIRST, bool DROP>
 static void ltr_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
 {
-    if (mask) ltr_launch<T, DROP, true, false>(w, s, a);
-    else if (w.neumann) ltr_launch<T, DROP, false, false>(w, s, a);
-    else ltr_launch<T, DROP, false, true>(w, s, a);
+    if (mask) ltr_launch<T, TU, FIRST, DROP, true, false>(w, s, a);
+    else if (w.neumann) ltr_launch<T, TU, FIRST, DROP, false, false>(w, s, a);
+    else ltr_launch<T, TU, FIRST, DROP, false, true>(w, s, a);
 }
 
 template <typename T>
 static void ltr(bool mask, const Work &w, hipStream_t s, const KArgs &a)
 {
-    if (a.drop1) ltr_drop<T, true>(mask, w, s, a);
-    else ltr_drop<T, false>(mask, w, s, a);
+    if (a.drop1) ltr_drop<T, T, false, true>(mask, w, s, a);
+    else ltr_drop<T, T, false, false>(mask, w, s, a);
 }
 
 void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, const KArgs &a)
 {
     if (mixed) ltr<float>(mask, w, s, a);
     else ltr<double>(mask, w, s, a);
+}
+
+void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    ltr_drop<float, double, true, false>(mask, w, s, a);
 }
 
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

@@ -269,14 +269,21 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         // reading y_{i-1} and z_{i-2} and writing w_i, w_{i+1} to two other buffers
         // of the ring {RA, RB, RC, RD} (nothing is written in place: every input is
         // read by neighbouring tiles); an odd last step runs alone
-        launch_cheb_first_pair(mixed, mask, w, grid, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
+        // three steps per pass where that is on (LDS-staged single problems):
+        // (i, i+1, i+2) read y_{i-1} and z_{i-2} and write w_{i+1}, w_{i+2}; the
+        // steps left over run as a pair or alone. The first pass is steps 1-2, or
+        // in the mixed mode with degree >= 5 steps 1-3 (in FP64 the two divisions
+        // per point of that pass made it slower than a pair: 980 against 605 us)
+        const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
+        const bool first3 = tri && mixed && m >= 5;
+        if (first3)
+            launch_cheb_first_triple(mask, w, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
+        else
+            launch_cheb_first_pair(mixed, mask, w, grid, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
         int y = V_RB, z = V_RA;
-        int i = 3;
-        // three steps per pass where that is on (LDS-staged single problems):
-        // steps (i, i+1, i+2) read y_{i-1}, z_{i-2} and write w_{i+1}, w_{i+2};
-        // the steps left over run as a pair or alone
-        if (fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0) {
+        int i = first3 ? 4 : 3;
+        if (tri) {
             for (; i + 2 <= m; i += 3) {
                 int o[2], n = 0;
                 for (int b : ring)
@@ -344,10 +351,12 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse)
     else if (is_cheb(pc)) {
         const double tc = mixed ? 4 : 8;
         if (fused(pc, m, mixed, fuse)) {
-            pcb = 8 + 2 * tc + (mixed ? 4 : 0);          // steps 1, 2: v in; y_1, w_2 (+ v32) out
-            int steps = m - 2;
+            // steps 1-2 (or 1-3, mixed with triples): v in; two outputs (+ v32) out
+            pcb = 8 + 2 * tc + (mixed ? 4 : 0);
+            const bool tri = fuse >= 2;
+            int steps = m - ((tri && mixed && m >= 5) ? 3 : 2);
             int passes = 0;                             // passes of two or three steps
-            if (fuse >= 2) {                            // triples: y, z, v in; w_{i+1}, w_{i+2} out
+            if (tri) {                                  // triples: y, z, v in; w_{i+1}, w_{i+2} out
                 pcb += (steps / 3) * 5 * tc;
                 passes += steps / 3;
                 steps %= 3;

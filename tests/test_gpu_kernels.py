@@ -126,10 +126,10 @@ def test_lds_pairs_match_register_pairs(gpu, cfg, mixed, shape):
                                    (257, 33, 9)])
 def test_triples_match_pairs(gpu, cfg, mixed, shape):
     """Three Chebyshev steps per pass (LDS-staged, 128 x 8 tiles in FP64 and 128 x 16
-    in FP32) against two per pass and the oracle, bitwise, on ragged shapes, for
-    every face type and block mask; degrees whose steps after the first pair split
-    into triples only (5, 8), triples and a single step (6, 9) or triples and a pair
-    (7, 10)."""
+    in FP32; steps 1-3 first) against two per pass and the oracle, bitwise, on ragged
+    shapes, for every face type and block mask; degrees whose steps after the first
+    triple split into triples only (6, 9), triples and a pair (5, 8) or triples and
+    a single step (7, 10)."""
     nx, ny, nz = shape
     bc, pc, block = cfg["bc"], cfg["pc"], cfg["block"]
     for axis, n in enumerate(shape):
