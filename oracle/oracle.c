@@ -321,7 +321,11 @@ void orc_apply_A(int nx, int ny, int nz, double h, int block, const double *u, d
     orc_apply_A_bc(nx, ny, nz, h, block, 0u, u, out);
 }
 
-/* the same operator on FP32 data in FP32 arithmetic (mixed-precision preconditioner) */
+/* the same operator on FP32 data in FP32 arithmetic (mixed-precision            */
+/* preconditioner). The paper fixes no precision; in FP32 the sum is taken as the */
+/* three axes' second differences, (c - minus) + (c - plus), added x, y, z, then  */
+/* scaled by ih2. On smooth data each difference and each pair sum is exact,     */
+/* where 6c minus the six neighbours would cancel most of FP32's digits.          */
 static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, unsigned bc, const float *u,
                         float *out)
 {
@@ -342,7 +346,10 @@ static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, unsigned b
                 float yp = jp >= 0 ? u[IDX(i, jp, k)] : 0.0f;
                 float zm = km >= 0 ? u[IDX(i, j, km)] : 0.0f;
                 float zp = kp >= 0 ? u[IDX(i, j, kp)] : 0.0f;
-                out[IDX(i, j, k)] = (6.0f * c - xm - xp - ym - yp - zm - zp) * ih2;
+                float dx = (c - xm) + (c - xp);
+                float dy = (c - ym) + (c - yp);
+                float dz = (c - zm) + (c - zp);
+                out[IDX(i, j, k)] = ((dx + dy) + dz) * ih2;
             }
 }
 

@@ -17,7 +17,9 @@
 // Arithmetic contract (matched by the independent CPU oracle):
 //   * no contraction (built with -ffp-contract=off); the only FMA is the
 //     explicit error-free product of the dot products;
-//   * (A u) = ((((((6u - u_x-) - u_x+) - u_y-) - u_y+) - u_z-) - u_z+) * (1/(h*h));
+//   * (A u) = ((((((6u - u_x-) - u_x+) - u_y-) - u_y+) - u_z-) - u_z+) * (1/(h*h))
+//     in FP64, and in FP32 (the mixed-precision preconditioner)
+//     ((((u - u_x-) + (u - u_x+)) + ((u - u_y-) + (u - u_y+))) + ((u - u_z-) + (u - u_z+))) * (1/(h*h));
 //   * vector updates evaluate left to right exactly as written in Alg. 1 / 2;
 //   * dot products: per thread Dot2 (TwoProduct + TwoSum, Ogita, Rump and
 //     Oishi 2005), then double-double additions (AccurateDWPlusDW, Joldes,
@@ -349,6 +351,25 @@ template <> struct Coef<float> {
     static __device__ float jac(const Prob &P) { return P.jac_df; }
 };
 
+// A u at one point from the centre c and its six neighbours, times ih2. FP64
+// evaluates 6c minus the neighbours left to right. FP32 sums the second
+// differences of the three axes, each as (c - u_minus) + (c - u_plus): where u
+// is smooth each difference is exact and so is their sum, so the result keeps
+// FP32's relative accuracy; 6c minus the neighbours cancels there and loses up
+// to 6 ih2 / lambda_min of it (about 1e5 at 768^3).
+template <typename T>
+__device__ __forceinline__ T lap7(T c, T xm, T xp, T ym, T yp, T zm, T zp, T ih2)
+{
+    return (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+}
+template <>
+__device__ __forceinline__ float lap7<float>(float c, float xm, float xp, float ym, float yp,
+                                             float zm, float zp, float ih2)
+{
+    const float dx = (c - xm) + (c - xp), dy = (c - ym) + (c - yp), dz = (c - zm) + (c - zp);
+    return ((dx + dy) + dz) * ih2;
+}
+
 // ------------------------------------------------------------------------
 // wave64 lane exchange: DPP wavefront shift by one lane (the lane without a
 // source reads 0) and lane broadcast
@@ -557,7 +578,7 @@ __device__ __forceinline__ void stencil_tile(const Prob &P, const KArgs &A, int 
                 ym = pick(sym[r], yl, yr), yp = pick(syp[r], yr, yl);
                 zmv = pick(szm, zm[r], zr[r]), zpv = pick(szp, zr[r], zm[r]);
             }
-            const TC a = (((((((TC)6 * c[r] - xm) - xp) - ym) - yp) - zmv) - zpv) * ih2;
+            const TC a = lap7<TC>(c[r], xm, xp, ym, yp, zmv, zpv, ih2);
             if (rin[r]) {
                 const size_t idx = pk + roff[r];
                 if constexpr (OP == S_APPLY) {
@@ -837,8 +858,8 @@ __device__ __forceinline__ void cheb_f32x2_tile(const Prob &P, const KArgs &A, i
                 zm0 = pick(szm, zm[r].a, zr[r].a), zm1 = pick(szm, zm[r].b, zr[r].b);
                 zp0 = pick(szp, zr[r].a, zm[r].a), zp1 = pick(szp, zr[r].b, zm[r].b);
             }
-            const float a0 = ((((((6.0f * c[r].a - xm0) - xp0) - ym0) - yp0) - zm0) - zp0) * ih2;
-            const float a1 = ((((((6.0f * c[r].b - xm1) - xp1) - ym1) - yp1) - zm1) - zp1) * ih2;
+            const float a0 = lap7<float>(c[r].a, xm0, xp0, ym0, yp0, zm0, zp0, ih2);
+            const float a1 = lap7<float>(c[r].b, xm1, xp1, ym1, yp1, zm1, zp1, ih2);
             const size_t idx = base + r * NXs;
             const bool ok0 = in0 && rin[r], ok1 = in1 && rin[r];
             float w0, w1;
@@ -995,7 +1016,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     // w_i at one point from its 7 y values, v and z (the k_stencil step)
     auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm,
                      T zp, T v, T z) {
-        const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        const T a = lap7<T>(yc, xm, xp, ym, yp, zm, zp, ih2);
         if constexpr (FIRST) return c1 * ((T)2 * yc - a / theta);
         else return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
     };
@@ -1161,7 +1182,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
                     ym = pick(wsym[q], wb[q - 1], wb[q + 1]), yp = pick(wsyp[q], wb[q + 1], wb[q - 1]);
                     zm = pick(szm, wa[q], wc[q]), zp = pick(szp, wc[q], wa[q]);
                 }
-                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                const T a = lap7<T>(c, xm, xp, ym, yp, zm, zp, ih2);
                 // step i+1 reads z = y_{i-1}, the pair's stencil input at plane k
                 // (for the first pair, z = v/theta with v = that input)
                 const T v = FIRST ? ya[q + 1] : vb[r];
@@ -1359,7 +1380,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     const Sel csyh = to_sel(cact ? sel_hi(hj, ny, MASK, B, nyh) : 0);
 
     auto step1 = [&](T yc, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z) {
-        const T a = (((((((T)6 * yc - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        const T a = lap7<T>(yc, xm, xp, ym, yp, zm, zp, ih2);
         if constexpr (FIRST) return c1 * ((T)2 * yc - a / theta);
         else return rc1 * ((ts * yc + tod * (v - a)) - ro1 * z);
     };
@@ -1545,7 +1566,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
                     ym = pick(sym[e], ym0, yp), yp = pick(syp[e], yp, ym0);
                     zm = pick(sz2m, zm0, zp), zp = pick(sz2p, zp, zm0);
                 }
-                const T a = (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+                const T a = lap7<T>(c, xm, xp, ym, yp, zm, zp, ih2);
                 // step i+1 reads z = y_{i-1}, the pair's stencil input at plane k-1
                 // (for the first pair, z = v/theta with v = that input)
                 const T v = FIRST ? ya[e] : vb[e];
@@ -1756,7 +1777,7 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
             ym = pick(syl, ym0, yp), yp = pick(syh, yp, ym0);
             zm = pick(szl, zm0, zp), zp = pick(szh, zp, zm0);
         }
-        return (((((((T)6 * c - xm) - xp) - ym) - yp) - zm) - zp) * ih2;
+        return lap7<T>(c, xm, xp, ym, yp, zm, zp, ih2);
     };
     auto step = [&](T rc, T ro, T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl,
                     Sel szh, Sel sxl, Sel sxh, Sel syl, Sel syh) {
