@@ -131,3 +131,41 @@ def test_block_jacobi_equals_blockwise_dense_chebyshev():
         ref[sel] = V @ (q(w, lo, hi, m) * (V.T @ v[sel]))
     got = oracle.chebyshev(v.reshape(5, 4, 6), h, lo, hi, m, block=bs).ravel()
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def _first_step_fp32(u, h, lo, hi, au):
+    """y = c1 (2u - A u / theta) in float32 for a given float32 A u, with c1 and
+    theta computed in FP64 and rounded once (the first step of Alg. 2)."""
+    theta, delta = (hi + lo) / 2.0, (hi - lo) / 2.0
+    sigma = theta / delta
+    rho_cur = 1.0 / (2.0 * sigma - 1.0 / sigma)
+    c1 = np.float32(2.0 * rho_cur / delta)
+    return c1 * (np.float32(2.0) * u.astype(np.float32) - au / np.float32(theta))
+
+
+def test_fp32_operator_exact_on_smooth_quadratic():
+    """The FP32 operator of the mixed mode keeps full accuracy where u is smooth.
+
+    u = 1 + (i^2 + j^2 + k^2) 2^-23 is exact in float32, and at interior points
+    (A u) = -6 * 2^-23 / h^2 exactly (each axis' second difference of i^2 is 2).
+    Summing the differences (u - u_minus) + (u - u_plus) gets this exactly; 6u
+    minus the neighbours would round 6u, whose bits span 2^2 .. 2^-22. The first
+    Chebyshev step then equals the float32 evaluation of its formula with that
+    A u, bit for bit."""
+    n = 40
+    shape = (n, n, n)
+    h = 1.0 / (n + 1)
+    ih2f = np.float32(1.0 / (h * h))
+    i = np.arange(n, dtype=np.float64)
+    q2 = i[:, None, None] ** 2 + i[None, :, None] ** 2 + i[None, None, :] ** 2
+    u = 1.0 + q2 * 2.0 ** -23
+    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
+    lo, hi = oracle.interval(shape, h)
+    got = oracle.chebyshev(u, h, lo, hi, 1, mixed=True).reshape(shape)
+    au = np.float32(-6.0 * 2.0 ** -23) * ih2f
+    ref = _first_step_fp32(u, h, lo, hi, au).astype(np.float64)
+    inner = (slice(1, -1),) * 3
+    assert np.array_equal(got[inner], ref[inner])
+    # 6u first would not be exact here: the float32 rounding of 6u already moves it
+    six_u = np.float32(6.0) * u.astype(np.float32)
+    assert not np.array_equal(six_u.astype(np.float64), 6.0 * u)
