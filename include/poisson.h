@@ -70,7 +70,10 @@ enum {
                                     FP32: its input is rounded to FP32 once, its scalar
                                     coefficients (computed in FP64) are rounded to FP32
                                     once, all its arithmetic is FP32, and its output p^ / s^
-                                    is stored in FP32 and widened exactly where FP64 uses it */
+                                    is stored in FP32 and widened exactly where FP64 uses it.
+                                    Its A u sums the axes' second differences,
+                                    ((u - u_x-) + (u - u_x+)) + ... , which keeps FP32's
+                                    relative accuracy where u is smooth */
 };
 
 /* ---- options (poisson_set_option keys) ---------------------------------- */
