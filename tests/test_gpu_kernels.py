@@ -149,3 +149,33 @@ def test_triples_match_pairs(gpu, cfg, mixed, shape):
         assert np.array_equal(got[0], got[1]), m
         ref = oracle.precond(v, h, pc, degree=m, mixed=mixed, block=block, bc=bc)
         assert np.array_equal(got[0], ref), m
+
+
+@pytest.mark.parametrize("fuse", [0, 1, 2])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8])
+def test_fp32_operator_on_smooth_field(gpu, fuse, m):
+    """Mixed mode on u = 1 + (i^2 + j^2 + k^2) 2^-23 (exact in FP32), where the
+    FP32 operator's second-difference order is exact and 6u first is not: every
+    FP32 kernel (one step per pass, pairs, triples) matches the oracle bit for
+    bit, and the first step matches the float32 evaluation of its formula with
+    A u = -6 * 2^-23 / h^2 at interior points."""
+    shape = (70, 40, 36)
+    nx, ny, nz = shape
+    h = 1.0 / (nx + 1)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = 1.0 + (i * i + j * j + k * k).astype(np.float64) * 2.0 ** -23
+    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
+    with P.Solver(shape, h, precision=P.MIXED, fuse=fuse) as s:
+        out = torch.empty(u.shape, dtype=torch.float32, device=gpu)
+        s.apply_precond(P.PC_CHEBYSHEV, m, dev(u), out)
+        got = host(out).astype(np.float64)
+    assert np.array_equal(got, oracle.precond(u, h, P.PC_CHEBYSHEV, degree=m, mixed=True))
+    if m == 1:
+        lo, hi = oracle.interval(shape, h)
+        theta, delta = (hi + lo) / 2.0, (hi - lo) / 2.0
+        sigma = theta / delta
+        c1 = np.float32(2.0 * (1.0 / (2.0 * sigma - 1.0 / sigma)) / delta)
+        au = np.float32(-6.0 * 2.0 ** -23) * np.float32(1.0 / (h * h))
+        ref = c1 * (np.float32(2.0) * u.astype(np.float32) - au / np.float32(theta))
+        inner = (slice(1, -1),) * 3
+        assert np.array_equal(got[inner], ref.astype(np.float64)[inner])
