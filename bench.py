@@ -7,11 +7,14 @@ relative residual 1e-8. The right-hand side is generated on the device with the
 same counter-based generator as the host-side workloads, so inputs are resident
 in HBM before the timed region. Printed as one JSON line:
   value        iterations per second over the timed solves (whole solves)
+  loop_iter_per_s  iterations per second of the iteration loops' device time
+               (HIP events); outside_loop_ms_per_solve is the rest of a solve
+               (initial residual, interval and coefficients, true residual, host)
   hbm_gbps     algorithmic bytes of the iteration loop / loop device time
   tts_*        time to 1e-8 of the FP64 solve and of the mixed solve (FP32
                Chebyshev inside FP64 Bi-CGSTAB), same right-hand side
-  roofline     dominant kernel (interior Chebyshev step, FP64), timed with HIP
-               events on the stream it runs on
+  roofline     dominant kernel (three fused interior Chebyshev steps, FP64),
+               timed with HIP events on the stream it runs on
   cpu_baseline the CPU oracle on a bounded sample (2 iterations vs 1 iteration
                of the same 512^3 solve; the difference is one iteration)
   p99_solve_ms the serving stream: 2000 requests of n^3 grids, n uniform over
@@ -286,8 +289,8 @@ def main():
         f"{last['relres_true']:.3e}")
     x64 = x.clone()
 
-    # dominant kernel (two fused interior Chebyshev steps, FP64), timed with HIP
-    # events on the solver's stream; the single interior step for reference
+    # kernels timed with HIP events on the solver's stream: the dominant one
+    # (below), the fused pair and the single interior step for reference
     reps = a.kernel_reps
 
     def kernel_time(kernel):
@@ -347,6 +350,8 @@ def main():
                       "grid": n, "unknowns": N, "precond": "chebyshev", "degree": a.degree,
                       "tol": a.tol},
            "iterations_per_solve": last["iterations"],
+           "loop_iter_per_s": round(iters / (loop_ms / 1e3), 3),
+           "outside_loop_ms_per_solve": round((wall * 1e3 - loop_ms) / a.steps, 2),
            "hbm_gbps": round(model_bytes / (loop_ms * 1e6), 1),
            "hbm_frac": round(model_bytes / (loop_ms * 1e6) / PEAK_HBM_GBPS, 4),
            "tts_fp64_s": round(last["solve_ms"] / 1e3, 4),
