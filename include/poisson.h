@@ -174,6 +174,21 @@ int poisson_stats(const poisson_ctx *c, poisson_stats_t *out);
    (host memory) and returns the number of rows copied (>= 0) or an error. */
 int poisson_trace(const poisson_ctx *c, double *out, int cap);
 
+/* The interval [lambda_min, lambda_max] a Chebyshev (G(CI)) or Block-Jacobi
+   (BJ(CI) / GNoComm(CI)) preconditioner of this context would use, with the
+   current options (POISSON_OPT_BLOCK, _BJ_GLOBAL_INTERVAL, _LMIN_SCALE,
+   _LMAX_SCALE). The spectrum of the grid operator is the sum over the axes of
+   the 1D spectra divided by h^2 (eqs. eigenvaluesPoissonDirichletMatrix,
+   lambdaMin and lambdaMax; the matrix N of eq. matrix_neuman on a Neumann axis);
+   BJ(CI) bounds the spectra of all its diagonal blocks (eq.
+   blockJacobiPreconditioner), GNoComm(CI) takes the global interval
+   (Methodology section). The same values poisson_stats reports after a solve.
+   Host-only: touches no device. ERR_ARG for a NULL argument, precond not
+   CHEBYSHEV / BLOCK_JACOBI, or a degenerate interval (lambda_min <= 0 or
+   lambda_max <= lambda_min, e.g. on a 1x1x1 grid); outputs unchanged then. */
+int poisson_cheb_interval(const poisson_ctx *c, int precond, double *lambda_min,
+                          double *lambda_max);
+
 /* Release everything the context owns. NULL-safe. */
 void poisson_destroy(poisson_ctx *c);
 

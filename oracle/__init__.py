@@ -29,7 +29,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 PC_NONE, PC_JACOBI, PC_CHEBYSHEV, PC_BLOCK_JACOBI = 0, 1, 2, 3
 OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE = 0, 1, -1, -5, -6
 
-BUILD_CMD = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+BUILD_CMD = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
              "-shared", "-o", _LIB, _SRC, "-lm"]
 
 

@@ -23,7 +23,7 @@ EXPORTS = [
     "poisson_create", "poisson_set_option", "poisson_set_stream", "poisson_solve",
     "poisson_stats", "poisson_trace", "poisson_destroy", "poisson_strerror",
     "poisson_apply_operator", "poisson_apply_precond", "poisson_dot", "poisson_kernel_bench",
-    "poisson_kernel_bytes", "poisson_fill_uniform",
+    "poisson_kernel_bytes", "poisson_fill_uniform", "poisson_cheb_interval",
     "poisson_server_create", "poisson_server_set_option", "poisson_server_footprint",
     "poisson_server_submit", "poisson_server_step", "poisson_server_poll", "poisson_server_info",
     "poisson_server_destroy",
@@ -78,6 +78,7 @@ def lib():
         L.poisson_solve.argtypes = [vp, vp, vp, ip, ip, ctypes.c_double, ip]
         L.poisson_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.poisson_trace.argtypes = [vp, dp, ip]
+        L.poisson_cheb_interval.argtypes = [vp, ip, dp, dp]
         L.poisson_destroy.argtypes = [vp]
         L.poisson_destroy.restype = None
         L.poisson_strerror.argtypes = [ip]
@@ -208,6 +209,13 @@ class Solver:
         got = _check(lib().poisson_trace(self._ctx, buf.ctypes.data_as(
             ctypes.POINTER(ctypes.c_double)), n), "poisson_trace")
         return buf[:got]
+
+    def cheb_interval(self, precond=PC_CHEBYSHEV):
+        """(lambda_min, lambda_max) a Chebyshev / Block-Jacobi solve would use (host only)."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib().poisson_cheb_interval(self._ctx, int(precond), ctypes.byref(lo),
+                                           ctypes.byref(hi)), "poisson_cheb_interval")
+        return lo.value, hi.value
 
     def apply_operator(self, u, out):
         import torch

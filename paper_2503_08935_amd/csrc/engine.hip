@@ -418,6 +418,18 @@ int poisson_trace(const poisson_ctx *c, double *out, int cap)
     return n;
 }
 
+int poisson_cheb_interval(const poisson_ctx *c, int precond, double *lambda_min,
+                          double *lambda_max)
+{
+    if (!c || !lambda_min || !lambda_max || !is_cheb(precond)) return POISSON_ERR_ARG;
+    double lo, hi;
+    if (!cheb_interval(c->nx, c->ny, c->nz, c->h, c->bc, precond, c->opt, lo, hi))
+        return POISSON_ERR_ARG;
+    *lambda_min = lo;
+    *lambda_max = hi;
+    return POISSON_OK;
+}
+
 void poisson_destroy(poisson_ctx *c)
 {
     if (!c) return;

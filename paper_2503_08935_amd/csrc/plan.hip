@@ -21,65 +21,62 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// i-th eigenvalue of the order-n Dirichlet matrix D (eq. eigenvaluesPoissonDirichletMatrix)
-static double dirichlet_eig(int i, int n)
+// ---- Chebyshev interval ----------------------------------------------------
+// Every 1D operator on a run of L points (matrix D of eq. matrix_dirichlet, or
+// the matrix N of eq. matrix_neuman with a mirror ghost at one or both ends) has
+// the eigenvalues 4 sin^2(phi), with phi on an evenly spaced ladder a * pi / q:
+//   no Neumann end   a = 1, 2, ..., L          q = 2 (L + 1)   (sine modes)
+//   one Neumann end  a = 1, 3, ..., 2L - 1     q = 4 L         (quarter-wave cosines)
+//   two Neumann ends a = 0, 1, ..., L - 1      q = 2 (L - 1)   (cosine modes)
+// Every rung lies in [0, pi/2], where sin^2 increases, so the bottom rung gives
+// the smallest eigenvalue and the top rung the largest.
+struct Ladder {
+    double bottom, top, q;
+};
+
+static Ladder ladder_of(int L, bool neu_lo, bool neu_hi)
 {
-    const double s = sin((double)i * M_PI / (2.0 * (double)(n + 1)));
+    const int neumann_ends = (neu_lo ? 1 : 0) + (neu_hi ? 1 : 0);
+    if (neumann_ends == 0) return {1.0, (double)L, 2.0 * (double)(L + 1)};
+    if (neumann_ends == 1) return {1.0, (double)(2 * L - 1), 4.0 * (double)L};
+    return {0.0, (double)(L - 1), 2.0 * (double)(L - 1)};   // L >= 2 (check_bc)
+}
+
+static double rung_eigenvalue(double a, double q)
+{
+    const double s = sin(a * M_PI / q);
     return 4.0 * s * s;
 }
 
-// smallest and largest eigenvalue of the 1D operator of an axis of length n:
-// D (eq. matrix_dirichlet), or N (eq. matrix_neuman) with one or two Neumann
-// ends; the one-sided eigenvalues are 4 sin^2((2k-1) pi / (4n)), k = 1..n, the
-// two-sided ones 4 sin^2(k pi / (2(n-1))), k = 0..n-1 (cosine eigenvectors)
-static void axis_eigs(int n, int neu_lo, int neu_hi, double &mn, double &mx)
-{
-    if (!neu_lo && !neu_hi) {
-        mn = dirichlet_eig(1, n);
-        mx = dirichlet_eig(n, n);
-    } else if (neu_lo != neu_hi) {
-        const double a = sin(1.0 * M_PI / (4.0 * (double)n));
-        const double b = sin((double)(2 * n - 1) * M_PI / (4.0 * (double)n));
-        mn = 4.0 * a * a;
-        mx = 4.0 * b * b;
-    } else {
-        const double b = sin((double)(n - 1) * M_PI / (2.0 * (double)(n - 1)));
-        mn = 0.0;
-        mx = 4.0 * b * b;
-    }
-}
+// One axis, seen by the operator the Chebyshev iteration runs on: the whole
+// axis, or (Block-Jacobi, eq. blockJacobiPreconditioner) the runs of `block`
+// points cut out by R_s, whose cut ends act as Dirichlet ends because the
+// coupling across them is dropped. A run keeps a Neumann face only if it
+// touches that face. A clipped last run lies inside the full-length run of the
+// same kind (interlacing), so full-length runs bound every block.
+struct AxisRange {
+    double mu_lo, mu_hi;
+};
 
-// interval containing every diagonal block's spectrum along one axis: the first
-// block keeps the low face's condition, the last the high face's, interior
-// blocks are Dirichlet, and a shorter block lies inside its full-length type
-static void axis_interval(int n, int block, int neu_lo, int neu_hi, double &mn, double &mx)
+static AxisRange axis_range(int n, int block, bool face_lo_neumann, bool face_hi_neumann)
 {
+    struct Run { int len; bool lo, hi; };
+    Run runs[3];
+    int nruns = 0;
     if (block <= 0 || n <= block) {
-        axis_eigs(n, neu_lo, neu_hi, mn, mx);
-        return;
+        runs[nruns++] = {n, face_lo_neumann, face_hi_neumann};
+    } else {
+        runs[nruns++] = {block, face_lo_neumann, false};        // touches the low face
+        runs[nruns++] = {block, false, face_hi_neumann};        // touches the high face
+        if (n > 2 * block) runs[nruns++] = {block, false, false};  // strictly inside
     }
-    double a, b;
-    axis_eigs(block, 0, 0, mn, mx);
-    axis_eigs(block, neu_lo, 0, a, b);
-    mn = std::min(mn, a);
-    mx = std::max(mx, b);
-    axis_eigs(block, 0, neu_hi, a, b);
-    mn = std::min(mn, a);
-    mx = std::max(mx, b);
-}
-
-// lambda_min, lambda_max of the Kronecker sum (eqs. lambdaMin, lambdaMax); with
-// block > 0 an interval containing every block x block x block diagonal block
-static void grid_interval(int nx, int ny, int nz, double h, unsigned bc, int block, double &lo,
-                          double &hi)
-{
-    const int n[3] = {nx, ny, nz};
-    double mn[3], mx[3];
-    for (int d = 0; d < 3; ++d)
-        axis_interval(n[d], block, (bc >> (2 * d)) & 1, (bc >> (2 * d + 1)) & 1, mn[d], mx[d]);
-    const double h2 = h * h;
-    lo = mn[0] / h2 + mn[1] / h2 + mn[2] / h2;
-    hi = mx[0] / h2 + mx[1] / h2 + mx[2] / h2;
+    AxisRange r{INFINITY, -INFINITY};
+    for (int k = 0; k < nruns; ++k) {
+        const Ladder l = ladder_of(runs[k].len, runs[k].lo, runs[k].hi);
+        r.mu_lo = std::min(r.mu_lo, rung_eigenvalue(l.bottom, l.q));
+        r.mu_hi = std::max(r.mu_hi, rung_eigenvalue(l.top, l.q));
+    }
+    return r;
 }
 
 int check_bc(int nx, int ny, int nz, unsigned bc)
@@ -146,10 +143,22 @@ bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLO
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
                    double &lo, double &hi)
 {
-    const int local = (pc == POISSON_PC_BLOCK_JACOBI && !o.bj_global) ? o.block : 0;
-    grid_interval(nx, ny, nz, h, bc, local, lo, hi);
-    lo = lo * o.lmin_scale;
-    hi = hi * o.lmax_scale;
+    // The grid operator is a Kronecker sum, so its extreme eigenvalues add over
+    // the axes (eqs. lambdaMin, lambdaMax), each axis' divided by h^2. BJ(CI)
+    // takes the blocks' interval, GNoComm(CI) the global one (Methodology), and
+    // the optional factors rescale the ends (Experimental Setup).
+    const bool blocks = pc == POISSON_PC_BLOCK_JACOBI && !o.bj_global;
+    const int len[3] = {nx, ny, nz};
+    const double h2 = h * h;
+    double sum_lo = 0.0, sum_hi = 0.0;
+    for (int axis = 0; axis < 3; ++axis) {
+        const unsigned faces = bc >> (2 * axis);
+        const AxisRange r = axis_range(len[axis], blocks ? o.block : 0, faces & 1u, faces & 2u);
+        sum_lo += r.mu_lo / h2;
+        sum_hi += r.mu_hi / h2;
+    }
+    lo = sum_lo * o.lmin_scale;
+    hi = sum_hi * o.lmax_scale;
     return lo > 0 && hi > lo && std::isfinite(hi);
 }
 
@@ -181,20 +190,20 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
         if (!cheb_interval(nx, ny, nz, h, bc, pc, o, lo, hi)) return POISSON_ERR_ARG;
         if (lo_out) *lo_out = lo;
         if (hi_out) *hi_out = hi;
-        // Alg. 2 scalars: theta, delta, sigma (eq. chebyshevQuantities) and the
-        // rho recurrence rho_0 = 1/sigma, rho_i = 1/(2 sigma - rho_{i-1})
+        // Alg. 2's scalars (eq. chebyshevQuantities) and its rho sequence,
+        // rho[0] = 1/sigma and rho[k] = 1/(2 sigma - rho[k-1]); step i >= 2 of
+        // an apply takes rho[i] and rho[i-1], the first step rho[1]
         const double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
-        double rho_old = 1.0 / sigma;
-        double rho_cur = 1.0 / (2.0 * sigma - rho_old);
+        double rho[MAXDEG + 1];
+        rho[0] = 1.0 / sigma;
+        for (int k = 1; k <= std::max(deg, 1); ++k) rho[k] = 1.0 / (2.0 * sigma - rho[k - 1]);
         p.theta = theta;
-        p.c1 = 2.0 * rho_cur / delta;
+        p.c1 = 2.0 * rho[1] / delta;
         p.two_sigma = 2.0 * sigma;
         p.two_over_delta = 2.0 / delta;
         for (int i = 2; i <= deg; ++i) {
-            rho_old = rho_cur;
-            rho_cur = 1.0 / (2.0 * sigma - rho_old);
-            p.rc[i] = rho_cur;
-            p.ro[i] = rho_old;
+            p.rc[i] = rho[i];
+            p.ro[i] = rho[i - 1];
         }
         p.thetaf = (float)p.theta;
         p.c1f = (float)p.c1;

@@ -1,11 +1,17 @@
 #!/usr/bin/env python3
 """Write the stored trajectories under tests/golden/ from the oracle alone.
 
-Each fixture is a seeded solve on a small grid with a ragged tile tail: the
-per-iteration scalars alpha, omega, rho and r.r of right-preconditioned
-Bi-CGSTAB (Alg. 1, scalar formulas of Alg. 3) as hex floats, and the final x
-as the sha256 of its bytes plus 16 sampled entries, so that the bits are exact. Run from the repository root:
-    python tests/golden/make_golden.py
+Each fixture is a seeded solve: the per-iteration scalars alpha, omega, rho and
+r.r of right-preconditioned Bi-CGSTAB (Alg. 1, scalar formulas of Alg. 3) as hex
+floats, and the final x as the sha256 of its bytes plus 16 sampled entries, so
+that the bits are exact. The full-size fixtures also store b.b and the squared
+true residual ||b - A x||^2 of the oracle's own x (exact dot products).
+
+    python tests/golden/make_golden.py           # small grids with ragged tile tails
+    python tests/golden/make_golden.py --full    # the 256^3 and 512^3 workloads
+
+Run from the repository root. The full-size set takes hours of CPU time (about
+14 GiB of memory at 512^3); a fixture already on disk is kept unless --force.
 """
 import hashlib
 import os
@@ -34,6 +40,48 @@ def solve(case):
     return oracle.bicgstab(f, 1.0 / (nx + 1), pc=pc, degree=m, mixed=mixed, tol=tol, bc=bc)
 
 
+# Full-size workloads: name -> (n, rhs, precond, degree, mixed, tol, maxit).
+# rhs is ("uniform", seed) for f ~ U[-1, 1) or ("noisy", seed) for the
+# manufactured right-hand side plus 1e-3 N(0, 1) noise; zero Dirichlet faces,
+# h = 1/(n+1), x0 = 0, Block-Jacobi blocks of 64^3.
+FULL = {
+    "full_256_none": (256, ("uniform", 2), oracle.PC_NONE, 0, False, 1e-8, 5000),
+    "full_256_jacobi": (256, ("uniform", 2), oracle.PC_JACOBI, 0, False, 1e-8, 5000),
+    "full_256_bj64x8": (256, ("uniform", 2), oracle.PC_BLOCK_JACOBI, 8, False, 1e-8, 5000),
+    "full_256_cheb4": (256, ("uniform", 2), oracle.PC_CHEBYSHEV, 4, False, 1e-8, 5000),
+    "full_256_cheb8": (256, ("uniform", 2), oracle.PC_CHEBYSHEV, 8, False, 1e-8, 5000),
+    "full_512_cheb8_fp64": (512, ("uniform", 4), oracle.PC_CHEBYSHEV, 8, False, 1e-8, 5000),
+    "full_512_cheb8_mixed": (512, ("uniform", 4), oracle.PC_CHEBYSHEV, 8, True, 1e-8, 5000),
+    "full_512_cheb8_fp64_tol1e-10": (512, ("uniform", 4), oracle.PC_CHEBYSHEV, 8, False, 1e-10,
+                                     5000),
+    "full_512_cheb8_mixed_tol1e-10": (512, ("uniform", 4), oracle.PC_CHEBYSHEV, 8, True, 1e-10,
+                                      5000),
+    "full_512_noisy_cheb8_tol1e-10": (512, ("noisy", 3), oracle.PC_CHEBYSHEV, 8, False, 1e-10,
+                                      5000),
+    "full_512_noisy_bj64x8_tol1e-10": (512, ("noisy", 3), oracle.PC_BLOCK_JACOBI, 8, False,
+                                       1e-10, 5000),
+}
+
+
+def full_rhs(case):
+    n, (kind, seed) = case[0], case[1]
+    shape = (n, n, n)
+    if kind == "uniform":
+        return workloads.uniform_grid(seed, shape)
+    return workloads.manufactured_noisy(shape, seed)
+
+
+def solve_full(case):
+    n, _, pc, m, mixed, tol, maxit = case
+    f = full_rhs(case)
+    h = workloads.spacing(n)
+    res = oracle.bicgstab(f, h, pc=pc, degree=m, mixed=mixed, tol=tol, maxit=maxit, block=64)
+    res.bb = oracle.dot(f, f)
+    r = f - oracle.apply_A(res.x, h)
+    res.rr_true = oracle.dot(r, r)
+    return res
+
+
 SAMPLES = 16
 
 
@@ -51,10 +99,17 @@ def write(name, res):
             fh.write(" ".join(float(v).hex() for v in res.trace[k]) + "\n")
         fh.write(f"x_sha256 {hashlib.sha256(xs.tobytes()).hexdigest()} n {xs.size}\n")
         fh.write(" ".join(float(xs[i]).hex() for i in sample_indices(xs.size)) + "\n")
+        if hasattr(res, "rr_true"):
+            fh.write(f"bb {float(res.bb).hex()} rr_true {float(res.rr_true).hex()}\n")
 
 
 def read(name):
     """(status, iterations, half, trace[its, 4], x sha256, n, {index: x value})"""
+    return read_full(name)[:7]
+
+
+def read_full(name):
+    """read() plus (b.b, ||b - A x||^2), both None where the fixture has no such line"""
     with open(os.path.join(HERE, name + ".txt")) as fh:
         lines = [ln for ln in fh.read().splitlines() if not ln.startswith("#")]
     head = lines[0].split()
@@ -63,7 +118,16 @@ def read(name):
     tail = lines[1 + its].split()
     sha, n = tail[1], int(tail[3])
     vals = [float.fromhex(t) for t in lines[2 + its].split()]
-    return status, its, half, trace.reshape(its, 4), sha, n, dict(zip(sample_indices(n), vals))
+    bb = rr_true = None
+    if len(lines) > 3 + its and lines[3 + its].startswith("bb "):
+        extra = lines[3 + its].split()
+        bb, rr_true = float.fromhex(extra[1]), float.fromhex(extra[3])
+    return (status, its, half, trace.reshape(its, 4), sha, n, dict(zip(sample_indices(n), vals)),
+            bb, rr_true)
+
+
+def have(name):
+    return os.path.exists(os.path.join(HERE, name + ".txt"))
 
 
 def x_sha256(x):
@@ -71,7 +135,19 @@ def x_sha256(x):
 
 
 if __name__ == "__main__":
-    for name, case in CASES.items():
-        r = solve(case)
-        write(name, r)
-        print(name, r.status, r.iterations)
+    import time
+    force = "--force" in sys.argv
+    if "--full" in sys.argv:
+        only = [a for a in sys.argv[1:] if not a.startswith("--")]
+        for name, case in FULL.items():
+            if (only and name not in only) or (have(name) and not force):
+                continue
+            t0 = time.time()
+            r = solve_full(case)
+            write(name, r)
+            print(name, r.status, r.iterations, f"{time.time() - t0:.0f} s", flush=True)
+    else:
+        for name, case in CASES.items():
+            r = solve(case)
+            write(name, r)
+            print(name, r.status, r.iterations)
