@@ -179,3 +179,39 @@ def test_fp32_operator_on_smooth_field(gpu, fuse, m):
         ref = c1 * (np.float32(2.0) * u.astype(np.float32) - au / np.float32(theta))
         inner = (slice(1, -1),) * 3
         assert np.array_equal(got[inner], ref.astype(np.float64)[inner])
+
+
+def test_dot_rounding_ties(gpu):
+    """The rounding-tie cases the oracle's dot is pinned on, fed to the GPU's
+    double-double reduction. A tie that the two words of the double-double hold
+    exactly rounds to even as the exact dot does. A tie broken only by a term more
+    than 106 bits below the sum (a sticky bit) is lost by the double-double, which
+    then rounds the tie to even: one unit in the last place below the exact result.
+    Solve data never comes that close to a tie (every trajectory test agrees bit for
+    bit), but this is where the GPU's dot and the exact one differ, besides products
+    that underflow below the subnormal range (there the product's error term is not
+    representable)."""
+    e53 = 2.0 ** -53
+    cases = [
+        # x, y, exact (= oracle), GPU
+        ([1.0, e53], [1.0, 1.0], 1.0, 1.0),
+        ([1.0, 3 * e53], [1.0, 1.0], 1.0 + 2.0 ** -51, 1.0 + 2.0 ** -51),
+        ([-1.0, -e53], [1.0, 1.0], -1.0, -1.0),
+        ([e53, 1.0], [1.0, 1.0], 1.0, 1.0),
+        ([1.0, e53, 2.0 ** -300], [1.0, 1.0, 1.0], 1.0 + 2.0 ** -52, 1.0),
+        ([1.0, e53, 2.0 ** -104], [1.0, 1.0, 1.0], 1.0 + 2.0 ** -52, 1.0 + 2.0 ** -52),
+        # each product is half the smallest subnormal: the exact sum is one subnormal
+        # step, while each rounded product and its FMA error term round to zero
+        ([5e-324, 5e-324], [0.5, 0.5], 5e-324, 0.0),
+        ([1e300, 1e300], [1e8, -1e8], 0.0, 0.0),
+    ]
+    for x, y, exact, want in cases:
+        n = 130  # several waves; the values sit in the first and last lanes
+        xs = np.zeros(n)
+        ys = np.zeros(n)
+        pos = [0, n - 1, 64][:len(x)]
+        xs[pos], ys[pos] = x, y
+        assert oracle.dot(xs, ys) == exact
+        with P.Solver((n, 1, 1), 0.1) as s:
+            got = s.dot(dev(xs), dev(ys))
+        assert got == want, (x, y, got.hex(), want.hex())
