@@ -564,8 +564,9 @@ void poisson_server_destroy(poisson_server *s)
         for (auto &kv : s->groups) {
             if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
             if (kv.second.graph_src) (void)hipGraphDestroy(kv.second.graph_src);
-            for (int *p : {kv.second.tiles.d_prob, kv.second.tiles.d_local, kv.second.tiles.d_count})
-                if (p) (void)hipFree(p);
+            for (TileList *t : {&kv.second.tiles, &kv.second.ptiles})
+                for (int *p : {t->d_prob, t->d_local, t->d_count})
+                    if (p) (void)hipFree(p);
         }
         for (TileList *t : {&s->init_list, &s->true_list})
             for (int *p : {t->d_prob, t->d_local, t->d_count})
