@@ -146,6 +146,28 @@ int poisson_set_stream(poisson_ctx *c, void *hip_stream);
 int poisson_solve(poisson_ctx *c, const double *rhs, double *x, int precond, int degree,
                   double tol, int maxit);
 
+/* Bytes of the static device scratch of poisson_solve_noalloc, per GPU. */
+#define POISSON_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* poisson_solve for callers that cannot allocate device or pinned host memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc). Same arguments, kernels and results as poisson_solve: the same x,
+   iterations and status bit for bit. The library keeps one static device array
+   of POISSON_NOALLOC_SCRATCH_BYTES per GPU for this call (held until the process
+   ends) and carves from it the problem descriptor, the scalar block, the
+   reduction partials and the workspace vectors; it calls no hipMalloc, hipFree,
+   hipHostMalloc or graph instantiation. Kernels are launched on the context
+   stream without graphs; the descriptor and scalars cross through pageable host
+   copies (synchronous). Limits: the plan's scratch must fit, e.g. up to 90^3
+   unknowns for an FP64 Chebyshev plan of degree >= 5 (88 bytes per unknown plus
+   the partials), otherwise ERR_NOMEM with nothing touched. No history is kept
+   (poisson_stats reports history_len = 0; poisson_trace returns 0 rows);
+   loop_ms is host wall time. Every call on one GPU shares that GPU's array and
+   leaves its contents behind: calls that overlap on the same GPU (from several
+   threads or contexts) race and must be serialised by the caller. */
+int poisson_solve_noalloc(poisson_ctx *c, const double *rhs, double *x, int precond, int degree,
+                          double tol, int maxit);
+
 typedef struct {
     size_t struct_size;         /* set by the caller to sizeof(poisson_stats_t) */
     int status;                 /* status of the last solve */

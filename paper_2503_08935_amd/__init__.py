@@ -7,7 +7,7 @@ package is its Python binding plus the seeded input generators.
 """
 from ._binding import (ERR_ARG, ERR_BREAKDOWN, ERR_DEVICE, ERR_INTERNAL, ERR_NOMEM,  # noqa: F401
                        ERR_NONFINITE, ERR_UNSUPPORTED, EXPORTS, FP64, KERNEL_CHEB_PAIR, KERNEL_CHEB_STEP,
-                       KERNEL_CHEB_TRIPLE,
+                       KERNEL_CHEB_TRIPLE, NOALLOC_SCRATCH_BYTES,
                        KERNEL_STENCIL_DOT, KERNEL_UPDATE_XR, MIXED, NOT_CONVERGED, OK, PC_BLOCK_JACOBI,
                        PC_CHEBYSHEV, PC_JACOBI, PC_NONE, PENDING, PoissonError, Server, Solver,
                        fill_uniform, footprint, lib, strerror)

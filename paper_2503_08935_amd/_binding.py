@@ -17,10 +17,12 @@ OPT_BJ_GLOBAL_INTERVAL, OPT_GRAPH_ITERS, OPT_USE_GRAPH, OPT_DEBUG_BREAKDOWN_AT =
 OPT_FUSE, OPT_TILE_ORDER, OPT_PAIR_LDS = 9, 10, 11
 KERNEL_CHEB_STEP, KERNEL_STENCIL_DOT, KERNEL_UPDATE_XR, KERNEL_CHEB_PAIR = 0, 1, 2, 3
 KERNEL_CHEB_TRIPLE = 4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every symbol declared in include/poisson.h
 EXPORTS = [
     "poisson_create", "poisson_set_option", "poisson_set_stream", "poisson_solve",
+    "poisson_solve_noalloc",
     "poisson_stats", "poisson_trace", "poisson_destroy", "poisson_strerror",
     "poisson_apply_operator", "poisson_apply_precond", "poisson_dot", "poisson_kernel_bench",
     "poisson_kernel_bytes", "poisson_fill_uniform", "poisson_cheb_interval",
@@ -76,6 +78,7 @@ def lib():
         L.poisson_set_option.argtypes = [vp, ip, ctypes.c_double]
         L.poisson_set_stream.argtypes = [vp, vp]
         L.poisson_solve.argtypes = [vp, vp, vp, ip, ip, ctypes.c_double, ip]
+        L.poisson_solve_noalloc.argtypes = [vp, vp, vp, ip, ip, ctypes.c_double, ip]
         L.poisson_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.poisson_trace.argtypes = [vp, dp, ip]
         L.poisson_cheb_interval.argtypes = [vp, ip, dp, dp]
@@ -194,6 +197,18 @@ class Solver:
                                  float(tol), int(maxit))
         if st in (ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_INTERNAL):
             raise PoissonError(st, "poisson_solve")
+        return st
+
+    def solve_noalloc(self, rhs, x, precond=PC_CHEBYSHEV, degree=8, tol=1e-8, maxit=5000):
+        """solve() through poisson_solve_noalloc: no device allocation, the
+        library's static scratch (NOALLOC_SCRATCH_BYTES per GPU) instead."""
+        import torch
+        self._bind_stream()
+        st = lib().poisson_solve_noalloc(self._ctx, _ptr(rhs, self.n, (torch.float64,)),
+                                         _ptr(x, self.n, (torch.float64,)), int(precond),
+                                         int(degree), float(tol), int(maxit))
+        if st in (ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_INTERNAL):
+            raise PoissonError(st, "poisson_solve_noalloc")
         return st
 
     def stats(self):

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -180,6 +181,29 @@ int read_scalars(poisson_ctx *c, int slot)
     return POISSON_OK;
 }
 
+// statistics of a finished solve, without the history
+void put_stats(poisson_ctx *c, const Scalars &sc, double rr_true, int pc, int deg, double loop_ms)
+{
+    const bool mixed = c->precision == POISSON_MIXED;
+    const double bb = sc.bb;
+    poisson_stats_t &st = c->st;
+    memset(&st, 0, sizeof(st));
+    st.struct_size = sizeof(st);
+    st.status = sc.status;
+    st.iterations = sc.iter;
+    st.half_step_exit = sc.half;
+    st.precond = pc;
+    st.degree = deg;
+    st.precision = c->precision;
+    st.relres_recursive = bb > 0 ? std::sqrt(sc.rr / bb) : 0.0;
+    st.relres_true = bb > 0 ? std::sqrt(rr_true / bb) : 0.0;
+    st.lambda_min = c->plan_lo;
+    st.lambda_max = c->plan_hi;
+    st.loop_ms = loop_ms;
+    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c)) * (double)c->N * sc.iter;
+    st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
+}
+
 int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, double tol,
                int maxit)
 {
@@ -268,27 +292,150 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
         c->hist_rel[0] = std::sqrt(rr0 / bb);
         for (int i = 1; i <= iters; ++i) c->hist_rel[i] = std::sqrt(c->trace[4 * (i - 1) + 3] / bb);
     }
+    put_stats(c, sc, rr_true, pc, deg, loop_ms);
     poisson_stats_t &st = c->st;
-    memset(&st, 0, sizeof(st));
-    st.struct_size = sizeof(st);
-    st.status = sc.status;
-    st.iterations = sc.iter;
-    st.half_step_exit = sc.half;
-    st.precond = pc;
-    st.degree = deg;
-    st.precision = c->precision;
-    st.relres_recursive = bb > 0 ? std::sqrt(sc.rr / bb) : 0.0;
-    st.relres_true = bb > 0 ? std::sqrt(rr_true / bb) : 0.0;
-    st.lambda_min = c->plan_lo;
-    st.lambda_max = c->plan_hi;
-    st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c)) * (double)c->N * sc.iter;
-    st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
     st.history_len = (int)c->hist_rel.size();
     st.history = c->hist_rel.data();
     st.solve_ms = now_ms() - t0;
     c->have_stats = true;
     return sc.status;
+}
+
+// ---- the allocation-free solve ----------------------------------------------
+// Its device state lives in one static array of POISSON_NOALLOC_SCRATCH_BYTES per
+// GPU: the problem descriptor, the scalar block, the tile partials and the
+// workspace vectors. On the host the array's name is not a device address; the
+// address is taken once per device with hipGetSymbolAddress and only that
+// address is handed to the kernels and copies. Every call on a GPU uses the same
+// array, so calls that overlap on one GPU race.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+} // namespace
+
+static __device__ __align__(256) unsigned char scratch[POISSON_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// the current device's address of `scratch`, taken at its first use there
+int scratch_base(char **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return POISSON_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return POISSON_ERR_DEVICE;
+        g_scratch[dev] = (char *)p;
+    }
+    *out = g_scratch[dev];
+    return POISSON_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// bytes of the scratch a solve of this plan takes: descriptor, scalars, the
+// partials of one problem and the workspace
+size_t noalloc_bytes(const poisson_ctx *c, int pc, int deg, bool mixed)
+{
+    return round256(sizeof(Prob)) + round256(sizeof(Scalars)) +
+           round256((size_t)c->ntiles * PARTIAL_STRIDE * sizeof(double)) +
+           workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse);
+}
+
+// the solve of solve_impl with every device buffer carved from the scratch,
+// launched without graphs, with pageable host copies of the descriptor and the
+// scalar block and no history: no device or pinned memory is allocated
+int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, double tol,
+                       int maxit)
+{
+    const double t0 = now_ms();
+    const bool mixed = c->precision == POISSON_MIXED;
+    int rc;
+    if ((rc = validate_ptr(rhs)) != POISSON_OK) return rc;
+    if ((rc = validate_ptr(x)) != POISSON_OK) return rc;
+    if (noalloc_bytes(c, pc, deg, mixed) > POISSON_NOALLOC_SCRATCH_BYTES) return POISSON_ERR_NOMEM;
+    char *base = nullptr;
+    if ((rc = scratch_base(&base)) != POISSON_OK) return rc;
+    Prob *d_prob = (Prob *)base;
+    Scalars *d_sc = (Scalars *)(base + round256(sizeof(Prob)));
+    double *d_part = (double *)((char *)d_sc + round256(sizeof(Scalars)));
+    char *ws = (char *)d_part + round256((size_t)c->ntiles * PARTIAL_STRIDE * sizeof(double));
+
+    Prob p;
+    memset(&p, 0, sizeof(p));
+    if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
+    carve_workspace(p, ws, c->N, pc, deg, mixed, c->opt.fuse);
+    p.vec[V_X] = x;
+    p.vec[V_B] = (void *)rhs;
+    p.sc = d_sc;
+    p.partials = d_part;
+    p.hist = nullptr;
+    p.hist_iters = 0;
+    HIPCHK(hipMemcpyAsync(d_prob, &p, sizeof(Prob), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+
+    Scalars sc;
+    auto read_sc = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(&sc, d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return POISSON_OK;
+    };
+    const Work w = single_work(c, d_prob);
+    // the initial residual's finalize rewrites every flag and scalar the loop
+    // reads, so nothing left in the scratch by an earlier call is used
+    launch_stencil(S_INIT, false, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
+    HIPCHK(hipGetLastError());
+    if ((rc = read_sc()) != POISSON_OK) return rc;
+    double loop_ms = 0;
+    if (!sc.done) {
+        const double l0 = now_ms();
+        const int K = c->graph_iters;
+        const long max_rounds = (long)maxit / K + 2;
+        for (long round = 0; round < max_rounds; ++round) {
+            for (int i = 0; i < K; ++i)
+                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse);
+            HIPCHK(hipGetLastError());
+            if ((rc = read_sc()) != POISSON_OK) return rc;
+            if (sc.done) break;
+        }
+        loop_ms = now_ms() - l0;
+    }
+    if (!sc.done) return POISSON_ERR_INTERNAL;
+    const Scalars fin = sc;
+    if (fin.zero_x) HIPCHK(hipMemsetAsync(x, 0, c->N * sizeof(double), c->stream));
+    launch_stencil(S_TRUE, false, false, w, c->ntiles, c->stream, KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
+    HIPCHK(hipGetLastError());
+    if ((rc = read_sc()) != POISSON_OK) return rc;
+    put_stats(c, fin, sc.rr_true, pc, deg, loop_ms);
+    c->trace.clear();
+    c->hist_rel.clear();
+    c->st.history_len = 0;
+    c->st.history = nullptr;
+    c->st.solve_ms = now_ms() - t0;
+    c->have_stats = true;
+    return fin.status;
+}
+
+// argument checks shared by the solve entry points; a degenerate Chebyshev
+// interval is rejected before the device is touched
+int check_solve_args(const poisson_ctx *c, const double *rhs, const double *x, int precond,
+                     int degree, double tol, int maxit)
+{
+    if (!c || !rhs || !x) return POISSON_ERR_ARG;
+    if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
+    if (is_cheb(precond) && (degree < 0 || degree > MAXDEG)) return POISSON_ERR_ARG;
+    if (!(tol > 0) || !(tol < 1)) return POISSON_ERR_ARG;
+    if (maxit < 1 || maxit > 10000000) return POISSON_ERR_ARG;
+    if (is_cheb(precond)) {
+        double lo, hi;
+        if (!cheb_interval(c->nx, c->ny, c->nz, c->h, c->bc, precond, c->opt, lo, hi))
+            return POISSON_ERR_ARG;
+    }
+    return POISSON_OK;
 }
 
 } // namespace
@@ -380,23 +527,26 @@ int poisson_set_stream(poisson_ctx *c, void *s)
 int poisson_solve(poisson_ctx *c, const double *rhs, double *x, int precond, int degree,
                   double tol, int maxit)
 {
-    if (!c || !rhs || !x) return POISSON_ERR_ARG;
-    if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
-    if ((precond == POISSON_PC_CHEBYSHEV || precond == POISSON_PC_BLOCK_JACOBI) &&
-        (degree < 0 || degree > MAXDEG))
-        return POISSON_ERR_ARG;
-    if (precond != POISSON_PC_CHEBYSHEV && precond != POISSON_PC_BLOCK_JACOBI) degree = 0;
-    if (!(tol > 0) || !(tol < 1)) return POISSON_ERR_ARG;
-    if (maxit < 1 || maxit > 10000000) return POISSON_ERR_ARG;
-    if (is_cheb(precond)) {
-        // reject a degenerate interval before touching the device
-        double lo, hi;
-        if (!cheb_interval(c->nx, c->ny, c->nz, c->h, c->bc, precond, c->opt, lo, hi))
-            return POISSON_ERR_ARG;
-    }
+    int rc;
+    if ((rc = check_solve_args(c, rhs, x, precond, degree, tol, maxit)) != POISSON_OK) return rc;
+    if (!is_cheb(precond)) degree = 0;
     try {
         c->have_stats = false;
         return solve_impl(c, rhs, x, precond, degree, tol, maxit);
+    } catch (...) {
+        return POISSON_ERR_INTERNAL;
+    }
+}
+
+int poisson_solve_noalloc(poisson_ctx *c, const double *rhs, double *x, int precond, int degree,
+                          double tol, int maxit)
+{
+    int rc;
+    if ((rc = check_solve_args(c, rhs, x, precond, degree, tol, maxit)) != POISSON_OK) return rc;
+    if (!is_cheb(precond)) degree = 0;
+    try {
+        c->have_stats = false;
+        return solve_noalloc_impl(c, rhs, x, precond, degree, tol, maxit);
     } catch (...) {
         return POISSON_ERR_INTERNAL;
     }
