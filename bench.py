@@ -11,15 +11,24 @@ in HBM before the timed region. Printed as one JSON line:
                (HIP events); outside_loop_ms_per_solve is the rest of a solve
                (initial residual, interval and coefficients, true residual, host)
   hbm_gbps     algorithmic bytes of the iteration loop / loop device time
-  tts_*        time to 1e-8 of the FP64 solve and of the mixed solve (FP32
-               Chebyshev inside FP64 Bi-CGSTAB), same right-hand side
+  tts_*        time to 1e-8 of the FP64 solve (median over the timed solves) and of
+               the mixed solve (FP32 Chebyshev inside FP64 Bi-CGSTAB; median of 5),
+               same right-hand side; fp64_x_is_oracle_x compares the FP64 x with the
+               sha256 of the oracle's x stored under tests/golden/
+  tol_1e-10, noisy_manufactured_tol_1e-10
+               the other 512^3 configurations: FP64 and mixed to 1e-10, and the noisy
+               manufactured problem with Block-Jacobi(CI) 64^3 vs Chebyshev-8 to 1e-10
+               (median of 3 each)
   roofline     dominant kernel (three fused interior Chebyshev steps, FP64),
                timed with HIP events on the stream it runs on
   cpu_baseline the CPU oracle on a bounded sample (2 iterations vs 1 iteration
-               of the same 512^3 solve; the difference is one iteration)
+               of the same 512^3 solve, median of 3; the difference is one
+               iteration), all threads, plus one thread at 128^3, the host's CPU
+               model, sockets, cores and memory, and the oracle's GB/s
   p99_solve_ms the serving stream: 2000 requests of n^3 grids, n uniform over
                {32,48,64,96,128,192,256}, Poisson arrivals at 200/s, mixed
-               Chebyshev-4 to 1e-8, admitted by HBM footprint (serving.py)
+               Chebyshev-4 to 1e-8, admitted by HBM footprint (serving.py);
+               serving_below_saturation: 400 requests at 10/s
 """
 import argparse
 import hashlib
@@ -50,6 +59,10 @@ def parse():
     ap.add_argument("--no-unfused", action="store_true",
                     help="skip the comparison solve with one Chebyshev step per pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra 512^3 configurations (tol 1e-10 FP64 and mixed, Block-"
+                         "Jacobi vs Chebyshev on the noisy manufactured problem) and the "
+                         "below-saturation serving point")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-iters", type=int, default=4,
@@ -88,27 +101,156 @@ def traffic_record(kernel_file, workload):
     return None
 
 
-def cpu_baseline(n, h, degree, seed):
-    import numpy as np
+def host_record():
+    """CPU model, sockets, cores and memory of the host the oracle runs on (from /proc)."""
+    rec = {"model": None, "sockets": None, "cores": None, "logical_cpus": os.cpu_count(),
+           "usable_cpus": len(os.sched_getaffinity(0)), "ram_gib": None}
+    try:
+        phys, cores = set(), {}
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and rec["model"] is None:
+                rec["model"] = v
+            elif k == "physical id":
+                cur["pid"] = v
+                phys.add(v)
+            elif k == "cpu cores":
+                cores[cur.get("pid")] = int(v)
+        rec["sockets"] = len(phys) or None
+        rec["cores"] = sum(cores.values()) or None
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                rec["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:
+        pass
+    return rec
 
+
+def oracle_iteration_s(n, h, degree, seed, reps):
+    """Seconds of one oracle iteration of the n^3 FP64 Chebyshev solve: the median over
+    reps of time(maxit=2) - time(maxit=1), which cancels the setup."""
     import oracle
     from paper_2503_08935_amd import workloads
+    b = workloads.uniform_grid(seed, (n, n, n))
+    diffs, raw = [], []
+    for _ in range(reps):
+        ts = []
+        for it in (1, 2):
+            t0 = time.perf_counter()
+            oracle.bicgstab(b, h, pc=oracle.PC_CHEBYSHEV, degree=degree, tol=1e-8, maxit=it)
+            ts.append(time.perf_counter() - t0)
+        diffs.append(max(ts[1] - ts[0], 1e-9))
+        raw.append([round(t, 3) for t in ts])
+    diffs.sort()
+    return diffs[len(diffs) // 2], raw
+
+
+def cpu_baseline(n, h, degree, seed):
+    """The CPU oracle (oracle.c: -O3 -ffp-contract=off, OpenMP over z-planes, exact dots)
+    on a bounded sample of the benchmark solve: one iteration at n^3 with every thread
+    of this host (median of 3), and one iteration at 128^3 on one thread (median of 3),
+    with the oracle's GB/s under the byte model of one Chebyshev step per pass (the
+    oracle's own pass structure)."""
+    import oracle
+    from paper_2503_08935_amd import workloads
+    threads = oracle.get_threads()
+    per_it, raw = oracle_iteration_s(n, h, degree, seed, 3)
+    log(f"cpu oracle {n}^3, {threads} threads: {per_it:.2f} s per iteration {raw}")
+    model_b = 632.0 if degree == 8 else None
+    oracle.set_threads(1)
+    n1 = 128
+    try:
+        per_it1, raw1 = oracle_iteration_s(n1, workloads.spacing(n1), degree, seed, 3)
+    finally:
+        oracle.set_threads(threads)
+    log(f"cpu oracle {n1}^3, 1 thread: {per_it1:.3f} s per iteration {raw1}")
+    rec = {"value": 1.0 / per_it, "unit": "iter/s", "cores": threads, "kind": "oracle",
+           "sample": f"one Bi-CGSTAB iteration of the {n}^3 FP64 Chebyshev-{degree} solve "
+                     f"(seed {seed}): median over 3 of time(maxit=2) - time(maxit=1), setup "
+                     f"excluded, {threads} OpenMP threads",
+           "seconds_per_iteration": round(per_it, 4), "seconds_maxit_1_2": raw,
+           "one_thread": {"grid": n1, "seconds_per_iteration": round(per_it1, 4),
+                          "seconds_maxit_1_2": raw1,
+                          "unknown_iterations_per_s": round(n1 ** 3 / per_it1, 1)},
+           "unknown_iterations_per_s": round(n ** 3 / per_it, 1),
+           "host": host_record()}
+    if model_b:
+        rec["model_bytes_per_unknown"] = model_b
+        rec["oracle_gbps"] = round(model_b * n ** 3 / per_it / 1e9, 2)
+        rec["oracle_gbps_one_thread"] = round(model_b * n1 ** 3 / per_it1 / 1e9, 3)
+    return rec
+
+
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+
+
+def golden_x_sha256(name):
+    """sha256 of the oracle's x stored by tests/golden/make_golden.py (None if absent)."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("x_sha256 "):
+            return line.split()[1]
+    return None
+
+
+def sha256_of(t):
+    return hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest()
+
+
+def extra_configs(P, workloads, b, stream, degree):
+    """The other 512^3 configurations: f ~ U[-1,1) seed 4 to 1e-10 in FP64 and mixed
+    (median of 3 time-to-tolerance each), and the noisy manufactured problem (seed 3)
+    with Block-Jacobi(CI) on 64^3 blocks vs Chebyshev, both degree 8, to 1e-10."""
+    import torch
+    n = 512
     shape = (n, n, n)
-    b = workloads.uniform_grid(seed, shape)
-    ts = []
-    for it in (1, 2):
-        t0 = time.perf_counter()
-        r = oracle.bicgstab(b, h, pc=oracle.PC_CHEBYSHEV, degree=degree, tol=1e-8, maxit=it)
-        ts.append(time.perf_counter() - t0)
-        log(f"cpu oracle maxit={it}: {ts[-1]:.2f} s (iterations {r.iterations})")
-        del r
-    del b
-    per_it = max(ts[1] - ts[0], 1e-9)
-    return {"value": 1.0 / per_it, "unit": "iter/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
-            "sample": f"one Bi-CGSTAB iteration of the {n}^3 FP64 Chebyshev-{degree} solve "
-                      f"(seed {seed}): time(maxit=2) - time(maxit=1), setup excluded",
-            "seconds_maxit1": ts[0], "seconds_maxit2": ts[1]}
+    h = workloads.spacing(n)
+
+    def timed(rhs, pc, tol, precision, reps=3):
+        x = torch.zeros_like(rhs)
+        with P.Solver(shape, h, stream=stream, precision=precision) as s:
+            tts = []
+            for _ in range(reps):
+                with torch.cuda.stream(stream):
+                    x.zero_()
+                st = s.solve(rhs, x, pc, degree, tol, 5000)
+                d = s.stats()
+                tts.append(d["solve_ms"] / 1e3)
+        torch.cuda.synchronize()
+        return x, {"status": st, "iterations": d["iterations"], "tts_s": round(median(tts), 4),
+                   "runs": reps, "relres_true": d["relres_true"],
+                   "hbm_gbps": round(d["model_gbps"], 1)}
+
+    out = {}
+    x64, r64 = timed(b, P.PC_CHEBYSHEV, 1e-10, P.FP64)
+    xm, rm = timed(b, P.PC_CHEBYSHEV, 1e-10, P.MIXED)
+    rel = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
+    out["tol_1e-10"] = {"fp64": r64, "mixed": rm,
+                        "mixed_speedup": round(r64["tts_s"] / rm["tts_s"], 3),
+                        "mixed_vs_fp64_rel_diff": rel}
+    ref = golden_x_sha256(f"full_512_cheb{degree}_fp64_tol1e-10")
+    if ref is not None:
+        out["tol_1e-10"]["fp64_x_is_oracle_x"] = sha256_of(x64) == ref
+    log(f"1e-10: FP64 {r64['iterations']} it {r64['tts_s']} s, mixed {rm['iterations']} it "
+        f"{rm['tts_s']} s, rel diff {rel:.2e}")
+    del x64, xm
+    f = torch.from_numpy(workloads.manufactured_noisy(shape, 3).ravel()).to(b.device)
+    noisy = {}
+    for name, pc in (("block_jacobi_64", P.PC_BLOCK_JACOBI), ("chebyshev", P.PC_CHEBYSHEV)):
+        x, r = timed(f, pc, 1e-10, P.FP64)
+        noisy[name] = r
+        log(f"noisy 1e-10 {name}: {r['iterations']} it {r['tts_s']} s")
+        del x
+    del f
+    torch.cuda.empty_cache()
+    out["noisy_manufactured_tol_1e-10"] = noisy
+    return out
 
 
 def table2():
@@ -354,15 +496,19 @@ def main():
            "outside_loop_ms_per_solve": round((wall * 1e3 - loop_ms) / a.steps, 2),
            "hbm_gbps": round(model_bytes / (loop_ms * 1e6), 1),
            "hbm_frac": round(model_bytes / (loop_ms * 1e6) / PEAK_HBM_GBPS, 4),
-           "tts_fp64_s": round(last["solve_ms"] / 1e3, 4),
+           "tts_fp64_s": round(median([st["solve_ms"] for st in stats]) / 1e3, 4),
+           "tts_fp64_runs": len(stats),
            "relres_true_fp64": last["relres_true"]}
     out.update(others)
 
+    fp64_oracle = golden_x_sha256(f"full_{n}_cheb{a.degree}_fp64") if a.seed == 4 else None
+    if fp64_oracle is not None and a.tol == 1e-8:
+        out["fp64_x_is_oracle_x"] = sha256_of(x64) == fp64_oracle
     if not a.no_mixed:
         sm = P.Solver(shape, h, stream=stream, precision=P.MIXED)
         xm = torch.zeros_like(x)
         tts = []
-        for rep in range(2):
+        for rep in range(5):
             with torch.cuda.stream(stream):
                 xm.zero_()
                 st = sm.solve(b, xm, P.PC_CHEBYSHEV, a.degree, a.tol, 5000)
@@ -372,14 +518,17 @@ def main():
             tts.append(ms["solve_ms"] / 1e3)
         torch.cuda.synchronize()
         rel = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
-        out.update({"tts_mixed_s": round(min(tts), 4), "iterations_mixed": ms["iterations"],
-                    "mixed_speedup": round(out["tts_fp64_s"] / min(tts), 3),
+        out.update({"tts_mixed_s": round(median(tts), 4), "tts_mixed_runs": len(tts),
+                    "iterations_mixed": ms["iterations"],
+                    "mixed_speedup": round(out["tts_fp64_s"] / median(tts), 3),
                     "relres_true_mixed": ms["relres_true"],
                     "mixed_vs_fp64_rel_diff": rel,
                     "hbm_gbps_mixed": round(ms["model_gbps"], 1)})
-        log(f"mixed: {ms['iterations']} iterations, {min(tts):.3f} s, rel diff vs FP64 {rel:.2e}")
+        log(f"mixed: {ms['iterations']} iterations, {median(tts):.3f} s, rel diff vs FP64 {rel:.2e}")
         sm.close()
         del xm
+    if not a.no_extra and n == 512:
+        out.update(extra_configs(P, workloads, b, stream, a.degree))
     out["roofline"] = roofline
     del b, x, x64
     torch.cuda.empty_cache()
@@ -394,6 +543,14 @@ def main():
         out["serving"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
                           for k, v in sv.items()}
         torch.cuda.empty_cache()
+        if not a.no_extra:
+            log("serving below saturation: 400 requests at 10/s ...")
+            sv = serving.run_stream(n_requests=400, rate=10.0, iters=a.serve_iters, progress=log)
+            log(f"serving at 10/s: p50 {sv['p50_ms']:.0f} ms, p99 {sv['p99_ms']:.0f} ms, "
+                f"utilization {sv['utilization']:.2f}")
+            out["serving_below_saturation"] = {
+                k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in sv.items()}
+            torch.cuda.empty_cache()
     if not a.no_cpu:
         log("cpu oracle baseline (bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(n, h, a.degree, a.seed)

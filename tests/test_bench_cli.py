@@ -49,3 +49,14 @@ def test_traffic_record_format_and_source_binding(tmp_path, monkeypatch):
     (csrc / "device.hip").write_text("// not the kernels\n")
     monkeypatch.setattr(b, "ROOT", str(tmp_path))
     assert b.traffic_record("device.hip", "cheb_pair_fp64_512^3") is None
+
+
+def test_cpu_baseline_record_on_a_small_grid():
+    b = load_bench()
+    assert b.median([3, 1, 2]) == 2 and b.median([4, 1, 2, 3]) == 2.5
+    host = b.host_record()
+    assert host["logical_cpus"] >= 1 and host["usable_cpus"] >= 1
+    rec = b.cpu_baseline(48, 1.0 / 49, 8, 4)
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] >= 1
+    assert rec["one_thread"]["seconds_per_iteration"] > 0
+    assert rec["oracle_gbps"] > 0 and len(rec["seconds_maxit_1_2"]) == 3
