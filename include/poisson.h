@@ -99,9 +99,18 @@ enum {
                                            pairs), 1 x-grouped everywhere (the x-tiles of a
                                            tile row on one XCD), 2 slabs (each XCD one
                                            contiguous eighth of the tiles); same results */
-    POISSON_OPT_PAIR_LDS = 11           /* fused Chebyshev pairs of single solves: 1 (default)
+    POISSON_OPT_PAIR_LDS = 11,          /* fused Chebyshev pairs of single solves: 1 (default)
                                            stage 128 x 16 (FP64) or 256 x 16 (FP32) tiles in
                                            LDS, 0 use the 64 x 16 register tiles; same
+                                           arithmetic, same results */
+    POISSON_OPT_FUSE_UPDATES = 12       /* Chebyshev / Block-Jacobi plans whose first pass of an
+                                           apply is LDS-staged (degree >= 3, FUSE >= 1,
+                                           PAIR_LDS = 1): 1 (default) forms s = r - alpha w
+                                           with s.s (Alg. 1 half step) inside the first pass
+                                           of the second apply, and p = r + beta (p - omega w)
+                                           inside the first pass of the next iteration's
+                                           first apply, instead of in passes of their own;
+                                           0 keeps the separate update passes; same
                                            arithmetic, same results */
 };
 

@@ -14,7 +14,7 @@ PC_NONE, PC_JACOBI, PC_CHEBYSHEV, PC_BLOCK_JACOBI = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 OPT_PRECISION, OPT_BLOCK, OPT_LMIN_SCALE, OPT_LMAX_SCALE = 1, 2, 3, 4
 OPT_BJ_GLOBAL_INTERVAL, OPT_GRAPH_ITERS, OPT_USE_GRAPH, OPT_DEBUG_BREAKDOWN_AT = 5, 6, 7, 8
-OPT_FUSE, OPT_TILE_ORDER, OPT_PAIR_LDS = 9, 10, 11
+OPT_FUSE, OPT_TILE_ORDER, OPT_PAIR_LDS, OPT_FUSE_UPDATES = 9, 10, 11, 12
 KERNEL_CHEB_STEP, KERNEL_STENCIL_DOT, KERNEL_UPDATE_XR, KERNEL_CHEB_PAIR = 0, 1, 2, 3
 KERNEL_CHEB_TRIPLE = 4
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -177,7 +177,7 @@ class Solver:
                  lmax_scale=OPT_LMAX_SCALE, bj_global_interval=OPT_BJ_GLOBAL_INTERVAL,
                  graph_iters=OPT_GRAPH_ITERS, use_graph=OPT_USE_GRAPH,
                  debug_breakdown_at=OPT_DEBUG_BREAKDOWN_AT, fuse=OPT_FUSE,
-                 tile_order=OPT_TILE_ORDER, pair_lds=OPT_PAIR_LDS)
+                 tile_order=OPT_TILE_ORDER, pair_lds=OPT_PAIR_LDS, fuse_updates=OPT_FUSE_UPDATES)
 
     def set_option(self, key, value):
         k = self._OPTS[key] if isinstance(key, str) else key

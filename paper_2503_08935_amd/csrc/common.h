@@ -30,9 +30,21 @@ constexpr int pair_nxw(bool fp32) { return fp32 ? 4 : 2; }
 constexpr int triple_nxw(bool fp32) { return fp32 ? 2 : 2; }
 constexpr int triple_pr(bool fp32) { return fp32 ? 8 : 4; }
 
-// vector slots of a problem
+// vector slots of a problem. V_S and V_P2 exist only when the vector updates are
+// folded into the first pass of the preconditioner applies (upd_fusion): s is
+// then written to a vector of its own (neighbouring tiles still read r), and p
+// alternates between V_P and V_P2 from one iteration to the next. V_PCUR is not
+// a slot: a kernel handed it reads p of the current iteration, (iter & 1) ?
+// V_P2 : V_P.
 enum Vec {
-    V_X = 0, V_B, V_R, V_RT, V_P, V_W, V_T, V_PH, V_SH, V_RA, V_RB, V_V32, V_RC, V_RD, V_COUNT
+    V_X = 0, V_B, V_R, V_RT, V_P, V_W, V_T, V_PH, V_SH, V_RA, V_RB, V_V32, V_RC, V_RD, V_S, V_P2,
+    V_COUNT, V_PCUR = 31
+};
+
+// which vector updates a plan folds into the first pass of an apply
+enum Upd {
+    U_S = 1,       // s = r - alpha w and s.s in the first pass of the second apply
+    U_P = 2        // p = r + beta (p - omega w) in the first pass of the first apply
 };
 
 // status codes mirrored from poisson.h
@@ -68,6 +80,9 @@ struct Prob {
     double rc[MAXDEG + 1], ro[MAXDEG + 1];   // rho_cur, rho_old of Chebyshev step i
     float rcf[MAXDEG + 1], rof[MAXDEG + 1];
     void *vec[V_COUNT];
+    int s_slot;                  // where the second half of an iteration reads s: V_R, or
+                                 // V_S when the first pass of the second apply forms it
+    int pad_s;
     Scalars *sc;
     double *partials;            // ntiles * PARTIAL_STRIDE
     double *hist;                // 1 + 4*hist_iters, or null
@@ -122,6 +137,11 @@ struct KArgs {
     int x2;                      // E_DOT second operand slot / E_UPD s^ slot
     int drop1;                   // fused pair: 1 = w_i is not stored (the last pair of an
                                  // apply, whose w_i no later step reads)
+    int upd;                     // first pass of an apply: 0 reads v = in; U_S forms
+                                 // v = s = r - alpha w (stored to V_S, s.s reduced); U_P
+                                 // forms v = p = r + beta (p - omega w) (stored to the p
+                                 // of this iteration)
+    int nparts;                  // partial slots the reduction's finalize sums (0: ntiles)
 };
 
 // host-side launchers (device.hip)
@@ -132,9 +152,12 @@ void launch_elem(int op, bool mixed, const Work &w, int grid, hipStream_t s, con
 // z = z_{i-2}, v; out = w_i, x2 = w_{i+1}; step = i
 void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
 // Chebyshev steps 1 and 2 in one pass: in = v (FP64), out = y_1, x2 = w_2, step = 1;
-// in mixed mode the FP32 copy of v is written to V_V32 as well
+// in mixed mode the FP32 copy of v is written to V_V32 as well. a.upd folds a
+// vector update into the pass (LDS-staged single problems only)
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                             const KArgs &a);
+// the half-step test on the s.s partials of a first pass with a.upd = U_S
+void launch_finalize_ss(const Work &w, hipStream_t s, const KArgs &a);
 // three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored

@@ -53,6 +53,15 @@ template <typename T> __device__ __forceinline__ T ld_g(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// the vector of slot v of a problem; V_PCUR names p of the current iteration,
+// which alternates between V_P and V_P2 when the p update is folded into the
+// first pass of the first apply
+__device__ __forceinline__ void *vec_at(const Prob &P, int v)
+{
+    if (v == V_PCUR) return P.vec[(P.sc->iter & 1) ? V_P2 : V_P];
+    return P.vec[v];
+}
+
 // ------------------------------------------------------------------------
 // Tile order of a single problem. Workgroup g runs on XCD g % 8 (round-robin
 // dispatch). Natural order puts neighbouring x-tiles on different XCDs, so the
@@ -126,8 +135,9 @@ __device__ __forceinline__ void dd_add(double ah, double al, double bh, double b
     fast_two_sum(vh, w, zh, zl);
 }
 
-// Reduce ND double-double values over the workgroup; result valid in thread 0.
-template <int ND>
+// Reduce ND double-double values over a workgroup of NW waves; result valid in
+// thread 0. lds holds 2 * ND * NW doubles.
+template <int ND, int NW = TY>
 __device__ __forceinline__ void block_reduce_dd(double (&hi)[ND], double (&lo)[ND], double *lds)
 {
     const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
@@ -159,7 +169,7 @@ __device__ __forceinline__ void block_reduce_dd(double (&hi)[ND], double (&lo)[N
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             double h = lds[d * 2], l = lds[d * 2 + 1];
-            for (int w = 1; w < TY; ++w)
+            for (int w = 1; w < NW; ++w)
                 dd_add(h, l, lds[(w * ND + d) * 2], lds[(w * ND + d) * 2 + 1], h, l);
             hi[d] = h;
             lo[d] = l;
@@ -190,9 +200,8 @@ __device__ void tile_publish(const Prob &P, int local, double (&hi)[ND], double 
 
 // Sum a problem's tile partials in tile order (res valid in thread 0).
 template <int ND>
-__device__ void sum_partials(const Prob &P, double *lds, double (&res)[ND])
+__device__ void sum_partials(const Prob &P, int nt, double *lds, double (&res)[ND])
 {
-    const int nt = P.ntiles;
     const int chunk = (nt + NTHREADS - 1) / NTHREADS;
     const int b0 = threadIdx.x * chunk, b1 = min(b0 + chunk, nt);
     double h2[ND], l2[ND];
@@ -508,12 +517,12 @@ __device__ __forceinline__ void stencil_tile(const Prob &P, const KArgs &A, int 
         cE = Coef<TC>::theta(P);
     }
     TC *out = (TC *)P.vec[A.out];
-    const TC *vv = (const TC *)P.vec[A.v];
+    const TC *vv = (const TC *)vec_at(P, A.v);
     const TC *zz = (const TC *)P.vec[A.z];
     float *v32 = (float *)P.vec[V_V32];
     const double *__restrict__ rt = (const double *)P.vec[V_RT];
     const double *__restrict__ bv = (const double *)P.vec[V_B];
-    const double *sv = (const double *)P.vec[V_R];
+    const double *sv = (const double *)P.vec[P.s_slot];
     double *rr = (double *)P.vec[V_R];
     double *rtw = (double *)P.vec[V_RT];
     double *pw = (double *)P.vec[V_P];
@@ -789,7 +798,7 @@ __device__ __forceinline__ void cheb_f32x2_tile(const Prob &P, const KArgs &A, i
 
     const TU *__restrict__ u = (const TU *)P.vec[A.in];
     float *out = (float *)P.vec[A.out];
-    const float *vv = (const float *)P.vec[A.v];
+    const float *vv = (const float *)vec_at(P, A.v);
     const float *zz = (const float *)P.vec[A.z];
     float *v32 = (float *)P.vec[V_V32];
     const float ih2 = P.ih2f;
@@ -957,7 +966,7 @@ __device__ __forceinline__ void cheb_pair_tile(const Prob &P, const KArgs &A, in
     const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
     const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
     const char *Yb = (const char *)P.vec[A.in];
-    const char *Vb = (const char *)P.vec[A.v];
+    const char *Vb = (const char *)vec_at(P, A.v);
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
@@ -1279,11 +1288,19 @@ template <int NXW, int PR> struct LPair {
 // neighbour outside the grid is the +0.0 that the zeroed loads already hold and
 // no neighbour select is needed. Otherwise each neighbour goes through the same
 // selection (neighbour, zero or mirror) as in k_stencil.
+// UPD (first pass only): 0 reads v = in; U_S forms v = s = r - alpha w at every
+// point it reads, stores s at the tile's points and adds their s.s to (ssh,
+// ssl); U_P forms v = p = r + beta (p_prev - omega w) and stores it as this
+// iteration's p (in the first iteration v is p itself).
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
-          bool SIMPLE>
+          bool SIMPLE, int UPD>
 __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A, int tile,
-                                                   int lane, int xw, T *lds)
+                                                   int lane, int xw, T *lds, double &ssh,
+                                                   double &ssl)
 {
+    static_assert(UPD == 0 || FIRST, "a vector update folds only into a first pass");
+    constexpr int NU = UPD == U_P ? 2 : (UPD == U_S ? 1 : 0);   // extra operands of v
+    constexpr int NUA = NU > 0 ? NU : 1;
     using L = LPair<NXW, PR>;
     constexpr int E = PR + 1;           // rows held: PR own rows and the halo row outside them
     constexpr int EOWN = TOP ? 1 : 0;   // first own row among the held rows
@@ -1303,7 +1320,34 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
     const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU);
     const char *Yb = (const char *)P.vec[A.in];
-    const char *Vb = (const char *)P.vec[A.v];
+    // the folded update's operands: Ub[0] = w, Ub[1] = the previous p
+    const char *Ub[2] = {nullptr, nullptr};
+    char *Ob = nullptr;
+    double ua = 0.0, ub = 0.0, uo = 0.0;
+    bool ufirst = false;
+    if constexpr (UPD == U_S) {
+        Yb = (const char *)P.vec[V_R];
+        Ub[0] = (const char *)P.vec[V_W];
+        Ob = (char *)P.vec[V_S];
+        ua = P.sc->alpha;
+    } else if constexpr (UPD == U_P) {
+        const int it = P.sc->iter;
+        ufirst = it == 0;
+        const int pold = ((it - 1) & 1) ? V_P2 : V_P, pnew = (it & 1) ? V_P2 : V_P;
+        Yb = (const char *)P.vec[ufirst ? V_P : V_R];
+        Ub[0] = (const char *)P.vec[ufirst ? V_P : V_W];
+        Ub[1] = (const char *)P.vec[ufirst ? V_P : pold];
+        Ob = (char *)P.vec[pnew];
+        ub = P.sc->beta;
+        uo = P.sc->omega;
+    }
+    // v from its raw operands, in the rounding order of the standalone updates
+    auto comb = [&](TU r, TU w, TU pp) -> TU {
+        if constexpr (UPD == U_S) return r - (TU)ua * w;
+        else if constexpr (UPD == U_P) return ufirst ? pp : r + (TU)ub * (pp - (TU)uo * w);
+        else return r;
+    };
+    const char *Vb = (const char *)vec_at(P, A.v);
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
@@ -1390,18 +1434,40 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     // the plane before their own and consumed straight from these registers.
     struct RawY {
         TU y[E], yo, he;
+        TU uy[NUA][E], uyo[NUA], uhe[NUA];
     };
     struct RawV {
         T v[E], z[E], hv, hz;
-        TU hf;
+        TU hf, uhf[NUA];
     };
-    auto issueY = [&](int p, RawY &R) {
-        const char *Yp = Yb + (size_t)clampi(p, nz) * PBY;
+    // the folded update's extra operands of plane p; in the plane loop they are
+    // issued after step i, so fewer loads are in flight across its arithmetic
+    auto issueU = [&](int p, RawY &R) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const char *Up = Ub[u] + pb;
+#pragma unroll
+            for (int e = 0; e < E; ++e) R.uy[u][e] = ldy(Up, ryoff[e]);
+            R.uyo[u] = ldy(Up, ooff);
+            R.uhe[u] = ldy(Up, hoff);
+        }
+    };
+    auto issueY = [&](int p, RawY &R, bool extra) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+        const char *Yp = Yb + pb;
 #pragma unroll
         for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
         R.yo = ldy(Yp, ooff);
         R.he = ldy(Yp, hoff);
+        if (extra) issueU(p, R);
     };
+    // the input v at held row e, the outer row and the halo column
+    auto gy = [&](const RawY &R, int e) {
+        return comb(R.y[e], R.uy[0][e], R.uy[NUA - 1][e]);
+    };
+    auto gyo = [&](const RawY &R) { return comb(R.yo, R.uyo[0], R.uyo[NUA - 1]); };
+    auto ghe = [&](const RawY &R) { return comb(R.he, R.uhe[0], R.uhe[NUA - 1]); };
     auto issueV = [&](int p, RawV &R) {
         const size_t po = (size_t)clampi(p, nz) * PB;
         if constexpr (!FIRST) {
@@ -1414,7 +1480,10 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
             R.hz = ld(Zb + po, coff);
         }
         R.hf = ldy(Yb + (size_t)clampi(p, nz) * PBY, foff);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) R.uhf[u] = ldy(Ub[u] + (size_t)clampi(p, nz) * PBY, foff);
     };
+    auto ghf = [&](const RawV &R) { return comb(R.hf, R.uhf[0], R.uhf[NUA - 1]); };
     auto bufy = [&](int k) { return lds + (k & 1) * L::PLANE; };
     auto bufw = [&](int k) { return lds + (2 + (k & 1)) * L::PLANE; };
 
@@ -1431,26 +1500,26 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     {
         // planes k0-2 and k0-1 of y; plane k0-1 into LDS
         RawY t;
-        issueY(k0 - 2, t);
+        issueY(k0 - 2, t, true);
         {
             const bool pin = k0 - 2 >= 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
-            ha = (pin && hload) ? (T)t.he : (T)0;
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            ha = (pin && hload) ? (T)ghe(t) : (T)0;
         }
-        issueY(k0 - 1, t);
+        issueY(k0 - 1, t, true);
         {
             const bool pin = k0 - 1 >= 0;
             T *yd = bufy(k0 - 1);
 #pragma unroll
-            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
-            yob = (pin && ook) ? (T)t.yo : (T)0;
-            if (hact) yd[lhself] = (pin && hload) ? (T)t.he : (T)0;
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            yob = (pin && ook) ? (T)gyo(t) : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? (T)ghe(t) : (T)0;
         }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) wa[e] = vb[e] = (T)0;
-    issueY(k0, RY);
+    issueY(k0, RY, true);
     issueV(k0 - 1, RV);
     __syncthreads();
 
@@ -1458,17 +1527,33 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         const bool pin1 = k + 1 >= 0 && k + 1 < nz, pin0 = k >= 0 && k < nz;
         // take y at plane k+1, publish it for the next plane, issue plane k+2
         T yc[E];
+        TU vn[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? (T)RY.y[e] : (T)0;
-        const T yoc = (pin1 && ook) ? (T)RY.yo : (T)0;
-        const T hc = (pin1 && hload) ? (T)RY.he : (T)0;
+        for (int e = 0; e < E; ++e) {
+            vn[e] = gy(RY, e);
+            yc[e] = (pin1 && rok[e]) ? (T)vn[e] : (T)0;
+        }
+        const T yoc = (pin1 && ook) ? (T)gyo(RY) : (T)0;
+        const T hc = (pin1 && hload) ? (T)ghe(RY) : (T)0;
+        if constexpr (UPD != 0) {
+            // the formed v at the tile's own points of plane k+1: stored, and s.s
+            if (k + 1 >= k0 && k + 1 < k1 && !ufirst) {
+                const size_t po = (size_t)(k + 1) * PBY;
+#pragma unroll
+                for (int e = EOWN; e < EOWN + PR; ++e)
+                    if (rok[e]) {
+                        st_nt((TU *)(Ob + po + ryoff[e]), vn[e]);
+                        if constexpr (UPD == U_S) dd_acc(ssh, ssl, (double)vn[e], (double)vn[e]);
+                    }
+            }
+        }
         {
             T *yd = bufy(k + 1);
 #pragma unroll
             for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = yc[e];
             if (hact) yd[lhself] = hc;
         }
-        issueY(k + 2, RY);
+        issueY(k + 2, RY, false);
 
         // w_i at plane k on the held rows, from y planes k-1 (ya), k (LDS), k+1 (yc)
         const T *ys = bufy(k);
@@ -1514,7 +1599,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         {
             hb = ys[lhself];
             const T xn = ys[lhin], d = ys[lhup], u = ys[lhdn];
-            const T hf = (fload && pin0) ? (T)RV.hf : (T)0;
+            const T hf = (fload && pin0) ? (T)ghf(RV) : (T)0;
             const T hv = (!FIRST && cact && pin0) ? RV.hv : (T)0;
             const T hz = (!FIRST && cact && pin0) ? RV.hz : (T)0;
             const T l = hside ? xn : hf, r = hside ? hf : xn;
@@ -1534,6 +1619,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
             if (hown) wd[lhself] = hw;
         }
         issueV(k + 1, RV);
+        issueU(k + 2, RY);
 
         // w_{i+1} at plane k-1 from w_i at planes k-2 (wa), k-1 (LDS), k (wc)
         const T *ws = bufw(k - 1);
@@ -1594,11 +1680,13 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 
 // DROP: the last pair of an apply, which stores w_{i+1} only (a kernel of its
 // own, so that profiles report the two traffic figures apart)
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE,
+          int UPD = 0>
 __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
 {
     using L = LPair<NXW, PR>;
     __shared__ T lds[4 * L::PLANE];
+    __shared__ double red[2 * 2 * NXW];
     constexpr int F32 = sizeof(T) == 4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int xw = wv % NXW, yw = wv / NXW;
@@ -1628,10 +1716,23 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
         // the tiles of a tile row share the L2 that holds their halo columns
         const int ltx = (P.nx + L::X - 1) / L::X;
         const int t = W.pair_prob ? W.pair_local[g] : tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
-            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
+                                                                                   lds, ssh, ssl);
         else
-            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
+                                                                                    lds, ssh, ssl);
+        if constexpr (UPD == U_S) {
+            // this tile's s.s in its partial slot (summed by the half-step finalize)
+            double hh[1] = {ssh}, ll[1] = {ssl};
+            block_reduce_dd<1, 2 * NXW>(hh, ll, red);
+            if (threadIdx.x == 0) {
+                double *pp = P.partials + (size_t)t * PARTIAL_STRIDE;
+                pp[0] = hh[0];
+                pp[1] = ll[0];
+            }
+        }
     }
 }
 
@@ -1663,11 +1764,16 @@ template <int NXW, int PR> struct LTriple {
 // at step 2; step 3 reads v = the input and z = w_1). The input is then v
 // itself, read as TU (FP64 also in the mixed mode, rounded once on load, with
 // the FP32 copy of v written out).
+// UPD: a vector update folded into the first triple, as in cheb_pair_lds_tile.
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
-          bool SIMPLE>
+          bool SIMPLE, int UPD>
 __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs &A, int tile,
-                                                     int lane, int xw, T *lds)
+                                                     int lane, int xw, T *lds, double &ssh,
+                                                     double &ssl)
 {
+    static_assert(UPD == 0 || FIRST, "a vector update folds only into a first pass");
+    constexpr int NU = UPD == U_P ? 2 : (UPD == U_S ? 1 : 0);
+    constexpr int NUA = NU > 0 ? NU : 1;
     using L = LTriple<NXW, PR>;
     constexpr int E = PR + 2;                      // held rows: own PR and two halo rows
     constexpr int L2LO = TOP ? 1 : 0, L2HI = TOP ? E : E - 1;   // rows of w_{i+1}
@@ -1689,7 +1795,32 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
     const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU); // the input's planes
     const char *Yb = (const char *)P.vec[A.in];
-    const char *Vb = (const char *)P.vec[A.v];
+    const char *Ub[2] = {nullptr, nullptr};
+    char *Ob = nullptr;
+    double ua = 0.0, ub = 0.0, uo = 0.0;
+    bool ufirst = false;
+    if constexpr (UPD == U_S) {
+        Yb = (const char *)P.vec[V_R];
+        Ub[0] = (const char *)P.vec[V_W];
+        Ob = (char *)P.vec[V_S];
+        ua = P.sc->alpha;
+    } else if constexpr (UPD == U_P) {
+        const int it = P.sc->iter;
+        ufirst = it == 0;
+        const int pold = ((it - 1) & 1) ? V_P2 : V_P, pnew = (it & 1) ? V_P2 : V_P;
+        Yb = (const char *)P.vec[ufirst ? V_P : V_R];
+        Ub[0] = (const char *)P.vec[ufirst ? V_P : V_W];
+        Ub[1] = (const char *)P.vec[ufirst ? V_P : pold];
+        Ob = (char *)P.vec[pnew];
+        ub = P.sc->beta;
+        uo = P.sc->omega;
+    }
+    auto comb = [&](TU r, TU w, TU pp) -> TU {
+        if constexpr (UPD == U_S) return r - (TU)ua * w;
+        else if constexpr (UPD == U_P) return ufirst ? pp : r + (TU)ub * (pp - (TU)uo * w);
+        else return r;
+    };
+    const char *Vb = (const char *)vec_at(P, A.v);
     const char *Zb = (const char *)P.vec[A.z];
     char *W1b = (char *)P.vec[A.out];
     char *W2b = (char *)P.vec[A.x2];
@@ -1794,18 +1925,39 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 
     struct RawY {
         TU y[E], yo, he;
+        TU uy[NUA][E], uyo[NUA], uhe[NUA];
     };
     struct RawV {
         T v[E], z[E], hv, hz;
-        TU hf;
+        TU hf, uhf[NUA];
     };
-    auto issueY = [&](int p, RawY &R) {
-        const char *Yp = Yb + (size_t)clampi(p, nz) * PBY;
+    // the folded update's extra operands of plane p; in the plane loop they are
+    // issued after step i, so fewer loads are in flight across its arithmetic
+    auto issueU = [&](int p, RawY &R) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const char *Up = Ub[u] + pb;
+#pragma unroll
+            for (int e = 0; e < E; ++e) R.uy[u][e] = ldy(Up, ryoff[e]);
+            R.uyo[u] = ldy(Up, ooff);
+            R.uhe[u] = ldy(Up, hoffy);
+        }
+    };
+    auto issueY = [&](int p, RawY &R, bool extra) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+        const char *Yp = Yb + pb;
 #pragma unroll
         for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
         R.yo = ldy(Yp, ooff);
         R.he = ldy(Yp, hoffy);
+        if (extra) issueU(p, R);
     };
+    auto gy = [&](const RawY &R, int e) {
+        return comb(R.y[e], R.uy[0][e], R.uy[NUA - 1][e]);
+    };
+    auto gyo = [&](const RawY &R) { return comb(R.yo, R.uyo[0], R.uyo[NUA - 1]); };
+    auto ghe = [&](const RawY &R) { return comb(R.he, R.uhe[0], R.uhe[NUA - 1]); };
     auto issueV = [&](int p, RawV &R) {
         const size_t po = (size_t)clampi(p, nz) * PB;
         if constexpr (!FIRST) {
@@ -1818,7 +1970,10 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
             R.hz = ld(Zb + po, hoff);
         }
         R.hf = ldy(Yb + (size_t)clampi(p, nz) * PBY, foff);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) R.uhf[u] = ldy(Ub[u] + (size_t)clampi(p, nz) * PBY, foff);
     };
+    auto ghf = [&](const RawV &R) { return comb(R.hf, R.uhf[0], R.uhf[NUA - 1]); };
     auto buf = [&](int f, int k) { return lds + (2 * f + (k & 1)) * L::PLANE; }; // f: 0 y, 1 w_i, 2 w_{i+1}
 
     // registers across planes (k = the plane of w_i): y at k-1 (ya), w_i at
@@ -1834,27 +1989,27 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     RV.hv = RV.hz = (T)0;
     {
         RawY t;
-        issueY(k0 - 3, t);
+        issueY(k0 - 3, t, true);
         {
             const bool pin = k0 - 3 >= 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
-            ha = (pin && hload) ? (T)t.he : (T)0;
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            ha = (pin && hload) ? (T)ghe(t) : (T)0;
         }
-        issueY(k0 - 2, t);
+        issueY(k0 - 2, t, true);
         {
             const bool pin = k0 - 2 >= 0;
             T *yd = buf(0, k0 - 2);
 #pragma unroll
-            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)t.y[e] : (T)0;
-            yob = (pin && ook) ? (T)t.yo : (T)0;
-            if (hact) yd[lhself] = (pin && hload) ? (T)t.he : (T)0;
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            yob = (pin && ook) ? (T)gyo(t) : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? (T)ghe(t) : (T)0;
         }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) w1a[e] = w2a[e] = vb[e] = vbb[e] = (T)0;
     h1a = hvb = (T)0;
-    issueY(k0 - 1, RY);
+    issueY(k0 - 1, RY, true);
     issueV(k0 - 2, RV);
     __syncthreads();
 
@@ -1863,17 +2018,32 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         const bool pinm = k - 1 >= 0 && k - 1 < nz;
         // take y at plane k+1, publish it, issue plane k+2
         T yc[E];
+        TU vn[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) yc[e] = (pin1 && rok[e]) ? (T)RY.y[e] : (T)0;
-        const T yoc = (pin1 && ook) ? (T)RY.yo : (T)0;
-        const T hc = (pin1 && hload) ? (T)RY.he : (T)0;
+        for (int e = 0; e < E; ++e) {
+            vn[e] = gy(RY, e);
+            yc[e] = (pin1 && rok[e]) ? (T)vn[e] : (T)0;
+        }
+        const T yoc = (pin1 && ook) ? (T)gyo(RY) : (T)0;
+        const T hc = (pin1 && hload) ? (T)ghe(RY) : (T)0;
+        if constexpr (UPD != 0) {
+            if (k + 1 >= k0 && k + 1 < k1 && !ufirst) {
+                const size_t po = (size_t)(k + 1) * PBY;
+#pragma unroll
+                for (int e = OWNLO; e < OWNHI; ++e)
+                    if (rok[e]) {
+                        st_nt((TU *)(Ob + po + ryoff[e]), vn[e]);
+                        if constexpr (UPD == U_S) dd_acc(ssh, ssl, (double)vn[e], (double)vn[e]);
+                    }
+            }
+        }
         {
             T *yd = buf(0, k + 1);
 #pragma unroll
             for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = yc[e];
             if (hact) yd[lhself] = hc;
         }
-        issueY(k + 2, RY);
+        issueY(k + 2, RY, false);
 
         // w_i at plane k on the held rows
         const T *ys = buf(0, k);
@@ -1912,7 +2082,7 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         {
             hb = ys[lhself];
             const T xn = ys[lhnear], d = ys[lhup], u = ys[lhdn];
-            const T xf = grpb ? ((fload && pin0) ? (T)RV.hf : (T)0) : ys[lhfar];
+            const T xf = grpb ? ((fload && pin0) ? (T)ghf(RV) : (T)0) : ys[lhfar];
             const bool ok = c1act && pin0;
             hvc = (!FIRST && hload && pin0) ? RV.hv : (T)0;
             const T hz = (!FIRST && ok) ? RV.hz : (T)0;
@@ -1927,6 +2097,7 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
             if (h1) wd[lhself] = h1c;
         }
         issueV(k + 1, RV);
+        issueU(k + 2, RY);
 
         // w_{i+1} at plane k-1 on its rows, from w_i at k-2 (w1a), k-1 (LDS), k (w1c)
         const T *w1s = buf(1, k - 1);
@@ -2032,12 +2203,14 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 
 // At most 256 VGPRs (two waves per SIMD): the bodies with neighbour selects
 // need a few more and spill them (measured faster than one wave per SIMD)
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE,
+          int UPD = 0>
 __global__ void __launch_bounds__(128 * NXW) __attribute__((amdgpu_waves_per_eu(2)))
 k_cheb_triple_lds(Work W, KArgs A)
 {
     using L = LTriple<NXW, PR>;
     __shared__ T lds[6 * L::PLANE];
+    __shared__ double red[2 * 2 * NXW];
     constexpr int F32 = sizeof(T) == 4;
     const Prob &P = W.probs[0];
     const int tkz = P.tkz[F32];
@@ -2052,10 +2225,22 @@ k_cheb_triple_lds(Work W, KArgs A)
     const int total = ltx * lty * ((P.nz + tkz - 1) / tkz);
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
-            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
+                                                                                     lds, ssh, ssl);
         else
-            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE>(P, A, t, lane, xw, lds);
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE, UPD>(P, A, t, lane,
+                                                                                      xw, lds, ssh, ssl);
+        if constexpr (UPD == U_S) {
+            double hh[1] = {ssh}, ll[1] = {ssl};
+            block_reduce_dd<1, 2 * NXW>(hh, ll, red);
+            if (threadIdx.x == 0) {
+                double *pp = P.partials + (size_t)t * PARTIAL_STRIDE;
+                pp[0] = hh[0];
+                pp[1] = ll[0];
+            }
+        }
     }
 }
 
@@ -2094,6 +2279,7 @@ __device__ __forceinline__ void elem_tile(const Prob &P, const KArgs &A, const S
             const TP *ph = (const TP *)P.vec[A.in];
             const TP *sh = (const TP *)P.vec[A.x2];
             double *r_ = (double *)P.vec[V_R];
+            const double *s_ = (const double *)P.vec[P.s_slot];
             const double *__restrict__ tv = (const double *)P.vec[V_T];
             const double *__restrict__ rt = (const double *)P.vec[V_RT];
             double xv[RY], pv[RY];
@@ -2110,7 +2296,7 @@ __device__ __forceinline__ void elem_tile(const Prob &P, const KArgs &A, const S
                 for (int r = 0; r < RY; ++r)
                     if (rin[r]) {
                         const size_t idx = base + r * NXs;
-                        sv[r] = ld_nt(r_ + idx);
+                        sv[r] = ld_nt(s_ + idx);
                         shv[r] = (double)ld_nt(sh + idx);
                         tt[r] = ld_nt(tv + idx);
                         rtv[r] = ld_nt(rt + idx);
@@ -2257,7 +2443,7 @@ __global__ void __launch_bounds__(NTHREADS) k_finalize(Work W, KArgs A)
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
         double res[ND];
-        sum_partials<ND>(P, lds, res);
+        sum_partials<ND>(P, A.nparts > 0 ? A.nparts : P.ntiles, lds, res);
         if (threadIdx.x == 0) {
             if constexpr (F == F_SDOT) fin_sdot(P, res[0]);
             else if constexpr (F == F_SDOT2) fin_sdot2(P, res[0], res[1]);
@@ -2308,6 +2494,20 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW, bool MASK, bool SIMPLE>
 static void lpl_launch(const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
+    if constexpr (FIRST) {
+        // a folded vector update: single problems only (the server keeps the
+        // standalone update kernels)
+        if (a.upd == U_S) {
+            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, LPR, MASK, SIMPLE, U_S>),
+                               dim3(grid), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+            return;
+        }
+        if (a.upd == U_P) {
+            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, LPR, MASK, SIMPLE, U_P>),
+                               dim3(grid), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, LPR, MASK, SIMPLE>), dim3(grid),
                        dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
 }
@@ -2362,6 +2562,18 @@ static void ltr_launch(const Work &w, hipStream_t s, const KArgs &a)
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NXW = triple_nxw(F32), PR = triple_pr(F32);
+    if constexpr (FIRST) {
+        if (a.upd == U_S) {
+            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, MASK, SIMPLE, U_S>),
+                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+            return;
+        }
+        if (a.upd == U_P) {
+            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, MASK, SIMPLE, U_P>),
+                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, FIRST, DROP, NXW, PR, MASK, SIMPLE>),
                        dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
 }
@@ -2390,6 +2602,11 @@ void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, con
 void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KArgs &a)
 {
     ltr_drop<float, double, true, false>(mask, w, s, a);
+}
+
+void launch_finalize_ss(const Work &w, hipStream_t s, const KArgs &a)
+{
+    lfin<F_AXPY>(w, 1, s, a);
 }
 
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

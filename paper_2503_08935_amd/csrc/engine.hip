@@ -25,11 +25,11 @@ using namespace pz;
 namespace {
 
 struct GraphKey {
-    int pc, deg, mixed, iters, fuse, order, pair_lds;
+    int pc, deg, mixed, iters, fuse, order, pair_lds, upd;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(pc, deg, mixed, iters, fuse, order, pair_lds) <
-               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order, o.pair_lds);
+        return std::tie(pc, deg, mixed, iters, fuse, order, pair_lds, upd) <
+               std::tie(o.pc, o.deg, o.mixed, o.iters, o.fuse, o.order, o.pair_lds, o.upd);
     }
 };
 
@@ -46,9 +46,11 @@ struct poisson_ctx {
     // options
     int precision = POISSON_FP64, graph_iters = 8, use_graph = 1, tile_order = 0;
     int pair_lds = 1;
+    int fuse_updates = 1;       // fold the s and p updates into the applies' first passes
     PlanOpts opt;
     // tiling
     int ntiles = 1;
+    int nparts = 1;             // reduction partial slots per problem (every tiling)
     // device state
     bool dev = false;
     hipStream_t cap_stream = nullptr;
@@ -56,7 +58,7 @@ struct poisson_ctx {
     Prob *h_prob = nullptr;     // pinned staging, 2 entries
     Scalars *d_sc = nullptr;    // [0] solve, [1] single operations
     Scalars *h_sc = nullptr;    // pinned
-    double *d_partials = nullptr; // 2 * ntiles * PARTIAL_STRIDE
+    double *d_partials = nullptr; // 2 * nparts * PARTIAL_STRIDE
     double *d_hist = nullptr;
     int hist_cap = 0;
     char *ws = nullptr;
@@ -66,8 +68,9 @@ struct poisson_ctx {
     std::vector<hipGraph_t> graph_src;
     // plan of the last solve
     bool plan_ok = false;
-    int plan_pc = -1, plan_deg = 0, plan_mixed = 0, plan_fuse = 0;
+    int plan_pc = -1, plan_deg = 0, plan_mixed = 0, plan_fuse = 0, plan_upd = 0;
     void *vec[V_COUNT] = {};
+    int s_slot = V_R;
     double plan_lo = 0, plan_hi = 0;
     // results
     bool have_stats = false;
@@ -88,7 +91,7 @@ int ensure_device(poisson_ctx *c)
     HIPCHK(hipMalloc(&c->d_sc, 2 * sizeof(Scalars)));
     HIPCHK(hipMemset(c->d_sc, 0, 2 * sizeof(Scalars)));
     HIPCHK(hipHostMalloc(&c->h_sc, 2 * sizeof(Scalars), hipHostMallocDefault));
-    HIPCHK(hipMalloc(&c->d_partials, 2 * (size_t)c->ntiles * PARTIAL_STRIDE * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_partials, 2 * (size_t)c->nparts * PARTIAL_STRIDE * sizeof(double)));
     HIPCHK(hipEventCreate(&c->ev_a));
     HIPCHK(hipEventCreate(&c->ev_b));
     memset(c->h_prob, 0, 2 * sizeof(Prob));
@@ -97,9 +100,9 @@ int ensure_device(poisson_ctx *c)
 }
 
 // size the workspace for a plan; grows (never shrinks) the allocation
-int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
+int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
-    const size_t need = workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse);
+    const size_t need = workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse, upd);
     if (need > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -113,8 +116,9 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed)
     }
     Prob tmp;
     memset(&tmp, 0, sizeof(tmp));
-    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, c->opt.fuse);
+    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, c->opt.fuse, upd);
     for (int v = 0; v < V_COUNT; ++v) c->vec[v] = tmp.vec[v];
+    c->s_slot = tmp.s_slot;
     return POISSON_OK;
 }
 
@@ -136,6 +140,13 @@ int plan_fuse_level(const poisson_ctx *c)
     return (c->opt.fuse >= 2 && !c->pair_lds) ? 1 : c->opt.fuse;
 }
 
+// the vector updates a solve of this plan folds into the applies' first passes
+int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
+{
+    if (!c->fuse_updates) return 0;
+    return upd_fusion(pc, deg, mixed, c->opt.fuse, single_work(c, nullptr));
+}
+
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 {
     return fill_prob(p, c->nx, c->ny, c->nz, c->h, c->bc, pc, deg, c->opt, tol, maxit,
@@ -145,7 +156,8 @@ int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
 int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec_t *out)
 {
     const Work w = single_work(c, c->d_prob);
-    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order, w.pair_tiles[0] > 0};
+    const int upd = plan_updates(c, pc, m, mixed);
+    GraphKey k{pc, m, mixed ? 1 : 0, iters, c->opt.fuse, c->tile_order, w.pair_tiles[0] > 0, upd};
     auto it = c->graphs.find(k);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -154,7 +166,7 @@ int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i)
-        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, c->opt.fuse);
+        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, c->opt.fuse, upd);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipGraphExec_t e = nullptr;
     HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -200,7 +212,8 @@ void put_stats(poisson_ctx *c, const Scalars &sc, double rr_true, int pc, int de
     st.lambda_min = c->plan_lo;
     st.lambda_max = c->plan_hi;
     st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c)) * (double)c->N * sc.iter;
+    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c), plan_updates(c, pc, deg, mixed)) *
+                     (double)c->N * sc.iter;
     st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
 }
 
@@ -213,7 +226,8 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     if ((rc = validate_ptr(rhs)) != POISSON_OK) return rc;
     if ((rc = validate_ptr(x)) != POISSON_OK) return rc;
     if ((rc = ensure_device(c)) != POISSON_OK) return rc;
-    if ((rc = plan_workspace(c, pc, deg, mixed)) != POISSON_OK) return rc;
+    const int upd = plan_updates(c, pc, deg, mixed);
+    if ((rc = plan_workspace(c, pc, deg, mixed, upd)) != POISSON_OK) return rc;
     const int hist_iters = std::min(maxit, MAX_HIST_ITERS);
     if (c->hist_cap < 1 + 4 * hist_iters) {
         if (c->d_hist) HIPCHK(hipFree(c->d_hist));
@@ -225,6 +239,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     Prob &p = c->h_prob[0];
     if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
     for (int v = 0; v < V_COUNT; ++v) p.vec[v] = c->vec[v];
+    p.s_slot = c->s_slot;
     p.vec[V_X] = x;
     p.vec[V_B] = (void *)rhs;
     p.sc = c->d_sc;
@@ -236,6 +251,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     c->plan_deg = deg;
     c->plan_mixed = mixed;
     c->plan_fuse = fused(pc, deg, mixed, c->opt.fuse);
+    c->plan_upd = upd;
     if ((rc = upload_prob(c, 0)) != POISSON_OK) return rc;
 
     const Work w = single_work(c, c->d_prob);
@@ -255,7 +271,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
                 HIPCHK(hipGraphLaunch(g, c->stream));
             } else {
                 for (int i = 0; i < K; ++i)
-                    enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse);
+                    enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse, upd);
                 HIPCHK(hipGetLastError());
             }
             if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -339,11 +355,11 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // bytes of the scratch a solve of this plan takes: descriptor, scalars, the
 // partials of one problem and the workspace
-size_t noalloc_bytes(const poisson_ctx *c, int pc, int deg, bool mixed)
+size_t noalloc_bytes(const poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
     return round256(sizeof(Prob)) + round256(sizeof(Scalars)) +
-           round256((size_t)c->ntiles * PARTIAL_STRIDE * sizeof(double)) +
-           workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse);
+           round256((size_t)c->nparts * PARTIAL_STRIDE * sizeof(double)) +
+           workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse, upd);
 }
 
 // the solve of solve_impl with every device buffer carved from the scratch,
@@ -357,18 +373,20 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
     int rc;
     if ((rc = validate_ptr(rhs)) != POISSON_OK) return rc;
     if ((rc = validate_ptr(x)) != POISSON_OK) return rc;
-    if (noalloc_bytes(c, pc, deg, mixed) > POISSON_NOALLOC_SCRATCH_BYTES) return POISSON_ERR_NOMEM;
+    const int upd = plan_updates(c, pc, deg, mixed);
+    if (noalloc_bytes(c, pc, deg, mixed, upd) > POISSON_NOALLOC_SCRATCH_BYTES)
+        return POISSON_ERR_NOMEM;
     char *base = nullptr;
     if ((rc = scratch_base(&base)) != POISSON_OK) return rc;
     Prob *d_prob = (Prob *)base;
     Scalars *d_sc = (Scalars *)(base + round256(sizeof(Prob)));
     double *d_part = (double *)((char *)d_sc + round256(sizeof(Scalars)));
-    char *ws = (char *)d_part + round256((size_t)c->ntiles * PARTIAL_STRIDE * sizeof(double));
+    char *ws = (char *)d_part + round256((size_t)c->nparts * PARTIAL_STRIDE * sizeof(double));
 
     Prob p;
     memset(&p, 0, sizeof(p));
     if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
-    carve_workspace(p, ws, c->N, pc, deg, mixed, c->opt.fuse);
+    carve_workspace(p, ws, c->N, pc, deg, mixed, c->opt.fuse, upd);
     p.vec[V_X] = x;
     p.vec[V_B] = (void *)rhs;
     p.sc = d_sc;
@@ -397,7 +415,7 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
         const long max_rounds = (long)maxit / K + 2;
         for (long round = 0; round < max_rounds; ++round) {
             for (int i = 0; i < K; ++i)
-                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse);
+                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse, upd);
             HIPCHK(hipGetLastError());
             if ((rc = read_sc()) != POISSON_OK) return rc;
             if (sc.done) break;
@@ -460,6 +478,7 @@ int poisson_create(int nx, int ny, int nz, double h, unsigned bc, poisson_ctx **
     c->nx = nx; c->ny = ny; c->nz = nz; c->h = h; c->bc = bc;
     c->N = (size_t)nx * ny * nz;
     c->ntiles = make_tiling(nx, ny, nz).ntiles;
+    c->nparts = partial_slots(nx, ny, nz);
     *out = c;
     return POISSON_OK;
 }
@@ -511,6 +530,10 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
     case POISSON_OPT_PAIR_LDS:
         if (v != 0 && v != 1) return POISSON_ERR_ARG;
         c->pair_lds = (int)v;
+        return POISSON_OK;
+    case POISSON_OPT_FUSE_UPDATES:
+        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        c->fuse_updates = (int)v;
         return POISSON_OK;
     default:
         return POISSON_ERR_ARG;
@@ -627,7 +650,7 @@ static int prim_begin(poisson_ctx *c, int pc, int deg, bool mixed)
     Prob &p = c->h_prob[1];
     if ((rc = fill(c, p, pc, deg, 0.5, 1)) != POISSON_OK) return rc;
     p.sc = c->d_sc + 1;
-    p.partials = c->d_partials + (size_t)c->ntiles * PARTIAL_STRIDE;
+    p.partials = c->d_partials + (size_t)c->nparts * PARTIAL_STRIDE;
     p.hist = nullptr;
     (void)mixed;
     return POISSON_OK;
@@ -662,7 +685,7 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
     try {
         const bool mixed = c->precision == POISSON_MIXED;
         if ((rc = ensure_device(c)) != POISSON_OK) return rc;
-        if ((rc = plan_workspace(c, precond, degree, mixed)) != POISSON_OK) return rc;
+        if ((rc = plan_workspace(c, precond, degree, mixed, 0)) != POISSON_OK) return rc;
         c->plan_ok = false; // the workspace no longer matches the last solve's plan
         if ((rc = prim_begin(c, precond, degree, mixed)) != POISSON_OK) return rc;
         Prob &p = c->h_prob[1];
@@ -740,7 +763,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
         Prob &p = c->h_prob[1];
         p = c->h_prob[0];
         p.sc = c->d_sc + 1;
-        p.partials = c->d_partials + (size_t)c->ntiles * PARTIAL_STRIDE;
+        p.partials = c->d_partials + (size_t)c->nparts * PARTIAL_STRIDE;
         p.hist = nullptr;
         p.vec[V_X] = c->vec[V_W];
         p.vec[V_B] = c->vec[V_T];

@@ -52,17 +52,23 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
               const PlanOpts &o, double tol, int maxit, double *lo, double *hi);
 // whether a plan runs fused Chebyshev step pairs
 bool fused(int pc, int deg, bool mixed, int fuse);
+// the vector updates (U_S | U_P) a plan can fold into the first passes of its
+// applies: fused plans of a single problem with LDS-staged first passes
+int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w);
 // bytes of vector slot v for a plan (0 if unused)
-size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse);
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse, int upd = 0);
 // total workspace of a plan, each slot 256-byte aligned
-size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse);
-// carve a workspace into the vector slots of p
-void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse);
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse, int upd = 0);
+// carve a workspace into the vector slots of p (and set p.s_slot)
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse,
+                     int upd = 0);
+// reduction partial slots a problem needs: its tiles in every tiling
+int partial_slots(int nx, int ny, int nz);
 void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int fuse,
-                int vin, int vout, int second);
+                int vin, int vout, int second, int upd = 0);
 void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed,
-                       int fuse);
-double iteration_bytes(int pc, int m, bool mixed, int fuse);
+                       int fuse, int upd = 0);
+double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd = 0);
 int validate_ptr(const void *p);
 double now_ms();
 

@@ -166,6 +166,7 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
               const PlanOpts &o, double tol, int maxit, double *lo_out, double *hi_out)
 {
     memset(&p, 0, sizeof(Prob));
+    p.s_slot = V_R;
     const Tiling t = make_tiling(nx, ny, nz);
     p.nx = nx; p.ny = ny; p.nz = nz; p.kz = t.kz;
     p.tx = t.tx; p.ty = t.ty; p.tz = t.tz; p.ntiles = t.ntiles;
@@ -223,7 +224,16 @@ bool fused(int pc, int deg, bool mixed, int fuse)
     return fuse && is_cheb(pc) && deg >= 3;
 }
 
-size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
+int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w)
+{
+    if (!fused(pc, deg, mixed, fuse) || w.tile_prob || w.pair_prob) return 0;
+    const int f = mixed ? 1 : 0;
+    const bool first3 = fuse >= 2 && w.triple_tiles[f] > 0 && mixed && deg >= 5;
+    if (first3) return U_S | U_P;
+    return w.pair_tiles[f] > 0 ? (U_S | U_P) : 0;
+}
+
+size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse, int upd)
 {
     const bool cheb = is_cheb(pc);
     const size_t tp = (mixed && pc != POISSON_PC_NONE) ? 4 : 8;
@@ -237,32 +247,45 @@ size_t vec_bytes(size_t N, int v, int pc, int deg, bool mixed, int fuse)
     case V_RC: return fz && deg >= 4 ? tp * N : 0;
     case V_RD: return fz && deg >= 5 ? tp * N : 0;
     case V_V32: return cheb && mixed && deg >= 1 ? 4 * N : 0;
+    case V_S: return (upd & U_S) ? 8 * N : 0;
+    case V_P2: return (upd & U_P) ? 8 * N : 0;
     default: return 0;
     }
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse)
+size_t workspace_bytes(size_t N, int pc, int deg, bool mixed, int fuse, int upd)
 {
     size_t need = 0;
-    for (int v = 0; v < V_COUNT; ++v) need += align256(vec_bytes(N, v, pc, deg, mixed, fuse));
+    for (int v = 0; v < V_COUNT; ++v) need += align256(vec_bytes(N, v, pc, deg, mixed, fuse, upd));
     return need;
 }
 
-void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse)
+void carve_workspace(Prob &p, char *ws, size_t N, int pc, int deg, bool mixed, int fuse, int upd)
 {
     size_t off = 0;
     for (int v = 0; v < V_COUNT; ++v) {
-        const size_t b = vec_bytes(N, v, pc, deg, mixed, fuse);
+        const size_t b = vec_bytes(N, v, pc, deg, mixed, fuse, upd);
         if (v != V_X && v != V_B) p.vec[v] = b ? ws + off : nullptr;
         off += align256(b);
     }
+    p.s_slot = (upd & U_S) ? V_S : V_R;
+}
+
+int partial_slots(int nx, int ny, int nz)
+{
+    int n = make_tiling(nx, ny, nz).ntiles;
+    for (int f = 0; f < 2; ++f) {
+        n = std::max(n, make_pair_tiling(nx, ny, nz, f).ntiles);
+        n = std::max(n, make_triple_tiling(nx, ny, nz, f).ntiles);
+    }
+    return n;
 }
 
 // preconditioner apply vout = M^-1 vin (Alg. 2; BJ(CI) with the masked operator)
 void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed, int fuse,
-                int vin, int vout, int second)
+                int vin, int vout, int second, int upd)
 {
     if (pc == POISSON_PC_NONE) return;
     if (pc == POISSON_PC_JACOBI || m == 0) {
@@ -271,7 +294,12 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         return;
     }
     const bool mask = pc == POISSON_PC_BLOCK_JACOBI;
-    const int vsrc = mixed ? (int)V_V32 : vin;
+    // where later steps read v: the FP32 copy in the mixed mode; with a folded
+    // update the vector the first pass formed (s, or this iteration's p)
+    int vsrc = vin;
+    if (upd == U_S) vsrc = V_S;
+    if (upd == U_P) vsrc = V_PCUR;
+    if (mixed) vsrc = V_V32;
     if (fused(pc, m, mixed, fuse)) {
         // steps 1 and 2 in one pass: reads v, writes y_1 (RA) and w_2 (RB), and in
         // mixed mode the FP32 copy of v; then steps (i, i+1) in fused pairs, each
@@ -285,10 +313,16 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         // per point of that pass made it slower than a pair: 980 against 605 us)
         const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
         const bool first3 = tri && mixed && m >= 5;
+        // a folded update (upd): the first pass forms its input itself; the
+        // half-step test of a formed s follows that pass
+        const int f = mixed ? 1 : 0;
+        const int parts = first3 ? w.triple_tiles[f] : w.pair_tiles[f];
+        const KArgs a1{vin, V_RA, vin, 0, 1, second, 0, V_RB, 0, upd, parts};
         if (first3)
-            launch_cheb_first_triple(mask, w, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
+            launch_cheb_first_triple(mask, w, s, a1);
         else
-            launch_cheb_first_pair(mixed, mask, w, grid, s, KArgs{vin, V_RA, vin, 0, 1, second, 0, V_RB});
+            launch_cheb_first_pair(mixed, mask, w, grid, s, a1);
+        if (upd == U_S) launch_finalize_ss(w, s, a1);
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
         int y = V_RB, z = V_RA;
         int i = first3 ? 4 : 3;
@@ -335,22 +369,25 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
 
 // one Bi-CGSTAB iteration in the kernel order of Alg. 3
 void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed,
-                       int fuse)
+                       int fuse, int upd)
 {
     const bool pm = mixed && pc != POISSON_PC_NONE;
     const int ph = pc == POISSON_PC_NONE ? V_P : V_PH;
     const int sh = pc == POISSON_PC_NONE ? V_R : V_SH;
-    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_P, V_PH, 0);                      // M p^ = p
+    // M p^ = p (with U_P the p update of the previous iteration happens here)
+    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_P, V_PH, 0, upd & U_P);
     launch_stencil(S_SDOT, pm, false, w, grid, s, KArgs{ph, V_W, 0, 0, 0, 0, 0, 0});  // w, alpha
-    launch_elem(E_AXPY, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // s, half step
-    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_R, V_SH, 1);                      // M s^ = s
+    if (!(upd & U_S))
+        launch_elem(E_AXPY, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});      // s, half step
+    enqueue_pc(w, grid, s, pc, m, mixed, fuse, V_R, V_SH, 1, upd & U_S);            // M s^ = s
     launch_stencil(S_SDOT2, pm, false, w, grid, s, KArgs{sh, V_T, 0, 0, 0, 1, 0, 0}); // t, omega
     launch_elem(E_UPD, pm, w, grid, s, KArgs{ph, 0, 0, 0, 0, 0, 0, sh});            // x, r, beta
-    launch_elem(E_PUPD, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});          // p
+    if (!(upd & U_P))
+        launch_elem(E_PUPD, false, w, grid, s, KArgs{0, 0, 0, 0, 0, 0, 0, 0});      // p
 }
 
 // algorithmic bytes per unknown of one iteration of a plan
-double iteration_bytes(int pc, int m, bool mixed, int fuse)
+double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd)
 {
     const bool pm = mixed && pc != POISSON_PC_NONE;
     const double tp = pm ? 4 : 8;
@@ -386,6 +423,12 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse)
     b += tp + 16;                                        // t = A s^, t.s, t.t
     b += pc == POISSON_PC_NONE ? 56 : 48 + 2 * tp;       // x, r updates
     b += 32;                                             // p update
+    // folded updates: the first pass of the second apply reads r and w instead of
+    // s and also writes s (+16) in place of the s update (-24); the first pass of
+    // the first apply reads r, w and the previous p instead of p and also writes
+    // p (+24) in place of the p update (-32)
+    if (upd & U_S) b += 16 - 24;
+    if (upd & U_P) b += 24 - 32;
     return b;
 }
 

@@ -24,7 +24,7 @@ using namespace pz;
 
 namespace {
 
-enum Kind { K_STENCIL, K_ELEM, K_PAIR, K_FIRST_PAIR, K_TRIPLE, K_FIRST_TRIPLE };
+enum Kind { K_STENCIL, K_ELEM, K_PAIR, K_FIRST_PAIR, K_TRIPLE, K_FIRST_TRIPLE, K_FIN_SS };
 
 struct Launch {
     Kind kind;
@@ -73,6 +73,10 @@ void launch_cheb_first_triple(bool, const Work &, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_TRIPLE, 0, true, a});
 }
+void launch_finalize_ss(const Work &, hipStream_t, const KArgs &a)
+{
+    g_log.push_back({K_FIN_SS, 0, false, a});
+}
 void launch_fill_uniform(double *, int64_t, uint64_t, hipStream_t) {}
 } // namespace pz
 
@@ -85,11 +89,15 @@ double launch_bytes(const Launch &l, int pc)
     const bool pm = l.mixed && pc != POISSON_PC_NONE;
     const double tp = pm ? 4 : 8;          // p^, s^
     const double tc = l.mixed ? 4 : 8;     // Chebyshev buffers
+    // a first pass that forms its v: reads r, w (s) or r, w, p (p) and writes v
+    const double vin = l.a.upd == U_S ? 8 + 8 + 8 : l.a.upd == U_P ? 8 + 8 + 8 + 8 : 8;
     switch (l.kind) {
+    case K_FIN_SS:
+        return 0;
     case K_FIRST_PAIR:
-        return 8 + 2 * tc + (l.mixed ? 4 : 0);          // v in; y_1, w_2 (+ v32) out
+        return vin + 2 * tc + (l.mixed ? 4 : 0);        // v in; y_1, w_2 (+ v32) out
     case K_FIRST_TRIPLE:
-        return 8 + 2 * tc + 4;                          // v in; y_2, y_3, v32 out
+        return vin + 2 * tc + 4;                        // v in; y_2, y_3, v32 out
     case K_PAIR:
     case K_TRIPLE:
         return (l.a.drop1 ? 4 : 5) * tc;                // y, z, v in; one or two outputs
@@ -116,27 +124,49 @@ double launch_bytes(const Launch &l, int pc)
 
 bool is_cheb_launch(const Launch &l)
 {
+    if (l.kind == K_FIN_SS) return false;
     if (l.kind != K_STENCIL) return l.kind != K_ELEM;
     return l.op == S_CHEB1 || l.op == S_CHEB2 || l.op == S_CHEBK;
 }
 
-void check_plan(int pc, int deg, bool mixed, int fuse, bool lds)
+void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
 {
     char tag[160];
-    snprintf(tag, sizeof tag, "pc %d degree %d mixed %d fuse %d lds %d", pc, deg, (int)mixed, fuse,
-             (int)lds);
+    snprintf(tag, sizeof tag, "pc %d degree %d mixed %d fuse %d lds %d fold %d", pc, deg, (int)mixed,
+             fuse, (int)lds, (int)fold);
     const size_t N = 1000;
     Work w{};
     w.count = 1;
     if (lds && fuse >= 2) w.triple_tiles[0] = w.triple_tiles[1] = 7;
     if (lds) w.pair_tiles[0] = w.pair_tiles[1] = 7;
+    const int upd = fold ? upd_fusion(pc, deg, mixed, fuse, w) : 0;
+    if (fold && !upd) return;
+    CHECK(!upd || (lds && is_cheb(pc) && deg >= 3 && fuse >= 1), "%s: folds %d", tag, upd);
     g_log.clear();
-    enqueue_iteration(w, 8, nullptr, pc, deg, mixed, fuse);
+    enqueue_iteration(w, 8, nullptr, pc, deg, mixed, fuse, upd);
     const int level = (fuse >= 2 && !lds) ? 1 : fuse;
     double sum = 0;
     for (const Launch &l : g_log) sum += launch_bytes(l, pc);
-    const double model = iteration_bytes(pc, deg, mixed, level);
+    const double model = iteration_bytes(pc, deg, mixed, level, upd);
     CHECK(sum == model, "%s: launches %g B, model %g B", tag, sum, model);
+    // the standalone updates run exactly when they are not folded, and a folded
+    // s is followed by its half-step test over the first pass's tiles
+    int n_axpy = 0, n_pupd = 0, n_fin = 0;
+    for (size_t k = 0; k < g_log.size(); ++k) {
+        const Launch &l = g_log[k];
+        if (l.kind == K_ELEM && l.op == E_AXPY) ++n_axpy;
+        if (l.kind == K_ELEM && l.op == E_PUPD) ++n_pupd;
+        if (l.kind == K_FIN_SS) {
+            ++n_fin;
+            CHECK(k > 0 && g_log[k - 1].a.upd == U_S && l.a.nparts == 7, "%s: finalize", tag);
+        }
+        if (l.a.upd && l.kind != K_FIN_SS)
+            CHECK(l.kind == K_FIRST_PAIR || l.kind == K_FIRST_TRIPLE, "%s: upd on kind %d", tag,
+                  (int)l.kind);
+    }
+    CHECK(n_axpy == ((upd & U_S) ? 0 : 1) && n_pupd == ((upd & U_P) ? 0 : 1) &&
+              n_fin == ((upd & U_S) ? 1 : 0),
+          "%s: %d axpy, %d p updates, %d finalizes", tag, n_axpy, n_pupd, n_fin);
 
     // the Chebyshev chain of each apply
     const bool cheb = is_cheb(pc) && deg >= 1;
@@ -144,6 +174,7 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds)
     int expect_in = -1, prev_out = -1, prev_x2 = -1;
     for (size_t k = 0; k < g_log.size(); ++k) {
         const Launch &l = g_log[k];
+        if (l.kind == K_FIN_SS) continue;
         if (!is_cheb_launch(l)) {
             prev_out = prev_x2 = -1;
             continue;
@@ -164,7 +195,7 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds)
         const int outs[2] = {a.out, (l.kind == K_STENCIL) ? -1 : a.x2};
         for (int o : outs) {
             if (o < 0) continue;
-            CHECK(vec_bytes(N, o, pc, deg, mixed, level) > 0 || o == V_PH || o == V_SH,
+            CHECK(vec_bytes(N, o, pc, deg, mixed, level, upd) > 0 || o == V_PH || o == V_SH,
                   "%s: launch %zu writes unallocated slot %d", tag, k, o);
             // a fused pass reads y, z and v at neighbouring points: it must not
             // overwrite them; a single step reads z only at its own point
@@ -176,13 +207,15 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds)
         // step 2 forms z = v / theta itself; later steps read z
         const bool reads_z = !first && !(l.kind == K_STENCIL && l.op == S_CHEB2);
         if (reads_z)
-            CHECK(vec_bytes(N, a.z, pc, deg, mixed, level) > 0 || a.z == V_P || a.z == V_R,
+            CHECK(vec_bytes(N, a.z, pc, deg, mixed, level, upd) > 0 || a.z == V_P || a.z == V_R,
                   "%s: launch %zu reads unallocated z slot %d", tag, k, a.z);
         prev_out = a.out;
         prev_x2 = (l.kind == K_STENCIL) ? -1 : a.x2;
         // the apply's last pass writes p^ or s^
-        const bool last = k + 1 == g_log.size() || !is_cheb_launch(g_log[k + 1]) ||
-                          g_log[k + 1].kind == K_FIRST_PAIR || g_log[k + 1].kind == K_FIRST_TRIPLE;
+        size_t nk = k + 1;
+        while (nk < g_log.size() && g_log[nk].kind == K_FIN_SS) ++nk;
+        const bool last = nk == g_log.size() || !is_cheb_launch(g_log[nk]) ||
+                          g_log[nk].kind == K_FIRST_PAIR || g_log[nk].kind == K_FIRST_TRIPLE;
         if (last) {
             const int fin = prev_x2 >= 0 ? prev_x2 : prev_out;
             CHECK(fin == (applies == 1 ? (int)V_PH : (int)V_SH), "%s: apply %d ends in slot %d",
@@ -192,20 +225,21 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds)
     if (cheb) CHECK(applies == 2, "%s: %d applies", tag, applies);
 
     // workspace: disjoint, aligned, inside
-    const size_t total = workspace_bytes(N, pc, deg, mixed, level);
+    const size_t total = workspace_bytes(N, pc, deg, mixed, level, upd);
     std::vector<char> ws(total + 256);
     char *base = (char *)(((uintptr_t)ws.data() + 255) & ~(uintptr_t)255);
     Prob p;
     memset(&p, 0, sizeof p);
-    carve_workspace(p, base, N, pc, deg, mixed, level);
+    carve_workspace(p, base, N, pc, deg, mixed, level, upd);
+    CHECK(p.s_slot == ((upd & U_S) ? (int)V_S : (int)V_R), "%s: s slot %d", tag, p.s_slot);
     for (int v = 0; v < V_COUNT; ++v) {
-        const size_t b = vec_bytes(N, v, pc, deg, mixed, level);
+        const size_t b = vec_bytes(N, v, pc, deg, mixed, level, upd);
         if (!b || v == V_X || v == V_B) continue;
         const char *s = (const char *)p.vec[v];
         CHECK(s && ((uintptr_t)s & 255) == 0, "%s: slot %d misaligned", tag, v);
         CHECK(s >= base && s + b <= base + total, "%s: slot %d outside the workspace", tag, v);
         for (int u = 0; u < v; ++u) {
-            const size_t c = vec_bytes(N, u, pc, deg, mixed, level);
+            const size_t c = vec_bytes(N, u, pc, deg, mixed, level, upd);
             if (!c || u == V_X || u == V_B) continue;
             const char *t = (const char *)p.vec[u];
             CHECK(s + b <= t || t + c <= s, "%s: slots %d and %d overlap", tag, u, v);
@@ -243,10 +277,11 @@ int main()
         for (int deg = 0; deg <= 12; ++deg)
             for (int mixed = 0; mixed < 2; ++mixed)
                 for (int fuse = 0; fuse <= 2; ++fuse)
-                    for (int lds = 0; lds < 2; ++lds) {
-                        if (!is_cheb(pc) && deg) continue;
-                        check_plan(pc, deg, mixed != 0, fuse, lds != 0);
-                    }
+                    for (int lds = 0; lds < 2; ++lds)
+                        for (int fold = 0; fold < 2; ++fold) {
+                            if (!is_cheb(pc) && deg) continue;
+                            check_plan(pc, deg, mixed != 0, fuse, lds != 0, fold != 0);
+                        }
     const unsigned bcs[5] = {0u, 1u, 22u, 3u | 12u, 33u};
     for (unsigned bc : bcs)
         for (int n : {2, 5, 17, 64, 100})

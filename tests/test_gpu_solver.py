@@ -235,12 +235,15 @@ def test_three_steps_per_pass_solve(gpu, mixed):
 def test_byte_model_per_iteration(gpu):
     """The stats' model bytes follow the passes the plan runs: FP64 Chebyshev-8 moves
     632 B per unknown and iteration with one step per pass, 440 with two, 360 with
-    steps 1-2, 3-5 and 6-8 (the default); mixed 264 by default."""
+    steps 1-2, 3-5 and 6-8; mixed 264. Folding the s and p updates into the first
+    passes (the default for the fused plans) saves 8 B each: 424, 344 and 248."""
     shape = (64, 48, 40)
     n = 64 * 48 * 40
     f = workloads.uniform_grid(5, shape)
-    for fuse, mixed, per in ((0, False, 632), (1, False, 440), (2, False, 360), (2, True, 264)):
+    for fuse, mixed, fold, per in ((0, False, 1, 632), (1, False, 0, 440), (2, False, 0, 360),
+                                   (2, True, 0, 264), (1, False, 1, 424), (2, False, 1, 344),
+                                   (2, True, 1, 248)):
         st, stats, tr, x = gpu_solve(shape, 1.0 / 65, f, P.PC_CHEBYSHEV, 8, 1e-8, fuse=fuse,
-                                     precision=P.MIXED if mixed else P.FP64)
+                                     fuse_updates=fold, precision=P.MIXED if mixed else P.FP64)
         assert st == P.OK
-        assert stats["model_bytes"] == per * n * stats["iterations"], (fuse, mixed)
+        assert stats["model_bytes"] == per * n * stats["iterations"], (fuse, mixed, fold)
