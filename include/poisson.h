@@ -289,13 +289,26 @@ typedef struct {
     long completed;             /* finished requests (any status) */
     long steps;                 /* poisson_server_step calls that did work */
     size_t bytes_in_use, peak_bytes, budget_bytes; /* arena accounting */
-    double busy_ms;             /* device time of all steps (HIP events) */
+    double busy_ms;             /* device time of all batches (HIP events), summed over
+                                   the size classes, whose batches may overlap */
 } poisson_server_info_t;
 
-enum { POISSON_SERVER_OPT_USE_GRAPH = 1 /* 1 = replay captured graphs (default), 0 = launch */ };
+enum {
+    POISSON_SERVER_OPT_USE_GRAPH = 1,    /* 1 = replay captured graphs (default), 0 = launch */
+    POISSON_SERVER_OPT_SIZE_CLASSES = 2  /* 1..4 size classes by unknowns (default 3: up to
+                                            64^3, up to 160^3, larger); each class advances in
+                                            its own batches on a stream of its own (default
+                                            priority), so small requests are not paced by
+                                            large ones; 1 = every request in one batch on the
+                                            server's stream. Set before the first step */
+};
 
-/* Create a server. hip_stream: stream of all its work (NULL = null stream).
-   Host-only: the arena is allocated by the first poisson_server_step.
+/* Create a server. hip_stream: the caller's stream (NULL = null stream); the
+   inputs of every request are taken to be ready once the work queued on it at
+   the step that admits the request has run. With one size class all of the
+   server's work runs on it; with several, each class runs on a stream the server
+   creates. Host-only: the arena and streams are created by the first
+   poisson_server_step.
    ERR_ARG if hbm_budget_bytes < 4096, max_slots outside 1..4096 or out == NULL. */
 int poisson_server_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream,
                           poisson_server **out);
@@ -316,11 +329,17 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
                           const double *rhs, double *x, int precond, int degree, int precision,
                           double tol, int maxit, uint64_t *ticket);
 
-/* One scheduling round: retire the requests found finished by the previous
-   round (true residual, stats, free the arena block and slot), admit queued
-   requests in order, compute their initial residuals, advance every running
-   request by `iters` iterations (1..4096), and read all requests' flags.
-   Synchronous. Returns the number of queued + running requests (>= 0). */
+/* One scheduling round. If every size class that has work still has a batch in
+   flight, first wait until one finishes. Then every class whose last batch has
+   finished retires the requests that batch finished (true residual, stats, free
+   the arena block and slot), admits queued requests of its size class in
+   arrival order (a request that does not fit in the arena stops admission, so no
+   later request passes it), computes their initial residuals, and starts its next
+   batch: `iters` iterations (1..4096) of all its running requests, on the class's
+   stream, after the work already on the server's stream (the inputs). Returns
+   without waiting for the new batches, with the number of queued + running
+   requests (>= 0); a request's final status is visible to poll after the step
+   that sees its batch finished. */
 int poisson_server_step(poisson_server *s, int iters);
 
 /* POISSON_PENDING while queued or running; otherwise the final status

@@ -1,23 +1,29 @@
 // server.hip -- continuous-batching solve server.
 //
-// Requests (one Poisson solve each, any grid size) are queued FIFO and
-// admitted while a slot is free and their workspace fits in a fixed HBM arena
-// (first-fit allocation, freed on retirement). Every admitted request keeps its
-// Krylov vectors resident in its arena block. poisson_server_step() retires
-// finished requests, admits new ones (one batched initial-residual launch for
-// all of them), then advances every running request by the same number of
-// Bi-CGSTAB iterations: each kernel of the iteration is launched once per plan
-// group (precond, degree, precision) over the tiles of all requests in the
-// group, from a captured HIP graph whose tile list and tile count live in
-// device memory, so the graph does not change when the batch does.
-// Reductions are per request and per tile, so a request's result is bitwise
-// the same alone, in any mix, and through poisson_solve().
+// Requests (one Poisson solve each, any grid size) are queued in arrival order
+// and admitted while a slot is free and their workspace fits in a fixed HBM
+// arena (first-fit allocation, freed on retirement). Every admitted request
+// keeps its Krylov vectors resident in its arena block. Requests fall into size
+// classes by their unknowns; each class advances on a stream of its own, in
+// batches of a few Bi-CGSTAB iterations: each kernel of the iteration is
+// launched once per plan group (precond, degree, precision, Neumann faces, size
+// class) over the tiles of all the group's requests, from a captured HIP graph
+// whose tile list and tile count live in device memory, so the graph does not
+// change when the batch does. poisson_server_step() lets every class whose last
+// batch has finished retire its finished requests, admit queued requests of its
+// size (one batched initial-residual launch) and start its next batch, while
+// the other classes' batches keep running: a 32^3 request is not paced by the
+// batches of 256^3 ones. Reductions are per request and per tile, so a
+// request's result is bitwise the same alone, in any mix, and through
+// poisson_solve().
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -29,11 +35,14 @@ namespace {
 
 constexpr int GRID = 2048;   // persistent workgroups of the batched kernels (multiple of 8)
 
+constexpr int MAX_CLASSES = 4; // size classes, each with a stream of its own
+
 struct PlanKey {
     int pc, deg, mixed, neu; // neu: the requests have a Neumann face
+    int cls;                 // size class
     bool operator<(const PlanKey &o) const
     {
-        return std::tie(pc, deg, mixed, neu) < std::tie(o.pc, o.deg, o.mixed, o.neu);
+        return std::tie(pc, deg, mixed, neu, cls) < std::tie(o.pc, o.deg, o.mixed, o.neu, o.cls);
     }
 };
 
@@ -61,6 +70,7 @@ struct Slot {
     Request req{};
     size_t off = 0;          // arena offset of the block
     int ntiles = 0;
+    int cls = 0;             // size class
     double t_admit = 0;
     double lo = 0, hi = 0;
 };
@@ -124,6 +134,17 @@ struct Group {
     bool dirty = true;        // tile list must be rebuilt
 };
 
+// a size class: its stream, its flags after each batch, and the tile lists of
+// its initial-residual and true-residual launches
+struct ClassState {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_in = nullptr;
+    Scalars *h_sc = nullptr;  // pinned copy of every slot's scalars after a batch
+    TileList init_list, true_list;
+    bool busy = false;        // a batch is in flight
+};
+
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 } // namespace
@@ -131,24 +152,24 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct poisson_server {
     size_t budget = 0;
     int max_slots = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the caller's stream (inputs are written there)
     hipStream_t cap_stream = nullptr;
     bool dev = false;
     bool use_graph = true;
+    int nclasses = 3;               // size classes, each on a stream of its own
     char *arena_base = nullptr;
     Arena arena;
     size_t in_use = 0, peak = 0;
     Prob *d_probs = nullptr, *h_probs = nullptr;
-    Scalars *d_sc = nullptr, *h_sc = nullptr;
+    Scalars *d_sc = nullptr;
     std::vector<Slot> slots;
     std::deque<Request> queue;
     std::map<uint64_t, Result> results;
     std::map<PlanKey, Group> groups;
-    TileList init_list, true_list;
+    ClassState cls[MAX_CLASSES];
     uint64_t next_ticket = 1;
     long steps = 0;
-    double busy_ms = 0;       // device time spent in steps
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    double busy_ms = 0;       // device time of all batches, summed over the classes
 };
 
 namespace {
@@ -167,18 +188,40 @@ int ensure_dev(poisson_server *s)
     HIPCHK(hipHostMalloc(&s->h_probs, s->max_slots * sizeof(Prob), hipHostMallocDefault));
     HIPCHK(hipMalloc(&s->d_sc, s->max_slots * sizeof(Scalars)));
     HIPCHK(hipMemset(s->d_sc, 0, s->max_slots * sizeof(Scalars)));
-    HIPCHK(hipHostMalloc(&s->h_sc, s->max_slots * sizeof(Scalars), hipHostMallocDefault));
     memset(s->h_probs, 0, s->max_slots * sizeof(Prob));
-    memset(s->h_sc, 0, s->max_slots * sizeof(Scalars));
-    HIPCHK(hipEventCreate(&s->ev_a));
-    HIPCHK(hipEventCreate(&s->ev_b));
+    for (int c = 0; c < s->nclasses; ++c) {
+        ClassState &k = s->cls[c];
+        // one class runs on the caller's stream; several run on streams of their
+        // own, all at the default priority
+        if (s->nclasses == 1) k.stream = s->stream;
+        else HIPCHK(hipStreamCreateWithFlags(&k.stream, hipStreamNonBlocking));
+        k.own_stream = s->nclasses > 1;
+        HIPCHK(hipEventCreate(&k.ev_a));
+        HIPCHK(hipEventCreate(&k.ev_b));
+        HIPCHK(hipEventCreateWithFlags(&k.ev_in, hipEventDisableTiming));
+        HIPCHK(hipHostMalloc(&k.h_sc, s->max_slots * sizeof(Scalars), hipHostMallocDefault));
+        memset(k.h_sc, 0, s->max_slots * sizeof(Scalars));
+    }
     s->dev = true;
     return POISSON_OK;
 }
 
-// upload a tile list, growing its device arrays if needed; returns whether the
-// device arrays moved (graphs that captured them must be re-captured)
-int upload_tiles(poisson_server *s, TileList &t, bool &moved)
+// size class of a request by its unknowns: small grids get classes of their own,
+// so that their batches are not paced by the largest grids'
+int class_of(const poisson_server *s, const Request &r)
+{
+    static const double bounds[MAX_CLASSES][MAX_CLASSES - 1] = {
+        {0, 0, 0}, {96.0 * 96 * 96, 0, 0}, {64.0 * 64 * 64, 160.0 * 160 * 160, 0},
+        {48.0 * 48 * 48, 96.0 * 96 * 96, 192.0 * 192 * 192}};
+    const double N = (double)r.nx * r.ny * r.nz;
+    int c = 0;
+    while (c < s->nclasses - 1 && N > bounds[s->nclasses - 1][c]) ++c;
+    return c;
+}
+
+// upload a tile list on stream st, growing its device arrays if needed; returns
+// whether the device arrays moved (graphs that captured them must be re-captured)
+int upload_tiles(hipStream_t st, TileList &t, bool &moved)
 {
     moved = false;
     const int n = (int)t.h_prob.size();
@@ -195,14 +238,13 @@ int upload_tiles(poisson_server *s, TileList &t, bool &moved)
     }
     t.count = n;
     if (n) {
-        HIPCHK(hipMemcpyAsync(t.d_prob, t.h_prob.data(), n * sizeof(int), hipMemcpyHostToDevice,
-                              s->stream));
+        HIPCHK(hipMemcpyAsync(t.d_prob, t.h_prob.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(t.d_local, t.h_local.data(), n * sizeof(int), hipMemcpyHostToDevice,
-                              s->stream));
+                              st));
     }
-    HIPCHK(hipMemcpyAsync(t.d_count, &t.count, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(t.d_count, &t.count, sizeof(int), hipMemcpyHostToDevice, st));
     // the host vectors are the source of async copies: keep them until the copy ran
-    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipStreamSynchronize(st));
     return POISSON_OK;
 }
 
@@ -249,31 +291,33 @@ Work group_work(const poisson_server *s, const PlanKey &k, const Group &g, int c
     return w;
 }
 
-int finish_requests(poisson_server *s, const std::vector<int> &ids)
+// retire finished requests of class c (its stream is idle): true residuals in one
+// launch, statistics, arena block and slot freed
+int finish_requests(poisson_server *s, int c, const std::vector<int> &ids)
 {
     if (ids.empty()) return POISSON_OK;
+    ClassState &k = s->cls[c];
     for (int id : ids) {
         const Slot &sl = s->slots[id];
-        if (s->h_sc[id].zero_x)
+        if (k.h_sc[id].zero_x)
             HIPCHK(hipMemsetAsync(sl.req.x, 0, (size_t)sl.req.nx * sl.req.ny * sl.req.nz * 8,
-                                  s->stream));
+                                  k.stream));
     }
-    // true residual of every retiring request in one launch
-    list_tiles(s, s->true_list, ids);
+    list_tiles(s, k.true_list, ids);
     bool moved;
     int rc;
-    if ((rc = upload_tiles(s, s->true_list, moved)) != POISSON_OK) return rc;
-    launch_stencil(S_TRUE, false, false, work_of(s, s->true_list),
-                   std::min(GRID, std::max(8, s->true_list.count)), s->stream,
+    if ((rc = upload_tiles(k.stream, k.true_list, moved)) != POISSON_OK) return rc;
+    launch_stencil(S_TRUE, false, false, work_of(s, k.true_list),
+                   std::min(GRID, std::max(8, k.true_list.count)), k.stream,
                    KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(s->h_sc, s->d_sc, s->max_slots * sizeof(Scalars), hipMemcpyDeviceToHost,
-                          s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpyAsync(k.h_sc, s->d_sc, s->max_slots * sizeof(Scalars), hipMemcpyDeviceToHost,
+                          k.stream));
+    HIPCHK(hipStreamSynchronize(k.stream));
     const double t = now_ms();
     for (int id : ids) {
         Slot &sl = s->slots[id];
-        const Scalars &sc = s->h_sc[id];
+        const Scalars &sc = k.h_sc[id];
         Result r;
         memset(&r.st, 0, sizeof(r.st));
         r.status = sc.status;
@@ -299,7 +343,8 @@ int finish_requests(poisson_server *s, const std::vector<int> &ids)
         s->arena.release(sl.off, sl.req.footprint);
         s->in_use -= sl.req.footprint;
         sl.active = false;
-        for (auto &g : s->groups) g.second.dirty = true;
+        for (auto &g : s->groups)
+            if (g.first.cls == c) g.second.dirty = true;
     }
     return POISSON_OK;
 }
@@ -322,34 +367,114 @@ int capture_group(poisson_server *s, const PlanKey &k, Group &g)
     return POISSON_OK;
 }
 
+bool has_work(const poisson_server *s, int c)
+{
+    for (const Slot &sl : s->slots)
+        if (sl.active && sl.cls == c) return true;
+    for (const Request &r : s->queue)
+        if (class_of(s, r) == c) return true;
+    return false;
+}
+
+int round_impl(poisson_server *s, int iters, int &progress);
+
+// Mark the classes whose batch has finished as idle; with `wait`, first wait
+// until at least one busy class has finished.
+int poll_classes(poisson_server *s, bool wait)
+{
+    for (;;) {
+        bool any_busy = false, finished = false;
+        for (int c = 0; c < s->nclasses; ++c) {
+            ClassState &k = s->cls[c];
+            if (!k.busy) continue;
+            const hipError_t q = hipEventQuery(k.ev_b);
+            if (q == hipSuccess) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, k.ev_a, k.ev_b));
+                s->busy_ms += ms;
+                k.busy = false;
+                finished = true;
+            } else if (q != hipErrorNotReady) {
+                HIPCHK(q);
+            } else {
+                any_busy = true;
+            }
+        }
+        if (!wait || finished || !any_busy) return POISSON_OK;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// One scheduling round. Each size class runs its batches on its own stream: a
+// class whose last batch has finished retires its finished requests, admits
+// queued requests of its class and starts its next batch of `iters` iterations,
+// while the other classes' batches keep running. If every class that has work
+// is still running, or nothing could be done (a queued request waits for arena
+// space or a slot that a running class holds), wait for the first batch to
+// finish and try again.
 int step_impl(poisson_server *s, int iters)
 {
     int rc;
     if ((rc = ensure_dev(s)) != POISSON_OK) return rc;
-    // 1. retire requests whose flag was seen at the end of a previous step
-    std::vector<int> done;
-    for (int i = 0; i < s->max_slots; ++i)
-        if (s->slots[i].active && s->h_sc[i].done) done.push_back(i);
-    if ((rc = finish_requests(s, done)) != POISSON_OK) return rc;
+    for (bool wait = false;; wait = true) {
+        if ((rc = poll_classes(s, wait)) != POISSON_OK) return rc;
+        bool ready = false, any_busy = false;
+        for (int c = 0; c < s->nclasses; ++c) {
+            if (s->cls[c].busy) any_busy = true;
+            else if (has_work(s, c)) ready = true;
+        }
+        if (!ready) {
+            if (any_busy) continue;              // wait for a batch
+            break;                               // nothing running, nothing queued
+        }
+        int progress = 0;
+        if ((rc = round_impl(s, iters, progress)) != POISSON_OK) return rc;
+        if (progress || !any_busy) break;
+    }
+    int active = 0;
+    for (const Slot &sl : s->slots) active += sl.active;
+    return active + (int)s->queue.size();
+}
 
-    // 2. admit in arrival order while a slot is free and the block fits
-    std::vector<int> admitted;
-    while (!s->queue.empty()) {
+// retire, admit and launch for every idle class; progress counts what happened
+int round_impl(poisson_server *s, int iters, int &progress)
+{
+    int rc;
+    // 2. retire what the idle classes' last batches finished
+    for (int c = 0; c < s->nclasses; ++c) {
+        ClassState &k = s->cls[c];
+        if (k.busy) continue;
+        std::vector<int> done;
+        for (int i = 0; i < s->max_slots; ++i)
+            if (s->slots[i].active && s->slots[i].cls == c && k.h_sc[i].done) done.push_back(i);
+        if ((rc = finish_requests(s, c, done)) != POISSON_OK) return rc;
+        progress += (int)done.size();
+    }
+    // 3. admit in arrival order into idle classes while a slot is free and the
+    // block fits; a request that does not fit stops admission (no later request
+    // passes it), a request whose class is busy waits for that class
+    std::vector<int> admitted[MAX_CLASSES];
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        const int c = class_of(s, *it);
+        if (s->cls[c].busy) {
+            ++it;
+            continue;
+        }
         int id = -1;
         for (int i = 0; i < s->max_slots; ++i)
             if (!s->slots[i].active) { id = i; break; }
         if (id < 0) break;
-        Request &rq = s->queue.front();
         size_t off;
-        if (!s->arena.alloc(rq.footprint, off)) break;
+        if (!s->arena.alloc(it->footprint, off)) break;
         Slot &sl = s->slots[id];
         sl.active = true;
-        sl.req = rq;
+        sl.req = *it;
         sl.off = off;
+        sl.cls = c;
         sl.t_admit = now_ms();
-        s->in_use += rq.footprint;
+        s->in_use += it->footprint;
         s->peak = std::max(s->peak, s->in_use);
-        s->queue.pop_front();
+        it = s->queue.erase(it);
         // descriptor: workspace, partials, scalars in the arena block
         PlanOpts o;
         Prob &p = s->h_probs[id];
@@ -367,70 +492,76 @@ int step_impl(poisson_server *s, int iters)
         p.hist = nullptr;
         p.hist_iters = 0;
         HIPCHK(hipMemcpyAsync(s->d_probs + id, s->h_probs + id, sizeof(Prob), hipMemcpyHostToDevice,
-                              s->stream));
-        admitted.push_back(id);
-        s->groups[PlanKey{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0}].dirty = true;
+                              s->cls[c].stream));
+        admitted[c].push_back(id);
+        s->groups[PlanKey{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0, c}].dirty = true;
     }
-    HIPCHK(hipEventRecord(s->ev_a, s->stream));
-    // 3. initial residuals of the new requests, one launch
-    if (!admitted.empty()) {
-        list_tiles(s, s->init_list, admitted);
-        bool moved;
-        if ((rc = upload_tiles(s, s->init_list, moved)) != POISSON_OK) return rc;
-        launch_stencil(S_INIT, false, false, work_of(s, s->init_list),
-                       std::min(GRID, std::max(8, s->init_list.count)), s->stream,
-                       KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
-        HIPCHK(hipGetLastError());
-    }
-    // 4. advance every running request, one batched sequence per plan group
-    for (auto &kv : s->groups) {
-        Group &g = kv.second;
-        if (g.dirty) {
-            std::vector<int> ids;
-            for (int i = 0; i < s->max_slots; ++i) {
-                const Slot &sl = s->slots[i];
-                const PlanKey k{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0};
-                if (sl.active && !(k < kv.first) && !(kv.first < k)) ids.push_back(i);
-            }
-            list_tiles(s, g.tiles, ids);
-            list_pair_tiles(s, g.ptiles, ids, kv.first.mixed == POISSON_MIXED);
-            bool moved, pmoved;
-            if ((rc = upload_tiles(s, g.tiles, moved)) != POISSON_OK) return rc;
-            if ((rc = upload_tiles(s, g.ptiles, pmoved)) != POISSON_OK) return rc;
-            if ((moved || pmoved) && g.graph) g.graph_cap = -1;
-            g.dirty = false;
+    // 4. every idle class with running requests starts its next batch
+    bool launched = false;
+    for (int c = 0; c < s->nclasses; ++c) {
+        ClassState &k = s->cls[c];
+        if (k.busy) continue;
+        bool any = false;
+        for (const Slot &sl : s->slots) any = any || (sl.active && sl.cls == c);
+        if (!any) continue;
+        if (!admitted[c].empty() && k.own_stream) {
+            // the new requests' rhs and x were written on the caller's stream
+            HIPCHK(hipEventRecord(k.ev_in, s->stream));
+            HIPCHK(hipStreamWaitEvent(k.stream, k.ev_in, 0));
         }
-        if (g.tiles.count == 0) continue;
-        if (s->use_graph) {
-            if ((g.graph_cap != g.tiles.cap || g.pgraph_cap != g.ptiles.cap) &&
-                (rc = capture_group(s, kv.first, g)) != POISSON_OK)
-                return rc;
-            for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(g.graph, s->stream));
-        } else {
-            const Work w = group_work(s, kv.first, g, g.tiles.count);
-            for (int i = 0; i < iters; ++i)
-                enqueue_iteration(w, GRID, s->stream, kv.first.pc, kv.first.deg, kv.first.mixed != 0,
-                                  1);
+        HIPCHK(hipEventRecord(k.ev_a, k.stream));
+        if (!admitted[c].empty()) {
+            // initial residuals of the new requests, one launch
+            list_tiles(s, k.init_list, admitted[c]);
+            bool moved;
+            if ((rc = upload_tiles(k.stream, k.init_list, moved)) != POISSON_OK) return rc;
+            launch_stencil(S_INIT, false, false, work_of(s, k.init_list),
+                           std::min(GRID, std::max(8, k.init_list.count)), k.stream,
+                           KArgs{V_X, 0, 0, 0, 0, 0, 0, 0});
             HIPCHK(hipGetLastError());
         }
+        for (auto &kv : s->groups) {
+            if (kv.first.cls != c) continue;
+            Group &g = kv.second;
+            if (g.dirty) {
+                std::vector<int> ids;
+                for (int i = 0; i < s->max_slots; ++i) {
+                    const Slot &sl = s->slots[i];
+                    const PlanKey key{sl.req.pc, sl.req.deg, sl.req.prec, sl.req.bc != 0, sl.cls};
+                    if (sl.active && !(key < kv.first) && !(kv.first < key)) ids.push_back(i);
+                }
+                list_tiles(s, g.tiles, ids);
+                list_pair_tiles(s, g.ptiles, ids, kv.first.mixed == POISSON_MIXED);
+                bool moved, pmoved;
+                if ((rc = upload_tiles(k.stream, g.tiles, moved)) != POISSON_OK) return rc;
+                if ((rc = upload_tiles(k.stream, g.ptiles, pmoved)) != POISSON_OK) return rc;
+                if ((moved || pmoved) && g.graph) g.graph_cap = -1;
+                g.dirty = false;
+            }
+            if (g.tiles.count == 0) continue;
+            if (s->use_graph) {
+                if ((g.graph_cap != g.tiles.cap || g.pgraph_cap != g.ptiles.cap) &&
+                    (rc = capture_group(s, kv.first, g)) != POISSON_OK)
+                    return rc;
+                for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(g.graph, k.stream));
+            } else {
+                const Work w = group_work(s, kv.first, g, g.tiles.count);
+                for (int i = 0; i < iters; ++i)
+                    enqueue_iteration(w, GRID, k.stream, kv.first.pc, kv.first.deg,
+                                      kv.first.mixed != 0, 1);
+                HIPCHK(hipGetLastError());
+            }
+        }
+        // the class's flags after the batch, read when the batch is seen finished
+        HIPCHK(hipMemcpyAsync(k.h_sc, s->d_sc, s->max_slots * sizeof(Scalars),
+                              hipMemcpyDeviceToHost, k.stream));
+        HIPCHK(hipEventRecord(k.ev_b, k.stream));
+        k.busy = true;
+        launched = true;
+        ++progress;
     }
-    HIPCHK(hipEventRecord(s->ev_b, s->stream));
-    // 5. read every request's flags
-    HIPCHK(hipMemcpyAsync(s->h_sc, s->d_sc, s->max_slots * sizeof(Scalars), hipMemcpyDeviceToHost,
-                          s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b));
-    s->busy_ms += ms;
-    ++s->steps;
-    // 6. retire what finished during this step, so poll reports it now
-    done.clear();
-    for (int i = 0; i < s->max_slots; ++i)
-        if (s->slots[i].active && s->h_sc[i].done) done.push_back(i);
-    if ((rc = finish_requests(s, done)) != POISSON_OK) return rc;
-    int active = 0;
-    for (const Slot &sl : s->slots) active += sl.active;
-    return active + (int)s->queue.size();
+    if (launched) ++s->steps;
+    return POISSON_OK;
 }
 
 } // namespace
@@ -459,6 +590,13 @@ int poisson_server_set_option(poisson_server *s, int key, double value)
     if (key == POISSON_SERVER_OPT_USE_GRAPH) {
         if (value != 0 && value != 1) return POISSON_ERR_ARG;
         s->use_graph = value != 0;
+        return POISSON_OK;
+    }
+    if (key == POISSON_SERVER_OPT_SIZE_CLASSES) {
+        // fixed once the server has started (its streams exist)
+        if (s->dev || value < 1 || value > MAX_CLASSES || value != std::floor(value))
+            return POISSON_ERR_ARG;
+        s->nclasses = (int)value;
         return POISSON_OK;
     }
     return POISSON_ERR_ARG;
@@ -561,6 +699,8 @@ void poisson_server_destroy(poisson_server *s)
     if (!s) return;
     if (s->dev) {
         (void)hipStreamSynchronize(s->stream);
+        for (int c = 0; c < s->nclasses; ++c)
+            if (s->cls[c].stream) (void)hipStreamSynchronize(s->cls[c].stream);
         for (auto &kv : s->groups) {
             if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
             if (kv.second.graph_src) (void)hipGraphDestroy(kv.second.graph_src);
@@ -568,16 +708,21 @@ void poisson_server_destroy(poisson_server *s)
                 for (int *p : {t->d_prob, t->d_local, t->d_count})
                     if (p) (void)hipFree(p);
         }
-        for (TileList *t : {&s->init_list, &s->true_list})
-            for (int *p : {t->d_prob, t->d_local, t->d_count})
-                if (p) (void)hipFree(p);
+        for (int c = 0; c < s->nclasses; ++c) {
+            ClassState &k = s->cls[c];
+            for (TileList *t : {&k.init_list, &k.true_list})
+                for (int *p : {t->d_prob, t->d_local, t->d_count})
+                    if (p) (void)hipFree(p);
+            if (k.h_sc) (void)hipHostFree(k.h_sc);
+            if (k.ev_a) (void)hipEventDestroy(k.ev_a);
+            if (k.ev_b) (void)hipEventDestroy(k.ev_b);
+            if (k.ev_in) (void)hipEventDestroy(k.ev_in);
+            if (k.own_stream && k.stream) (void)hipStreamDestroy(k.stream);
+        }
         (void)hipFree(s->arena_base);
         (void)hipFree(s->d_probs);
         (void)hipFree(s->d_sc);
         (void)hipHostFree(s->h_probs);
-        (void)hipHostFree(s->h_sc);
-        (void)hipEventDestroy(s->ev_a);
-        (void)hipEventDestroy(s->ev_b);
         (void)hipStreamDestroy(s->cap_stream);
     }
     delete s;

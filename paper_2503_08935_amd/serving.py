@@ -3,8 +3,9 @@
 A synthetic stream of Poisson solves arrives in real time; each request is
 submitted when it arrives (its right-hand side generated on the device with the
 counter-based generator), and the loop keeps calling poisson_server_step, which
-retires finished requests, admits queued ones by HBM footprint and advances
-all running ones together. Latency is arrival to observed completion.
+retires finished requests, admits queued ones by HBM footprint and advances the
+running ones in batches, one size class per stream. Latency is arrival to
+observed completion.
 
 Stream recipe (seeded, host side): request i has grid edge
 n_i = sizes[floor(len(sizes) * u_i)] with u_i the i-th uniform of
@@ -34,13 +35,14 @@ def make_stream(n_requests, sizes, rate, seed):
 def run_stream(n_requests=2000, sizes=(32, 48, 64, 96, 128, 192, 256), rate=200.0, seed=5,
                precond=B.PC_CHEBYSHEV, degree=4, precision=B.MIXED, tol=1e-8, maxit=5000,
                budget_bytes=64 << 30, max_slots=64, iters=4, queue_extra=16, use_graph=True,
-               progress=None):
+               size_classes=None, progress=None):
     """Run the stream; returns a dict of latency / throughput metrics."""
     import torch
     dev = torch.device("cuda:0")
     edges, arrivals = make_stream(n_requests, sizes, rate, seed)
     stream = torch.cuda.Stream()
-    srv = B.Server(budget_bytes, max_slots, stream=stream, use_graph=use_graph)
+    srv = B.Server(budget_bytes, max_slots, stream=stream, use_graph=use_graph,
+                   size_classes=size_classes)
     waiting = collections.deque()           # arrived, not yet submitted
     inflight = {}                           # ticket -> (request id, rhs, x)
     lat = np.full(n_requests, np.nan)
@@ -92,6 +94,10 @@ def run_stream(n_requests=2000, sizes=(32, 48, 64, 96, 128, 192, 256), rate=200.
     srv.close()
     unknowns = edges.astype(np.float64) ** 3
     ms = lat * 1e3
+    by_size = {int(n): {"count": int((edges == n).sum()),
+                        "p50_ms": float(np.percentile(ms[edges == n], 50)),
+                        "p99_ms": float(np.percentile(ms[edges == n], 99))}
+               for n in sorted(set(int(e) for e in edges))}
     return {
         "requests": n_requests, "rate_per_s": rate, "sizes": list(sizes), "degree": degree,
         "precision": "mixed" if precision == B.MIXED else "fp64", "tol": tol,
@@ -99,7 +105,10 @@ def run_stream(n_requests=2000, sizes=(32, 48, 64, 96, 128, 192, 256), rate=200.
         "max_ms": float(ms.max()), "mean_ms": float(ms.mean()),
         "makespan_s": makespan, "solves_per_s": n_requests / makespan,
         "unknown_iters_per_s": float((unknowns * iters_done).sum() / makespan),
+        # device time of the batches summed over the size classes (whose batches
+        # overlap), over the makespan: above 1 when classes ran side by side
         "utilization": info["busy_ms"] / (makespan * 1e3),
+        "latency_by_grid": by_size,
         "all_ok": bool(np.all(status == B.OK)), "max_relres_true": float(relres.max()),
         "mean_iterations": float(iters_done.mean()), "peak_arena_bytes": info["peak_bytes"],
         "budget_bytes": info["budget_bytes"], "steps": info["steps"],

@@ -195,3 +195,75 @@ def test_neumann_and_dirichlet_requests_in_one_batch(gpu):
         ref = oracle.bicgstab(f, h, pc=OPC[pc], degree=deg, mixed=prec == P.MIXED, tol=tol,
                               maxit=5000, bc=bc)
         assert ref.iterations == it1 and np.array_equal(xs, ref.x), i
+
+
+def test_large_requests_in_the_mix(gpu):
+    """A 256^3 and a 128^3 request beside small ones (each size class on its own
+    stream): every result equals the solve done alone; n <= 128 also the oracle's."""
+    reqs = [
+        ((256, 256, 256), 41, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+        ((32, 32, 32), 42, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+        ((128, 128, 128), 43, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+        ((48, 48, 48), 44, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+        ((96, 96, 96), 45, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8),
+    ]
+    budget = sum(P.footprint(r[0], r[2], r[3], r[4]) for r in reqs)
+    out, info = run_server(reqs, budget, slots=8, late=(3,))
+    assert info["completed"] == len(reqs) and info["peak_bytes"] <= budget
+    for i, (shape, seed, pc, deg, prec, tol) in enumerate(reqs):
+        st, stats, x = out[i]
+        st1, it1, x1 = alone(shape, seed, pc, deg, prec, tol)
+        assert st == st1 == P.OK and stats["iterations"] == it1, i
+        assert np.array_equal(x, x1), i
+        if shape[0] <= 128:
+            ref = oracle.bicgstab(rhs_of(shape, seed), workloads.spacing(shape[0]), pc=OPC[pc],
+                                  degree=deg, mixed=True, tol=tol, maxit=5000)
+            assert ref.iterations == it1 and np.array_equal(x, ref.x), i
+
+
+@pytest.mark.parametrize("classes", [1, 2, 4])
+def test_size_classes_change_no_bits(gpu, classes):
+    reqs = REQS[:6]
+    budget = 2 * max(P.footprint(r[0], r[2], r[3], r[4]) for r in reqs)
+    base, _ = run_server(reqs, budget, 3)
+    got = {}
+    with P.Server(budget, 3, size_classes=classes) as srv:
+        bufs, tickets = {}, {}
+        for i, (shape, seed, pc, deg, prec, tol) in enumerate(reqs):
+            b = torch.from_numpy(rhs_of(shape, seed)).to("cuda:0")
+            x = torch.zeros_like(b)
+            bufs[i] = (b, x)
+            tickets[i] = srv.submit(b, x, shape, workloads.spacing(shape[0]), pc, deg, prec, tol,
+                                    5000)
+        for _ in range(100000):
+            if srv.step(3) == 0:
+                break
+        for i, t in tickets.items():
+            st, stats = srv.poll(t)
+            got[i] = (st, stats["iterations"], bufs[i][1].cpu().numpy())
+    for i in range(len(reqs)):
+        assert got[i][0] == base[i][0] and got[i][1] == base[i][1]["iterations"]
+        assert np.array_equal(got[i][2], base[i][2]), i
+
+
+def test_server_releases_device_memory(gpu):
+    """Creating, running and destroying servers leaves the device's free memory
+    where it was (tile lists, arenas, descriptors and streams are all freed)."""
+    shape = (40, 36, 30)
+    b = torch.from_numpy(workloads.uniform_grid(3, shape)).to("cuda:0")
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+
+    def one_server():
+        with P.Server(1 << 28, 4) as srv:
+            t = srv.submit(b, x, shape, workloads.spacing(40), P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+            while srv.step(4):
+                pass
+            assert srv.poll(t)[0] == P.OK
+        torch.cuda.synchronize()
+
+    one_server()   # first use: code objects and runtime pools
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(5):
+        one_server()
+    assert torch.cuda.mem_get_info()[0] == free0
