@@ -1392,7 +1392,6 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
     // own position in LDS (held row 0); row e adds e*PW. The lane's x
     // neighbour across the wave edge: column cx-1 for lane 0, cx+1 for lane 63.
     const int lown = lidx(trow(0), cx);
-    const int lpatch = lown + (lane == 0 ? -1 : (lane == 63 ? 1 : 0));
     // the row across the wave's inner boundary, at the lane's column
     const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
 
@@ -1568,9 +1567,9 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T c = cen[e];
-                const T pv = lane_prev(c), nv = lane_next(c);
-                const T patch = ys[lpatch + e * L::PW];
-                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                // x neighbours from the LDS plane, which holds every column of the
+                // tile and its halo (no lane shifts, no edge patches)
+                const T xm = ys[lown - 1 + e * L::PW], xp = ys[lown + 1 + e * L::PW];
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
@@ -1634,9 +1633,7 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 #pragma unroll
             for (int e = EOWN; e < EOWN + PR; ++e) {
                 const T c = wcen[e];
-                const T pv = lane_prev(c), nv = lane_next(c);
-                const T patch = ws[lpatch + e * L::PW];
-                T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                T xm = ws[lown - 1 + e * L::PW], xp = ws[lown + 1 + e * L::PW];
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = wcen[e - 1];
@@ -1861,7 +1858,6 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
     const bool ook = xin && jo >= 0 && jo < ny;
     const unsigned ooff = offy(ic, clampi(jo, ny));
     const int lown = lidx(trow(0), cx);
-    const int lpatch = lown + (lane == 0 ? -1 : (lane == 63 ? 1 : 0));
     const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
 
     // Halo lanes. Lanes 0-15 (left) and 32-47 (right) hold the column one out
@@ -2058,9 +2054,9 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T c = cen[e];
-                const T pv = lane_prev(c), nv = lane_next(c);
-                const T patch = ys[lpatch + e * L::PW];
-                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                // x neighbours from the LDS plane, which holds every column of the
+                // tile and its halo (no lane shifts, no edge patches)
+                const T xm = ys[lown - 1 + e * L::PW], xp = ys[lown + 1 + e * L::PW];
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
@@ -2112,9 +2108,9 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 #pragma unroll
             for (int e = L2LO; e < L2HI; ++e) {
                 const T c = cen1[e];
-                const T pv = lane_prev(c), nv = lane_next(c);
-                const T patch = w1s[lpatch + e * L::PW];
-                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                // x neighbours from the LDS plane, which holds every column of the
+                // tile and its halo (no lane shifts, no edge patches)
+                const T xm = w1s[lown - 1 + e * L::PW], xp = w1s[lown + 1 + e * L::PW];
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = cen1[e - 1];
@@ -2161,9 +2157,9 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 #pragma unroll
             for (int e = OWNLO; e < OWNHI; ++e) {
                 const T c = cen2[e];
-                const T pv = lane_prev(c), nv = lane_next(c);
-                const T patch = w2s[lpatch + e * L::PW];
-                const T xm = lane == 0 ? patch : pv, xp = lane == 63 ? patch : nv;
+                // x neighbours from the LDS plane, which holds every column of the
+                // tile and its halo (no lane shifts, no edge patches)
+                const T xm = w2s[lown - 1 + e * L::PW], xp = w2s[lown + 1 + e * L::PW];
                 T ym, yp;
                 if constexpr (TOP) {
                     ym = cen2[e - 1];
