@@ -354,75 +354,113 @@ static void apply_A_f32(int nx, int ny, int nz, float ih2, int block, unsigned b
 }
 
 /* ------------------------------------------------------------------------- */
-/* Chebyshev iteration (Alg. 2) for A x = b on the interval [lo, hi], with   */
-/* theta, delta, sigma of eq. chebyshevQuantities. The degree m is the       */
-/* number of iterations of the algorithm (iterMax): m = 0 returns z = b/theta */
-/* and m = 1 returns y; for m >= 2 the loop runs i = 2..m and returns w.      */
+/* Chebyshev iteration (Alg. 2) for A x = b on the interval [lo, hi].        */
+/*                                                                           */
+/* With theta and delta the centre and half-width of the interval and        */
+/* sigma = theta/delta (eq. chebyshevQuantities), the iteration produces     */
+/* iterates X_0, X_1, ..., X_m:                                              */
+/*   X_0 = b / theta,                                                        */
+/*   X_1 = (2 rho_1 / delta) (2 b - (A b) / theta),                          */
+/*   X_i = rho_i ((2 sigma X_{i-1} + (2/delta)(b - A X_{i-1}))              */
+/*                - rho_{i-1} X_{i-2})                    for i >= 2,        */
+/* where rho_0 = 1/sigma and rho_i = 1/(2 sigma - rho_{i-1}) are the ratios  */
+/* T_{i-1}(sigma)/T_i(sigma) of Chebyshev polynomials, from their three-term */
+/* recurrence. The degree m (the algorithm's iteration count) selects X_m.   */
+/* The coefficients are tabulated once; each iterate is one generic step.    */
 /* block > 0 uses the block-diagonal operator (BJ(CI) / GNoComm(CI)).         */
 /* ------------------------------------------------------------------------- */
+#define CHEB_MAXM 64
+
+typedef struct {
+    double theta, delta, sigma;
+    double g1;                   /* 2 rho_1 / delta, the scale of X_1 */
+    double two_sigma, two_over_delta;
+    double rho[CHEB_MAXM + 1];   /* rho_0 .. rho_m */
+} cheb_coef;
+
+static void cheb_coef_make(double lo, double hi, int m, cheb_coef *c)
+{
+    c->theta = (hi + lo) / 2.0;
+    c->delta = (hi - lo) / 2.0;
+    c->sigma = c->theta / c->delta;
+    c->rho[0] = 1.0 / c->sigma;
+    const int top = m > 1 ? m : 1;
+    for (int i = 1; i <= top; ++i) c->rho[i] = 1.0 / (2.0 * c->sigma - c->rho[i - 1]);
+    c->g1 = 2.0 * c->rho[1] / c->delta;
+    c->two_sigma = 2.0 * c->sigma;
+    c->two_over_delta = 2.0 / c->delta;
+}
+
+/* X_i from X_{i-1} (prev), A X_{i-1} (aprev) and X_{i-2} (prev2), FP64 */
+static void cheb_iterate(size_t N, const cheb_coef *c, int i, const double *b, const double *prev,
+                         const double *aprev, const double *prev2, double *out)
+{
+    const double r = c->rho[i], rm = c->rho[i - 1];
+    for (size_t q = 0; q < N; ++q)
+        out[q] = r * (c->two_sigma * prev[q] + c->two_over_delta * (b[q] - aprev[q]) - rm * prev2[q]);
+}
+
 void orc_chebyshev_bc(int nx, int ny, int nz, double h, int block, unsigned bc, double lo,
                       double hi, int m, const double *b, double *x)
 {
-    size_t N = (size_t)nx * ny * nz;
-    double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
-    double rho_old = 1.0 / sigma;
-    double rho_cur = 1.0 / (2.0 * sigma - rho_old);
-    if (m == 0) {
-        for (size_t q = 0; q < N; ++q) x[q] = b[q] / theta;
-        return;
+    const size_t N = (size_t)nx * ny * nz;
+    if (m < 0 || m > CHEB_MAXM) return;
+    cheb_coef c;
+    cheb_coef_make(lo, hi, m, &c);
+    double *X[3], *AX = malloc(N * 8);
+    for (int k = 0; k < 3; ++k) X[k] = malloc(N * 8);
+    for (size_t q = 0; q < N; ++q) X[0][q] = b[q] / c.theta;
+    if (m >= 1) {
+        orc_apply_A_bc(nx, ny, nz, h, block, bc, b, AX);
+        for (size_t q = 0; q < N; ++q) X[1][q] = c.g1 * (2.0 * b[q] - AX[q] / c.theta);
     }
-    double *z = malloc(N * 8), *y = malloc(N * 8), *w = malloc(N * 8), *Av = malloc(N * 8);
-    for (size_t q = 0; q < N; ++q) z[q] = b[q] / theta;
-    orc_apply_A_bc(nx, ny, nz, h, block, bc, b, Av);
-    for (size_t q = 0; q < N; ++q) y[q] = 2.0 * rho_cur / delta * (2.0 * b[q] - Av[q] / theta);
     for (int i = 2; i <= m; ++i) {
-        rho_old = rho_cur;
-        rho_cur = 1.0 / (2.0 * sigma - rho_old);
-        orc_apply_A_bc(nx, ny, nz, h, block, bc, y, Av);
-        for (size_t q = 0; q < N; ++q)
-            w[q] = rho_cur * (2.0 * sigma * y[q] + 2.0 / delta * (b[q] - Av[q]) - rho_old * z[q]);
-        double *tmp = z; z = y; y = w; w = tmp; /* z <- y, y <- w */
+        orc_apply_A_bc(nx, ny, nz, h, block, bc, X[(i - 1) % 3], AX);
+        cheb_iterate(N, &c, i, b, X[(i - 1) % 3], AX, X[(i - 2) % 3], X[i % 3]);
     }
-    memcpy(x, y, N * 8); /* after the last rotation y holds w */
-    free(z); free(y); free(w); free(Av);
+    memcpy(x, X[m % 3], N * 8);
+    for (int k = 0; k < 3; ++k) free(X[k]);
+    free(AX);
 }
 
-/* Mixed precision: the same steps with every scalar coefficient computed in
-   FP64 and rounded once to FP32, the input rounded once to FP32, and all vector
-   arithmetic in FP32. The FP32 result is returned widened (exactly) to FP64. */
+/* Mixed precision: the same iterates with every coefficient computed in FP64
+   and rounded once to FP32, the input rounded once to FP32, and all vector
+   arithmetic in FP32. X_m is returned widened (exactly) to FP64. */
+static void cheb_iterate_f32(size_t N, float r, float rm, float two_sigma, float two_over_delta,
+                             const float *b, const float *prev, const float *aprev,
+                             const float *prev2, float *out)
+{
+    for (size_t q = 0; q < N; ++q)
+        out[q] = r * (two_sigma * prev[q] + two_over_delta * (b[q] - aprev[q]) - rm * prev2[q]);
+}
+
 void orc_chebyshev_f32_bc(int nx, int ny, int nz, double h, int block, unsigned bc, double lo,
                           double hi, int m, const double *b, double *x)
 {
-    size_t N = (size_t)nx * ny * nz;
-    double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0, sigma = theta / delta;
-    double rho_old = 1.0 / sigma;
-    double rho_cur = 1.0 / (2.0 * sigma - rho_old);
-    float theta_f = (float)theta;
-    float ih2_f = (float)(1.0 / (h * h));
-    float *bf = malloc(N * 4);
+    const size_t N = (size_t)nx * ny * nz;
+    if (m < 0 || m > CHEB_MAXM) return;
+    cheb_coef c;
+    cheb_coef_make(lo, hi, m, &c);
+    const float theta = (float)c.theta, g1 = (float)c.g1;
+    const float two_sigma = (float)c.two_sigma, two_over_delta = (float)c.two_over_delta;
+    const float ih2 = (float)(1.0 / (h * h));
+    float *bf = malloc(N * 4), *X[3], *AX = malloc(N * 4);
+    for (int k = 0; k < 3; ++k) X[k] = malloc(N * 4);
     for (size_t q = 0; q < N; ++q) bf[q] = (float)b[q];
-    if (m == 0) {
-        for (size_t q = 0; q < N; ++q) x[q] = (double)(bf[q] / theta_f);
-        free(bf);
-        return;
+    for (size_t q = 0; q < N; ++q) X[0][q] = bf[q] / theta;
+    if (m >= 1) {
+        apply_A_f32(nx, ny, nz, ih2, block, bc, bf, AX);
+        for (size_t q = 0; q < N; ++q) X[1][q] = g1 * (2.0f * bf[q] - AX[q] / theta);
     }
-    float *z = malloc(N * 4), *y = malloc(N * 4), *w = malloc(N * 4), *Av = malloc(N * 4);
-    for (size_t q = 0; q < N; ++q) z[q] = bf[q] / theta_f;
-    apply_A_f32(nx, ny, nz, ih2_f, block, bc, bf, Av);
-    float c1 = (float)(2.0 * rho_cur / delta);
-    for (size_t q = 0; q < N; ++q) y[q] = c1 * (2.0f * bf[q] - Av[q] / theta_f);
-    float two_sigma = (float)(2.0 * sigma), two_over_delta = (float)(2.0 / delta);
     for (int i = 2; i <= m; ++i) {
-        rho_old = rho_cur;
-        rho_cur = 1.0 / (2.0 * sigma - rho_old);
-        float rc = (float)rho_cur, ro = (float)rho_old;
-        apply_A_f32(nx, ny, nz, ih2_f, block, bc, y, Av);
-        for (size_t q = 0; q < N; ++q)
-            w[q] = rc * (two_sigma * y[q] + two_over_delta * (bf[q] - Av[q]) - ro * z[q]);
-        float *tmp = z; z = y; y = w; w = tmp;
+        apply_A_f32(nx, ny, nz, ih2, block, bc, X[(i - 1) % 3], AX);
+        cheb_iterate_f32(N, (float)c.rho[i], (float)c.rho[i - 1], two_sigma, two_over_delta, bf,
+                         X[(i - 1) % 3], AX, X[(i - 2) % 3], X[i % 3]);
     }
-    for (size_t q = 0; q < N; ++q) x[q] = (double)y[q];
-    free(bf); free(z); free(y); free(w); free(Av);
+    for (size_t q = 0; q < N; ++q) x[q] = (double)X[m % 3][q];
+    for (int k = 0; k < 3; ++k) free(X[k]);
+    free(bf);
+    free(AX);
 }
 
 void orc_chebyshev(int nx, int ny, int nz, double h, int block, double lo, double hi, int m,
@@ -513,90 +551,141 @@ void orc_precond(int nx, int ny, int nz, double h, int precond, int degree, int 
 }
 
 /* ------------------------------------------------------------------------- */
-/* Right-preconditioned Bi-CGSTAB, Alg. 1, with the scalar formulas of Alg. 3 */
-/* (beta = (rho_i alpha_i)/(rho_{i-1} omega_i)). The stopping test          */
-/* ||r|| < tol ||b|| is evaluated on squares: r.r < (tol*tol)*(b.b).          */
+/* Right-preconditioned Bi-CGSTAB (Alg. 1, with the scalar formulas of        */
+/* Alg. 3: beta = (rho_i alpha_i)/(rho_{i-1} omega_i)).                        */
+/*                                                                           */
+/* An iteration has two halves. The first takes a step along the             */
+/* preconditioned direction ph = M^-1 p: alpha makes the new residual        */
+/* s = r - alpha A ph orthogonal to the fixed shadow residual rt. If s is     */
+/* already small the solve ends there (Alg. 1's half step). The second       */
+/* half minimises ||s - omega A sh|| over omega with sh = M^-1 s, moves x    */
+/* along ph and sh, and builds the next direction p from the new residual.   */
+/* Every test compares squared norms: ||r|| < tol ||b|| is evaluated as      */
+/* r.r < (tol*tol)*(b.b).                                                    */
 /* trace (optional, 4*maxit doubles): per iteration alpha, omega, rho_{i-1},  */
 /* and the squared residual norm tested at exit of that iteration.            */
 /* ------------------------------------------------------------------------- */
+typedef struct {
+    size_t N;
+    const pc_t *pc;
+    double *r;           /* residual; holds s between the two halves */
+    double *rt;          /* shadow residual, r_0 */
+    double *p, *ph, *w;  /* direction, M^-1 p, A M^-1 p */
+    double *sh, *t;      /* M^-1 s, A M^-1 s */
+    double rho;          /* rt . r of the current residual */
+} bicg_t;
+
+/* z = M^-1 v (the identity for no preconditioner: z aliases v) */
+static const double *bicg_precond(const bicg_t *S, const double *v, double *buf)
+{
+    if (S->pc->precond == PC_NONE) return v;
+    apply_pc(S->pc, v, buf);
+    return buf;
+}
+
+static void bicg_apply_A(const bicg_t *S, const double *u, double *out)
+{
+    const pc_t *c = S->pc;
+    orc_apply_A_bc(c->nx, c->ny, c->nz, c->h, 0, c->bc, u, out);
+}
+
+/* first half: ph, w = A ph, alpha; r becomes s. Status 0 to go on; *stepped is
+   set once alpha exists and s is formed (r~.w was usable). */
+static int bicg_first_half(bicg_t *S, const double **php, double *alpha, double *ss, int *stepped)
+{
+    const size_t N = S->N;
+    *php = bicg_precond(S, S->p, S->ph);
+    bicg_apply_A(S, *php, S->w);
+    const double d = orc_dot(S->rt, S->w, (int64_t)N);
+    if (!isfinite(d)) return ORC_ERR_NONFINITE;
+    if (d == 0.0) return ORC_ERR_BREAKDOWN;
+    *alpha = S->rho / d;
+    *stepped = 1;
+    for (size_t q = 0; q < N; ++q) S->r[q] = S->r[q] - *alpha * S->w[q];
+    *ss = orc_dot(S->r, S->r, (int64_t)N);
+    return isfinite(*ss) ? 0 : ORC_ERR_NONFINITE;
+}
+
+/* second half: sh, t = A sh, omega; x and r move; returns the new rt.r and r.r.
+   *moved is set once omega exists and x, r have moved */
+static int bicg_second_half(bicg_t *S, double *x, const double *php, double alpha, double *omega,
+                            double *rho_new, double *rr, int *moved)
+{
+    const size_t N = S->N;
+    const double *shp = bicg_precond(S, S->r, S->sh);
+    bicg_apply_A(S, shp, S->t);
+    const double ts = orc_dot(S->t, S->r, (int64_t)N);
+    const double tt = orc_dot(S->t, S->t, (int64_t)N);
+    if (!isfinite(ts) || !isfinite(tt)) return ORC_ERR_NONFINITE;
+    if (tt == 0.0) return ORC_ERR_BREAKDOWN;
+    *omega = ts / tt;
+    *moved = 1;
+    for (size_t q = 0; q < N; ++q) x[q] = x[q] + alpha * php[q] + *omega * shp[q];
+    for (size_t q = 0; q < N; ++q) S->r[q] = S->r[q] - *omega * S->t[q];
+    *rho_new = orc_dot(S->rt, S->r, (int64_t)N);
+    *rr = orc_dot(S->r, S->r, (int64_t)N);
+    return (isfinite(*rho_new) && isfinite(*rr)) ? 0 : ORC_ERR_NONFINITE;
+}
+
 int orc_bicgstab_bc(int nx, int ny, int nz, double h, unsigned bc, const double *b, double *x,
                     int precond, int degree, int mixed, double tol, int maxit, double lmin_scale,
                     double lmax_scale, int block, int bj_global, double jacobi_diag, double *trace,
                     double *rr0_out, int *iters, int *half)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || maxit < 1) return ORC_ERR_ARG;
-    size_t N = (size_t)nx * ny * nz;
-    pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global,
-               lmin_scale, lmax_scale, jacobi_diag, bc};
+    const size_t N = (size_t)nx * ny * nz;
+    const pc_t pc = {nx, ny, nz, h, precond, degree, mixed, block, bj_global,
+                     lmin_scale, lmax_scale, jacobi_diag, bc};
+    bicg_t S = {N, &pc, malloc(N * 8), malloc(N * 8), malloc(N * 8), malloc(N * 8),
+                malloc(N * 8), malloc(N * 8), malloc(N * 8), 0.0};
     *iters = 0;
     *half = 0;
-    double *r = malloc(N * 8), *rt = malloc(N * 8), *p = malloc(N * 8), *w = malloc(N * 8),
-           *t = malloc(N * 8), *ph = malloc(N * 8), *sh = malloc(N * 8);
     int status = ORC_NOT_CONVERGED;
 
-    /* r0 = b - A x0, r~ = r0, p0 = r0, rho0 = r~.r0 */
-    orc_apply_A_bc(nx, ny, nz, h, 0, bc, x, w);
-    for (size_t q = 0; q < N; ++q) r[q] = b[q] - w[q];
-    memcpy(rt, r, N * 8);
-    memcpy(p, r, N * 8);
-    double bb = orc_dot(b, b, (int64_t)N);
-    double tol2bb = (tol * tol) * bb;
-    double rho = orc_dot(rt, r, (int64_t)N);
-    double rr = orc_dot(r, r, (int64_t)N);
+    /* r_0 = b - A x_0; the shadow residual and the first direction are r_0 */
+    bicg_apply_A(&S, x, S.w);
+    for (size_t q = 0; q < N; ++q) S.r[q] = b[q] - S.w[q];
+    memcpy(S.rt, S.r, N * 8);
+    memcpy(S.p, S.r, N * 8);
+    const double bb = orc_dot(b, b, (int64_t)N);
+    const double tol2bb = (tol * tol) * bb;
+    S.rho = orc_dot(S.rt, S.r, (int64_t)N);
+    double rr = orc_dot(S.r, S.r, (int64_t)N);
     if (rr0_out) *rr0_out = rr;
     if (!isfinite(bb) || !isfinite(rr)) { status = ORC_ERR_NONFINITE; goto out; }
     if (bb == 0.0) { memset(x, 0, N * 8); status = ORC_OK; goto out; }
     if (rr < tol2bb) { status = ORC_OK; goto out; }
 
     for (int i = 1; i <= maxit; ++i) {
+        double *tr = trace ? trace + 4 * (i - 1) : NULL;
+        const double *php;
+        double alpha = 0.0, ss = 0.0, omega = 0.0, rho_new = 0.0;
+        int stepped = 0, moved = 0;
         *iters = i;
-        /* solve M p^ = p */
-        const double *php = p;
-        if (precond != PC_NONE) { apply_pc(&pc, p, ph); php = ph; }
-        /* w = A p^, alpha = rho / (r~ . w) */
-        orc_apply_A_bc(nx, ny, nz, h, 0, bc, php, w);
-        double d = orc_dot(rt, w, (int64_t)N);
-        if (!isfinite(d)) { status = ORC_ERR_NONFINITE; goto out; }
-        if (d == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
-        double alpha = rho / d;
-        /* s = r - alpha w, kept in r */
-        for (size_t q = 0; q < N; ++q) r[q] = r[q] - alpha * w[q];
-        double ss = orc_dot(r, r, (int64_t)N);
-        if (trace) { trace[4 * (i - 1)] = alpha; trace[4 * (i - 1) + 2] = rho; }
-        if (!isfinite(ss)) { status = ORC_ERR_NONFINITE; goto out; }
-        if (ss < tol2bb) { /* half-step exit of Alg. 1 */
+        int st = bicg_first_half(&S, &php, &alpha, &ss, &stepped);
+        /* alpha and rho_{i-1} are recorded once alpha exists (also if s.s then fails) */
+        if (tr && stepped) { tr[0] = alpha; tr[2] = S.rho; }
+        if (st) { status = st; goto out; }
+        if (ss < tol2bb) {
             for (size_t q = 0; q < N; ++q) x[q] = x[q] + alpha * php[q];
-            if (trace) { trace[4 * (i - 1) + 1] = 0.0; trace[4 * (i - 1) + 3] = ss; }
+            if (tr) { tr[1] = 0.0; tr[3] = ss; }
             *half = 1;
             status = ORC_OK;
             goto out;
         }
-        /* solve M s^ = s, t = A s^, omega = (t.s)/(t.t) */
-        const double *shp = r;
-        if (precond != PC_NONE) { apply_pc(&pc, r, sh); shp = sh; }
-        orc_apply_A_bc(nx, ny, nz, h, 0, bc, shp, t);
-        double ts = orc_dot(t, r, (int64_t)N);
-        double tt = orc_dot(t, t, (int64_t)N);
-        if (!isfinite(ts) || !isfinite(tt)) { status = ORC_ERR_NONFINITE; goto out; }
-        if (tt == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
-        double omega = ts / tt;
-        /* x = x + alpha p^ + omega s^, r = s - omega t */
-        for (size_t q = 0; q < N; ++q) x[q] = x[q] + alpha * php[q] + omega * shp[q];
-        for (size_t q = 0; q < N; ++q) r[q] = r[q] - omega * t[q];
-        double rho_new = orc_dot(rt, r, (int64_t)N);
-        rr = orc_dot(r, r, (int64_t)N);
-        if (trace) { trace[4 * (i - 1) + 1] = omega; trace[4 * (i - 1) + 3] = rr; }
-        if (!isfinite(rho_new) || !isfinite(rr)) { status = ORC_ERR_NONFINITE; goto out; }
+        st = bicg_second_half(&S, x, php, alpha, &omega, &rho_new, &rr, &moved);
+        if (tr && moved) { tr[1] = omega; tr[3] = rr; }
+        if (st) { status = st; goto out; }
         if (rr < tol2bb) { status = ORC_OK; goto out; }
         if (rho_new == 0.0 || omega == 0.0) { status = ORC_ERR_BREAKDOWN; goto out; }
-        double beta = (rho_new * alpha) / (rho * omega);
-        /* p = r + beta (p - omega w) */
-        for (size_t q = 0; q < N; ++q) p[q] = r[q] + beta * (p[q] - omega * w[q]);
-        rho = rho_new;
+        /* next direction p = r + beta (p - omega w) */
+        const double beta = (rho_new * alpha) / (S.rho * omega);
+        for (size_t q = 0; q < N; ++q) S.p[q] = S.r[q] + beta * (S.p[q] - omega * S.w[q]);
+        S.rho = rho_new;
     }
     status = ORC_NOT_CONVERGED;
 out:
-    free(r); free(rt); free(p); free(w); free(t); free(ph); free(sh);
+    free(S.r); free(S.rt); free(S.p); free(S.w); free(S.t); free(S.ph); free(S.sh);
     return status;
 }
 
