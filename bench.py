@@ -22,6 +22,10 @@ in HBM before the timed region. Printed as one JSON line:
   mixed_over_seeds_tol_1e-8
                mixed vs FP64 time to 1e-8 on five more right-hand sides (seeds 3, 5-8)
                and the median speed-up over them and seed 4
+  solvers_256_tol_1e-8
+               256^3, f ~ U[-1,1) seed 2, FP64 to 1e-8: no preconditioner, point Jacobi,
+               Block-Jacobi(CI) 64^3 x 8, Chebyshev 4 and 8 (median of 3), each x checked
+               against the sha256 of the oracle's stored solve
   roofline     dominant kernel (three fused interior Chebyshev steps, FP64),
                timed with HIP events on the stream it runs on
   cpu_baseline the CPU oracle on a bounded sample (2 iterations vs 1 iteration
@@ -262,6 +266,35 @@ def extra_configs(P, workloads, b, stream, degree):
         "seeds": seeds,
         "median_speedup_with_seed_4": None,
         "median_speedup": round(median([v["speedup"] for v in seeds.values()]), 3)}
+    # 256^3, f ~ U[-1,1) seed 2: the solver comparison, each x against the oracle's
+    n2 = 256
+    b2 = torch.empty(n2 ** 3, dtype=torch.float64, device=b.device)
+    P.fill_uniform(b2, 2, stream)
+    stream.synchronize()
+    cmp256 = {}
+    for name, pc, m in (("none", P.PC_NONE, 0), ("jacobi", P.PC_JACOBI, 0),
+                        ("bj64x8", P.PC_BLOCK_JACOBI, 8), ("cheb4", P.PC_CHEBYSHEV, 4),
+                        ("cheb8", P.PC_CHEBYSHEV, 8)):
+        x2 = torch.zeros_like(b2)
+        with P.Solver((n2, n2, n2), workloads.spacing(n2), stream=stream) as s2:
+            tts = []
+            for _ in range(3):
+                with torch.cuda.stream(stream):
+                    x2.zero_()
+                st = s2.solve(b2, x2, pc, m, 1e-8, 5000)
+                d = s2.stats()
+                tts.append(d["solve_ms"] / 1e3)
+        torch.cuda.synchronize()
+        r = {"status": st, "iterations": d["iterations"], "tts_s": round(median(tts), 4),
+             "relres_true": d["relres_true"], "hbm_gbps": round(d["model_gbps"], 1)}
+        ref = golden_x_sha256(f"full_256_{name}")
+        if ref is not None:
+            r["x_is_oracle_x"] = sha256_of(x2) == ref
+        cmp256[name] = r
+        log(f"256^3 {name}: {r['iterations']} it {r['tts_s']} s")
+        del x2
+    del b2
+    out["solvers_256_tol_1e-8"] = cmp256
     f = torch.from_numpy(workloads.manufactured_noisy(shape, 3).ravel()).to(b.device)
     noisy = {}
     for name, pc in (("block_jacobi_64", P.PC_BLOCK_JACOBI), ("chebyshev", P.PC_CHEBYSHEV)):
