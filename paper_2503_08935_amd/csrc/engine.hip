@@ -46,7 +46,8 @@ struct poisson_ctx {
     // options
     int precision = POISSON_FP64, graph_iters = 8, use_graph = 1, tile_order = 0;
     int pair_lds = 1;
-    int fuse_updates = 1;       // fold the s and p updates into the applies' first passes
+    int fuse_updates = 2;       // fold the s and p updates into the applies' first passes:
+                                // 0 never, 1 always, 2 when the grid is large enough
     PlanOpts opt;
     // tiling
     int ntiles = 1;
@@ -140,10 +141,18 @@ int plan_fuse_level(const poisson_ctx *c)
     return (c->opt.fuse >= 2 && !c->pair_lds) ? 1 : c->opt.fuse;
 }
 
+// Unknowns from which the folds pay by default. Below, the vectors partly fit
+// the 256 MB Infinity Cache, the standalone update passes run from it, and the
+// folded first passes' extra halo reads cost more than the passes they replace
+// (measured per iteration, Chebyshev 4 and 8, FP64 and mixed: 0.7-3.8% slower
+// at 256^3-320^3, 1.5-2.5% faster at 384^3, 3.6-5.5% faster at 512^3).
+constexpr size_t FOLD_MIN_UNKNOWNS = (size_t)352 * 352 * 352;
+
 // the vector updates a solve of this plan folds into the applies' first passes
 int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
     if (!c->fuse_updates) return 0;
+    if (c->fuse_updates == 2 && c->N < FOLD_MIN_UNKNOWNS) return 0;
     return upd_fusion(pc, deg, mixed, c->opt.fuse, single_work(c, nullptr));
 }
 
@@ -532,7 +541,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         c->pair_lds = (int)v;
         return POISSON_OK;
     case POISSON_OPT_FUSE_UPDATES:
-        if (v != 0 && v != 1) return POISSON_ERR_ARG;
+        if (v != 0 && v != 1 && v != 2) return POISSON_ERR_ARG;
         c->fuse_updates = (int)v;
         return POISSON_OK;
     default:

@@ -247,3 +247,21 @@ def test_byte_model_per_iteration(gpu):
                                      fuse_updates=fold, precision=P.MIXED if mixed else P.FP64)
         assert st == P.OK
         assert stats["model_bytes"] == per * n * stats["iterations"], (fuse, mixed, fold)
+
+
+def test_update_folding_follows_the_grid_size(gpu):
+    """By default the s and p updates are folded into the first passes from 352^3
+    unknowns on (where it was measured faster) and not below: the stats' byte model
+    shows which plan ran (344 against 360 B per unknown and iteration, FP64
+    Chebyshev-8)."""
+    for shape, per in (((351, 352, 352), 360), ((352, 352, 352), 344)):
+        n = shape[0] * shape[1] * shape[2]
+        b = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        P.fill_uniform(b, 9)
+        with P.Solver(shape, 1.0 / (shape[0] + 1)) as s:
+            x = torch.zeros_like(b)
+            st = s.solve(b, x, P.PC_CHEBYSHEV, 8, 1e-12, 2)
+            torch.cuda.synchronize()
+            stats = s.stats()
+        assert st == P.NOT_CONVERGED and stats["iterations"] == 2
+        assert stats["model_bytes"] == per * n * 2, shape
