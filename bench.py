@@ -506,7 +506,7 @@ def main():
     # pass (two per pass where three are not available)
     try:
         k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_TRIPLE)
-        dom, dom_name, dom_work = "triple", "k_cheb_triple_lds<double,double,false,false,2,4,false,true,0>", "cheb_triple"
+        dom, dom_name, dom_work = "triple", "k_cheb_triple_lds<double,double,false,false,1,4,8,false,true,0>", "cheb_triple"
     except P.PoissonError:
         k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
         dom, dom_name, dom_work = "pair", "k_cheb_pair_lds<double,double,false,false,2,8,false,true,0>", "cheb_pair"

@@ -1742,41 +1742,47 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
 //   w_{i+2} = rc_{i+2} ((2 sigma w_{i+1} + (2/delta)(v - A w_{i+1})) - ro_{i+2} w_i)
 // Plane k of the march computes w_i at plane k, w_{i+1} at k-1 and w_{i+2}
 // at k-2. w_i is computed on the tile plus a halo ring of two, w_{i+1} on the
-// tile plus one. A wave owns 64 columns x PR rows and holds PR + 2 rows: a top
-// wave also the two halo rows above, a bottom wave the two below. At each side
+// tile plus one. The workgroup has NXW x NYW waves; a wave owns 64 columns x
+// PR rows. The top wave of a column of waves also holds the two halo rows
+// above the tile, the bottom wave the two below; waves between them hold only
+// their own rows and take the rows across their edges from LDS. At each side
 // 2 x 16 halo lanes hold the columns one and two out; they load y, v and z
 // there, the lanes two out also y three out, and they compute w_i (and w_{i+1}
 // one out) at those points. y, w_i and w_{i+1} each have two LDS planes
 // alternating by plane, with one barrier per plane. The arithmetic per point
 // is that of k_stencil's step.
 // ------------------------------------------------------------------------
-template <int NXW, int PR> struct LTriple {
-    static constexpr int X = 64 * NXW, Y = 2 * PR;
+template <int NXW, int PR, int NYW> struct LTriple {
+    static constexpr int X = 64 * NXW, Y = NYW * PR;
     static constexpr int PW = X + 4, PH = Y + 4; // LDS plane: rows -2..Y+1, columns -2..X+1
     static constexpr int PLANE = PW * PH;
-    static constexpr int NT = 128 * NXW;
+    static constexpr int NT = 64 * NXW * NYW;
 };
+// the rows a wave of the triple holds: R_TOP and R_BOT add the tile's halo rows
+enum { R_TOP = 0, R_MID = 1, R_BOT = 2 };
 
 // FIRST: steps 1, 2 and 3 (the first step's own formula, y_0 := v, z = v/theta
 // at step 2; step 3 reads v = the input and z = w_1). The input is then v
 // itself, read as TU (FP64 also in the mixed mode, rounded once on load, with
 // the FP32 copy of v written out).
 // UPD: a vector update folded into the first triple, as in cheb_pair_lds_tile.
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
-          bool SIMPLE, int UPD>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, int NYW, int ROLE,
+          bool MASK, bool SIMPLE, int UPD>
 __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs &A, int tile,
-                                                     int lane, int xw, T *lds, double &ssh,
+                                                     int lane, int xw, int yw, T *lds, double &ssh,
                                                      double &ssl)
 {
     static_assert(UPD == 0 || FIRST, "a vector update folds only into a first pass");
     constexpr int NU = UPD == U_P ? 2 : (UPD == U_S ? 1 : 0);
     constexpr int NUA = NU > 0 ? NU : 1;
-    using L = LTriple<NXW, PR>;
-    constexpr int E = PR + 2;                      // held rows: own PR and two halo rows
-    constexpr int L2LO = TOP ? 1 : 0, L2HI = TOP ? E : E - 1;   // rows of w_{i+1}
-    constexpr int OWNLO = TOP ? 2 : 0, OWNHI = TOP ? E : PR;    // own rows (w_{i+2})
-    constexpr int TRO = TOP ? -3 : 2 * PR + 2;     // tile row of the outer row (y only)
-    auto trow = [](int e) { return TOP ? e - 2 : PR + e; };
+    using L = LTriple<NXW, PR, NYW>;
+    constexpr bool TOP = ROLE == R_TOP, BOT = ROLE == R_BOT, MID = ROLE == R_MID;
+    constexpr int E = MID ? PR : PR + 2;           // held rows: own PR (and two halo rows)
+    constexpr int L2LO = TOP ? 1 : 0, L2HI = BOT ? E - 1 : E;   // rows of w_{i+1}
+    constexpr int OWNLO = TOP ? 2 : 0, OWNHI = BOT ? PR : E;    // own rows (w_{i+2})
+    constexpr int TRO = TOP ? -3 : L::Y + 2;       // tile row of the outer row (y only)
+    const int r0 = TOP ? -2 : (BOT ? (NYW - 1) * PR : yw * PR); // tile row of held row 0
+    auto trow = [r0](int e) { return r0 + e; };
     auto in2 = [](int e) { return e >= L2LO && e < L2HI; };
     auto own = [](int e) { return e >= OWNLO && e < OWNHI; };
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -1855,10 +1861,11 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
     }
     const int jo = y0 + TRO;
-    const bool ook = xin && jo >= 0 && jo < ny;
+    const bool ook = !MID && xin && jo >= 0 && jo < ny;
     const unsigned ooff = offy(ic, clampi(jo, ny));
     const int lown = lidx(trow(0), cx);
-    const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
+    // the rows next to the held ones (held by the waves above and below)
+    const int linU = lidx(r0 - 1, cx), linD = lidx(r0 + E, cx);
 
     // Halo lanes. Lanes 0-15 (left) and 32-47 (right) hold the column one out
     // (A), lanes 16-31 and 48-63 the column two out (B); lane e of a group
@@ -1936,7 +1943,8 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
             const char *Up = Ub[u] + pb;
 #pragma unroll
             for (int e = 0; e < E; ++e) R.uy[u][e] = ldy(Up, ryoff[e]);
-            R.uyo[u] = ldy(Up, ooff);
+            if constexpr (!MID) R.uyo[u] = ldy(Up, ooff);
+            else R.uyo[u] = (TU)0;
             R.uhe[u] = ldy(Up, hoffy);
         }
     };
@@ -1945,7 +1953,8 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         const char *Yp = Yb + pb;
 #pragma unroll
         for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
-        R.yo = ldy(Yp, ooff);
+        if constexpr (!MID) R.yo = ldy(Yp, ooff);
+        else R.yo = (TU)0;
         R.he = ldy(Yp, hoffy);
         if (extra) issueU(p, R);
     };
@@ -2047,7 +2056,11 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         const Sel s1p = to_sel(pin0 ? sel_hi(k, nz, MASK, B, nzh) : 0);
         T w1c[E], vc[E];
         {
-            const T inner = ys[linner];
+            // the rows across the held rows' edges: the outer row (top, bottom
+            // wave) or a row of the neighbouring wave from LDS
+            T inU = (T)0, inD = (T)0;
+            if constexpr (TOP) inU = yob; else inU = ys[linU];
+            if constexpr (BOT) inD = yob; else inD = ys[linD];
             T cen[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) cen[e] = ys[lown + e * L::PW];
@@ -2057,14 +2070,8 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                 // x neighbours from the LDS plane, which holds every column of the
                 // tile and its halo (no lane shifts, no edge patches)
                 const T xm = ys[lown - 1 + e * L::PW], xp = ys[lown + 1 + e * L::PW];
-                T ym, yp;
-                if constexpr (TOP) {
-                    ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
-                    yp = e == E - 1 ? inner : cen[e < E - 1 ? e + 1 : e];
-                } else {
-                    ym = e == 0 ? inner : cen[e > 0 ? e - 1 : 0];
-                    yp = e == E - 1 ? yob : cen[e < E - 1 ? e + 1 : e];
-                }
+                const T ym = e == 0 ? inU : cen[e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : cen[e < E - 1 ? e + 1 : e];
                 const bool ok = pin0 && rok[e];
                 const T v = (!FIRST && ok) ? RV.v[e] : (T)0, z = (!FIRST && ok) ? RV.z[e] : (T)0;
                 vc[e] = v;
@@ -2104,21 +2111,19 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
         for (int e = 0; e < E; ++e) cen1[e] = w1s[lown + e * L::PW];
         T h2c = (T)0;
         if (k >= k0) {
-            const T inner = w1s[linner];
+            // rows of the neighbouring waves (the top wave's first and the bottom
+            // wave's last held row compute no w_{i+1})
+            T inU = (T)0, inD = (T)0;
+            if constexpr (!TOP) inU = w1s[linU];
+            if constexpr (!BOT) inD = w1s[linD];
 #pragma unroll
             for (int e = L2LO; e < L2HI; ++e) {
                 const T c = cen1[e];
                 // x neighbours from the LDS plane, which holds every column of the
                 // tile and its halo (no lane shifts, no edge patches)
                 const T xm = w1s[lown - 1 + e * L::PW], xp = w1s[lown + 1 + e * L::PW];
-                T ym, yp;
-                if constexpr (TOP) {
-                    ym = cen1[e - 1];
-                    yp = e == E - 1 ? inner : cen1[e < E - 1 ? e + 1 : e];
-                } else {
-                    ym = e == 0 ? inner : cen1[e > 0 ? e - 1 : 0];
-                    yp = cen1[e + 1];
-                }
+                const T ym = e == 0 ? inU : cen1[e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : cen1[e < E - 1 ? e + 1 : e];
                 // step i+1 reads z = y_{i-1}, the stencil input at plane k-1 (for the
                 // first triple v = that input and z = v/theta)
                 const T v = FIRST ? ya[e] : vb[e];
@@ -2150,7 +2155,9 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 #pragma unroll
         for (int e = 0; e < E; ++e) cen2[e] = w2s[lown + e * L::PW];
         if (k >= k0 + 2) {
-            const T inner = w2s[linner];
+            T inU = (T)0, inD = (T)0;
+            if constexpr (!TOP) inU = w2s[linU];
+            if constexpr (!BOT) inD = w2s[linD];
             const Sel s3m = to_sel(sel_lo(k - 2, nz, MASK, B, nzl));
             const Sel s3p = to_sel(sel_hi(k - 2, nz, MASK, B, nzh));
             const size_t po = (size_t)(k - 2) * PB;
@@ -2160,14 +2167,8 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
                 // x neighbours from the LDS plane, which holds every column of the
                 // tile and its halo (no lane shifts, no edge patches)
                 const T xm = w2s[lown - 1 + e * L::PW], xp = w2s[lown + 1 + e * L::PW];
-                T ym, yp;
-                if constexpr (TOP) {
-                    ym = cen2[e - 1];
-                    yp = e == E - 1 ? inner : cen2[e < E - 1 ? e + 1 : e];
-                } else {
-                    ym = e == 0 ? inner : cen2[e > 0 ? e - 1 : 0];
-                    yp = cen2[e + 1];
-                }
+                const T ym = e == 0 ? inU : cen2[e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : cen2[e < E - 1 ? e + 1 : e];
                 // step i+2 reads z = w_i at plane k-2, held in w1a
                 const T v = FIRST ? yaa[e] : vbb[e];
                 const T w3 = step(rc3, ro3, c, xm, xp, ym, yp, w2a[e], w2c[e], v, w1a[e], s3m, s3p,
@@ -2199,14 +2200,14 @@ __device__ __forceinline__ void cheb_triple_lds_tile(const Prob &P, const KArgs 
 
 // At most 256 VGPRs (two waves per SIMD): the bodies with neighbour selects
 // need a few more and spill them (measured faster than one wave per SIMD)
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE,
-          int UPD = 0>
-__global__ void __launch_bounds__(128 * NXW) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, int NYW, bool MASK,
+          bool SIMPLE, int UPD = 0>
+__global__ void __launch_bounds__(64 * NXW * NYW) __attribute__((amdgpu_waves_per_eu(2)))
 k_cheb_triple_lds(Work W, KArgs A)
 {
-    using L = LTriple<NXW, PR>;
+    using L = LTriple<NXW, PR, NYW>;
     __shared__ T lds[6 * L::PLANE];
-    __shared__ double red[2 * 2 * NXW];
+    __shared__ double red[2 * NXW * NYW];
     constexpr int F32 = sizeof(T) == 4;
     const Prob &P = W.probs[0];
     const int tkz = P.tkz[F32];
@@ -2223,14 +2224,17 @@ k_cheb_triple_lds(Work W, KArgs A)
         const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
         double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
-            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
-                                                                                     lds, ssh, ssl);
-        else
-            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE, UPD>(P, A, t, lane,
-                                                                                      xw, lds, ssh, ssl);
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if (yw == NYW - 1)
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_BOT, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if constexpr (NYW > 2)
+            cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_MID, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
         if constexpr (UPD == U_S) {
             double hh[1] = {ssh}, ll[1] = {ssl};
-            block_reduce_dd<1, 2 * NXW>(hh, ll, red);
+            block_reduce_dd<1, NXW * NYW>(hh, ll, red);
             if (threadIdx.x == 0) {
                 double *pp = P.partials + (size_t)t * PARTIAL_STRIDE;
                 pp[0] = hh[0];
@@ -2557,21 +2561,21 @@ template <typename T, typename TU, bool FIRST, bool DROP, bool MASK, bool SIMPLE
 static void ltr_launch(const Work &w, hipStream_t s, const KArgs &a)
 {
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int NXW = triple_nxw(F32), PR = triple_pr(F32);
+    constexpr int NXW = triple_nxw(F32), PR = triple_pr(F32), NYW = triple_nyw(F32);
     if constexpr (FIRST) {
         if (a.upd == U_S) {
-            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, MASK, SIMPLE, U_S>),
-                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, NYW, MASK, SIMPLE, U_S>),
+                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR, NYW>::NT), 0, s, w, a);
             return;
         }
         if (a.upd == U_P) {
-            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, MASK, SIMPLE, U_P>),
-                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+            hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, true, DROP, NXW, PR, NYW, MASK, SIMPLE, U_P>),
+                               dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR, NYW>::NT), 0, s, w, a);
             return;
         }
     }
-    hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, FIRST, DROP, NXW, PR, MASK, SIMPLE>),
-                       dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR>::NT), 0, s, w, a);
+    hipLaunchKernelGGL((k_cheb_triple_lds<T, TU, FIRST, DROP, NXW, PR, NYW, MASK, SIMPLE>),
+                       dim3(w.triple_tiles[F32]), dim3(LTriple<NXW, PR, NYW>::NT), 0, s, w, a);
 }
 
 template <typename T, typename TU, bool FIRST, bool DROP>

@@ -123,13 +123,14 @@ def test_lds_pairs_match_register_pairs(gpu, cfg, mixed, shape):
 @pytest.mark.parametrize("cfg", LDS_CONFIGS, ids=lambda c: f"bc{c['bc']}-pc{c['pc']}-b{c['block']}")
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("shape", [(200, 37, 21), (128, 16, 8), (64, 8, 70), (3, 50, 2),
-                                   (257, 33, 9)])
+                                   (257, 33, 9), (66, 70, 19)])
 def test_triples_match_pairs(gpu, cfg, mixed, shape):
-    """Three Chebyshev steps per pass (LDS-staged, 128 x 8 tiles in FP64 and 128 x 16
-    in FP32; steps 1-3 first) against two per pass and the oracle, bitwise, on ragged
-    shapes, for every face type and block mask; degrees whose steps after the first
-    triple split into triples only (6, 9), triples and a pair (5, 8) or triples and
-    a single step (7, 10)."""
+    """Three Chebyshev steps per pass (LDS-staged, 64 x 32 tiles of eight waves in FP64
+    and 128 x 16 in FP32; steps 1-3 first) against two per pass and the oracle,
+    bitwise, on ragged shapes (waves between the top and bottom one partly or wholly
+    outside the grid; a tile row with grid rows on both sides), for every face type
+    and block mask; degrees whose steps after the first triple split into triples
+    only (6, 9), triples and a pair (5, 8) or triples and a single step (7, 10)."""
     nx, ny, nz = shape
     bc, pc, block = cfg["bc"], cfg["pc"], cfg["block"]
     for axis, n in enumerate(shape):
