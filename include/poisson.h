@@ -96,9 +96,10 @@ enum {
                                            same arithmetic, same results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the fused Chebyshev
-                                           pairs), 1 x-grouped everywhere (the x-tiles of a
-                                           tile row on one XCD), 2 slabs (each XCD one
-                                           contiguous eighth of the tiles); same results */
+                                           pairs and FP32 triples, slabs for FP64 triples),
+                                           1 x-grouped everywhere (the x-tiles of a tile row
+                                           on one XCD), 2 slabs (each XCD one contiguous
+                                           eighth of the tiles); same results */
     POISSON_OPT_PAIR_LDS = 11,          /* fused Chebyshev pairs of single solves: 1 (default)
                                            stage 128 x 16 (FP64) or 256 x 16 (FP32) tiles in
                                            LDS, 0 use the 64 x 16 register tiles; same

@@ -70,7 +70,8 @@ __device__ __forceinline__ void *vec_at(const Prob &P, int v)
 // gives each XCD one whole row: dispatch d of the group runs row d % 8, x-tile
 // d / 8. Rows left over at the end keep natural order. The slab order gives
 // XCD x the x-th eighth of all tiles, a contiguous range of whole tile rows,
-// when the tile count is a multiple of 8.
+// when the tile count is a multiple of 8: y-neighbouring tiles then run on one
+// XCD, at the same time when there is one tile per workgroup slot.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ int tile_order_tx(int order, int tx, int g, int total)
 {
@@ -2221,7 +2222,10 @@ k_cheb_triple_lds(Work W, KArgs A)
     const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
     const int total = ltx * lty * ((P.nz + tkz - 1) / tkz);
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int t = tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        // default order: slabs for FP64 (512^3: each XCD runs four tile rows of
+        // all x-tiles, one tile per CU, so the y-halo rows between them come
+        // from its L2), x-grouped for FP32
+        const int t = tile_order_tx(W.order ? W.order : (sizeof(T) == 8 ? 2 : 1), ltx, g, total);
         double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
             cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(
