@@ -509,7 +509,7 @@ def main():
         dom, dom_name, dom_work = "triple", "k_cheb_triple_lds<double,double,false,false,1,4,8,false,true,0>", "cheb_triple"
     except P.PoissonError:
         k_ms, k_bytes, k_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
-        dom, dom_name, dom_work = "pair", "k_cheb_pair_lds<double,double,false,false,2,8,false,true,0>", "cheb_pair"
+        dom, dom_name, dom_work = "pair", "k_cheb_pair_lds<double,double,false,false,2,8,4,false,true,0>", "cheb_pair"
     p_ms, p_bytes, p_gbps = kernel_time(P.KERNEL_CHEB_PAIR)
     s_ms, s_bytes, s_gbps = kernel_time(P.KERNEL_CHEB_STEP)
     log(f"cheb {dom} FP64: {k_ms * 1e3:.1f} us/launch, {k_gbps:.0f} GB/s algorithmic; pair "
@@ -520,7 +520,7 @@ def main():
                 "traffic": traffic_record("device.hip", workload),
                 "kernel": dom_name, "kernel_us": round(k_ms * 1e3, 2),
                 "bytes_per_launch": k_bytes,
-                "pair": {"kernel": "k_cheb_pair_lds<double,double,false,false,2,8,false,true,0>",
+                "pair": {"kernel": "k_cheb_pair_lds<double,double,false,false,2,8,4,false,true,0>",
                          "kernel_us": round(p_ms * 1e3, 2), "bytes_per_launch": p_bytes,
                          "achieved": round(p_gbps, 1), "frac": round(p_gbps / PEAK_HBM_GBPS, 4),
                          "traffic": traffic_record("device.hip", f"cheb_pair_fp64_{n}^3")},

@@ -20,11 +20,12 @@ constexpr int RY = 4;           // y rows per wave (a tile is TY*RY rows)
 constexpr int NTHREADS = TX * TY;
 constexpr int MAXDEG = 64;      // largest Chebyshev degree
 constexpr int PARTIAL_STRIDE = 4; // doubles per tile partial: two double-double sums
-// tiles of the LDS-staged Chebyshev pair: 2*nxw waves, each 64 columns x LPR rows;
-// 128 columns in FP64, 256 in FP32 (measured fastest at 512^3 for each)
-constexpr int LPR = 8;
-constexpr int LY = 2 * LPR;
+// tiles of the LDS-staged Chebyshev pair: pair_nxw x pair_nyw waves, each 64
+// columns x pair_pr rows; 128 x 32 in FP64 (eight waves, one workgroup per CU),
+// 256 x 16 in FP32 (eight waves in two rows)
 constexpr int pair_nxw(bool fp32) { return fp32 ? 4 : 2; }
+constexpr int pair_nyw(bool fp32) { return fp32 ? 2 : 4; }
+constexpr int pair_pr(bool fp32) { return fp32 ? 8 : 8; }
 // tiles of the LDS-staged Chebyshev triple: triple_nxw x triple_nyw waves, each
 // 64 columns x triple_pr rows; 64 x 32 in FP64 (eight waves, one workgroup per
 // CU), 128 x 16 in FP32 (four waves, two workgroups per CU)

@@ -1278,11 +1278,15 @@ __global__ void __launch_bounds__(NTHREADS) k_cheb_pair(Work W, KArgs A)
 // plane loop is pipelined as in cheb_pair_tile, and the arithmetic per point
 // is exactly that of two k_stencil steps.
 // ------------------------------------------------------------------------
-template <int NXW, int PR> struct LPair {
-    static constexpr int X = 64 * NXW, Y = 2 * PR;
+// the rows a wave of an LDS-staged pair or triple holds: the top and bottom wave
+// of a column of waves add the tile's halo rows, the waves between them do not
+enum { R_TOP = 0, R_MID = 1, R_BOT = 2 };
+
+template <int NXW, int PR, int NYW> struct LPair {
+    static constexpr int X = 64 * NXW, Y = NYW * PR;
     static constexpr int PW = X + 2, PH = Y + 2; // LDS plane: rows -1..Y, columns -1..X
     static constexpr int PLANE = PW * PH;
-    static constexpr int NT = 128 * NXW;
+    static constexpr int NT = 64 * NXW * NYW;
 };
 
 // MASK: Block-Jacobi block faces; SIMPLE: no mask and no Neumann face, so every
@@ -1293,21 +1297,24 @@ template <int NXW, int PR> struct LPair {
 // point it reads, stores s at the tile's points and adds their s.s to (ssh,
 // ssl); U_P forms v = p = r + beta (p_prev - omega w) and stores it as this
 // iteration's p (in the first iteration v is p itself).
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool TOP, bool MASK,
-          bool SIMPLE, int UPD>
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, int NYW, int ROLE,
+          bool MASK, bool SIMPLE, int UPD>
 __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A, int tile,
-                                                   int lane, int xw, T *lds, double &ssh,
+                                                   int lane, int xw, int yw, T *lds, double &ssh,
                                                    double &ssl)
 {
     static_assert(UPD == 0 || FIRST, "a vector update folds only into a first pass");
     constexpr int NU = UPD == U_P ? 2 : (UPD == U_S ? 1 : 0);   // extra operands of v
     constexpr int NUA = NU > 0 ? NU : 1;
-    using L = LPair<NXW, PR>;
-    constexpr int E = PR + 1;           // rows held: PR own rows and the halo row outside them
+    using L = LPair<NXW, PR, NYW>;
+    constexpr bool TOP = ROLE == R_TOP, BOT = ROLE == R_BOT, MID = ROLE == R_MID;
+    // rows held: PR own rows, and for the top and bottom wave the halo row outside them
+    constexpr int E = MID ? PR : PR + 1;
     constexpr int EOWN = TOP ? 1 : 0;   // first own row among the held rows
-    constexpr int ERING = TOP ? 0 : PR; // the halo row among them
-    constexpr int TRO = TOP ? -2 : 2 * PR + 1; // tile row of the outer row (y only)
-    auto trow = [](int e) { return TOP ? e - 1 : PR + e; };
+    constexpr int ERING = TOP ? 0 : (BOT ? PR : -1); // the halo row among them
+    constexpr int TRO = TOP ? -2 : L::Y + 1; // tile row of the outer row (y only)
+    const int r0 = TOP ? -1 : (BOT ? (NYW - 1) * PR : yw * PR); // tile row of held row 0
+    auto trow = [r0](int e) { return r0 + e; };
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int ltx = (nx + L::X - 1) / L::X, lty = (ny + L::Y - 1) / L::Y;
     const int tix = tile % ltx, tiy = (tile / ltx) % lty, tiz = tile / (ltx * lty);
@@ -1388,20 +1395,19 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
     }
     const int jo = y0 + TRO;
-    const bool ook = xin && jo >= 0 && jo < ny;
+    const bool ook = !MID && xin && jo >= 0 && jo < ny;
     const unsigned ooff = offy(ic, clampi(jo, ny));
-    // own position in LDS (held row 0); row e adds e*PW. The lane's x
-    // neighbour across the wave edge: column cx-1 for lane 0, cx+1 for lane 63.
+    // own position in LDS (held row 0); row e adds e*PW
     const int lown = lidx(trow(0), cx);
-    // the row across the wave's inner boundary, at the lane's column
-    const int linner = TOP ? lidx(PR, cx) : lidx(PR - 1, cx);
+    // the rows next to the held ones (held by the waves above and below)
+    const int linU = lidx(r0 - 1, cx), linD = lidx(r0 + E, cx);
 
     // Halo lanes: lane e (< E) of the leftmost waves holds tile column -1 of
     // held row e, lane 32+e of the rightmost waves column X. Both write their y
     // value to LDS; on own rows they also compute w_i there, for which they
     // load y one column further out, v and z.
     const bool hside = lane >= 32;
-    const int eh = min(lane & 31, PR);
+    const int eh = min(lane & 31, E - 1);
     const bool hwave = hside ? xw == NXW - 1 : xw == 0;
     const bool hact = hwave && (lane & 31) < E;
     const int hcol = hside ? L::X : -1;
@@ -1449,7 +1455,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
             const char *Up = Ub[u] + pb;
 #pragma unroll
             for (int e = 0; e < E; ++e) R.uy[u][e] = ldy(Up, ryoff[e]);
-            R.uyo[u] = ldy(Up, ooff);
+            if constexpr (!MID) R.uyo[u] = ldy(Up, ooff);
+            else R.uyo[u] = (TU)0;
             R.uhe[u] = ldy(Up, hoff);
         }
     };
@@ -1458,7 +1465,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         const char *Yp = Yb + pb;
 #pragma unroll
         for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
-        R.yo = ldy(Yp, ooff);
+        if constexpr (!MID) R.yo = ldy(Yp, ooff);
+        else R.yo = (TU)0;
         R.he = ldy(Yp, hoff);
         if (extra) issueU(p, R);
     };
@@ -1561,7 +1569,11 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
         const Sel sz1m = to_sel(pin0 ? sel_lo(k, nz, MASK, B, nzl) : 0);
         const Sel sz1p = to_sel(pin0 ? sel_hi(k, nz, MASK, B, nzh) : 0);
         {
-            const T inner = ys[linner];
+            // the rows across the held rows' edges: the outer row (top, bottom
+            // wave) or a row of the neighbouring wave from LDS
+            T inU = (T)0, inD = (T)0;
+            if constexpr (TOP) inU = yob; else inU = ys[linU];
+            if constexpr (BOT) inD = yob; else inD = ys[linD];
             T cen[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) cen[e] = ys[lown + e * L::PW];
@@ -1571,14 +1583,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
                 // x neighbours from the LDS plane, which holds every column of the
                 // tile and its halo (no lane shifts, no edge patches)
                 const T xm = ys[lown - 1 + e * L::PW], xp = ys[lown + 1 + e * L::PW];
-                T ym, yp;
-                if constexpr (TOP) {
-                    ym = e == 0 ? yob : cen[e > 0 ? e - 1 : 0];
-                    yp = e == E - 1 ? inner : cen[e < E - 1 ? e + 1 : e];
-                } else {
-                    ym = e == 0 ? inner : cen[e > 0 ? e - 1 : 0];
-                    yp = e == E - 1 ? yob : cen[e < E - 1 ? e + 1 : e];
-                }
+                const T ym = e == 0 ? inU : cen[e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : cen[e < E - 1 ? e + 1 : e];
                 const bool ok = pin0 && rok[e];
                 const T v = FIRST ? c : (ok ? RV.v[e] : (T)0);
                 const T z = (!FIRST && ok) ? RV.z[e] : (T)0;
@@ -1627,7 +1633,11 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 #pragma unroll
         for (int e = 0; e < E; ++e) wcen[e] = ws[lown + e * L::PW];
         if (k - 1 >= k0) {
-            const T inner = ws[linner];
+            // rows of the neighbouring waves (the top wave's first and the bottom
+            // wave's last held row are halo rows, which compute no w_{i+1})
+            T inU = (T)0, inD = (T)0;
+            if constexpr (!TOP) inU = ws[linU];
+            if constexpr (!BOT) inD = ws[linD];
             const size_t po = (size_t)(k - 1) * PB;
             const Sel sz2m = to_sel(sel_lo(k - 1, nz, MASK, B, nzl));
             const Sel sz2p = to_sel(sel_hi(k - 1, nz, MASK, B, nzh));
@@ -1635,14 +1645,8 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
             for (int e = EOWN; e < EOWN + PR; ++e) {
                 const T c = wcen[e];
                 T xm = ws[lown - 1 + e * L::PW], xp = ws[lown + 1 + e * L::PW];
-                T ym, yp;
-                if constexpr (TOP) {
-                    ym = wcen[e - 1];
-                    yp = e == E - 1 ? inner : wcen[e < E - 1 ? e + 1 : e];
-                } else {
-                    ym = e == 0 ? inner : wcen[e > 0 ? e - 1 : 0];
-                    yp = wcen[e + 1];
-                }
+                T ym = e == 0 ? inU : wcen[e > 0 ? e - 1 : 0];
+                T yp = e == E - 1 ? inD : wcen[e < E - 1 ? e + 1 : e];
                 T zm = wa[e], zp = wc[e];
                 if constexpr (!SIMPLE) {
                     const T xm0 = xm, ym0 = ym, zm0 = zm;
@@ -1678,13 +1682,13 @@ __device__ __forceinline__ void cheb_pair_lds_tile(const Prob &P, const KArgs &A
 
 // DROP: the last pair of an apply, which stores w_{i+1} only (a kernel of its
 // own, so that profiles report the two traffic figures apart)
-template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, bool MASK, bool SIMPLE,
-          int UPD = 0>
-__global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
+template <typename T, typename TU, bool FIRST, bool DROP, int NXW, int PR, int NYW, bool MASK,
+          bool SIMPLE, int UPD = 0>
+__global__ void __launch_bounds__(64 * NXW * NYW) k_cheb_pair_lds(Work W, KArgs A)
 {
-    using L = LPair<NXW, PR>;
+    using L = LPair<NXW, PR, NYW>;
     __shared__ T lds[4 * L::PLANE];
-    __shared__ double red[2 * 2 * NXW];
+    __shared__ double red[2 * NXW * NYW];
     constexpr int F32 = sizeof(T) == 4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int xw = wv % NXW, yw = wv / NXW;
@@ -1710,21 +1714,27 @@ __global__ void __launch_bounds__(128 * NXW) k_cheb_pair_lds(Work W, KArgs A)
             const Scalars *sc = P.sc;
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
-        // single problem: x-grouped unless another order is asked for, so that
-        // the tiles of a tile row share the L2 that holds their halo columns
+        // single problem, unless another order is asked for: x-grouped in FP32, so
+        // that the tiles of a tile row share the L2 that holds their halo columns;
+        // slabs in FP64, whose tiles are all resident at once at 512^3, so that
+        // y-neighbouring tiles share it as well
         const int ltx = (P.nx + L::X - 1) / L::X;
-        const int t = W.pair_prob ? W.pair_local[g] : tile_order_tx(W.order ? W.order : 1, ltx, g, total);
+        const int t = W.pair_prob ? W.pair_local[g]
+                                  : tile_order_tx(W.order ? W.order : (sizeof(T) == 8 ? 2 : 1), ltx, g, total);
         double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
-            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, true, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
-                                                                                   lds, ssh, ssl);
-        else
-            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, false, MASK, SIMPLE, UPD>(P, A, t, lane, xw,
-                                                                                    lds, ssh, ssl);
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if (yw == NYW - 1)
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_BOT, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if constexpr (NYW > 2)
+            cheb_pair_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_MID, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
         if constexpr (UPD == U_S) {
             // this tile's s.s in its partial slot (summed by the half-step finalize)
             double hh[1] = {ssh}, ll[1] = {ssl};
-            block_reduce_dd<1, 2 * NXW>(hh, ll, red);
+            block_reduce_dd<1, NXW * NYW>(hh, ll, red);
             if (threadIdx.x == 0) {
                 double *pp = P.partials + (size_t)t * PARTIAL_STRIDE;
                 pp[0] = hh[0];
@@ -1759,8 +1769,6 @@ template <int NXW, int PR, int NYW> struct LTriple {
     static constexpr int PLANE = PW * PH;
     static constexpr int NT = 64 * NXW * NYW;
 };
-// the rows a wave of the triple holds: R_TOP and R_BOT add the tile's halo rows
-enum { R_TOP = 0, R_MID = 1, R_BOT = 2 };
 
 // FIRST: steps 1, 2 and 3 (the first step's own formula, y_0 := v, z = v/theta
 // at step 2; step 3 reads v = the input and z = w_1). The input is then v
@@ -2498,22 +2506,23 @@ static void lf2_mask(bool mask, const Work &w, int grid, hipStream_t s, const KA
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW, bool MASK, bool SIMPLE>
 static void lpl_launch(const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
+    constexpr int PPR = pair_pr(sizeof(T) == 4), PNYW = pair_nyw(sizeof(T) == 4);
     if constexpr (FIRST) {
         // a folded vector update: single problems only (the server keeps the
         // standalone update kernels)
         if (a.upd == U_S) {
-            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, LPR, MASK, SIMPLE, U_S>),
-                               dim3(grid), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, PPR, PNYW, MASK, SIMPLE, U_S>),
+                               dim3(grid), dim3(LPair<NXW, PPR, PNYW>::NT), 0, s, w, a);
             return;
         }
         if (a.upd == U_P) {
-            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, LPR, MASK, SIMPLE, U_P>),
-                               dim3(grid), dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+            hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, true, DROP, NXW, PPR, PNYW, MASK, SIMPLE, U_P>),
+                               dim3(grid), dim3(LPair<NXW, PPR, PNYW>::NT), 0, s, w, a);
             return;
         }
     }
-    hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, LPR, MASK, SIMPLE>), dim3(grid),
-                       dim3(LPair<NXW, LPR>::NT), 0, s, w, a);
+    hipLaunchKernelGGL((k_cheb_pair_lds<T, TU, FIRST, DROP, NXW, PPR, PNYW, MASK, SIMPLE>), dim3(grid),
+                       dim3(LPair<NXW, PPR, PNYW>::NT), 0, s, w, a);
 }
 
 template <typename T, typename TU, bool FIRST, bool DROP, int NXW>

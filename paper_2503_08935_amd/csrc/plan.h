@@ -36,7 +36,7 @@ struct PlanOpts {
 };
 
 Tiling make_tiling(int nx, int ny, int nz);
-// tiles of the LDS-staged Chebyshev pair (64 * pair_nxw(fp32) x LY columns, kz planes)
+// tiles of the LDS-staged Chebyshev pair (64 * pair_nxw x pair_nyw * pair_pr columns, kz planes)
 Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32);
 // tiles of the LDS-staged Chebyshev triple (64 * triple_nxw x triple_nyw * triple_pr columns)
 Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32);

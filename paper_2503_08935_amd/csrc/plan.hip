@@ -110,15 +110,16 @@ Tiling make_tiling(int nx, int ny, int nz)
 Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32)
 {
     Tiling t;
-    const int lx = 64 * pair_nxw(fp32);
+    const int lx = 64 * pair_nxw(fp32), ly = pair_nyw(fp32) * pair_pr(fp32);
     t.tx = (nx + lx - 1) / lx;
-    t.ty = (ny + LY - 1) / LY;
-    // the longest chunk that leaves a tile for each of the 512 workgroup slots
-    // (two per CU): 128-plane chunks measured slightly faster than 64-plane ones
-    // with 1024 tiles, mostly in the mixed mode
+    t.ty = (ny + ly - 1) / ly;
+    // the longest chunk that leaves a tile for each workgroup slot (FP64: one per
+    // CU, FP32: two): 128-plane chunks measured slightly faster than 64-plane
+    // ones with 1024 tiles, mostly in the mixed mode
     int kz = 128;
+    const long min_tiles = fp32 ? 512 : 256;
     const long base = (long)t.tx * t.ty;
-    while (kz > 8 && base * ((nz + kz - 1) / kz) < 512) kz /= 2;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < min_tiles) kz /= 2;
     t.kz = std::min(kz, std::max(nz, 1));
     t.tz = (nz + t.kz - 1) / t.kz;
     t.ntiles = t.tx * t.ty * t.tz;

@@ -259,7 +259,7 @@ void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids
         }
 }
 
-// the LDS-staged pairs' tiles of the requests in ids (64 * pair_nxw x LY columns)
+// the LDS-staged pairs' tiles of the requests in ids (make_pair_tiling)
 void list_pair_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids, bool fp32)
 {
     t.h_prob.clear();
