@@ -95,8 +95,8 @@ enum {
                                            alone), two per pass (1) or one per pass (0);
                                            same arithmetic, same results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
-                                           (natural; x-grouped for the fused Chebyshev
-                                           pairs and FP32 triples, slabs for FP64 triples),
+                                           (natural; x-grouped for the FP32 fused Chebyshev
+                                           pairs, slabs for the triples and FP64 pairs),
                                            1 x-grouped everywhere (the x-tiles of a tile row
                                            on one XCD), 2 slabs (each XCD one contiguous
                                            eighth of the tiles); same results */

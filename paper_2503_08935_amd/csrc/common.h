@@ -27,10 +27,10 @@ constexpr int pair_nxw(bool fp32) { return fp32 ? 4 : 2; }
 constexpr int pair_nyw(bool fp32) { return fp32 ? 2 : 4; }
 constexpr int pair_pr(bool fp32) { return fp32 ? 8 : 8; }
 // tiles of the LDS-staged Chebyshev triple: triple_nxw x triple_nyw waves, each
-// 64 columns x triple_pr rows; 64 x 32 in FP64 (eight waves, one workgroup per
-// CU), 128 x 16 in FP32 (four waves, two workgroups per CU)
+// 64 columns x triple_pr rows; 64 x 32 in FP64, 128 x 32 in FP32 (eight waves,
+// one workgroup per CU, in both)
 constexpr int triple_nxw(bool fp32) { return fp32 ? 2 : 1; }
-constexpr int triple_nyw(bool fp32) { return fp32 ? 2 : 8; }
+constexpr int triple_nyw(bool fp32) { return fp32 ? 4 : 8; }
 constexpr int triple_pr(bool fp32) { return fp32 ? 8 : 4; }
 
 // vector slots of a problem. V_S and V_P2 exist only when the vector updates are

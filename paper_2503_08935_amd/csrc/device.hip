@@ -2230,10 +2230,10 @@ k_cheb_triple_lds(Work W, KArgs A)
     const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
     const int total = ltx * lty * ((P.nz + tkz - 1) / tkz);
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        // default order: slabs for FP64 (512^3: each XCD runs four tile rows of
-        // all x-tiles, one tile per CU, so the y-halo rows between them come
-        // from its L2), x-grouped for FP32
-        const int t = tile_order_tx(W.order ? W.order : (sizeof(T) == 8 ? 2 : 1), ltx, g, total);
+        // default order: slabs (512^3: one tile per CU, each XCD running a band
+        // of tile rows of all x-tiles, so the y-halo rows between them come from
+        // its L2)
+        const int t = tile_order_tx(W.order ? W.order : 2, ltx, g, total);
         double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
             cheb_triple_lds_tile<T, TU, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(

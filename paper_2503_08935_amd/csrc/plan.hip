@@ -132,12 +132,12 @@ Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32)
     const int lx = 64 * triple_nxw(fp32), ly = triple_nyw(fp32) * triple_pr(fp32);
     t.tx = (nx + lx - 1) / lx;
     t.ty = (ny + ly - 1) / ly;
-    // the longest z-chunk that leaves a tile for every workgroup slot (an FP64
-    // workgroup fills a CU, two FP32 ones share it): long chunks spend fewer
-    // planes on each tile's three-plane start and drain. Measured against 64-plane
-    // chunks and 1024 tiles, solves 1-2% faster at 512^3 and 4% at 256^3
+    // the longest z-chunk that leaves a tile for every CU (a workgroup fills
+    // one): long chunks spend fewer planes on each tile's three-plane start and
+    // drain. Measured against 64-plane chunks and 1024 tiles, solves 1-2% faster
+    // at 512^3 and 4% at 256^3
     int kz = fp32 ? 128 : 256;
-    const long min_tiles = fp32 ? 512 : 256;
+    const long min_tiles = 256;
     const long base = (long)t.tx * t.ty;
     while (kz > 8 && base * ((nz + kz - 1) / kz) < min_tiles) kz /= 2;
     t.kz = std::min(kz, std::max(nz, 1));

@@ -126,7 +126,7 @@ def test_lds_pairs_match_register_pairs(gpu, cfg, mixed, shape):
                                    (257, 33, 9), (66, 70, 19)])
 def test_triples_match_pairs(gpu, cfg, mixed, shape):
     """Three Chebyshev steps per pass (LDS-staged, 64 x 32 tiles of eight waves in FP64
-    and 128 x 16 in FP32; steps 1-3 first) against two per pass and the oracle,
+    and 128 x 32 in FP32; steps 1-3 first) against two per pass and the oracle,
     bitwise, on ragged shapes (waves between the top and bottom one partly or wholly
     outside the grid; a tile row with grid rows on both sides), for every face type
     and block mask; degrees whose steps after the first triple split into triples
