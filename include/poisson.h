@@ -302,7 +302,15 @@ enum {
                                             its own batches on a stream of its own (default
                                             priority), so small requests are not paced by
                                             large ones; 1 = every request in one batch on the
-                                            server's stream. Set before the first step */
+                                            server's stream. Set before the first step */,
+    POISSON_SERVER_OPT_FUSE_UPDATES = 3  /* 1 (default): Chebyshev and Block-Jacobi plans of
+                                            degree >= 3 form s = r - alpha w and p = r +
+                                            beta (p - omega w) inside the first pass of each
+                                            preconditioner apply (Alg. 3's two update passes
+                                            folded away, as in poisson_solve from 352^3; two
+                                            more FP64 vectors per request); 0: standalone
+                                            update passes. Same results either way. Set
+                                            before the first submit */
 };
 
 /* Create a server. hip_stream: the caller's stream (NULL = null stream); the
@@ -318,7 +326,9 @@ int poisson_server_create(size_t hbm_budget_bytes, int max_slots, void *hip_stre
 /* Set a server option (POISSON_SERVER_OPT_*). */
 int poisson_server_set_option(poisson_server *s, int key, double value);
 
-/* Arena bytes a request of this plan needs (host-only). */
+/* Arena bytes a request of this plan needs with the default options (host-only);
+   with POISSON_SERVER_OPT_FUSE_UPDATES = 0 a Chebyshev or Block-Jacobi plan of
+   degree >= 3 needs 16 bytes per unknown less. */
 int poisson_server_footprint(int nx, int ny, int nz, int precond, int degree, int precision,
                              size_t *bytes);
 

@@ -30,7 +30,7 @@ EXPORTS = [
     "poisson_server_submit", "poisson_server_step", "poisson_server_poll", "poisson_server_info",
     "poisson_server_destroy",
 ]
-SERVER_OPT_USE_GRAPH, SERVER_OPT_SIZE_CLASSES = 1, 2
+SERVER_OPT_USE_GRAPH, SERVER_OPT_SIZE_CLASSES, SERVER_OPT_FUSE_UPDATES = 1, 2, 3
 
 
 class Stats(ctypes.Structure):
@@ -286,7 +286,8 @@ def footprint(shape, precond, degree, precision):
 class Server:
     """Continuous-batching server (poisson_server_*): FIFO admission by HBM footprint."""
 
-    def __init__(self, budget_bytes, max_slots=64, stream=None, use_graph=True, size_classes=None):
+    def __init__(self, budget_bytes, max_slots=64, stream=None, use_graph=True, size_classes=None,
+                 fuse_updates=None):
         srv = ctypes.c_void_p()
         self._stream = stream
         _check(lib().poisson_server_create(int(budget_bytes), int(max_slots),
@@ -299,6 +300,10 @@ class Server:
         if size_classes is not None:
             _check(lib().poisson_server_set_option(srv, SERVER_OPT_SIZE_CLASSES,
                                                    float(size_classes)),
+                   "poisson_server_set_option")
+        if fuse_updates is not None:
+            _check(lib().poisson_server_set_option(srv, SERVER_OPT_FUSE_UPDATES,
+                                                   float(fuse_updates)),
                    "poisson_server_set_option")
 
     def close(self):

@@ -85,7 +85,8 @@ struct Prob {
     void *vec[V_COUNT];
     int s_slot;                  // where the second half of an iteration reads s: V_R, or
                                  // V_S when the first pass of the second apply forms it
-    int pad_s;
+    int nparts_first;            // tile partials holding s.s when that pass forms s for
+                                 // batched problems (its tiles); 0: given by the launch
     Scalars *sc;
     double *partials;            // ntiles * PARTIAL_STRIDE
     double *hist;                // 1 + 4*hist_iters, or null
@@ -160,7 +161,7 @@ void launch_cheb_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
                             const KArgs &a);
 // the half-step test on the s.s partials of a first pass with a.upd = U_S
-void launch_finalize_ss(const Work &w, hipStream_t s, const KArgs &a);
+void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a);
 // three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored

@@ -2455,7 +2455,10 @@ __global__ void __launch_bounds__(NTHREADS) k_finalize(Work W, KArgs A)
             if (sc->done || (A.second && sc->half_pending)) continue;
         }
         double res[ND];
-        sum_partials<ND>(P, A.nparts > 0 ? A.nparts : P.ntiles, lds, res);
+        // s.s of a formed s sits in the partials of the first pass's tiles
+        const int np = A.nparts > 0 ? A.nparts
+                                    : ((F == F_AXPY && P.nparts_first > 0) ? P.nparts_first : P.ntiles);
+        sum_partials<ND>(P, np, lds, res);
         if (threadIdx.x == 0) {
             if constexpr (F == F_SDOT) fin_sdot(P, res[0]);
             else if constexpr (F == F_SDOT2) fin_sdot2(P, res[0], res[1]);
@@ -2617,9 +2620,9 @@ void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KAr
     ltr_drop<float, double, true, false>(mask, w, s, a);
 }
 
-void launch_finalize_ss(const Work &w, hipStream_t s, const KArgs &a)
+void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    lfin<F_AXPY>(w, 1, s, a);
+    lfin<F_AXPY>(w, grid, s, a);
 }
 
 void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,

@@ -330,7 +330,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
             launch_cheb_first_triple(mask, w, s, a1);
         else
             launch_cheb_first_pair(mixed, mask, w, grid, s, a1);
-        if (upd == U_S) launch_finalize_ss(w, s, a1);
+        if (upd == U_S) launch_finalize_ss(w, grid, s, a1);
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
         int y = V_RB, z = V_RA;
         int i = first3 ? 4 : 3;

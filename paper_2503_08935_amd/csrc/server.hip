@@ -54,6 +54,7 @@ struct Request {
     const double *rhs;
     double *x;
     int pc, deg, prec;
+    int upd;                 // vector updates folded into the applies' first passes
     double tol;
     int maxit;
     size_t ws_bytes, footprint;
@@ -147,6 +148,24 @@ struct ClassState {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// the vector updates folded into the first pass of each preconditioner apply
+// (s = r - alpha w and p = r + beta (p - omega w) formed there, as in single
+// solves): wherever the applies run as LDS-staged pairs, unless switched off
+int server_upd(int pc, int deg, int prec, bool on)
+{
+    return on && fused(pc, deg, prec == POISSON_MIXED, 1) ? (U_S | U_P) : 0;
+}
+
+// bytes of a request's arena block: its workspace (with the folds' two extra
+// vectors where they apply), then its reduction partials (one slot per tile
+// of the tiling with the most tiles)
+size_t block_bytes(int nx, int ny, int nz, int pc, int deg, int prec, int upd, size_t *ws)
+{
+    const size_t w = workspace_bytes((size_t)nx * ny * nz, pc, deg, prec == POISSON_MIXED, 1, upd);
+    if (ws) *ws = w;
+    return w + align256((size_t)partial_slots(nx, ny, nz) * PARTIAL_STRIDE * sizeof(double));
+}
+
 } // namespace
 
 struct poisson_server {
@@ -157,6 +176,7 @@ struct poisson_server {
     bool dev = false;
     bool use_graph = true;
     int nclasses = 3;               // size classes, each on a stream of its own
+    bool fuse_updates = true;       // fold the s and p updates into the first passes
     char *arena_base = nullptr;
     Arena arena;
     size_t in_use = 0, peak = 0;
@@ -359,7 +379,8 @@ int capture_group(poisson_server *s, const PlanKey &k, Group &g)
     }
     const Work w = group_work(s, k, g, 0);
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, 1);
+    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, 1,
+                      server_upd(k.pc, k.deg, k.mixed, s->fuse_updates));
     HIPCHK(hipStreamEndCapture(s->cap_stream, &g.graph_src));
     HIPCHK(hipGraphInstantiate(&g.graph, g.graph_src, nullptr, nullptr, 0));
     g.graph_cap = g.tiles.cap;
@@ -484,7 +505,12 @@ int round_impl(poisson_server *s, int iters, int &progress)
         sl.ntiles = p.ntiles;
         char *blk = s->arena_base + off;
         const size_t N = (size_t)sl.req.nx * sl.req.ny * sl.req.nz;
-        carve_workspace(p, blk, N, sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED, 1);
+        carve_workspace(p, blk, N, sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED, 1,
+                        sl.req.upd);
+        // with s formed in the first pass, its s.s is in that pass's tile partials
+        if (sl.req.upd & U_S)
+            p.nparts_first =
+                make_pair_tiling(sl.req.nx, sl.req.ny, sl.req.nz, sl.req.prec == POISSON_MIXED).ntiles;
         p.vec[V_X] = sl.req.x;
         p.vec[V_B] = (void *)sl.req.rhs;
         p.partials = (double *)(blk + sl.req.ws_bytes);
@@ -548,7 +574,9 @@ int round_impl(poisson_server *s, int iters, int &progress)
                 const Work w = group_work(s, kv.first, g, g.tiles.count);
                 for (int i = 0; i < iters; ++i)
                     enqueue_iteration(w, GRID, k.stream, kv.first.pc, kv.first.deg,
-                                      kv.first.mixed != 0, 1);
+                                      kv.first.mixed != 0, 1,
+                                      server_upd(kv.first.pc, kv.first.deg, kv.first.mixed,
+                                                 s->fuse_updates));
                 HIPCHK(hipGetLastError());
             }
         }
@@ -592,6 +620,12 @@ int poisson_server_set_option(poisson_server *s, int key, double value)
         s->use_graph = value != 0;
         return POISSON_OK;
     }
+    if (key == POISSON_SERVER_OPT_FUSE_UPDATES) {
+        // fixed once a request was submitted (its workspace is sized by it)
+        if (s->next_ticket != 1 || (value != 0 && value != 1)) return POISSON_ERR_ARG;
+        s->fuse_updates = value != 0;
+        return POISSON_OK;
+    }
     if (key == POISSON_SERVER_OPT_SIZE_CLASSES) {
         // fixed once the server has started (its streams exist)
         if (s->dev || value < 1 || value > MAX_CLASSES || value != std::floor(value))
@@ -608,10 +642,8 @@ int poisson_server_footprint(int nx, int ny, int nz, int precond, int degree, in
     if (!bytes || nx < 1 || ny < 1 || nz < 1) return POISSON_ERR_ARG;
     if (precond < POISSON_PC_NONE || precond > POISSON_PC_BLOCK_JACOBI) return POISSON_ERR_ARG;
     if (precision != POISSON_FP64 && precision != POISSON_MIXED) return POISSON_ERR_ARG;
-    const size_t N = (size_t)nx * ny * nz;
-    const Tiling t = make_tiling(nx, ny, nz);
-    *bytes = workspace_bytes(N, precond, degree, precision == POISSON_MIXED, 1) +
-             align256((size_t)t.ntiles * PARTIAL_STRIDE * sizeof(double));
+    *bytes = block_bytes(nx, ny, nz, precond, is_cheb(precond) ? degree : 0, precision,
+                         server_upd(precond, is_cheb(precond) ? degree : 0, precision, true), nullptr);
     return POISSON_OK;
 }
 
@@ -635,8 +667,9 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
         double lo, hi;
         if (!cheb_interval(nx, ny, nz, h, bc, precond, o, lo, hi)) return POISSON_ERR_ARG;
     }
-    size_t fp;
-    poisson_server_footprint(nx, ny, nz, precond, degree, precision, &fp);
+    const int upd = server_upd(precond, degree, precision, s->fuse_updates);
+    size_t ws;
+    const size_t fp = block_bytes(nx, ny, nz, precond, degree, precision, upd, &ws);
     if (fp > s->budget) return POISSON_ERR_NOMEM;
     int rc;
     if ((rc = validate_ptr(rhs)) != POISSON_OK) return rc;
@@ -646,9 +679,9 @@ int poisson_server_submit(poisson_server *s, int nx, int ny, int nz, double h, u
     r.nx = nx; r.ny = ny; r.nz = nz; r.h = h; r.bc = bc;
     r.rhs = rhs; r.x = x;
     r.pc = precond; r.deg = degree; r.prec = precision;
+    r.upd = upd;
     r.tol = tol; r.maxit = maxit;
-    r.ws_bytes =
-        workspace_bytes((size_t)nx * ny * nz, precond, degree, precision == POISSON_MIXED, 1);
+    r.ws_bytes = ws;
     r.footprint = fp;
     r.t_submit = now_ms();
     s->queue.push_back(r);

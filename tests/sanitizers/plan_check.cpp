@@ -73,7 +73,7 @@ void launch_cheb_first_triple(bool, const Work &, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_TRIPLE, 0, true, a});
 }
-void launch_finalize_ss(const Work &, hipStream_t, const KArgs &a)
+void launch_finalize_ss(const Work &, int, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIN_SS, 0, false, a});
 }

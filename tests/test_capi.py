@@ -149,11 +149,16 @@ def test_server_host_side_checks():
 def test_footprint_model():
     # mixed Chebyshev-4: r, r~, p, w, t in FP64 and p^, s^, three Chebyshev buffers (the
     # first pair writes y_1, w_2; the pair (3, 4) one more) and the FP32 copy of the
-    # input: 5*8 + 6*4 = 64 bytes per unknown, plus tile partials
+    # input: 5*8 + 6*4 = 64 bytes per unknown; with the s and p updates folded into the
+    # first passes (the server's default) s and the second p in FP64: 80; plus tile
+    # partials
     n = 128
     fp = P.footprint((n, n, n), P.PC_CHEBYSHEV, 4, P.MIXED)
-    assert 64 * n ** 3 <= fp <= 64 * n ** 3 + 64 * 1024 + 13 * 256
-    # FP64 Chebyshev-8: 7 FP64 vectors plus a ring of 4 for the fused step pairs
+    assert 80 * n ** 3 <= fp <= 80 * n ** 3 + 64 * 1024 + 15 * 256
+    # FP64 Chebyshev-8: 7 FP64 vectors plus a ring of 4 for the fused step pairs, plus
+    # the folds' two
     fp64 = P.footprint((n, n, n), P.PC_CHEBYSHEV, 8, P.FP64)
-    assert 88 * n ** 3 <= fp64 <= 88 * n ** 3 + 64 * 1024 + 14 * 256
+    assert 104 * n ** 3 <= fp64 <= 104 * n ** 3 + 64 * 1024 + 16 * 256
+    # no preconditioner, Jacobi and degrees below 3: no folds
     assert P.footprint((n, n, n), P.PC_NONE, 0, P.FP64) < fp
+    assert P.footprint((n, n, n), P.PC_CHEBYSHEV, 2, P.FP64) < 88 * n ** 3

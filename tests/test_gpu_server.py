@@ -197,6 +197,50 @@ def test_neumann_and_dirichlet_requests_in_one_batch(gpu):
         assert ref.iterations == it1 and np.array_equal(xs, ref.x), i
 
 
+def test_folded_updates_change_no_bits(gpu):
+    """The server forms s and p inside the first pass of each preconditioner apply
+    (its default) or runs Alg. 3's update passes on their own: the same bits for
+    every request (Chebyshev of degree 3, 4, 5 and 8, Block-Jacobi, FP64 and mixed,
+    Neumann faces, a request whose apply has no first pair to fold into)."""
+    reqs = [  # shape, seed, precond, degree, precision, tol, bc
+        ((40, 36, 30), 51, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 2 | 4 | 16),
+        ((61, 47, 35), 52, P.PC_CHEBYSHEV, 3, P.FP64, 1e-8, 0),
+        ((33, 40, 28), 53, P.PC_CHEBYSHEV, 8, P.FP64, 1e-9, 1 | 32),
+        ((70, 30, 20), 54, P.PC_BLOCK_JACOBI, 6, P.FP64, 1e-8, 4 | 8),
+        ((96, 96, 96), 55, P.PC_CHEBYSHEV, 5, P.MIXED, 1e-8, 0),
+        ((33, 21, 50), 56, P.PC_JACOBI, 0, P.MIXED, 1e-8, 0),
+        ((24, 24, 24), 57, P.PC_CHEBYSHEV, 2, P.FP64, 1e-8, 0),
+    ]
+    runs = []
+    for fold in (1, 0):
+        out = {}
+        with P.Server(1 << 30, 8, fuse_updates=fold) as srv:
+            bufs, tickets = {}, {}
+            for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
+                b = torch.from_numpy(workloads.uniform_grid(seed, shape)).to("cuda:0")
+                x = torch.zeros_like(b)
+                bufs[i] = (b, x)
+                tickets[i] = srv.submit(b, x, shape, workloads.spacing(shape[0]), pc, deg, prec,
+                                        tol, 5000, bc=bc)
+            for _ in range(100000):
+                if srv.step(3) == 0:
+                    break
+            for i, t in tickets.items():
+                st, stats = srv.poll(t)
+                out[i] = (st, stats["iterations"], stats["relres_true"], bufs[i][1].cpu().numpy())
+        runs.append(out)
+    for i in range(len(reqs)):
+        a, b = runs[0][i], runs[1][i]
+        assert a[0] == b[0] == P.OK and a[1] == b[1] and a[2] == b[2], (i, a[:3], b[:3])
+        assert np.array_equal(a[3], b[3]), i
+    # the option is fixed once a request was submitted
+    with P.Server(1 << 24, 2) as srv:
+        b = torch.zeros(8 ** 3, dtype=torch.float64, device="cuda:0")
+        srv.submit(b, b.clone(), (8, 8, 8), workloads.spacing(8), P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+        rc = P.lib().poisson_server_set_option(srv._srv, 3, 0.0)
+        assert rc == P.ERR_ARG
+
+
 def test_large_requests_in_the_mix(gpu):
     """A 256^3 and a 128^3 request beside small ones (each size class on its own
     stream): every result equals the solve done alone; n <= 128 also the oracle's."""
