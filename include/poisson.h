@@ -93,7 +93,10 @@ enum {
                                            the passes are LDS-staged (2, default; the steps
                                            left over, and the first two, run as pairs or
                                            alone), two per pass (1) or one per pass (0);
-                                           same arithmetic, same results */
+                                           3: in the mixed mode four per pass from degree 4
+                                           (steps 1-4 first, then fours, then the rest as
+                                           above), FP64 as 2; same arithmetic, same
+                                           results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the FP32 fused Chebyshev
                                            pairs, slabs for the triples and FP64 pairs),

@@ -32,6 +32,11 @@ constexpr int pair_pr(bool fp32) { return fp32 ? 8 : 8; }
 constexpr int triple_nxw(bool fp32) { return fp32 ? 2 : 1; }
 constexpr int triple_nyw(bool fp32) { return fp32 ? 4 : 8; }
 constexpr int triple_pr(bool fp32) { return fp32 ? 8 : 4; }
+// tiles of the LDS-staged four-step pass (mixed mode only): 64 x 32, eight waves
+// of 4 rows (a group of halo-column lanes per held row: at most 8 rows)
+constexpr int quad_nxw(bool fp32) { return fp32 ? 1 : 1; }
+constexpr int quad_nyw(bool fp32) { return fp32 ? 8 : 8; }
+constexpr int quad_pr(bool fp32) { return fp32 ? 4 : 4; }
 
 // vector slots of a problem. V_S and V_P2 exist only when the vector updates are
 // folded into the first pass of the preconditioner applies (upd_fusion): s is
@@ -75,6 +80,7 @@ struct Prob {
     unsigned bc;                 // bit f (x-, x+, y-, y+, z-, z+) = Neumann on face f
     int pkz[2];                  // z-chunk of the LDS-staged pair's tiles: [0] FP64, [1] FP32
     int tkz[2];                  // and of the LDS-staged triple's tiles
+    int qkz[2];                  // and of the LDS-staged four-step pass's tiles
     double ih2;                  // 1/(h*h)
     double tol2;                 // tol*tol
     double jac_d;                // diagonal of A = 6*ih2
@@ -106,6 +112,8 @@ struct Work {
                                  // pairs then select neighbours
     int triple_tiles[2];         // single problem: > 0 runs three Chebyshev steps per pass
                                  // (LDS-staged) over this many tiles ([0] FP64, [1] FP32)
+    int quad_tiles[2];           // single problem: > 0 runs four Chebyshev steps per pass
+                                 // (LDS-staged, mixed mode) over this many tiles
     // batched problems: the LDS-staged pairs' own tile list (null: single problem)
     const int *pair_prob;
     const int *pair_local;
@@ -162,6 +170,8 @@ void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipS
                             const KArgs &a);
 // the half-step test on the s.s partials of a first pass with a.upd = U_S
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a);
+void launch_cheb_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a);
+void launch_cheb_first_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a);
 // three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored

@@ -2256,6 +2256,504 @@ k_cheb_triple_lds(Work W, KArgs A)
     }
 }
 
+// ------------------------------------------------------------------------
+// S consecutive Chebyshev steps i, ..., i+S-1 in one pass, staged in LDS the
+// way k_cheb_triple_lds stages three (used with S = 4 in the mixed mode).
+// Level l = 0..S-1 of the march computes w_{i+l} at plane k - l. Step i+l
+// reads the level before it (the pass input y = y_{i-1} for level 0), v, and
+// z = the level two before it (for levels 0 and 1: z_{i-2} and y_{i-1}).
+// Level l is needed on the tile plus the points within S-1-l row and column
+// steps of it (each step widens the dependence by one point along one axis),
+// so the input is read with a halo of S. A wave owns 64 columns x PR rows;
+// the top and bottom wave of a column of waves also hold the S-1 halo rows
+// above or below the tile (and the input's outer row), the others only their
+// own rows. At each side S-1 groups of GS lanes hold the columns 1..S-1 out,
+// lane e of a group held row e: group g loads y, v and z there and computes
+// the levels up to S-1-g-d, d the row's distance from the tile; group S-1 also
+// loads y S columns out. Every level but the last has two LDS planes
+// alternating by plane (one barrier per plane), as has y. One pass reads y,
+// z, v and writes w_{i+S-2} and w_{i+S-1}: the bytes of a pair for S steps.
+// The arithmetic per point is that of k_stencil's step.
+// ------------------------------------------------------------------------
+template <int NXW, int PR, int NYW, int S> struct LSteps {
+    static constexpr int H = S - 1;
+    static constexpr int X = 64 * NXW, Y = NYW * PR;
+    static constexpr int PW = X + 2 * H, PH = Y + 2 * H; // rows -H..Y+H-1, columns -H..X+H-1
+    static constexpr int PLANE = PW * PH;
+    static constexpr int NT = 64 * NXW * NYW;
+    static constexpr int GS = H == 1 ? 32 : (H == 2 ? 16 : 8); // lanes per halo-column group
+};
+
+template <typename T, typename TU, int S, bool FIRST, bool DROP, int NXW, int PR, int NYW, int ROLE,
+          bool MASK, bool SIMPLE, int UPD>
+__device__ __forceinline__ void cheb_steps_lds_tile(const Prob &P, const KArgs &A, int tile,
+                                                    int lane, int xw, int yw, T *lds, double &ssh,
+                                                    double &ssl)
+{
+    static_assert(UPD == 0 || FIRST, "a vector update folds only into a first pass");
+    using L = LSteps<NXW, PR, NYW, S>;
+    constexpr int H = L::H;
+    static_assert(H >= 1 && H * L::GS <= 32, "halo-column groups fit half a wave");
+    constexpr int NU = UPD == U_P ? 2 : (UPD == U_S ? 1 : 0);
+    constexpr int NUA = NU > 0 ? NU : 1;
+    constexpr bool TOP = ROLE == R_TOP, BOT = ROLE == R_BOT, MID = ROLE == R_MID;
+    constexpr int E = MID ? PR : PR + H;           // held rows: own PR (and H halo rows)
+    static_assert(E <= L::GS, "a halo-column group holds every held row");
+    constexpr int EOWN = TOP ? H : 0;              // first own row among the held rows
+    constexpr int TRO = TOP ? -(H + 1) : L::Y + H; // tile row of the outer row (y only)
+    // distance of held row e from the tile's rows (0: an own row)
+    auto ydist = [](int e) { return TOP ? (e < H ? H - e : 0) : (BOT ? (e >= PR ? e - PR + 1 : 0) : 0); };
+    const int r0 = TOP ? -H : (BOT ? (NYW - 1) * PR : yw * PR); // tile row of held row 0
+    auto trow = [r0](int e) { return r0 + e; };
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int ltx = (nx + L::X - 1) / L::X, lty = (ny + L::Y - 1) / L::Y;
+    const int tix = tile % ltx, tiy = (tile / ltx) % lty, tiz = tile / (ltx * lty);
+    const int x0 = tix * L::X, y0 = tiy * L::Y;
+    const int pkz = P.qkz[sizeof(T) == 4];
+    const int k0 = tiz * pkz, k1 = min(k0 + pkz, nz);
+    const int cx = xw * 64 + lane;
+    const int i = x0 + cx;
+    const bool xin = i < nx;
+    const int ic = xin ? i : nx - 1;
+    const size_t PB = (size_t)nx * (size_t)ny * sizeof(T);
+    const size_t PBY = (size_t)nx * (size_t)ny * sizeof(TU); // the input's planes
+    const char *Yb = (const char *)P.vec[A.in];
+    const char *Ub[2] = {nullptr, nullptr};
+    char *Ob = nullptr;
+    double ua = 0.0, ub = 0.0, uo = 0.0;
+    bool ufirst = false;
+    if constexpr (UPD == U_S) {
+        Yb = (const char *)P.vec[V_R];
+        Ub[0] = (const char *)P.vec[V_W];
+        Ob = (char *)P.vec[V_S];
+        ua = P.sc->alpha;
+    } else if constexpr (UPD == U_P) {
+        const int it = P.sc->iter;
+        ufirst = it == 0;
+        const int pold = ((it - 1) & 1) ? V_P2 : V_P, pnew = (it & 1) ? V_P2 : V_P;
+        Yb = (const char *)P.vec[ufirst ? V_P : V_R];
+        Ub[0] = (const char *)P.vec[ufirst ? V_P : V_W];
+        Ub[1] = (const char *)P.vec[ufirst ? V_P : pold];
+        Ob = (char *)P.vec[pnew];
+        ub = P.sc->beta;
+        uo = P.sc->omega;
+    }
+    auto comb = [&](TU r, TU w, TU pp) -> TU {
+        if constexpr (UPD == U_S) return r - (TU)ua * w;
+        else if constexpr (UPD == U_P) return ufirst ? pp : r + (TU)ub * (pp - (TU)uo * w);
+        else return r;
+    };
+    const char *Vb = (const char *)vec_at(P, A.v);
+    const char *Zb = (const char *)P.vec[A.z];
+    char *W1b = (char *)P.vec[A.out];
+    char *W2b = (char *)P.vec[A.x2];
+    char *V32b = (char *)P.vec[V_V32];
+    const T ih2 = Coef<T>::ih2(P), theta = Coef<T>::theta(P), c1 = Coef<T>::c1(P);
+    const T ts = Coef<T>::two_sigma(P), tod = Coef<T>::two_over_delta(P);
+    T rcs[S], ros[S]; // the coefficients of step i+l (level 0 of a first pass uses c1)
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        rcs[l] = Coef<T>::rc(P, A.step + l);
+        ros[l] = Coef<T>::ro(P, A.step + l);
+    }
+    auto clampi = [](int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); };
+    auto inz = [nz](int p) { return p >= 0 && p < nz; };
+    auto off = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(T); };
+    auto offy = [&](int x, int j) { return (unsigned)(x + nx * j) * (unsigned)sizeof(TU); };
+    auto ld = [](const char *plane, unsigned o) { return ld_g((const T *)(plane + o)); };
+    auto ldy = [](const char *plane, unsigned o) { return ld_g((const TU *)(plane + o)); };
+    // LDS element of tile row r (-H..Y+H-1) and tile column c (-H..X+H-1)
+    auto lidx = [](int r, int c) { return (r + H) * L::PW + (c + H); };
+
+    const int B = MASK ? P.block : 1;
+    const unsigned bc = P.bc;
+    const bool nxl = bc & 1u, nxh = bc & 2u, nyl = bc & 4u, nyh = bc & 8u;
+    const bool nzl = bc & 16u, nzh = bc & 32u;
+    const Sel sxm = to_sel(xin ? sel_lo(i, nx, MASK, B, nxl) : 0);
+    const Sel sxp = to_sel(xin ? sel_hi(i, nx, MASK, B, nxh) : 0);
+    bool rok[E];
+    unsigned roff[E], ryoff[E];
+    Sel sym[E], syp[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = y0 + trow(e);
+        const bool jin = j >= 0 && j < ny;
+        rok[e] = xin && jin;
+        roff[e] = off(ic, clampi(j, ny));
+        ryoff[e] = offy(ic, clampi(j, ny));
+        sym[e] = to_sel(jin ? sel_lo(j, ny, MASK, B, nyl) : 0);
+        syp[e] = to_sel(jin ? sel_hi(j, ny, MASK, B, nyh) : 0);
+    }
+    const int jo = y0 + TRO;
+    const bool ook = !MID && xin && jo >= 0 && jo < ny;
+    const unsigned ooff = offy(ic, clampi(jo, ny));
+    const int lown = lidx(trow(0), cx);
+    // the rows next to the held ones (held by the waves above and below)
+    const int linU = lidx(r0 - 1, cx), linD = lidx(r0 + E, cx);
+
+    // Halo lanes: group hg (1..H) of each side holds the column hg out, lane he
+    // of the group held row he. hlev: the last level computed at that point.
+    const bool hside = lane >= 32;
+    const int hsl = lane & 31, hg = hsl / L::GS + 1, he = hsl % L::GS;
+    const int eh = min(he, E - 1);
+    const bool hwave = hside ? xw == NXW - 1 : xw == 0;
+    const bool hact = hwave && hg <= H && he < E;
+    const int hcol = hside ? L::X - 1 + hg : -hg;
+    const int hnear = hside ? hcol - 1 : hcol + 1;      // towards the tile
+    const int hfarc = hside ? hcol + 1 : hcol - 1;      // away from it
+    const int hi = x0 + hcol, hfi = x0 + hfarc;
+    const int hj = y0 + trow(eh);
+    const bool hrow = hj >= 0 && hj < ny;
+    const bool hload = hact && hrow && hi >= 0 && hi < nx;
+    const int hyd = TOP ? (eh < H ? H - eh : 0) : (BOT ? (eh >= PR ? eh - PR + 1 : 0) : 0);
+    const int hlev = hact ? H - hg - hyd : -1;
+    const bool fload = hact && hg == H && hrow && hfi >= 0 && hfi < nx; // y one column further out
+    const unsigned hoff = off(clampi(hi, nx), clampi(hj, ny));
+    const unsigned hoffy = offy(clampi(hi, nx), clampi(hj, ny));
+    const unsigned foff = offy(clampi(hfi, nx), clampi(hj, ny));
+    const int lhself = lidx(trow(eh), hcol);
+    const int lhnear = lidx(trow(eh), hnear);
+    const int lhfar = hg < H ? lidx(trow(eh), hfarc) : lhself;
+    const int lhup = lidx(max(trow(eh) - 1, -H), hcol);
+    const int lhdn = lidx(min(trow(eh) + 1, L::Y + H - 1), hcol);
+    const Sel csxl = to_sel(hload ? sel_lo(hi, nx, MASK, B, nxl) : 0);
+    const Sel csxh = to_sel(hload ? sel_hi(hi, nx, MASK, B, nxh) : 0);
+    const Sel csyl = to_sel(hload ? sel_lo(hj, ny, MASK, B, nyl) : 0);
+    const Sel csyh = to_sel(hload ? sel_hi(hj, ny, MASK, B, nyh) : 0);
+
+    // A u at one point from the centre and its six neighbours (in the order x-,
+    // x+, y-, y+, z-, z+), then the Chebyshev update
+    auto lap = [&](T c, T xm, T xp, T ym, T yp, T zm, T zp, Sel szl, Sel szh, Sel sxl, Sel sxh,
+                   Sel syl, Sel syh) {
+        if constexpr (!SIMPLE) {
+            const T xm0 = xm, ym0 = ym, zm0 = zm;
+            xm = pick(sxl, xm0, xp), xp = pick(sxh, xp, xm0);
+            ym = pick(syl, ym0, yp), yp = pick(syh, yp, ym0);
+            zm = pick(szl, zm0, zp), zp = pick(szh, zp, zm0);
+        }
+        return lap7<T>(c, xm, xp, ym, yp, zm, zp, ih2);
+    };
+    auto step = [&](T rc, T ro, T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl,
+                    Sel szh, Sel sxl, Sel sxh, Sel syl, Sel syh) {
+        const T a = lap(c, xm, xp, ym, yp, zm, zp, szl, szh, sxl, sxh, syl, syh);
+        return rc * ((ts * c + tod * (v - a)) - ro * z);
+    };
+    // level 0: step i (the first step's formula when FIRST)
+    auto step0 = [&](T c, T xm, T xp, T ym, T yp, T zm, T zp, T v, T z, Sel szl, Sel szh, Sel sxl,
+                     Sel sxh, Sel syl, Sel syh) {
+        const T a = lap(c, xm, xp, ym, yp, zm, zp, szl, szh, sxl, sxh, syl, syh);
+        if constexpr (FIRST) return c1 * ((T)2 * c - a / theta);
+        else return rcs[0] * ((ts * c + tod * (v - a)) - ros[0] * z);
+    };
+
+    struct RawY {
+        TU y[E], yo, he;
+        TU uy[NUA][E], uyo[NUA], uhe[NUA];
+    };
+    struct RawV {
+        T v[E], z[E], hv, hz;
+        TU hf, uhf[NUA];
+    };
+    // the folded update's extra operands of plane p; in the plane loop they are
+    // issued after level 0, so fewer loads are in flight across its arithmetic
+    auto issueU = [&](int p, RawY &R) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const char *Up = Ub[u] + pb;
+#pragma unroll
+            for (int e = 0; e < E; ++e) R.uy[u][e] = ldy(Up, ryoff[e]);
+            if constexpr (!MID) R.uyo[u] = ldy(Up, ooff);
+            else R.uyo[u] = (TU)0;
+            R.uhe[u] = ldy(Up, hoffy);
+        }
+    };
+    auto issueY = [&](int p, RawY &R, bool extra) {
+        const size_t pb = (size_t)clampi(p, nz) * PBY;
+        const char *Yp = Yb + pb;
+#pragma unroll
+        for (int e = 0; e < E; ++e) R.y[e] = ldy(Yp, ryoff[e]);
+        if constexpr (!MID) R.yo = ldy(Yp, ooff);
+        else R.yo = (TU)0;
+        R.he = ldy(Yp, hoffy);
+        if (extra) issueU(p, R);
+    };
+    auto gy = [&](const RawY &R, int e) { return comb(R.y[e], R.uy[0][e], R.uy[NUA - 1][e]); };
+    auto gyo = [&](const RawY &R) { return comb(R.yo, R.uyo[0], R.uyo[NUA - 1]); };
+    auto ghe = [&](const RawY &R) { return comb(R.he, R.uhe[0], R.uhe[NUA - 1]); };
+    auto issueV = [&](int p, RawV &R) {
+        const size_t po = (size_t)clampi(p, nz) * PB;
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                R.v[e] = ld(Vb + po, roff[e]);
+                R.z[e] = ld(Zb + po, roff[e]);
+            }
+            R.hv = ld(Vb + po, hoff);
+            R.hz = ld(Zb + po, hoff);
+        }
+        R.hf = ldy(Yb + (size_t)clampi(p, nz) * PBY, foff);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) R.uhf[u] = ldy(Ub[u] + (size_t)clampi(p, nz) * PBY, foff);
+    };
+    auto ghf = [&](const RawV &R) { return comb(R.hf, R.uhf[0], R.uhf[NUA - 1]); };
+    // f = 0: y; f = l + 1: the output of level l (l < H)
+    auto buf = [&](int f, int k) { return lds + (2 * f + (k & 1)) * L::PLANE; };
+
+    // registers across planes (k = the plane of level 0): y at k-1 (ya); the
+    // output of level l at plane k-l-2 (pv[l], for l < H), which the level
+    // after it reads below its centre and level l+2 reads as its z; v at planes
+    // k-1 .. k-H (vl[l-1] is the v of level l; a first pass carries its input
+    // there); the same at the halo point (ha, hpv, hvl); the outer row (yob)
+    T ya[E], pv[H][E], vl[H][E];
+    T yob, ha, hpv[H], hvl[H];
+    RawY RY;
+    RawV RV;
+#pragma unroll
+    for (int e = 0; e < E; ++e) RV.v[e] = RV.z[e] = (T)0;
+    RV.hv = RV.hz = (T)0;
+    {
+        RawY t;
+        issueY(k0 - H - 1, t, true);
+        {
+            const bool pin = k0 - H - 1 >= 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) ya[e] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            ha = (pin && hload) ? (T)ghe(t) : (T)0;
+        }
+        issueY(k0 - H, t, true);
+        {
+            const bool pin = k0 - H >= 0;
+            T *yd = buf(0, k0 - H);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = (pin && rok[e]) ? (T)gy(t, e) : (T)0;
+            yob = (pin && ook) ? (T)gyo(t) : (T)0;
+            if (hact) yd[lhself] = (pin && hload) ? (T)ghe(t) : (T)0;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) pv[l][e] = vl[l][e] = (T)0;
+        hpv[l] = hvl[l] = (T)0;
+    }
+    issueY(k0 - H + 1, RY, true);
+    issueV(k0 - H, RV);
+    __syncthreads();
+
+    for (int k = k0 - H; k <= k1 + H - 1; ++k) {
+        const bool pin1 = inz(k + 1), pin0 = inz(k);
+        // take y at plane k+1, publish it, issue plane k+2
+        T yc[E];
+        TU vn[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            vn[e] = gy(RY, e);
+            yc[e] = (pin1 && rok[e]) ? (T)vn[e] : (T)0;
+        }
+        const T yoc = (pin1 && ook) ? (T)gyo(RY) : (T)0;
+        const T hc = (pin1 && hload) ? (T)ghe(RY) : (T)0;
+        if constexpr (UPD != 0) {
+            if (k + 1 >= k0 && k + 1 < k1 && !ufirst) {
+                const size_t po = (size_t)(k + 1) * PBY;
+#pragma unroll
+                for (int e = EOWN; e < EOWN + PR; ++e)
+                    if (rok[e]) {
+                        st_nt((TU *)(Ob + po + ryoff[e]), vn[e]);
+                        if constexpr (UPD == U_S) dd_acc(ssh, ssl, (double)vn[e], (double)vn[e]);
+                    }
+            }
+        }
+        {
+            T *yd = buf(0, k + 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yd[lown + e * L::PW] = yc[e];
+            if (hact) yd[lhself] = hc;
+        }
+        issueY(k + 2, RY, false);
+
+        // level 0 at plane k on every held row
+        const T *ys = buf(0, k);
+        T cur[H][E], hcur[H];
+        T vc[E], ycen[E];
+        T hb, hv;
+        {
+            const Sel s0m = to_sel(pin0 ? sel_lo(k, nz, MASK, B, nzl) : 0);
+            const Sel s0p = to_sel(pin0 ? sel_hi(k, nz, MASK, B, nzh) : 0);
+            T inU = (T)0, inD = (T)0;
+            if constexpr (TOP) inU = yob; else inU = ys[linU];
+            if constexpr (BOT) inD = yob; else inD = ys[linD];
+#pragma unroll
+            for (int e = 0; e < E; ++e) ycen[e] = ys[lown + e * L::PW];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T c = ycen[e];
+                // x neighbours from the LDS plane, which holds every column of the
+                // tile and its halo
+                const T xm = ys[lown - 1 + e * L::PW], xp = ys[lown + 1 + e * L::PW];
+                const T ym = e == 0 ? inU : ycen[e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : ycen[e < E - 1 ? e + 1 : e];
+                const bool ok = pin0 && rok[e];
+                const T v = FIRST ? c : (ok ? RV.v[e] : (T)0);
+                const T z = (!FIRST && ok) ? RV.z[e] : (T)0;
+                vc[e] = v;
+                const T w = step0(c, xm, xp, ym, yp, ya[e], yc[e], v, z, s0m, s0p, sxm, sxp, sym[e],
+                                  syp[e]);
+                cur[0][e] = ok ? w : (T)0;
+            }
+            // level 0 at the halo point
+            hb = ys[lhself];
+            const T xn = ys[lhnear], d = ys[lhup], u = ys[lhdn];
+            const T xf = hg == H ? ((fload && pin0) ? (T)ghf(RV) : (T)0) : ys[lhfar];
+            const bool ok = hload && pin0 && hlev >= 0;
+            hv = FIRST ? hb : ((hload && pin0) ? RV.hv : (T)0);
+            const T hz = (!FIRST && ok) ? RV.hz : (T)0;
+            const T lft = hside ? xn : xf, rgt = hside ? xf : xn;
+            const T w = step0(hb, lft, rgt, d, u, ha, hc, hv, hz, s0m, s0p, csxl, csxh, csyl, csyh);
+            hcur[0] = ok ? w : (T)0;
+        }
+        {
+            T *wd = buf(1, k);
+#pragma unroll
+            for (int e = 0; e < E; ++e) wd[lown + e * L::PW] = cur[0][e];
+            if (hact && hlev >= 0) wd[lhself] = hcur[0];
+        }
+        issueV(k + 1, RV);
+        issueU(k + 2, RY);
+
+        // levels 1..H: level l at plane k-l from the output of level l-1 at
+        // planes k-l-1 (pv), k-l (LDS, written in the iteration before) and
+        // k-l+1 (this iteration)
+        T cen[H][E], hcen[H];
+#pragma unroll
+        for (int l = 1; l <= H; ++l) {
+            const int lc = l < H ? l : 0;          // index of this level's output (l < H)
+            const int p = k - l;
+            const T *ws = buf(l, p);
+#pragma unroll
+            for (int e = 0; e < E; ++e) cen[l - 1][e] = ws[lown + e * L::PW];
+            hcen[l - 1] = ws[lhself];
+            if (l < H) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) cur[lc][e] = (T)0;
+                hcur[lc] = (T)0;
+            }
+            if (k < k0 - H + 2 * l) continue;     // level l runs on planes k0-(H-l) .. k1-1+(H-l)
+            const bool pinp = inz(p);
+            const Sel slm = to_sel(pinp ? sel_lo(p, nz, MASK, B, nzl) : 0);
+            const Sel slp = to_sel(pinp ? sel_hi(p, nz, MASK, B, nzh) : 0);
+            T inU = (T)0, inD = (T)0;
+            if constexpr (!TOP) inU = ws[linU];
+            if constexpr (!BOT) inD = ws[linD];
+            const size_t po = (size_t)p * PB;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (ydist(e) > H - l) continue;
+                const T c = cen[l - 1][e];
+                const T xm = ws[lown - 1 + e * L::PW], xp = ws[lown + 1 + e * L::PW];
+                const T ym = e == 0 ? inU : cen[l - 1][e > 0 ? e - 1 : 0];
+                const T yp = e == E - 1 ? inD : cen[l - 1][e < E - 1 ? e + 1 : e];
+                const T v = vl[l - 1][e];
+                // z: y_{i-1} at plane k-1 for level 1 (v / theta in a first pass),
+                // else the output of level l-2 at plane k-l
+                const T z = l == 1 ? (FIRST ? v / theta : ya[e]) : pv[l >= 2 ? l - 2 : 0][e];
+                const T w = step(rcs[l], ros[l], c, xm, xp, ym, yp, pv[l - 1][e], cur[l - 1][e], v, z,
+                                 slm, slp, sxm, sxp, sym[e], syp[e]);
+                if (l < H) {
+                    cur[lc][e] = (pinp && rok[e]) ? w : (T)0;
+                } else if (rok[e]) {
+                    if constexpr (!DROP) st_nt((T *)(W1b + po + roff[e]), c);
+                    st_nt((T *)(W2b + po + roff[e]), w);
+                    // the FP32 copy of v for later passes (there are none after a
+                    // first pass that ends the apply)
+                    if constexpr (FIRST && !DROP && sizeof(T) == 4)
+                        st_nt((T *)(V32b + po + roff[e]), v);
+                }
+            }
+            if (l < H) {
+                // level l at the halo point, where hlev >= l
+                const T c = hcen[l - 1];
+                const T xn = ws[lhnear], xf = ws[lhfar], d = ws[lhup], u = ws[lhdn];
+                const T lft = hside ? xn : xf, rgt = hside ? xf : xn;
+                const T v = hvl[l - 1];
+                const T z = l == 1 ? (FIRST ? v / theta : ha) : hpv[l >= 2 ? l - 2 : 0];
+                const T w = step(rcs[l], ros[l], c, lft, rgt, d, u, hpv[l - 1], hcur[l - 1], v, z, slm,
+                                 slp, csxl, csxh, csyl, csyh);
+                hcur[lc] = (hload && pinp && hlev >= l) ? w : (T)0;
+                T *wd = buf(l + 1, p);
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (ydist(e) <= H - l) wd[lown + e * L::PW] = cur[lc][e];
+                if (hact && hlev >= l) wd[lhself] = hcur[lc];
+            }
+        }
+        // rotate: y at plane k, the levels' outputs read as centres, v
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            ya[e] = ycen[e];
+#pragma unroll
+            for (int l = 0; l < H; ++l) pv[l][e] = cen[l][e];
+#pragma unroll
+            for (int l = H - 1; l > 0; --l) vl[l][e] = vl[l - 1][e];
+            vl[0][e] = vc[e];
+        }
+        yob = yoc;
+        ha = hb;
+#pragma unroll
+        for (int l = 0; l < H; ++l) hpv[l] = hcen[l];
+#pragma unroll
+        for (int l = H - 1; l > 0; --l) hvl[l] = hvl[l - 1];
+        hvl[0] = hv;
+        __syncthreads();
+    }
+}
+
+// At most 256 VGPRs (two waves per SIMD)
+template <typename T, typename TU, int S, bool FIRST, bool DROP, int NXW, int PR, int NYW, bool MASK,
+          bool SIMPLE, int UPD = 0>
+__global__ void __launch_bounds__(64 * NXW * NYW) __attribute__((amdgpu_waves_per_eu(2)))
+k_cheb_steps_lds(Work W, KArgs A)
+{
+    using L = LSteps<NXW, PR, NYW, S>;
+    __shared__ T lds[2 * S * L::PLANE];
+    __shared__ double red[2 * NXW * NYW];
+    constexpr int F32 = sizeof(T) == 4;
+    const Prob &P = W.probs[0];
+    const int qkz = P.qkz[F32];
+    if (qkz < 1) return;
+    {
+        const Scalars *sc = P.sc;
+        if (sc->done || (A.second && sc->half_pending)) return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int xw = wv % NXW, yw = wv / NXW;
+    const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
+    const int total = ltx * lty * ((P.nz + qkz - 1) / qkz);
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        // slabs by default, as for the triples
+        const int t = tile_order_tx(W.order ? W.order : 2, ltx, g, total);
+        double ssh = 0.0, ssl = 0.0;
+        if (yw == 0)
+            cheb_steps_lds_tile<T, TU, S, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if (yw == NYW - 1)
+            cheb_steps_lds_tile<T, TU, S, FIRST, DROP, NXW, PR, NYW, R_BOT, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        else if constexpr (NYW > 2)
+            cheb_steps_lds_tile<T, TU, S, FIRST, DROP, NXW, PR, NYW, R_MID, MASK, SIMPLE, UPD>(
+                P, A, t, lane, xw, yw, lds, ssh, ssl);
+        if constexpr (UPD == U_S) {
+            double hh[1] = {ssh}, ll[1] = {ssl};
+            block_reduce_dd<1, NXW * NYW>(hh, ll, red);
+            if (threadIdx.x == 0) {
+                double *pp = P.partials + (size_t)t * PARTIAL_STRIDE;
+                pp[0] = hh[0];
+                pp[1] = ll[0];
+            }
+        }
+    }
+}
+
 // One tile of an elementwise pass for the lanes inside the grid (i < nx);
 // FULL: all RY rows of the wave are inside, so no row guard remains and the
 // loads of a plane issue together.
@@ -2618,6 +3116,49 @@ void launch_cheb_triple(bool mixed, bool mask, const Work &w, hipStream_t s, con
 void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KArgs &a)
 {
     ltr_drop<float, double, true, false>(mask, w, s, a);
+}
+
+// the four-step pass (mixed mode): its own tiles, one workgroup per tile
+template <typename T, typename TU, bool FIRST, bool DROP, bool MASK, bool SIMPLE>
+static void lq_launch(const Work &w, hipStream_t s, const KArgs &a)
+{
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int NXW = quad_nxw(F32), PR = quad_pr(F32), NYW = quad_nyw(F32);
+    const dim3 g(w.quad_tiles[F32]), b(LSteps<NXW, PR, NYW, 4>::NT);
+    if constexpr (FIRST) {
+        if (a.upd == U_S) {
+            hipLaunchKernelGGL((k_cheb_steps_lds<T, TU, 4, true, DROP, NXW, PR, NYW, MASK, SIMPLE, U_S>),
+                               g, b, 0, s, w, a);
+            return;
+        }
+        if (a.upd == U_P) {
+            hipLaunchKernelGGL((k_cheb_steps_lds<T, TU, 4, true, DROP, NXW, PR, NYW, MASK, SIMPLE, U_P>),
+                               g, b, 0, s, w, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_cheb_steps_lds<T, TU, 4, FIRST, DROP, NXW, PR, NYW, MASK, SIMPLE>), g, b, 0, s,
+                       w, a);
+}
+
+template <typename T, typename TU, bool FIRST, bool DROP>
+static void lq_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (mask) lq_launch<T, TU, FIRST, DROP, true, false>(w, s, a);
+    else if (w.neumann) lq_launch<T, TU, FIRST, DROP, false, false>(w, s, a);
+    else lq_launch<T, TU, FIRST, DROP, false, true>(w, s, a);
+}
+
+void launch_cheb_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (a.drop1) lq_drop<float, float, false, true>(mask, w, s, a);
+    else lq_drop<float, float, false, false>(mask, w, s, a);
+}
+
+void launch_cheb_first_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+{
+    if (a.drop1) lq_drop<float, double, true, true>(mask, w, s, a);
+    else lq_drop<float, double, true, false>(mask, w, s, a);
 }
 
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a)

@@ -130,6 +130,8 @@ Work single_work(const poisson_ctx *c, const Prob *prob)
     Work w{prob, nullptr, nullptr, nullptr, c->ntiles, c->tile_order, {0, 0}, c->bc != 0};
     if (c->pair_lds && c->opt.fuse >= 2)
         for (int f = 0; f < 2; ++f) w.triple_tiles[f] = make_triple_tiling(c->nx, c->ny, c->nz, f).ntiles;
+    if (c->pair_lds && c->opt.fuse >= 3)
+        w.quad_tiles[1] = make_quad_tiling(c->nx, c->ny, c->nz, true).ntiles;
     if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
@@ -529,7 +531,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         c->opt.debug_bd = (int)v;
         return POISSON_OK;
     case POISSON_OPT_FUSE:
-        if (v != 0 && v != 1 && v != 2) return POISSON_ERR_ARG;
+        if (v != 0 && v != 1 && v != 2 && v != 3) return POISSON_ERR_ARG;
         c->opt.fuse = (int)v;
         return POISSON_OK;
     case POISSON_OPT_TILE_ORDER:

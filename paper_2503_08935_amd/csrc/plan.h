@@ -40,6 +40,8 @@ Tiling make_tiling(int nx, int ny, int nz);
 Tiling make_pair_tiling(int nx, int ny, int nz, bool fp32);
 // tiles of the LDS-staged Chebyshev triple (64 * triple_nxw x triple_nyw * triple_pr columns)
 Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32);
+// tiles of the LDS-staged four-step pass (64 * quad_nxw x quad_nyw * quad_pr columns)
+Tiling make_quad_tiling(int nx, int ny, int nz, bool fp32);
 bool is_cheb(int pc);
 // interval handed to the Chebyshev iteration; false if degenerate
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,

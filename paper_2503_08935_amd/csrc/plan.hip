@@ -146,6 +146,23 @@ Tiling make_triple_tiling(int nx, int ny, int nz, bool fp32)
     return t;
 }
 
+Tiling make_quad_tiling(int nx, int ny, int nz, bool fp32)
+{
+    Tiling t;
+    const int lx = 64 * quad_nxw(fp32), ly = quad_nyw(fp32) * quad_pr(fp32);
+    t.tx = (nx + lx - 1) / lx;
+    t.ty = (ny + ly - 1) / ly;
+    // the triple's rule: the longest chunk (up to 128 planes) leaving a tile for
+    // every CU
+    int kz = 128;
+    const long base = (long)t.tx * t.ty;
+    while (kz > 8 && base * ((nz + kz - 1) / kz) < 256) kz /= 2;
+    t.kz = std::min(kz, std::max(nz, 1));
+    t.tz = (nz + t.kz - 1) / t.kz;
+    t.ntiles = t.tx * t.ty * t.tz;
+    return t;
+}
+
 bool is_cheb(int pc) { return pc == POISSON_PC_CHEBYSHEV || pc == POISSON_PC_BLOCK_JACOBI; }
 
 bool cheb_interval(int nx, int ny, int nz, double h, unsigned bc, int pc, const PlanOpts &o,
@@ -182,6 +199,8 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
     p.pkz[1] = make_pair_tiling(nx, ny, nz, true).kz;
     p.tkz[0] = make_triple_tiling(nx, ny, nz, false).kz;
     p.tkz[1] = make_triple_tiling(nx, ny, nz, true).kz;
+    p.qkz[0] = make_quad_tiling(nx, ny, nz, false).kz;
+    p.qkz[1] = make_quad_tiling(nx, ny, nz, true).kz;
     p.block = pc == POISSON_PC_BLOCK_JACOBI ? o.block : 0;
     p.bc = bc;
     p.maxit = maxit;
@@ -236,8 +255,9 @@ int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w)
 {
     if (!fused(pc, deg, mixed, fuse) || w.tile_prob || w.pair_prob) return 0;
     const int f = mixed ? 1 : 0;
+    const bool first4 = fuse >= 3 && w.quad_tiles[f] > 0 && mixed && deg >= 4;
     const bool first3 = fuse >= 2 && w.triple_tiles[f] > 0 && mixed && deg >= 5;
-    if (first3) return U_S | U_P;
+    if (first4 || first3) return U_S | U_P;
     return w.pair_tiles[f] > 0 ? (U_S | U_P) : 0;
 }
 
@@ -287,6 +307,7 @@ int partial_slots(int nx, int ny, int nz)
     for (int f = 0; f < 2; ++f) {
         n = std::max(n, make_pair_tiling(nx, ny, nz, f).ntiles);
         n = std::max(n, make_triple_tiling(nx, ny, nz, f).ntiles);
+        n = std::max(n, make_quad_tiling(nx, ny, nz, f).ntiles);
     }
     return n;
 }
@@ -320,20 +341,41 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         // in the mixed mode with degree >= 5 steps 1-3 (in FP64 the two divisions
         // per point of that pass made it slower than a pair: 980 against 605 us)
         const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
-        const bool first3 = tri && mixed && m >= 5;
+        // four steps per pass (mixed mode): steps 1-4 first, then fours, then
+        // what is left as a triple, pair or single step
+        const bool quad = fuse >= 3 && mixed && w.quad_tiles[1] > 0;
+        const bool first4 = quad && m >= 4;
+        const bool first3 = !first4 && tri && mixed && m >= 5;
         // a folded update (upd): the first pass forms its input itself; the
         // half-step test of a formed s follows that pass
         const int f = mixed ? 1 : 0;
-        const int parts = first3 ? w.triple_tiles[f] : w.pair_tiles[f];
-        const KArgs a1{vin, V_RA, vin, 0, 1, second, 0, V_RB, 0, upd, parts};
-        if (first3)
+        const int parts = first4 ? w.quad_tiles[f] : (first3 ? w.triple_tiles[f] : w.pair_tiles[f]);
+        // a first pass of four steps that ends the apply writes w_4 alone
+        const bool only4 = first4 && m == 4;
+        const KArgs a1{vin, V_RA, vin, 0, 1, second, 0, only4 ? vout : V_RB, only4 ? 1 : 0, upd, parts};
+        if (first4)
+            launch_cheb_first_quad(mask, w, s, a1);
+        else if (first3)
             launch_cheb_first_triple(mask, w, s, a1);
         else
             launch_cheb_first_pair(mixed, mask, w, grid, s, a1);
         if (upd == U_S) launch_finalize_ss(w, grid, s, a1);
+        if (only4) return;
         const int ring[4] = {V_RA, V_RB, V_RC, V_RD};
         int y = V_RB, z = V_RA;
-        int i = first3 ? 4 : 3;
+        int i = first4 ? 5 : (first3 ? 4 : 3);
+        if (quad) {
+            for (; i + 3 <= m; i += 4) {
+                int o[2], n = 0;
+                for (int b : ring)
+                    if (b != y && b != z && n < 2) o[n++] = b;
+                const bool last = i + 3 == m;
+                const int w4 = last ? vout : o[1];
+                launch_cheb_quad(mask, w, s, KArgs{y, o[0], vsrc, z, i, second, 0, w4, last ? 1 : 0});
+                z = o[0];
+                y = w4;
+            }
+        }
         if (tri) {
             for (; i + 2 <= m; i += 3) {
                 int o[2], n = 0;
@@ -405,20 +447,30 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd)
     else if (is_cheb(pc)) {
         const double tc = mixed ? 4 : 8;
         if (fused(pc, m, mixed, fuse)) {
-            // steps 1-2 (or 1-3, mixed with triples): v in; two outputs (+ v32) out
-            pcb = 8 + 2 * tc + (mixed ? 4 : 0);
-            const bool tri = fuse >= 2;
-            int steps = m - ((tri && mixed && m >= 5) ? 3 : 2);
-            int passes = 0;                             // passes of two or three steps
-            if (tri) {                                  // triples: y, z, v in; w_{i+1}, w_{i+2} out
-                pcb += (steps / 3) * 5 * tc;
-                passes += steps / 3;
-                steps %= 3;
+            // steps 1-2 (or 1-3, mixed with triples; 1-4 mixed with fours): v in;
+            // two outputs (+ v32) out, or w_4 alone when that pass ends the apply
+            const bool tri = fuse >= 2, quad = fuse >= 3 && mixed;
+            if (quad && m == 4) {
+                pcb = 8 + tc;
+            } else {
+                pcb = 8 + 2 * tc + (mixed ? 4 : 0);
+                int steps = m - ((quad && m >= 4) ? 4 : ((tri && mixed && m >= 5) ? 3 : 2));
+                int passes = 0;                         // passes after the first one
+                if (quad) {                             // fours: y, z, v in; two outputs
+                    pcb += (steps / 4) * 5 * tc;
+                    passes += steps / 4;
+                    steps %= 4;
+                }
+                if (tri) {                              // triples: y, z, v in; w_{i+1}, w_{i+2} out
+                    pcb += (steps / 3) * 5 * tc;
+                    passes += steps / 3;
+                    steps %= 3;
+                }
+                pcb += (steps / 2) * 5 * tc;            // pairs: y, z, v in; w_i, w_{i+1} out
+                passes += steps / 2;
+                if (steps & 1) pcb += 4 * tc;           // last step alone: y, v, z, w
+                else if (passes > 0) pcb -= tc;         // the last pass stores w_m only
             }
-            pcb += (steps / 2) * 5 * tc;                // pairs: y, z, v in; w_i, w_{i+1} out
-            passes += steps / 2;
-            if (steps & 1) pcb += 4 * tc;               // last step alone: y, v, z, w
-            else if (passes > 0) pcb -= tc;             // the last pass stores w_m only
         } else {
             pcb = 8 + tc + (mixed ? 4 : 0);             // first step: v, y (+ v32)
             if (m >= 2) pcb += 3 * tc;                  // step 2: y, v, w

@@ -24,7 +24,8 @@ using namespace pz;
 
 namespace {
 
-enum Kind { K_STENCIL, K_ELEM, K_PAIR, K_FIRST_PAIR, K_TRIPLE, K_FIRST_TRIPLE, K_FIN_SS };
+enum Kind { K_STENCIL, K_ELEM, K_PAIR, K_FIRST_PAIR, K_TRIPLE, K_FIRST_TRIPLE, K_QUAD, K_FIRST_QUAD,
+            K_FIN_SS };
 
 struct Launch {
     Kind kind;
@@ -73,6 +74,14 @@ void launch_cheb_first_triple(bool, const Work &, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_TRIPLE, 0, true, a});
 }
+void launch_cheb_quad(bool, const Work &, hipStream_t, const KArgs &a)
+{
+    g_log.push_back({K_QUAD, 0, true, a});
+}
+void launch_cheb_first_quad(bool, const Work &, hipStream_t, const KArgs &a)
+{
+    g_log.push_back({K_FIRST_QUAD, 0, true, a});
+}
 void launch_finalize_ss(const Work &, int, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIN_SS, 0, false, a});
@@ -98,8 +107,11 @@ double launch_bytes(const Launch &l, int pc)
         return vin + 2 * tc + (l.mixed ? 4 : 0);        // v in; y_1, w_2 (+ v32) out
     case K_FIRST_TRIPLE:
         return vin + 2 * tc + 4;                        // v in; y_2, y_3, v32 out
+    case K_FIRST_QUAD:                                  // v in; y_3, y_4, v32 out, or y_4
+        return l.a.drop1 ? vin + tc : vin + 2 * tc + 4;
     case K_PAIR:
     case K_TRIPLE:
+    case K_QUAD:
         return (l.a.drop1 ? 4 : 5) * tc;                // y, z, v in; one or two outputs
     case K_STENCIL:
         switch (l.op) {
@@ -138,6 +150,7 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
     Work w{};
     w.count = 1;
     if (lds && fuse >= 2) w.triple_tiles[0] = w.triple_tiles[1] = 7;
+    if (lds && fuse >= 3) w.quad_tiles[1] = 7;
     if (lds) w.pair_tiles[0] = w.pair_tiles[1] = 7;
     const int upd = fold ? upd_fusion(pc, deg, mixed, fuse, w) : 0;
     if (fold && !upd) return;
@@ -161,8 +174,8 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
             CHECK(k > 0 && g_log[k - 1].a.upd == U_S && l.a.nparts == 7, "%s: finalize", tag);
         }
         if (l.a.upd && l.kind != K_FIN_SS)
-            CHECK(l.kind == K_FIRST_PAIR || l.kind == K_FIRST_TRIPLE, "%s: upd on kind %d", tag,
-                  (int)l.kind);
+            CHECK(l.kind == K_FIRST_PAIR || l.kind == K_FIRST_TRIPLE || l.kind == K_FIRST_QUAD,
+                  "%s: upd on kind %d", tag, (int)l.kind);
     }
     CHECK(n_axpy == ((upd & U_S) ? 0 : 1) && n_pupd == ((upd & U_P) ? 0 : 1) &&
               n_fin == ((upd & U_S) ? 1 : 0),
@@ -181,7 +194,7 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
         }
         const KArgs &a = l.a;
         const bool first = l.kind == K_FIRST_PAIR || l.kind == K_FIRST_TRIPLE ||
-                           (l.kind == K_STENCIL && l.op == S_CHEB1);
+                           l.kind == K_FIRST_QUAD || (l.kind == K_STENCIL && l.op == S_CHEB1);
         if (first) {
             ++applies;
             expect_in = applies == 1 ? (int)V_P : (int)V_R;
@@ -215,7 +228,8 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
         size_t nk = k + 1;
         while (nk < g_log.size() && g_log[nk].kind == K_FIN_SS) ++nk;
         const bool last = nk == g_log.size() || !is_cheb_launch(g_log[nk]) ||
-                          g_log[nk].kind == K_FIRST_PAIR || g_log[nk].kind == K_FIRST_TRIPLE;
+                          g_log[nk].kind == K_FIRST_PAIR || g_log[nk].kind == K_FIRST_TRIPLE ||
+                          g_log[nk].kind == K_FIRST_QUAD;
         if (last) {
             const int fin = prev_x2 >= 0 ? prev_x2 : prev_out;
             CHECK(fin == (applies == 1 ? (int)V_PH : (int)V_SH), "%s: apply %d ends in slot %d",
@@ -276,7 +290,7 @@ int main()
     for (int pc : pcs)
         for (int deg = 0; deg <= 12; ++deg)
             for (int mixed = 0; mixed < 2; ++mixed)
-                for (int fuse = 0; fuse <= 2; ++fuse)
+                for (int fuse = 0; fuse <= 3; ++fuse)
                     for (int lds = 0; lds < 2; ++lds)
                         for (int fold = 0; fold < 2; ++fold) {
                             if (!is_cheb(pc) && deg) continue;
@@ -295,7 +309,8 @@ int main()
             const Tiling a = make_tiling(n, n + 1, n + 2);
             const Tiling b = make_pair_tiling(n, n + 1, n + 2, f);
             const Tiling c = make_triple_tiling(n, n + 1, n + 2, f);
-            for (const Tiling &t : {a, b, c})
+            const Tiling d = make_quad_tiling(n, n + 1, n + 2, f);
+            for (const Tiling &t : {a, b, c, d})
                 CHECK(t.kz >= 1 && (long)t.tz * t.kz >= n + 2 && t.ntiles == t.tx * t.ty * t.tz,
                       "tiling n %d", n);
         }
