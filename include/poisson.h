@@ -89,13 +89,13 @@ enum {
     POISSON_OPT_USE_GRAPH = 7,          /* 1 = replay captured HIP graphs (default), 0 = launch */
     POISSON_OPT_DEBUG_BREAKDOWN_AT = 8, /* testing: force omega = 0 at this iteration (-1 off) */
     POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
-                                           mixed): run Chebyshev steps three per pass where
-                                           the passes are LDS-staged (2, default; the steps
-                                           left over, and the first two, run as pairs or
-                                           alone), two per pass (1) or one per pass (0);
-                                           3: in the mixed mode four per pass from degree 4
-                                           (steps 1-4 first, then fours, then the rest as
-                                           above), FP64 as 2; same arithmetic, same
+                                           mixed): 3 (default) in the mixed mode four steps
+                                           per pass from degree 4 (steps 1-4 first, then
+                                           fours, then the rest as for 2), FP64 as 2;
+                                           2: three per pass where the passes are
+                                           LDS-staged (the steps left over, and the first
+                                           two, run as pairs or alone); two per pass (1)
+                                           or one per pass (0); same arithmetic, same
                                            results */
     POISSON_OPT_TILE_ORDER = 10,        /* order in which workgroups take tiles: 0 default
                                            (natural; x-grouped for the FP32 fused Chebyshev

