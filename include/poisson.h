@@ -115,8 +115,10 @@ enum {
                                            inside the first pass of the next iteration's
                                            first apply, instead of in passes of their own;
                                            0 keeps the separate update passes; 2 (default)
-                                           folds from 352^3 unknowns on, where it was
-                                           measured faster; same arithmetic, same results */
+                                           folds from 352^3 unknowns on, and from 128^3
+                                           when the first pass runs four steps (mixed,
+                                           degree >= 4), where it was measured faster;
+                                           same arithmetic, same results */
 };
 
 /* ---- solver context ----------------------------------------------------- */

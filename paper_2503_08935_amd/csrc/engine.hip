@@ -143,19 +143,27 @@ int plan_fuse_level(const poisson_ctx *c)
     return (c->opt.fuse >= 2 && !c->pair_lds) ? 1 : c->opt.fuse;
 }
 
-// Unknowns from which the folds pay by default. Below, the vectors partly fit
-// the 256 MB Infinity Cache, the standalone update passes run from it, and the
-// folded first passes' extra halo reads cost more than the passes they replace
-// (measured per iteration, Chebyshev 4 and 8, FP64 and mixed: 0.7-3.8% slower
-// at 256^3-320^3, 1.5-2.5% faster at 384^3, 3.6-5.5% faster at 512^3).
+// Unknowns from which the folds pay by default when the first pass of an apply
+// runs two or three steps. Below, the vectors partly fit the 256 MB Infinity
+// Cache, the standalone update passes run from it, and the folded first passes'
+// extra halo reads cost more than the passes they replace (measured per
+// iteration, Chebyshev 4 and 8, FP64 and mixed: 0.7-3.8% slower at 256^3-320^3,
+// 1.5-2.5% faster at 384^3, 3.6-5.5% faster at 512^3). With a first pass of
+// four steps (mixed, degree >= 4) the folds pay from 128^3 (Chebyshev 4 and 8:
+// 1-3% faster at 128^3-192^3 but for +0.7% at 192^3 degree 8, 3-14% at 256^3-
+// 512^3); at 64^3 and 96^3, where launches dominate, they cost 2-5%.
 constexpr size_t FOLD_MIN_UNKNOWNS = (size_t)352 * 352 * 352;
+constexpr size_t FOLD_MIN_UNKNOWNS_FOURS = (size_t)128 * 128 * 128;
 
 // the vector updates a solve of this plan folds into the applies' first passes
 int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
     if (!c->fuse_updates) return 0;
-    if (c->fuse_updates == 2 && c->N < FOLD_MIN_UNKNOWNS) return 0;
-    return upd_fusion(pc, deg, mixed, c->opt.fuse, single_work(c, nullptr));
+    const Work w = single_work(c, nullptr);
+    const bool first4 = mixed && deg >= 4 && c->opt.fuse >= 3 && w.quad_tiles[1] > 0;
+    if (c->fuse_updates == 2 && c->N < (first4 ? FOLD_MIN_UNKNOWNS_FOURS : FOLD_MIN_UNKNOWNS))
+        return 0;
+    return upd_fusion(pc, deg, mixed, c->opt.fuse, w);
 }
 
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)

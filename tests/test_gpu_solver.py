@@ -235,14 +235,16 @@ def test_three_steps_per_pass_solve(gpu, mixed):
 def test_byte_model_per_iteration(gpu):
     """The stats' model bytes follow the passes the plan runs: FP64 Chebyshev-8 moves
     632 B per unknown and iteration with one step per pass, 440 with two, 360 with
-    steps 1-2, 3-5 and 6-8; mixed 264. Folding the s and p updates into the first
-    passes (the default for the fused plans) saves 8 B each: 424, 344 and 248."""
+    steps 1-2, 3-5 and 6-8; mixed 264 with steps 1-3, 4-6, 7-8 and 224 with 1-4, 5-8.
+    Folding the s and p updates into the first passes saves 8 B each: 424, 344, 248
+    and 208."""
     shape = (64, 48, 40)
     n = 64 * 48 * 40
     f = workloads.uniform_grid(5, shape)
     for fuse, mixed, fold, per in ((0, False, 1, 632), (1, False, 0, 440), (2, False, 0, 360),
                                    (2, True, 0, 264), (1, False, 1, 424), (2, False, 1, 344),
-                                   (2, True, 1, 248)):
+                                   (2, True, 1, 248), (3, True, 0, 224), (3, True, 1, 208),
+                                   (3, False, 1, 344)):
         st, stats, tr, x = gpu_solve(shape, 1.0 / 65, f, P.PC_CHEBYSHEV, 8, 1e-8, fuse=fuse,
                                      fuse_updates=fold, precision=P.MIXED if mixed else P.FP64)
         assert st == P.OK
@@ -265,3 +267,22 @@ def test_update_folding_follows_the_grid_size(gpu):
             stats = s.stats()
         assert st == P.NOT_CONVERGED and stats["iterations"] == 2
         assert stats["model_bytes"] == per * n * 2, shape
+
+
+def test_update_folding_with_four_step_passes(gpu):
+    """A mixed plan whose applies start with a four-step pass (degree >= 4) folds the
+    updates by default from 128^3 unknowns on; below 352^3 a mixed plan of degree 3
+    (first pass: two steps) does not, and below 128^3 neither does."""
+    for deg, folded, shape in ((8, True, (128, 128, 128)), (4, True, (128, 128, 128)),
+                               (3, False, (128, 128, 128)), (8, False, (128, 128, 127))):
+        f = workloads.uniform_grid(6, shape)
+        got = {}
+        for fold in (None, 0, 1):
+            opts = {} if fold is None else dict(fuse_updates=fold)
+            st, stats, tr, x = gpu_solve(shape, 1.0 / 129, f, P.PC_CHEBYSHEV, deg, 1e-12,
+                                         maxit=3, precision=P.MIXED, **opts)
+            assert st == P.NOT_CONVERGED and stats["iterations"] == 3
+            got[fold] = (stats["model_bytes"], x)
+        assert got[1][0] < got[0][0]
+        assert got[None][0] == got[1 if folded else 0][0], deg
+        assert np.array_equal(got[None][1], got[0][1]) and np.array_equal(got[1][1], got[0][1])
