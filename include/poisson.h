@@ -315,7 +315,12 @@ enum {
                                             folded away, as in poisson_solve from 352^3; two
                                             more FP64 vectors per request); 0: standalone
                                             update passes. Same results either way. Set
-                                            before the first submit */
+                                            before the first submit */,
+    POISSON_SERVER_OPT_FOUR_STEPS = 4    /* 1 (default): mixed Chebyshev and Block-Jacobi
+                                            plans of degree >= 4 run their applies four
+                                            steps per pass (steps 1-4 first, as
+                                            poisson_solve does); 0: pairs. Same results
+                                            either way. Set before the first submit */
 };
 
 /* Create a server. hip_stream: the caller's stream (NULL = null stream); the

@@ -31,6 +31,7 @@ EXPORTS = [
     "poisson_server_destroy",
 ]
 SERVER_OPT_USE_GRAPH, SERVER_OPT_SIZE_CLASSES, SERVER_OPT_FUSE_UPDATES = 1, 2, 3
+SERVER_OPT_FOUR_STEPS = 4
 
 
 class Stats(ctypes.Structure):
@@ -287,7 +288,7 @@ class Server:
     """Continuous-batching server (poisson_server_*): FIFO admission by HBM footprint."""
 
     def __init__(self, budget_bytes, max_slots=64, stream=None, use_graph=True, size_classes=None,
-                 fuse_updates=None):
+                 fuse_updates=None, four_steps=None):
         srv = ctypes.c_void_p()
         self._stream = stream
         _check(lib().poisson_server_create(int(budget_bytes), int(max_slots),
@@ -304,6 +305,9 @@ class Server:
         if fuse_updates is not None:
             _check(lib().poisson_server_set_option(srv, SERVER_OPT_FUSE_UPDATES,
                                                    float(fuse_updates)),
+                   "poisson_server_set_option")
+        if four_steps is not None:
+            _check(lib().poisson_server_set_option(srv, SERVER_OPT_FOUR_STEPS, float(four_steps)),
                    "poisson_server_set_option")
 
     def close(self):

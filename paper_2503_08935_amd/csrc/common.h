@@ -118,6 +118,11 @@ struct Work {
     const int *pair_prob;
     const int *pair_local;
     const int *pair_count_dev;
+    // batched problems: the four-step passes' tile list (null: single problem, or
+    // no four-step passes)
+    const int *quad_prob;
+    const int *quad_local;
+    const int *quad_count_dev;
 };
 
 // operations of the stencil kernel family
@@ -170,8 +175,15 @@ void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipS
                             const KArgs &a);
 // the half-step test on the s.s partials of a first pass with a.upd = U_S
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a);
-void launch_cheb_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a);
-void launch_cheb_first_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a);
+// four fused Chebyshev steps i..i+3 (mixed mode), LDS-staged: in = y_{i-1}, z = y_{i-2},
+// v; out = w_{i+2}, x2 = w_{i+3}; drop1: w_{i+2} is not stored. Single problems
+// launch one workgroup per tile; batched ones (w.quad_prob) `grid` workgroups
+// over the list
+void launch_cheb_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
+// steps 1-4 in one pass: in = v (FP64), out = y_3, x2 = w_4 and the FP32 copy of v
+// (drop1: w_4 alone, the apply's output, when the degree is 4); a.upd as for the
+// first pair
+void launch_cheb_first_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
 // three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored

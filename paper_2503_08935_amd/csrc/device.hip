@@ -2718,20 +2718,31 @@ k_cheb_steps_lds(Work W, KArgs A)
     __shared__ T lds[2 * S * L::PLANE];
     __shared__ double red[2 * NXW * NYW];
     constexpr int F32 = sizeof(T) == 4;
-    const Prob &P = W.probs[0];
-    const int qkz = P.qkz[F32];
-    if (qkz < 1) return;
-    {
-        const Scalars *sc = P.sc;
-        if (sc->done || (A.second && sc->half_pending)) return;
-    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int xw = wv % NXW, yw = wv / NXW;
-    const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
-    const int total = ltx * lty * ((P.nz + qkz - 1) / qkz);
+    // batched problems walk the four-step tile list; a single problem all its
+    // tiles. A skipped tile is skipped by the whole workgroup, so every wave runs
+    // the same barriers
+    int total;
+    if (W.quad_prob) {
+        total = *W.quad_count_dev;
+    } else {
+        const Prob &P = W.probs[0];
+        const int qkz = P.qkz[F32];
+        if (qkz < 1) return;
+        const int ltx = (P.nx + L::X - 1) / L::X, lty = (P.ny + L::Y - 1) / L::Y;
+        total = ltx * lty * ((P.nz + qkz - 1) / qkz);
+    }
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        // slabs by default, as for the triples
-        const int t = tile_order_tx(W.order ? W.order : 2, ltx, g, total);
+        const Prob &P = W.probs[W.quad_prob ? W.quad_prob[g] : 0];
+        if (P.qkz[F32] < 1) continue;
+        {
+            const Scalars *sc = P.sc;
+            if (sc->done || (A.second && sc->half_pending)) continue;
+        }
+        // a single problem's tiles in slabs by default, as for the triples
+        const int ltx = (P.nx + L::X - 1) / L::X;
+        const int t = W.quad_prob ? W.quad_local[g] : tile_order_tx(W.order ? W.order : 2, ltx, g, total);
         double ssh = 0.0, ssl = 0.0;
         if (yw == 0)
             cheb_steps_lds_tile<T, TU, S, FIRST, DROP, NXW, PR, NYW, R_TOP, MASK, SIMPLE, UPD>(
@@ -3120,11 +3131,11 @@ void launch_cheb_first_triple(bool mask, const Work &w, hipStream_t s, const KAr
 
 // the four-step pass (mixed mode): its own tiles, one workgroup per tile
 template <typename T, typename TU, bool FIRST, bool DROP, bool MASK, bool SIMPLE>
-static void lq_launch(const Work &w, hipStream_t s, const KArgs &a)
+static void lq_launch(const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NXW = quad_nxw(F32), PR = quad_pr(F32), NYW = quad_nyw(F32);
-    const dim3 g(w.quad_tiles[F32]), b(LSteps<NXW, PR, NYW, 4>::NT);
+    const dim3 g(w.quad_prob ? grid : w.quad_tiles[F32]), b(LSteps<NXW, PR, NYW, 4>::NT);
     if constexpr (FIRST) {
         if (a.upd == U_S) {
             hipLaunchKernelGGL((k_cheb_steps_lds<T, TU, 4, true, DROP, NXW, PR, NYW, MASK, SIMPLE, U_S>),
@@ -3142,23 +3153,23 @@ static void lq_launch(const Work &w, hipStream_t s, const KArgs &a)
 }
 
 template <typename T, typename TU, bool FIRST, bool DROP>
-static void lq_drop(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+static void lq_drop(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (mask) lq_launch<T, TU, FIRST, DROP, true, false>(w, s, a);
-    else if (w.neumann) lq_launch<T, TU, FIRST, DROP, false, false>(w, s, a);
-    else lq_launch<T, TU, FIRST, DROP, false, true>(w, s, a);
+    if (mask) lq_launch<T, TU, FIRST, DROP, true, false>(w, grid, s, a);
+    else if (w.neumann) lq_launch<T, TU, FIRST, DROP, false, false>(w, grid, s, a);
+    else lq_launch<T, TU, FIRST, DROP, false, true>(w, grid, s, a);
 }
 
-void launch_cheb_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+void launch_cheb_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (a.drop1) lq_drop<float, float, false, true>(mask, w, s, a);
-    else lq_drop<float, float, false, false>(mask, w, s, a);
+    if (a.drop1) lq_drop<float, float, false, true>(mask, w, grid, s, a);
+    else lq_drop<float, float, false, false>(mask, w, grid, s, a);
 }
 
-void launch_cheb_first_quad(bool mask, const Work &w, hipStream_t s, const KArgs &a)
+void launch_cheb_first_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (a.drop1) lq_drop<float, double, true, true>(mask, w, s, a);
-    else lq_drop<float, double, true, false>(mask, w, s, a);
+    if (a.drop1) lq_drop<float, double, true, true>(mask, w, grid, s, a);
+    else lq_drop<float, double, true, false>(mask, w, grid, s, a);
 }
 
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a)

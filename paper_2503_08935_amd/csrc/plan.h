@@ -71,7 +71,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
                 int vin, int vout, int second, int upd = 0);
 void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixed,
                        int fuse, int upd = 0);
-double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd = 0);
+double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd = 0, bool triples = true);
 int validate_ptr(const void *p);
 double now_ms();
 

@@ -344,7 +344,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
         // four steps per pass (mixed mode): steps 1-4 first, then fours, then
         // what is left as a triple, pair or single step
-        const bool quad = fuse >= 3 && mixed && w.quad_tiles[1] > 0;
+        const bool quad = fuse >= 3 && mixed && (w.quad_tiles[1] > 0 || w.quad_prob);
         const bool first4 = quad && m >= 4;
         const bool first3 = !first4 && tri && mixed && m >= 5;
         // a folded update (upd): the first pass forms its input itself; the
@@ -355,7 +355,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         const bool only4 = first4 && m == 4;
         const KArgs a1{vin, V_RA, vin, 0, 1, second, 0, only4 ? vout : V_RB, only4 ? 1 : 0, upd, parts};
         if (first4)
-            launch_cheb_first_quad(mask, w, s, a1);
+            launch_cheb_first_quad(mask, w, grid, s, a1);
         else if (first3)
             launch_cheb_first_triple(mask, w, s, a1);
         else
@@ -372,7 +372,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
                     if (b != y && b != z && n < 2) o[n++] = b;
                 const bool last = i + 3 == m;
                 const int w4 = last ? vout : o[1];
-                launch_cheb_quad(mask, w, s, KArgs{y, o[0], vsrc, z, i, second, 0, w4, last ? 1 : 0});
+                launch_cheb_quad(mask, w, grid, s, KArgs{y, o[0], vsrc, z, i, second, 0, w4, last ? 1 : 0});
                 z = o[0];
                 y = w4;
             }
@@ -438,7 +438,7 @@ void enqueue_iteration(const Work &w, int grid, hipStream_t s, int pc, int m, bo
 }
 
 // algorithmic bytes per unknown of one iteration of a plan
-double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd)
+double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd, bool triples)
 {
     const bool pm = mixed && pc != POISSON_PC_NONE;
     const double tp = pm ? 4 : 8;
@@ -450,7 +450,7 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd)
         if (fused(pc, m, mixed, fuse)) {
             // steps 1-2 (or 1-3, mixed with triples; 1-4 mixed with fours): v in;
             // two outputs (+ v32) out, or w_4 alone when that pass ends the apply
-            const bool tri = fuse >= 2, quad = fuse >= 3 && mixed;
+            const bool tri = fuse >= 2 && triples, quad = fuse >= 3 && mixed;
             if (quad && m == 4) {
                 pcb = 8 + tc;
             } else {

@@ -128,10 +128,12 @@ struct TileList {
 struct Group {
     TileList tiles;
     TileList ptiles;          // tiles of the LDS-staged Chebyshev pairs
+    TileList qtiles;          // tiles of the four-step passes (mixed, degree >= 4)
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
     int graph_cap = -1;       // capacities the graph was captured with
     int pgraph_cap = -1;
+    int qgraph_cap = -1;
     bool dirty = true;        // tile list must be rebuilt
 };
 
@@ -177,6 +179,8 @@ struct poisson_server {
     bool use_graph = true;
     int nclasses = 3;               // size classes, each on a stream of its own
     bool fuse_updates = true;       // fold the s and p updates into the first passes
+    bool four_steps = true;         // mixed Chebyshev applies of degree >= 4: four steps
+                                    // per pass (pairs otherwise)
     char *arena_base = nullptr;
     Arena arena;
     size_t in_use = 0, peak = 0;
@@ -279,14 +283,24 @@ void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids
         }
 }
 
-// the LDS-staged pairs' tiles of the requests in ids (make_pair_tiling)
-void list_pair_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids, bool fp32)
+// whether a plan group's applies run four Chebyshev steps per pass: mixed
+// Chebyshev or Block-Jacobi of degree >= 4, as in single solves
+bool server_four(const poisson_server *s, int pc, int deg, int prec)
+{
+    return s->four_steps && prec == POISSON_MIXED && is_cheb(pc) && deg >= 4;
+}
+
+// the LDS-staged pairs' (make_pair_tiling) or four-step passes' (make_quad_tiling)
+// tiles of the requests in ids
+void list_pair_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids, bool fp32,
+                     bool four = false)
 {
     t.h_prob.clear();
     t.h_local.clear();
     for (int id : slot_ids) {
         const Request &rq = s->slots[id].req;
-        const int n = make_pair_tiling(rq.nx, rq.ny, rq.nz, fp32).ntiles;
+        const int n = four ? make_quad_tiling(rq.nx, rq.ny, rq.nz, fp32).ntiles
+                           : make_pair_tiling(rq.nx, rq.ny, rq.nz, fp32).ntiles;
         for (int l = 0; l < n; ++l) {
             t.h_prob.push_back(id);
             t.h_local.push_back(l);
@@ -299,8 +313,8 @@ Work work_of(const poisson_server *s, const TileList &t)
     return Work{s->d_probs, t.d_prob, t.d_local, t.d_count, t.count, 0};
 }
 
-// the work of a plan group: its tile list, and the pair tile list for the
-// LDS-staged Chebyshev pairs
+// the work of a plan group: its tile list, the pair tile list for the LDS-staged
+// Chebyshev pairs, and the four-step passes' tile list where they run
 Work group_work(const poisson_server *s, const PlanKey &k, const Group &g, int count)
 {
     Work w{s->d_probs, g.tiles.d_prob, g.tiles.d_local, g.tiles.d_count, count, 0};
@@ -308,7 +322,18 @@ Work group_work(const poisson_server *s, const PlanKey &k, const Group &g, int c
     w.pair_prob = g.ptiles.d_prob;
     w.pair_local = g.ptiles.d_local;
     w.pair_count_dev = g.ptiles.d_count;
+    if (server_four(s, k.pc, k.deg, k.mixed)) {
+        w.quad_prob = g.qtiles.d_prob;
+        w.quad_local = g.qtiles.d_local;
+        w.quad_count_dev = g.qtiles.d_count;
+    }
     return w;
+}
+
+// steps per pass of a plan group's applies (enqueue_iteration's fuse)
+int group_fuse(const poisson_server *s, const PlanKey &k)
+{
+    return server_four(s, k.pc, k.deg, k.mixed) ? 3 : 1;
 }
 
 // retire finished requests of class c (its stream is idle): true residuals in one
@@ -356,8 +381,9 @@ int finish_requests(poisson_server *s, int c, const std::vector<int> &ids)
         st.solve_ms = t - sl.req.t_submit;   // arrival to completion
         st.loop_ms = t - sl.t_admit;         // admission to completion
         const double N = (double)sl.req.nx * sl.req.ny * sl.req.nz;
-        st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED, 1) * N *
-                         sc.iter;
+        st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED,
+                                         server_four(s, sl.req.pc, sl.req.deg, sl.req.prec) ? 3 : 1,
+                                         sl.req.upd, false) * N * sc.iter;
         st.model_gbps = 0;
         s->results[sl.req.ticket] = r;
         s->arena.release(sl.off, sl.req.footprint);
@@ -379,12 +405,13 @@ int capture_group(poisson_server *s, const PlanKey &k, Group &g)
     }
     const Work w = group_work(s, k, g, 0);
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, 1,
+    enqueue_iteration(w, GRID, s->cap_stream, k.pc, k.deg, k.mixed != 0, group_fuse(s, k),
                       server_upd(k.pc, k.deg, k.mixed, s->fuse_updates));
     HIPCHK(hipStreamEndCapture(s->cap_stream, &g.graph_src));
     HIPCHK(hipGraphInstantiate(&g.graph, g.graph_src, nullptr, nullptr, 0));
     g.graph_cap = g.tiles.cap;
     g.pgraph_cap = g.ptiles.cap;
+    g.qgraph_cap = g.qtiles.cap;
     return POISSON_OK;
 }
 
@@ -510,7 +537,9 @@ int round_impl(poisson_server *s, int iters, int &progress)
         // with s formed in the first pass, its s.s is in that pass's tile partials
         if (sl.req.upd & U_S)
             p.nparts_first =
-                make_pair_tiling(sl.req.nx, sl.req.ny, sl.req.nz, sl.req.prec == POISSON_MIXED).ntiles;
+                server_four(s, sl.req.pc, sl.req.deg, sl.req.prec)
+                    ? make_quad_tiling(sl.req.nx, sl.req.ny, sl.req.nz, true).ntiles
+                    : make_pair_tiling(sl.req.nx, sl.req.ny, sl.req.nz, sl.req.prec == POISSON_MIXED).ntiles;
         p.vec[V_X] = sl.req.x;
         p.vec[V_B] = (void *)sl.req.rhs;
         p.partials = (double *)(blk + sl.req.ws_bytes);
@@ -558,15 +587,21 @@ int round_impl(poisson_server *s, int iters, int &progress)
                 }
                 list_tiles(s, g.tiles, ids);
                 list_pair_tiles(s, g.ptiles, ids, kv.first.mixed == POISSON_MIXED);
-                bool moved, pmoved;
+                const bool four = server_four(s, kv.first.pc, kv.first.deg, kv.first.mixed);
+                bool moved, pmoved, qmoved = false;
                 if ((rc = upload_tiles(k.stream, g.tiles, moved)) != POISSON_OK) return rc;
                 if ((rc = upload_tiles(k.stream, g.ptiles, pmoved)) != POISSON_OK) return rc;
-                if ((moved || pmoved) && g.graph) g.graph_cap = -1;
+                if (four) {
+                    list_pair_tiles(s, g.qtiles, ids, true, true);
+                    if ((rc = upload_tiles(k.stream, g.qtiles, qmoved)) != POISSON_OK) return rc;
+                }
+                if ((moved || pmoved || qmoved) && g.graph) g.graph_cap = -1;
                 g.dirty = false;
             }
             if (g.tiles.count == 0) continue;
             if (s->use_graph) {
-                if ((g.graph_cap != g.tiles.cap || g.pgraph_cap != g.ptiles.cap) &&
+                if ((g.graph_cap != g.tiles.cap || g.pgraph_cap != g.ptiles.cap ||
+                     g.qgraph_cap != g.qtiles.cap) &&
                     (rc = capture_group(s, kv.first, g)) != POISSON_OK)
                     return rc;
                 for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(g.graph, k.stream));
@@ -574,7 +609,7 @@ int round_impl(poisson_server *s, int iters, int &progress)
                 const Work w = group_work(s, kv.first, g, g.tiles.count);
                 for (int i = 0; i < iters; ++i)
                     enqueue_iteration(w, GRID, k.stream, kv.first.pc, kv.first.deg,
-                                      kv.first.mixed != 0, 1,
+                                      kv.first.mixed != 0, group_fuse(s, kv.first),
                                       server_upd(kv.first.pc, kv.first.deg, kv.first.mixed,
                                                  s->fuse_updates));
                 HIPCHK(hipGetLastError());
@@ -624,6 +659,12 @@ int poisson_server_set_option(poisson_server *s, int key, double value)
         // fixed once a request was submitted (its workspace is sized by it)
         if (s->next_ticket != 1 || (value != 0 && value != 1)) return POISSON_ERR_ARG;
         s->fuse_updates = value != 0;
+        return POISSON_OK;
+    }
+    if (key == POISSON_SERVER_OPT_FOUR_STEPS) {
+        // fixed once a request was submitted (its partials follow the tiling)
+        if (s->next_ticket != 1 || (value != 0 && value != 1)) return POISSON_ERR_ARG;
+        s->four_steps = value != 0;
         return POISSON_OK;
     }
     if (key == POISSON_SERVER_OPT_SIZE_CLASSES) {
@@ -737,7 +778,7 @@ void poisson_server_destroy(poisson_server *s)
         for (auto &kv : s->groups) {
             if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
             if (kv.second.graph_src) (void)hipGraphDestroy(kv.second.graph_src);
-            for (TileList *t : {&kv.second.tiles, &kv.second.ptiles})
+            for (TileList *t : {&kv.second.tiles, &kv.second.ptiles, &kv.second.qtiles})
                 for (int *p : {t->d_prob, t->d_local, t->d_count})
                     if (p) (void)hipFree(p);
         }

@@ -35,14 +35,14 @@ def make_stream(n_requests, sizes, rate, seed):
 def run_stream(n_requests=2000, sizes=(32, 48, 64, 96, 128, 192, 256), rate=200.0, seed=5,
                precond=B.PC_CHEBYSHEV, degree=4, precision=B.MIXED, tol=1e-8, maxit=5000,
                budget_bytes=64 << 30, max_slots=64, iters=4, queue_extra=16, use_graph=True,
-               size_classes=None, fuse_updates=None, progress=None):
+               size_classes=None, fuse_updates=None, four_steps=None, progress=None):
     """Run the stream; returns a dict of latency / throughput metrics."""
     import torch
     dev = torch.device("cuda:0")
     edges, arrivals = make_stream(n_requests, sizes, rate, seed)
     stream = torch.cuda.Stream()
     srv = B.Server(budget_bytes, max_slots, stream=stream, use_graph=use_graph,
-                   fuse_updates=fuse_updates,
+                   fuse_updates=fuse_updates, four_steps=four_steps,
                    size_classes=size_classes)
     waiting = collections.deque()           # arrived, not yet submitted
     inflight = {}                           # ticket -> (request id, rhs, x)

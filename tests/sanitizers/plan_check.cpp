@@ -74,11 +74,11 @@ void launch_cheb_first_triple(bool, const Work &, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_TRIPLE, 0, true, a});
 }
-void launch_cheb_quad(bool, const Work &, hipStream_t, const KArgs &a)
+void launch_cheb_quad(bool, const Work &, int, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_QUAD, 0, true, a});
 }
-void launch_cheb_first_quad(bool, const Work &, hipStream_t, const KArgs &a)
+void launch_cheb_first_quad(bool, const Work &, int, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_QUAD, 0, true, a});
 }

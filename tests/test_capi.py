@@ -139,6 +139,9 @@ def test_server_host_side_checks():
     assert L.poisson_server_poll(srv, 1, None) == P.ERR_ARG       # no such ticket
     assert L.poisson_server_step(srv, 0) == P.ERR_ARG
     assert L.poisson_server_set_option(srv, 99, 1.0) == P.ERR_ARG
+    assert L.poisson_server_set_option(srv, B.SERVER_OPT_FOUR_STEPS, 2.0) == P.ERR_ARG
+    assert L.poisson_server_set_option(srv, B.SERVER_OPT_FOUR_STEPS, 0.0) == P.OK
+    assert L.poisson_server_set_option(srv, B.SERVER_OPT_FOUR_STEPS, 1.0) == P.OK
     info = B.ServerInfo()
     info.struct_size = ctypes.sizeof(B.ServerInfo)
     assert L.poisson_server_info(srv, ctypes.byref(info)) == P.OK

@@ -311,3 +311,62 @@ def test_server_releases_device_memory(gpu):
     for _ in range(5):
         one_server()
     assert torch.cuda.mem_get_info()[0] == free0
+
+
+def serve_all(reqs, **opts):
+    """Serve reqs (shape, seed, precond, degree, precision, tol, bc) together."""
+    out = {}
+    with P.Server(1 << 30, 8, **opts) as srv:
+        bufs, tickets = {}, {}
+        for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
+            b = torch.from_numpy(workloads.uniform_grid(seed, shape)).to("cuda:0")
+            x = torch.zeros_like(b)
+            bufs[i] = (b, x)
+            tickets[i] = srv.submit(b, x, shape, workloads.spacing(shape[0]), pc, deg, prec, tol,
+                                    5000, bc=bc)
+        for _ in range(100000):
+            if srv.step(3) == 0:
+                break
+        for i, t in tickets.items():
+            st, stats = srv.poll(t)
+            out[i] = (st, stats["iterations"], stats["relres_true"], bufs[i][1].cpu().numpy(),
+                      stats["model_bytes"])
+    return out
+
+
+def test_four_step_passes_change_no_bits(gpu):
+    """Mixed plans of degree >= 4 run their applies four Chebyshev steps per pass
+    (the server's default, over a tile list of their own) or as pairs: the same
+    bits for every request, and the oracle's (degrees 4 to 9, Block-Jacobi masks,
+    Neumann faces, ragged tiles, several requests of one plan in one list, with
+    and without the folded updates and graphs)."""
+    reqs = [  # shape, seed, precond, degree, precision, tol, bc
+        ((40, 36, 30), 61, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 2 | 4 | 16),
+        ((70, 33, 21), 62, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 0),
+        ((33, 40, 28), 63, P.PC_CHEBYSHEV, 8, P.MIXED, 1e-9, 1 | 32),
+        ((70, 30, 20), 64, P.PC_BLOCK_JACOBI, 6, P.MIXED, 1e-8, 4 | 8),
+        ((65, 47, 35), 65, P.PC_CHEBYSHEV, 5, P.MIXED, 1e-8, 0),
+        ((29, 31, 37), 66, P.PC_CHEBYSHEV, 9, P.MIXED, 1e-8, 0),
+        ((45, 20, 66), 67, P.PC_CHEBYSHEV, 7, P.MIXED, 1e-8, 0),
+        ((31, 22, 19), 68, P.PC_CHEBYSHEV, 4, P.FP64, 1e-8, 0),
+    ]
+    base = serve_all(reqs, four_steps=0)
+    for opts in (dict(four_steps=1), dict(), dict(fuse_updates=0), dict(use_graph=False)):
+        got = serve_all(reqs, **opts)
+        for i in range(len(reqs)):
+            a, b = base[i], got[i]
+            assert a[0] == b[0] == P.OK and a[1] == b[1] and a[2] == b[2], (opts, i, a[:3], b[:3])
+            assert np.array_equal(a[3], b[3]), (opts, i)
+            # fewer bytes per iteration where the four-step passes run
+            if reqs[i][4] == P.MIXED and opts.get("fuse_updates", 1):
+                assert b[4] < a[4], (opts, i)
+    for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
+        f = workloads.uniform_grid(seed, shape)
+        ref = oracle.bicgstab(f, workloads.spacing(shape[0]), pc=OPC[pc], degree=deg,
+                              mixed=prec == P.MIXED, tol=tol, maxit=5000, bc=bc, block=64)
+        assert ref.iterations == base[i][1] and np.array_equal(base[i][3].ravel(), ref.x.ravel()), i
+    # the option is fixed once a request was submitted
+    with P.Server(1 << 24, 2) as srv:
+        b = torch.zeros(8 ** 3, dtype=torch.float64, device="cuda:0")
+        srv.submit(b, b.clone(), (8, 8, 8), workloads.spacing(8), P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8)
+        assert P.lib().poisson_server_set_option(srv._srv, 4, 0.0) == P.ERR_ARG
