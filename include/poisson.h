@@ -91,7 +91,8 @@ enum {
     POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
                                            mixed): 3 (default) in the mixed mode four steps
                                            per pass from degree 4 (steps 1-4 first, then
-                                           fours, then the rest as for 2), FP64 as 2;
+                                           fours, then the rest as for 2), FP64 as 2; 4:
+                                           four steps per pass in FP64 as well;
                                            2: three per pass where the passes are
                                            LDS-staged (the steps left over, and the first
                                            two, run as pairs or alone); two per pass (1)

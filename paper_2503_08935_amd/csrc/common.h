@@ -36,7 +36,8 @@ constexpr int triple_pr(bool fp32) { return fp32 ? 8 : 4; }
 // of 4 rows (a group of halo-column lanes per held row: at most 8 rows)
 constexpr int quad_nxw(bool fp32) { return fp32 ? 1 : 1; }
 constexpr int quad_nyw(bool fp32) { return fp32 ? 8 : 8; }
-constexpr int quad_pr(bool fp32) { return fp32 ? 4 : 4; }
+// two rows per wave in FP64: the LDS planes of 64 x 32 tiles would not fit a CU
+constexpr int quad_pr(bool fp32) { return fp32 ? 4 : 2; }
 
 // vector slots of a problem. V_S and V_P2 exist only when the vector updates are
 // folded into the first pass of the preconditioner applies (upd_fusion): s is
@@ -113,7 +114,7 @@ struct Work {
     int triple_tiles[2];         // single problem: > 0 runs three Chebyshev steps per pass
                                  // (LDS-staged) over this many tiles ([0] FP64, [1] FP32)
     int quad_tiles[2];           // single problem: > 0 runs four Chebyshev steps per pass
-                                 // (LDS-staged, mixed mode) over this many tiles
+                                 // (LDS-staged) over this many tiles ([0] FP64, [1] FP32)
     // batched problems: the LDS-staged pairs' own tile list (null: single problem)
     const int *pair_prob;
     const int *pair_local;
@@ -175,15 +176,16 @@ void launch_cheb_first_pair(bool mixed, bool mask, const Work &w, int grid, hipS
                             const KArgs &a);
 // the half-step test on the s.s partials of a first pass with a.upd = U_S
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a);
-// four fused Chebyshev steps i..i+3 (mixed mode), LDS-staged: in = y_{i-1}, z = y_{i-2},
+// four fused Chebyshev steps i..i+3, LDS-staged: in = y_{i-1}, z = y_{i-2},
 // v; out = w_{i+2}, x2 = w_{i+3}; drop1: w_{i+2} is not stored. Single problems
 // launch one workgroup per tile; batched ones (w.quad_prob) `grid` workgroups
 // over the list
-void launch_cheb_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
-// steps 1-4 in one pass: in = v (FP64), out = y_3, x2 = w_4 and the FP32 copy of v
-// (drop1: w_4 alone, the apply's output, when the degree is 4); a.upd as for the
-// first pair
-void launch_cheb_first_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
+void launch_cheb_quad(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a);
+// steps 1-4 in one pass: in = v (FP64), out = y_3, x2 = w_4, in mixed mode also the
+// FP32 copy of v (drop1: w_4 alone, the apply's output, when the degree is 4);
+// a.upd as for the first pair
+void launch_cheb_first_quad(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                            const KArgs &a);
 // three fused Chebyshev steps i, i+1, i+2 (i >= 3), LDS-staged, single problem:
 // in = y_{i-1}, z = y_{i-2}, v; out = w_{i+1}, x2 = w_{i+2}; step = i; drop1:
 // w_{i+1} is not stored

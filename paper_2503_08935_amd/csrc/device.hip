@@ -3160,16 +3160,27 @@ static void lq_drop(bool mask, const Work &w, int grid, hipStream_t s, const KAr
     else lq_launch<T, TU, FIRST, DROP, false, true>(w, grid, s, a);
 }
 
-void launch_cheb_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
+void launch_cheb_quad(bool mixed, bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
 {
-    if (a.drop1) lq_drop<float, float, false, true>(mask, w, grid, s, a);
-    else lq_drop<float, float, false, false>(mask, w, grid, s, a);
+    if (mixed) {
+        if (a.drop1) lq_drop<float, float, false, true>(mask, w, grid, s, a);
+        else lq_drop<float, float, false, false>(mask, w, grid, s, a);
+    } else {
+        if (a.drop1) lq_drop<double, double, false, true>(mask, w, grid, s, a);
+        else lq_drop<double, double, false, false>(mask, w, grid, s, a);
+    }
 }
 
-void launch_cheb_first_quad(bool mask, const Work &w, int grid, hipStream_t s, const KArgs &a)
+void launch_cheb_first_quad(bool mixed, bool mask, const Work &w, int grid, hipStream_t s,
+                            const KArgs &a)
 {
-    if (a.drop1) lq_drop<float, double, true, true>(mask, w, grid, s, a);
-    else lq_drop<float, double, true, false>(mask, w, grid, s, a);
+    if (mixed) {
+        if (a.drop1) lq_drop<float, double, true, true>(mask, w, grid, s, a);
+        else lq_drop<float, double, true, false>(mask, w, grid, s, a);
+    } else {
+        if (a.drop1) lq_drop<double, double, true, true>(mask, w, grid, s, a);
+        else lq_drop<double, double, true, false>(mask, w, grid, s, a);
+    }
 }
 
 void launch_finalize_ss(const Work &w, int grid, hipStream_t s, const KArgs &a)

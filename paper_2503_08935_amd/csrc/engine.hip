@@ -132,6 +132,8 @@ Work single_work(const poisson_ctx *c, const Prob *prob)
         for (int f = 0; f < 2; ++f) w.triple_tiles[f] = make_triple_tiling(c->nx, c->ny, c->nz, f).ntiles;
     if (c->pair_lds && c->opt.fuse >= 3)
         w.quad_tiles[1] = make_quad_tiling(c->nx, c->ny, c->nz, true).ntiles;
+    if (c->pair_lds && c->opt.fuse >= 4)
+        w.quad_tiles[0] = make_quad_tiling(c->nx, c->ny, c->nz, false).ntiles;
     if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
@@ -160,7 +162,7 @@ int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
     if (!c->fuse_updates) return 0;
     const Work w = single_work(c, nullptr);
-    const bool first4 = mixed && deg >= 4 && c->opt.fuse >= 3 && w.quad_tiles[1] > 0;
+    const bool first4 = deg >= 4 && quads_on(c->opt.fuse, mixed) && w.quad_tiles[mixed ? 1 : 0] > 0;
     if (c->fuse_updates == 2 && c->N < (first4 ? FOLD_MIN_UNKNOWNS_FOURS : FOLD_MIN_UNKNOWNS))
         return 0;
     return upd_fusion(pc, deg, mixed, c->opt.fuse, w);
@@ -539,7 +541,7 @@ int poisson_set_option(poisson_ctx *c, int key, double v)
         c->opt.debug_bd = (int)v;
         return POISSON_OK;
     case POISSON_OPT_FUSE:
-        if (v != 0 && v != 1 && v != 2 && v != 3) return POISSON_ERR_ARG;
+        if (v != 0 && v != 1 && v != 2 && v != 3 && v != 4) return POISSON_ERR_ARG;
         c->opt.fuse = (int)v;
         return POISSON_OK;
     case POISSON_OPT_TILE_ORDER:

@@ -33,7 +33,7 @@ struct PlanOpts {
     double lmin_scale = 1.0, lmax_scale = 1.0;
     int debug_bd = -1;
     int fuse = 3;            // Chebyshev steps per pass: 0 one, 1 two, 2 three where possible,
-                             // 3 as 2 and four in the mixed mode
+                             // 3 as 2 and four in the mixed mode, 4 four in both modes
 };
 
 Tiling make_tiling(int nx, int ny, int nz);
@@ -55,6 +55,8 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
               const PlanOpts &o, double tol, int maxit, double *lo, double *hi);
 // whether a plan runs fused Chebyshev step pairs
 bool fused(int pc, int deg, bool mixed, int fuse);
+// whether the fuse level runs four Chebyshev steps per pass in this precision
+inline bool quads_on(int fuse, bool mixed) { return fuse >= 4 || (fuse >= 3 && mixed); }
 // the vector updates (U_S | U_P) a plan can fold into the first passes of its
 // applies: fused plans of a single problem with LDS-staged first passes
 int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w);

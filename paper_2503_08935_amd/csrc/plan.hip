@@ -152,13 +152,25 @@ Tiling make_quad_tiling(int nx, int ny, int nz, bool fp32)
     const int lx = 64 * quad_nxw(fp32), ly = quad_nyw(fp32) * quad_pr(fp32);
     t.tx = (nx + lx - 1) / lx;
     t.ty = (ny + ly - 1) / ly;
-    // the longest chunk (up to 256 planes) leaving a tile for every CU: a quad
-    // recomputes three halo planes per chunk end, and at 512^3 the 256-plane
-    // chunks measured 1% faster per solve than 128
-    int kz = 256;
+    // One workgroup fills a CU, and the pass is bound by issue: its time is about
+    // the rounds of 256 tiles times the planes a tile marches (its chunk plus the
+    // three recomputed halo planes at each end). Take the chunk (8 to 512 planes)
+    // that minimises that product, the longer one on a tie: at 512^3 (FP32) 256
+    // planes in one round, measured 1% faster than 128 in two; at 384^3 (FP64)
+    // 128 planes in two rounds instead of 256 in two rounds of 288 tiles.
     const long base = (long)t.tx * t.ty;
-    while (kz > 8 && base * ((nz + kz - 1) / kz) < 256) kz /= 2;
-    t.kz = std::min(kz, std::max(nz, 1));
+    const int nzc = std::max(nz, 1);
+    long best = -1;
+    t.kz = nzc;
+    for (int kz = 512; kz >= 8; kz /= 2) {
+        const int k = std::min(kz, nzc);
+        const long rounds = (base * ((nzc + k - 1) / k) + 255) / 256;
+        const long cost = rounds * (k + 6);
+        if (best < 0 || cost < best) {
+            best = cost;
+            t.kz = k;
+        }
+    }
     t.tz = (nz + t.kz - 1) / t.kz;
     t.ntiles = t.tx * t.ty * t.tz;
     return t;
@@ -256,7 +268,7 @@ int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w)
 {
     if (!fused(pc, deg, mixed, fuse) || w.tile_prob || w.pair_prob) return 0;
     const int f = mixed ? 1 : 0;
-    const bool first4 = fuse >= 3 && w.quad_tiles[f] > 0 && mixed && deg >= 4;
+    const bool first4 = quads_on(fuse, mixed) && w.quad_tiles[f] > 0 && deg >= 4;
     const bool first3 = fuse >= 2 && w.triple_tiles[f] > 0 && mixed && deg >= 5;
     if (first4 || first3) return U_S | U_P;
     return w.pair_tiles[f] > 0 ? (U_S | U_P) : 0;
@@ -344,7 +356,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
         // four steps per pass (mixed mode): steps 1-4 first, then fours, then
         // what is left as a triple, pair or single step
-        const bool quad = fuse >= 3 && mixed && (w.quad_tiles[1] > 0 || w.quad_prob);
+        const bool quad = quads_on(fuse, mixed) && (w.quad_tiles[mixed ? 1 : 0] > 0 || w.quad_prob);
         const bool first4 = quad && m >= 4;
         const bool first3 = !first4 && tri && mixed && m >= 5;
         // a folded update (upd): the first pass forms its input itself; the
@@ -355,7 +367,7 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         const bool only4 = first4 && m == 4;
         const KArgs a1{vin, V_RA, vin, 0, 1, second, 0, only4 ? vout : V_RB, only4 ? 1 : 0, upd, parts};
         if (first4)
-            launch_cheb_first_quad(mask, w, grid, s, a1);
+            launch_cheb_first_quad(mixed, mask, w, grid, s, a1);
         else if (first3)
             launch_cheb_first_triple(mask, w, s, a1);
         else
@@ -372,7 +384,8 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
                     if (b != y && b != z && n < 2) o[n++] = b;
                 const bool last = i + 3 == m;
                 const int w4 = last ? vout : o[1];
-                launch_cheb_quad(mask, w, grid, s, KArgs{y, o[0], vsrc, z, i, second, 0, w4, last ? 1 : 0});
+                launch_cheb_quad(mixed, mask, w, grid, s,
+                                 KArgs{y, o[0], vsrc, z, i, second, 0, w4, last ? 1 : 0});
                 z = o[0];
                 y = w4;
             }
@@ -450,7 +463,7 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd, bool triple
         if (fused(pc, m, mixed, fuse)) {
             // steps 1-2 (or 1-3, mixed with triples; 1-4 mixed with fours): v in;
             // two outputs (+ v32) out, or w_4 alone when that pass ends the apply
-            const bool tri = fuse >= 2 && triples, quad = fuse >= 3 && mixed;
+            const bool tri = fuse >= 2 && triples, quad = quads_on(fuse, mixed);
             if (quad && m == 4) {
                 pcb = 8 + tc;
             } else {

@@ -74,13 +74,13 @@ void launch_cheb_first_triple(bool, const Work &, hipStream_t, const KArgs &a)
 {
     g_log.push_back({K_FIRST_TRIPLE, 0, true, a});
 }
-void launch_cheb_quad(bool, const Work &, int, hipStream_t, const KArgs &a)
+void launch_cheb_quad(bool mixed, bool, const Work &, int, hipStream_t, const KArgs &a)
 {
-    g_log.push_back({K_QUAD, 0, true, a});
+    g_log.push_back({K_QUAD, 0, mixed, a});
 }
-void launch_cheb_first_quad(bool, const Work &, int, hipStream_t, const KArgs &a)
+void launch_cheb_first_quad(bool mixed, bool, const Work &, int, hipStream_t, const KArgs &a)
 {
-    g_log.push_back({K_FIRST_QUAD, 0, true, a});
+    g_log.push_back({K_FIRST_QUAD, 0, mixed, a});
 }
 void launch_finalize_ss(const Work &, int, hipStream_t, const KArgs &a)
 {
@@ -107,8 +107,8 @@ double launch_bytes(const Launch &l, int pc)
         return vin + 2 * tc + (l.mixed ? 4 : 0);        // v in; y_1, w_2 (+ v32) out
     case K_FIRST_TRIPLE:
         return vin + 2 * tc + 4;                        // v in; y_2, y_3, v32 out
-    case K_FIRST_QUAD:                                  // v in; y_3, y_4, v32 out, or y_4
-        return l.a.drop1 ? vin + tc : vin + 2 * tc + 4;
+    case K_FIRST_QUAD:                                  // v in; y_3, y_4 (+ v32) out, or y_4
+        return l.a.drop1 ? vin + tc : vin + 2 * tc + (l.mixed ? 4 : 0);
     case K_PAIR:
     case K_TRIPLE:
     case K_QUAD:
@@ -151,6 +151,7 @@ void check_plan(int pc, int deg, bool mixed, int fuse, bool lds, bool fold)
     w.count = 1;
     if (lds && fuse >= 2) w.triple_tiles[0] = w.triple_tiles[1] = 7;
     if (lds && fuse >= 3) w.quad_tiles[1] = 7;
+    if (lds && fuse >= 4) w.quad_tiles[0] = 7;
     if (lds) w.pair_tiles[0] = w.pair_tiles[1] = 7;
     const int upd = fold ? upd_fusion(pc, deg, mixed, fuse, w) : 0;
     if (fold && !upd) return;
@@ -290,7 +291,7 @@ int main()
     for (int pc : pcs)
         for (int deg = 0; deg <= 12; ++deg)
             for (int mixed = 0; mixed < 2; ++mixed)
-                for (int fuse = 0; fuse <= 3; ++fuse)
+                for (int fuse = 0; fuse <= 4; ++fuse)
                     for (int lds = 0; lds < 2; ++lds)
                         for (int fold = 0; fold < 2; ++fold) {
                             if (!is_cheb(pc) && deg) continue;

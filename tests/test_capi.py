@@ -69,8 +69,9 @@ def test_options_and_solve_argument_checks():
     assert L.poisson_set_option(c, B.OPT_TILE_ORDER, 3.0) == P.ERR_ARG
     for v in (0, 1, 2):  # steps per pass: one, two, three
         assert L.poisson_set_option(c, B.OPT_FUSE, float(v)) == P.OK
-    assert L.poisson_set_option(c, B.OPT_FUSE, 3.0) == P.OK
-    assert L.poisson_set_option(c, B.OPT_FUSE, 4.0) == P.ERR_ARG
+    for v in (3, 4):  # four in the mixed mode, four in both
+        assert L.poisson_set_option(c, B.OPT_FUSE, float(v)) == P.OK
+    assert L.poisson_set_option(c, B.OPT_FUSE, 5.0) == P.ERR_ARG
     for v in (0, 1):
         assert L.poisson_set_option(c, B.OPT_PAIR_LDS, float(v)) == P.OK
     assert L.poisson_set_option(c, B.OPT_PAIR_LDS, 2.0) == P.ERR_ARG
