@@ -529,7 +529,8 @@ def main():
                                 "achieved": round(s_gbps, 1)}}
     others = {}
     if not a.no_unfused:
-        for fuse, key in ((1, "fp64_two_steps_per_pass"), (0, "fp64_one_step_per_pass")):
+        for fuse, key in ((4, "fp64_four_steps_per_pass"), (1, "fp64_two_steps_per_pass"),
+                          (0, "fp64_one_step_per_pass")):
             s64.set_option("fuse", fuse)
             st = solve64()
             others[key] = {"iterations": st["iterations"], "solve_s": round(st["solve_ms"] / 1e3, 4),
