@@ -490,15 +490,20 @@ def main():
     # (below), the fused pair and the single interior step for reference
     reps = a.kernel_reps
 
-    def kernel_time(kernel):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+    def kernel_time(kernel, batches=5):
+        # the median over batches of back-to-back launches, so that one slow
+        # batch does not stand for the kernel
         s64.kernel_bench(kernel, P.FP64, 2)  # warm
-        e0.record(stream)
-        s64.kernel_bench(kernel, P.FP64, reps)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        per = []
+        for _ in range(batches):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s64.kernel_bench(kernel, P.FP64, reps)
+            e1.record(stream)
+            e1.synchronize()
+            per.append(e0.elapsed_time(e1) / reps)
+        ms = sorted(per)[len(per) // 2]
         nbytes = s64.kernel_bytes(kernel, P.FP64)
         return ms, nbytes, nbytes / (ms * 1e6)
 
