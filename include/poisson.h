@@ -89,10 +89,13 @@ enum {
     POISSON_OPT_USE_GRAPH = 7,          /* 1 = replay captured HIP graphs (default), 0 = launch */
     POISSON_OPT_DEBUG_BREAKDOWN_AT = 8, /* testing: force omega = 0 at this iteration (-1 off) */
     POISSON_OPT_FUSE = 9,               /* Chebyshev / Block-Jacobi with degree >= 3 (FP64 or
-                                           mixed): 3 (default) in the mixed mode four steps
-                                           per pass from degree 4 (steps 1-4 first, then
-                                           fours, then the rest as for 2), FP64 as 2; 4:
-                                           four steps per pass in FP64 as well;
+                                           mixed): 3 (default) four steps per pass from
+                                           degree 4 (steps 1-4 first, then fours, then the
+                                           rest as for 2; a degree 4k+1 starts with 1-2,
+                                           or 1-3 mixed, and ends on a triple) in the mixed
+                                           mode, and in FP64 at degrees 4-7 and below 448^3
+                                           unknowns (elsewhere FP64 as 2); 4: four steps
+                                           per pass in FP64 at every size and degree;
                                            2: three per pass where the passes are
                                            LDS-staged (the steps left over, and the first
                                            two, run as pairs or alone); two per pass (1)

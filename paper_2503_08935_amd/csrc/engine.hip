@@ -100,10 +100,26 @@ int ensure_device(poisson_ctx *c)
     return POISSON_OK;
 }
 
+// Unknowns from which FP64 keeps three steps per pass at degree 8 and above by
+// default: there the four-step passes, over 64 x 16 tiles, cost per step what the
+// triples do (512^3 degree 8: 2.051 against 2.045 s); below, and at degrees 4-7
+// everywhere, they were measured 7-17% faster (256^3 degrees 4, 6, 8; 512^3
+// degrees 4, 6, 7).
+constexpr size_t FP64_FOURS_MAX_UNKNOWNS = (size_t)448 * 448 * 448;
+
+// steps per pass a solve runs: POISSON_OPT_FUSE, except that the default (3)
+// takes four in FP64 too where that was measured faster
+int solve_fuse(const poisson_ctx *c, int deg, bool mixed)
+{
+    if (c->opt.fuse == 3 && !mixed && deg >= 4 && (deg <= 7 || c->N < FP64_FOURS_MAX_UNKNOWNS))
+        return 4;
+    return c->opt.fuse;
+}
+
 // size the workspace for a plan; grows (never shrinks) the allocation
 int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
-    const size_t need = workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse, upd);
+    const size_t need = workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
     if (need > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -117,7 +133,7 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed, int upd)
     }
     Prob tmp;
     memset(&tmp, 0, sizeof(tmp));
-    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, c->opt.fuse, upd);
+    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
     for (int v = 0; v < V_COUNT; ++v) c->vec[v] = tmp.vec[v];
     c->s_slot = tmp.s_slot;
     return POISSON_OK;
@@ -132,17 +148,18 @@ Work single_work(const poisson_ctx *c, const Prob *prob)
         for (int f = 0; f < 2; ++f) w.triple_tiles[f] = make_triple_tiling(c->nx, c->ny, c->nz, f).ntiles;
     if (c->pair_lds && c->opt.fuse >= 3)
         w.quad_tiles[1] = make_quad_tiling(c->nx, c->ny, c->nz, true).ntiles;
-    if (c->pair_lds && c->opt.fuse >= 4)
+    if (c->pair_lds && c->opt.fuse >= 3)
         w.quad_tiles[0] = make_quad_tiling(c->nx, c->ny, c->nz, false).ntiles;
     if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
 }
 
-// steps per pass the plan runs: three only with the LDS-staged tiles
-int plan_fuse_level(const poisson_ctx *c)
+// steps per pass the plan runs: three or four only with the LDS-staged tiles
+int plan_fuse_level(const poisson_ctx *c, int deg, bool mixed)
 {
-    return (c->opt.fuse >= 2 && !c->pair_lds) ? 1 : c->opt.fuse;
+    const int f = solve_fuse(c, deg, mixed);
+    return (f >= 2 && !c->pair_lds) ? 1 : f;
 }
 
 // Unknowns from which the folds pay by default when the first pass of an apply
@@ -162,10 +179,12 @@ int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
     if (!c->fuse_updates) return 0;
     const Work w = single_work(c, nullptr);
-    const bool first4 = deg >= 4 && quads_on(c->opt.fuse, mixed) && w.quad_tiles[mixed ? 1 : 0] > 0;
+    const int fuse = solve_fuse(c, deg, mixed);
+    const bool first4 = starts_with_four(fuse, mixed, deg, w.quad_tiles[mixed ? 1 : 0] > 0,
+                                         fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0);
     if (c->fuse_updates == 2 && c->N < (first4 ? FOLD_MIN_UNKNOWNS_FOURS : FOLD_MIN_UNKNOWNS))
         return 0;
-    return upd_fusion(pc, deg, mixed, c->opt.fuse, w);
+    return upd_fusion(pc, deg, mixed, fuse, w);
 }
 
 int fill(poisson_ctx *c, Prob &p, int pc, int deg, double tol, int maxit)
@@ -187,7 +206,7 @@ int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i)
-        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, c->opt.fuse, upd);
+        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, solve_fuse(c, m, mixed), upd);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipGraphExec_t e = nullptr;
     HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -233,7 +252,8 @@ void put_stats(poisson_ctx *c, const Scalars &sc, double rr_true, int pc, int de
     st.lambda_min = c->plan_lo;
     st.lambda_max = c->plan_hi;
     st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c), plan_updates(c, pc, deg, mixed)) *
+    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c, deg, mixed),
+                                     plan_updates(c, pc, deg, mixed)) *
                      (double)c->N * sc.iter;
     st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
 }
@@ -271,7 +291,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     c->plan_pc = pc;
     c->plan_deg = deg;
     c->plan_mixed = mixed;
-    c->plan_fuse = fused(pc, deg, mixed, c->opt.fuse);
+    c->plan_fuse = fused(pc, deg, mixed, solve_fuse(c, deg, mixed));
     c->plan_upd = upd;
     if ((rc = upload_prob(c, 0)) != POISSON_OK) return rc;
 
@@ -292,7 +312,8 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
                 HIPCHK(hipGraphLaunch(g, c->stream));
             } else {
                 for (int i = 0; i < K; ++i)
-                    enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse, upd);
+                    enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed,
+                                      solve_fuse(c, deg, mixed), upd);
                 HIPCHK(hipGetLastError());
             }
             if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -380,7 +401,7 @@ size_t noalloc_bytes(const poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
     return round256(sizeof(Prob)) + round256(sizeof(Scalars)) +
            round256((size_t)c->nparts * PARTIAL_STRIDE * sizeof(double)) +
-           workspace_bytes(c->N, pc, deg, mixed, c->opt.fuse, upd);
+           workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
 }
 
 // the solve of solve_impl with every device buffer carved from the scratch,
@@ -407,7 +428,7 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
     Prob p;
     memset(&p, 0, sizeof(p));
     if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
-    carve_workspace(p, ws, c->N, pc, deg, mixed, c->opt.fuse, upd);
+    carve_workspace(p, ws, c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
     p.vec[V_X] = x;
     p.vec[V_B] = (void *)rhs;
     p.sc = d_sc;
@@ -436,7 +457,8 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
         const long max_rounds = (long)maxit / K + 2;
         for (long round = 0; round < max_rounds; ++round) {
             for (int i = 0; i < K; ++i)
-                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, c->opt.fuse, upd);
+                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, solve_fuse(c, deg, mixed),
+                                  upd);
             HIPCHK(hipGetLastError());
             if ((rc = read_sc()) != POISSON_OK) return rc;
             if (sc.done) break;
@@ -715,7 +737,8 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
         p.vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
         const Work w = single_work(c, c->d_prob + 1);
-        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, c->opt.fuse, V_B, V_X, 0);
+        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, solve_fuse(c, degree, mixed), V_B,
+                   V_X, 0);
         HIPCHK(hipGetLastError());
         return POISSON_OK;
     } catch (...) {
@@ -773,7 +796,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
     if (kernel == POISSON_KERNEL_CHEB_PAIR && !(c->plan_fuse && c->plan_deg >= 5))
         return POISSON_ERR_ARG;
     if (kernel == POISSON_KERNEL_CHEB_TRIPLE &&
-        !(c->plan_fuse && c->plan_deg >= 5 && plan_fuse_level(c) >= 2))
+        !(c->plan_fuse && c->plan_deg >= 5 && plan_fuse_level(c, c->plan_deg, c->plan_mixed) >= 2))
         return POISSON_ERR_ARG;
     if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_CHEB_TRIPLE)
         return POISSON_ERR_ARG;

@@ -57,6 +57,14 @@ int fill_prob(Prob &p, int nx, int ny, int nz, double h, unsigned bc, int pc, in
 bool fused(int pc, int deg, bool mixed, int fuse);
 // whether the fuse level runs four Chebyshev steps per pass in this precision
 inline bool quads_on(int fuse, bool mixed) { return fuse >= 4 || (fuse >= 3 && mixed); }
+// whether an apply of degree m starts with steps 1-4 in one pass: four-step
+// passes on, and not a degree 4k+1 where triples run (the fours would leave a
+// lone last step; such applies start with steps 1-2, or 1-3 in the mixed mode,
+// and end on a triple or pair)
+inline bool starts_with_four(int fuse, bool mixed, int m, bool quads, bool triples)
+{
+    return quads && quads_on(fuse, mixed) && m >= 4 && !(triples && m >= 5 && (m - 4) % 4 == 1);
+}
 // the vector updates (U_S | U_P) a plan can fold into the first passes of its
 // applies: fused plans of a single problem with LDS-staged first passes
 int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w);

@@ -268,7 +268,8 @@ int upd_fusion(int pc, int deg, bool mixed, int fuse, const Work &w)
 {
     if (!fused(pc, deg, mixed, fuse) || w.tile_prob || w.pair_prob) return 0;
     const int f = mixed ? 1 : 0;
-    const bool first4 = quads_on(fuse, mixed) && w.quad_tiles[f] > 0 && deg >= 4;
+    const bool first4 = starts_with_four(fuse, mixed, deg, w.quad_tiles[f] > 0,
+                                         fuse >= 2 && w.triple_tiles[f] > 0);
     const bool first3 = fuse >= 2 && w.triple_tiles[f] > 0 && mixed && deg >= 5;
     if (first4 || first3) return U_S | U_P;
     return w.pair_tiles[f] > 0 ? (U_S | U_P) : 0;
@@ -354,10 +355,11 @@ void enqueue_pc(const Work &w, int grid, hipStream_t s, int pc, int m, bool mixe
         // in the mixed mode with degree >= 5 steps 1-3 (in FP64 the two divisions
         // per point of that pass made it slower than a pair: 980 against 605 us)
         const bool tri = fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0;
-        // four steps per pass (mixed mode): steps 1-4 first, then fours, then
-        // what is left as a triple, pair or single step
+        // four steps per pass: steps 1-4 first, then fours, then what is left as
+        // a triple, pair or single step; a degree 4k+1 with triples starts with
+        // steps 1-2 (FP64) or 1-3 (mixed) instead, so that no step is left alone
         const bool quad = quads_on(fuse, mixed) && (w.quad_tiles[mixed ? 1 : 0] > 0 || w.quad_prob);
-        const bool first4 = quad && m >= 4;
+        const bool first4 = starts_with_four(fuse, mixed, m, quad, tri);
         const bool first3 = !first4 && tri && mixed && m >= 5;
         // a folded update (upd): the first pass forms its input itself; the
         // half-step test of a formed s follows that pass
@@ -464,11 +466,12 @@ double iteration_bytes(int pc, int m, bool mixed, int fuse, int upd, bool triple
             // steps 1-2 (or 1-3, mixed with triples; 1-4 mixed with fours): v in;
             // two outputs (+ v32) out, or w_4 alone when that pass ends the apply
             const bool tri = fuse >= 2 && triples, quad = quads_on(fuse, mixed);
-            if (quad && m == 4) {
+            const bool first4 = starts_with_four(fuse, mixed, m, quad, tri);
+            if (first4 && m == 4) {
                 pcb = 8 + tc;
             } else {
                 pcb = 8 + 2 * tc + (mixed ? 4 : 0);
-                int steps = m - ((quad && m >= 4) ? 4 : ((tri && mixed && m >= 5) ? 3 : 2));
+                int steps = m - (first4 ? 4 : ((tri && mixed && m >= 5) ? 3 : 2));
                 int passes = 0;                         // passes after the first one
                 if (quad) {                             // fours: y, z, v in; two outputs
                     pcb += (steps / 4) * 5 * tc;

@@ -237,14 +237,14 @@ def test_byte_model_per_iteration(gpu):
     632 B per unknown and iteration with one step per pass, 440 with two, 360 with
     steps 1-2, 3-5 and 6-8; mixed 264 with steps 1-3, 4-6, 7-8 and 224 with 1-4, 5-8.
     Folding the s and p updates into the first passes saves 8 B each: 424, 344, 248
-    and 208."""
+    and 208; FP64 with 1-4, 5-8 and both folds (the default below 448^3) 264."""
     shape = (64, 48, 40)
     n = 64 * 48 * 40
     f = workloads.uniform_grid(5, shape)
     for fuse, mixed, fold, per in ((0, False, 1, 632), (1, False, 0, 440), (2, False, 0, 360),
                                    (2, True, 0, 264), (1, False, 1, 424), (2, False, 1, 344),
                                    (2, True, 1, 248), (3, True, 0, 224), (3, True, 1, 208),
-                                   (3, False, 1, 344)):
+                                   (3, False, 1, 264), (4, False, 1, 264)):
         st, stats, tr, x = gpu_solve(shape, 1.0 / 65, f, P.PC_CHEBYSHEV, 8, 1e-8, fuse=fuse,
                                      fuse_updates=fold, precision=P.MIXED if mixed else P.FP64)
         assert st == P.OK
@@ -252,21 +252,52 @@ def test_byte_model_per_iteration(gpu):
 
 
 def test_update_folding_follows_the_grid_size(gpu):
-    """By default the s and p updates are folded into the first passes from 352^3
-    unknowns on (where it was measured faster) and not below: the stats' byte model
-    shows which plan ran (344 against 360 B per unknown and iteration, FP64
-    Chebyshev-8)."""
+    """By default the s and p updates are folded into first passes of two or three
+    steps from 352^3 unknowns on (where it was measured faster) and not below: the
+    stats' byte model shows which plan ran (344 against 360 B per unknown and
+    iteration, FP64 Chebyshev-8 with three steps per pass)."""
     for shape, per in (((351, 352, 352), 360), ((352, 352, 352), 344)):
         n = shape[0] * shape[1] * shape[2]
         b = torch.empty(n, dtype=torch.float64, device="cuda:0")
         P.fill_uniform(b, 9)
-        with P.Solver(shape, 1.0 / (shape[0] + 1)) as s:
+        with P.Solver(shape, 1.0 / (shape[0] + 1), fuse=2) as s:
             x = torch.zeros_like(b)
             st = s.solve(b, x, P.PC_CHEBYSHEV, 8, 1e-12, 2)
             torch.cuda.synchronize()
             stats = s.stats()
         assert st == P.NOT_CONVERGED and stats["iterations"] == 2
         assert stats["model_bytes"] == per * n * 2, shape
+
+
+def test_fp64_four_step_passes_follow_degree_and_size(gpu):
+    """By default FP64 runs four Chebyshev steps per pass (folded: 264 B per unknown
+    and iteration at degree 8) at degrees 4-7 and below 448^3 unknowns, and three
+    (344 B) at degree 8 from 448^3 on, where four were not faster; a degree 4k+1
+    starts with a pair and ends on a triple (degree 5: 1-2, 3-5, as with three)."""
+    cases = [((447, 448, 448), 8, 264), ((448, 448, 448), 8, 344), ((448, 448, 448), 6, None),
+             ((64, 48, 40), 5, None)]
+    for shape, deg, per in cases:
+        n = shape[0] * shape[1] * shape[2]
+        b = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        P.fill_uniform(b, 9)
+        got = {}
+        for fuse in (None, 2, 4):
+            opts = {} if fuse is None else dict(fuse=fuse)
+            with P.Solver(shape, 1.0 / (shape[0] + 1), **opts) as s:
+                x = torch.zeros_like(b)
+                st = s.solve(b, x, P.PC_CHEBYSHEV, deg, 1e-12, 2)
+                torch.cuda.synchronize()
+                stats = s.stats()
+            assert st == P.NOT_CONVERGED and stats["iterations"] == 2
+            got[fuse] = (stats["model_bytes"] / (n * 2), x.cpu().numpy())
+        if per is not None:
+            assert got[None][0] == per, (shape, deg, got[None][0])
+        if deg == 6:
+            assert got[None][0] == got[4][0] < got[2][0]
+        if deg == 5:
+            assert got[4][0] == got[2][0]
+        assert np.array_equal(got[None][1], got[2][1]) and np.array_equal(got[4][1], got[2][1])
+        del b
 
 
 def test_update_folding_with_four_step_passes(gpu):
