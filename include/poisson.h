@@ -92,10 +92,11 @@ enum {
                                            mixed): 3 (default) four steps per pass from
                                            degree 4 (steps 1-4 first, then fours, then the
                                            rest as for 2; a degree 4k+1 starts with 1-2,
-                                           or 1-3 mixed, and ends on a triple) in the mixed
-                                           mode, and in FP64 at degrees 4-7 and below 448^3
-                                           unknowns (elsewhere FP64 as 2); 4: four steps
-                                           per pass in FP64 at every size and degree;
+                                           or 1-3 mixed, and ends on a triple) where that
+                                           was measured faster: mixed Chebyshev always,
+                                           mixed Block-Jacobi and FP64 Chebyshev at
+                                           degrees 4-7 and below 448^3 unknowns; elsewhere
+                                           as 2; 4: four steps per pass in every plan;
                                            2: three per pass where the passes are
                                            LDS-staged (the steps left over, and the first
                                            two, run as pairs or alone); two per pass (1)
@@ -320,11 +321,12 @@ enum {
                                             more FP64 vectors per request); 0: standalone
                                             update passes. Same results either way. Set
                                             before the first submit */,
-    POISSON_SERVER_OPT_FOUR_STEPS = 4    /* 1 (default): mixed Chebyshev and Block-Jacobi
-                                            plans of degree >= 4 run their applies four
-                                            steps per pass (steps 1-4 first, as
-                                            poisson_solve does); 0: pairs. Same results
-                                            either way. Set before the first submit */
+    POISSON_SERVER_OPT_FOUR_STEPS = 4    /* 1 (default): plans of degree >= 4 (mixed
+                                            Chebyshev and Block-Jacobi, FP64 Chebyshev)
+                                            run their applies four steps per pass (steps
+                                            1-4 first, then fours, then a pair or a single
+                                            step); 0: pairs. Same results either way. Set
+                                            before the first submit */
 };
 
 /* Create a server. hip_stream: the caller's stream (NULL = null stream); the

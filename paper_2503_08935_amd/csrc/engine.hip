@@ -100,26 +100,31 @@ int ensure_device(poisson_ctx *c)
     return POISSON_OK;
 }
 
-// Unknowns from which FP64 keeps three steps per pass at degree 8 and above by
-// default: there the four-step passes, over 64 x 16 tiles, cost per step what the
-// triples do (512^3 degree 8: 2.051 against 2.045 s); below, and at degrees 4-7
-// everywhere, they were measured 7-17% faster (256^3 degrees 4, 6, 8; 512^3
-// degrees 4, 6, 7).
-constexpr size_t FP64_FOURS_MAX_UNKNOWNS = (size_t)448 * 448 * 448;
+// Unknowns from which the default keeps three steps per pass at degree 8 and
+// above where four were not faster: FP64 Chebyshev (four-step passes over 64 x 16
+// tiles cost per step what the triples do; 512^3 degree 8: 2.051 against
+// 2.045 s) and mixed Block-Jacobi (the masked bodies' selects; 512^3 degree 8:
+// 2.537 against 2.317 s). Below, and at degrees 4-7 everywhere, four were
+// measured faster: FP64 Chebyshev 7-17% (256^3 degrees 4, 6, 8; 512^3 degrees 4,
+// 6, 7), mixed Block-Jacobi 5-6% (256^3 degree 8, 512^3 degree 4).
+constexpr size_t FOURS_MAX_UNKNOWNS = (size_t)448 * 448 * 448;
 
-// steps per pass a solve runs: POISSON_OPT_FUSE, except that the default (3)
-// takes four in FP64 too where that was measured faster
-int solve_fuse(const poisson_ctx *c, int deg, bool mixed)
+// steps per pass a solve runs: POISSON_OPT_FUSE, except where the default (3)
+// was measured faster otherwise. FP64 Block-Jacobi keeps the triples: its
+// four-step passes were slower (the paper's problem at 255^3, degree 24: BJ(CI)
+// 0.79 -> 0.86 s, GNoComm(CI) 0.59 -> 0.64 s; 512^3 degree 8: +25%).
+int solve_fuse(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
-    if (c->opt.fuse == 3 && !mixed && deg >= 4 && (deg <= 7 || c->N < FP64_FOURS_MAX_UNKNOWNS))
-        return 4;
-    return c->opt.fuse;
+    if (c->opt.fuse != 3) return c->opt.fuse;
+    const bool small = deg <= 7 || c->N < FOURS_MAX_UNKNOWNS;
+    if (mixed) return (pc == POISSON_PC_BLOCK_JACOBI && !small) ? 2 : 3;
+    return (pc == POISSON_PC_CHEBYSHEV && deg >= 4 && small) ? 4 : 3;
 }
 
 // size the workspace for a plan; grows (never shrinks) the allocation
 int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
-    const size_t need = workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
+    const size_t need = workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, pc, deg, mixed), upd);
     if (need > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -133,7 +138,7 @@ int plan_workspace(poisson_ctx *c, int pc, int deg, bool mixed, int upd)
     }
     Prob tmp;
     memset(&tmp, 0, sizeof(tmp));
-    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
+    carve_workspace(tmp, c->ws, c->N, pc, deg, mixed, solve_fuse(c, pc, deg, mixed), upd);
     for (int v = 0; v < V_COUNT; ++v) c->vec[v] = tmp.vec[v];
     c->s_slot = tmp.s_slot;
     return POISSON_OK;
@@ -156,9 +161,9 @@ Work single_work(const poisson_ctx *c, const Prob *prob)
 }
 
 // steps per pass the plan runs: three or four only with the LDS-staged tiles
-int plan_fuse_level(const poisson_ctx *c, int deg, bool mixed)
+int plan_fuse_level(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
-    const int f = solve_fuse(c, deg, mixed);
+    const int f = solve_fuse(c, pc, deg, mixed);
     return (f >= 2 && !c->pair_lds) ? 1 : f;
 }
 
@@ -179,7 +184,7 @@ int plan_updates(const poisson_ctx *c, int pc, int deg, bool mixed)
 {
     if (!c->fuse_updates) return 0;
     const Work w = single_work(c, nullptr);
-    const int fuse = solve_fuse(c, deg, mixed);
+    const int fuse = solve_fuse(c, pc, deg, mixed);
     const bool first4 = starts_with_four(fuse, mixed, deg, w.quad_tiles[mixed ? 1 : 0] > 0,
                                          fuse >= 2 && w.triple_tiles[mixed ? 1 : 0] > 0);
     if (c->fuse_updates == 2 && c->N < (first4 ? FOLD_MIN_UNKNOWNS_FOURS : FOLD_MIN_UNKNOWNS))
@@ -206,7 +211,7 @@ int get_graph(poisson_ctx *c, int pc, int m, bool mixed, int iters, hipGraphExec
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i)
-        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, solve_fuse(c, m, mixed), upd);
+        enqueue_iteration(w, c->ntiles, c->cap_stream, pc, m, mixed, solve_fuse(c, pc, m, mixed), upd);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipGraphExec_t e = nullptr;
     HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -252,7 +257,7 @@ void put_stats(poisson_ctx *c, const Scalars &sc, double rr_true, int pc, int de
     st.lambda_min = c->plan_lo;
     st.lambda_max = c->plan_hi;
     st.loop_ms = loop_ms;
-    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c, deg, mixed),
+    st.model_bytes = iteration_bytes(pc, deg, mixed, plan_fuse_level(c, pc, deg, mixed),
                                      plan_updates(c, pc, deg, mixed)) *
                      (double)c->N * sc.iter;
     st.model_gbps = loop_ms > 0 ? st.model_bytes / (loop_ms * 1e6) : 0.0;
@@ -291,7 +296,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
     c->plan_pc = pc;
     c->plan_deg = deg;
     c->plan_mixed = mixed;
-    c->plan_fuse = fused(pc, deg, mixed, solve_fuse(c, deg, mixed));
+    c->plan_fuse = fused(pc, deg, mixed, solve_fuse(c, pc, deg, mixed));
     c->plan_upd = upd;
     if ((rc = upload_prob(c, 0)) != POISSON_OK) return rc;
 
@@ -313,7 +318,7 @@ int solve_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int deg, do
             } else {
                 for (int i = 0; i < K; ++i)
                     enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed,
-                                      solve_fuse(c, deg, mixed), upd);
+                                      solve_fuse(c, pc, deg, mixed), upd);
                 HIPCHK(hipGetLastError());
             }
             if ((rc = read_scalars(c, 0)) != POISSON_OK) return rc;
@@ -401,7 +406,7 @@ size_t noalloc_bytes(const poisson_ctx *c, int pc, int deg, bool mixed, int upd)
 {
     return round256(sizeof(Prob)) + round256(sizeof(Scalars)) +
            round256((size_t)c->nparts * PARTIAL_STRIDE * sizeof(double)) +
-           workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
+           workspace_bytes(c->N, pc, deg, mixed, solve_fuse(c, pc, deg, mixed), upd);
 }
 
 // the solve of solve_impl with every device buffer carved from the scratch,
@@ -428,7 +433,7 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
     Prob p;
     memset(&p, 0, sizeof(p));
     if ((rc = fill(c, p, pc, deg, tol, maxit)) != POISSON_OK) return rc;
-    carve_workspace(p, ws, c->N, pc, deg, mixed, solve_fuse(c, deg, mixed), upd);
+    carve_workspace(p, ws, c->N, pc, deg, mixed, solve_fuse(c, pc, deg, mixed), upd);
     p.vec[V_X] = x;
     p.vec[V_B] = (void *)rhs;
     p.sc = d_sc;
@@ -457,8 +462,8 @@ int solve_noalloc_impl(poisson_ctx *c, const double *rhs, double *x, int pc, int
         const long max_rounds = (long)maxit / K + 2;
         for (long round = 0; round < max_rounds; ++round) {
             for (int i = 0; i < K; ++i)
-                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed, solve_fuse(c, deg, mixed),
-                                  upd);
+                enqueue_iteration(w, c->ntiles, c->stream, pc, deg, mixed,
+                                  solve_fuse(c, pc, deg, mixed), upd);
             HIPCHK(hipGetLastError());
             if ((rc = read_sc()) != POISSON_OK) return rc;
             if (sc.done) break;
@@ -737,8 +742,8 @@ int poisson_apply_precond(poisson_ctx *c, int precond, int degree, const double 
         p.vec[V_X] = out;
         if ((rc = upload_prob(c, 1)) != POISSON_OK) return rc;
         const Work w = single_work(c, c->d_prob + 1);
-        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed, solve_fuse(c, degree, mixed), V_B,
-                   V_X, 0);
+        enqueue_pc(w, c->ntiles, c->stream, precond, degree, mixed,
+                   solve_fuse(c, precond, degree, mixed), V_B, V_X, 0);
         HIPCHK(hipGetLastError());
         return POISSON_OK;
     } catch (...) {
@@ -796,7 +801,7 @@ int poisson_kernel_bench(poisson_ctx *c, int kernel, int precision, int reps)
     if (kernel == POISSON_KERNEL_CHEB_PAIR && !(c->plan_fuse && c->plan_deg >= 5))
         return POISSON_ERR_ARG;
     if (kernel == POISSON_KERNEL_CHEB_TRIPLE &&
-        !(c->plan_fuse && c->plan_deg >= 5 && plan_fuse_level(c, c->plan_deg, c->plan_mixed) >= 2))
+        !(c->plan_fuse && c->plan_deg >= 5 && plan_fuse_level(c, c->plan_pc, c->plan_deg, c->plan_mixed) >= 2))
         return POISSON_ERR_ARG;
     if (kernel < POISSON_KERNEL_CHEB_STEP || kernel > POISSON_KERNEL_CHEB_TRIPLE)
         return POISSON_ERR_ARG;

@@ -283,11 +283,13 @@ void list_tiles(poisson_server *s, TileList &t, const std::vector<int> &slot_ids
         }
 }
 
-// whether a plan group's applies run four Chebyshev steps per pass: mixed
-// Chebyshev or Block-Jacobi of degree >= 4, as in single solves
+// whether a plan group's applies run four Chebyshev steps per pass: degree >= 4,
+// mixed Chebyshev or Block-Jacobi and FP64 Chebyshev, as single solves of the
+// server's grid sizes do (FP64 Block-Jacobi keeps the pairs)
 bool server_four(const poisson_server *s, int pc, int deg, int prec)
 {
-    return s->four_steps && prec == POISSON_MIXED && is_cheb(pc) && deg >= 4;
+    return s->four_steps && is_cheb(pc) && deg >= 4 &&
+           (prec == POISSON_MIXED || pc == POISSON_PC_CHEBYSHEV);
 }
 
 // the LDS-staged pairs' (make_pair_tiling) or four-step passes' (make_quad_tiling)
@@ -333,7 +335,7 @@ Work group_work(const poisson_server *s, const PlanKey &k, const Group &g, int c
 // steps per pass of a plan group's applies (enqueue_iteration's fuse)
 int group_fuse(const poisson_server *s, const PlanKey &k)
 {
-    return server_four(s, k.pc, k.deg, k.mixed) ? 3 : 1;
+    return server_four(s, k.pc, k.deg, k.mixed) ? 4 : 1;
 }
 
 // retire finished requests of class c (its stream is idle): true residuals in one
@@ -382,7 +384,7 @@ int finish_requests(poisson_server *s, int c, const std::vector<int> &ids)
         st.loop_ms = t - sl.t_admit;         // admission to completion
         const double N = (double)sl.req.nx * sl.req.ny * sl.req.nz;
         st.model_bytes = iteration_bytes(sl.req.pc, sl.req.deg, sl.req.prec == POISSON_MIXED,
-                                         server_four(s, sl.req.pc, sl.req.deg, sl.req.prec) ? 3 : 1,
+                                         server_four(s, sl.req.pc, sl.req.deg, sl.req.prec) ? 4 : 1,
                                          sl.req.upd, false) * N * sc.iter;
         st.model_gbps = 0;
         s->results[sl.req.ticket] = r;
@@ -538,7 +540,7 @@ int round_impl(poisson_server *s, int iters, int &progress)
         if (sl.req.upd & U_S)
             p.nparts_first =
                 server_four(s, sl.req.pc, sl.req.deg, sl.req.prec)
-                    ? make_quad_tiling(sl.req.nx, sl.req.ny, sl.req.nz, true).ntiles
+                    ? make_quad_tiling(sl.req.nx, sl.req.ny, sl.req.nz, sl.req.prec == POISSON_MIXED).ntiles
                     : make_pair_tiling(sl.req.nx, sl.req.ny, sl.req.nz, sl.req.prec == POISSON_MIXED).ntiles;
         p.vec[V_X] = sl.req.x;
         p.vec[V_B] = (void *)sl.req.rhs;
@@ -592,7 +594,7 @@ int round_impl(poisson_server *s, int iters, int &progress)
                 if ((rc = upload_tiles(k.stream, g.tiles, moved)) != POISSON_OK) return rc;
                 if ((rc = upload_tiles(k.stream, g.ptiles, pmoved)) != POISSON_OK) return rc;
                 if (four) {
-                    list_pair_tiles(s, g.qtiles, ids, true, true);
+                    list_pair_tiles(s, g.qtiles, ids, kv.first.mixed == POISSON_MIXED, true);
                     if ((rc = upload_tiles(k.stream, g.qtiles, qmoved)) != POISSON_OK) return rc;
                 }
                 if ((moved || pmoved || qmoved) && g.graph) g.graph_cap = -1;

@@ -335,11 +335,11 @@ def serve_all(reqs, **opts):
 
 
 def test_four_step_passes_change_no_bits(gpu):
-    """Mixed plans of degree >= 4 run their applies four Chebyshev steps per pass
-    (the server's default, over a tile list of their own) or as pairs: the same
-    bits for every request, and the oracle's (degrees 4 to 9, Block-Jacobi masks,
-    Neumann faces, ragged tiles, several requests of one plan in one list, with
-    and without the folded updates and graphs)."""
+    """Plans of degree >= 4 run their applies four Chebyshev steps per pass (the
+    server's default, over a tile list of their own) or as pairs: the same bits for
+    every request, and the oracle's (FP64 and mixed, degrees 3 to 9, Block-Jacobi
+    masks, Neumann faces, ragged tiles, several requests of one plan in one list,
+    with and without the folded updates and graphs)."""
     reqs = [  # shape, seed, precond, degree, precision, tol, bc
         ((40, 36, 30), 61, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 2 | 4 | 16),
         ((70, 33, 21), 62, P.PC_CHEBYSHEV, 4, P.MIXED, 1e-8, 0),
@@ -349,6 +349,9 @@ def test_four_step_passes_change_no_bits(gpu):
         ((29, 31, 37), 66, P.PC_CHEBYSHEV, 9, P.MIXED, 1e-8, 0),
         ((45, 20, 66), 67, P.PC_CHEBYSHEV, 7, P.MIXED, 1e-8, 0),
         ((31, 22, 19), 68, P.PC_CHEBYSHEV, 4, P.FP64, 1e-8, 0),
+        ((40, 26, 33), 69, P.PC_CHEBYSHEV, 8, P.FP64, 1e-9, 2 | 8),
+        ((37, 50, 21), 70, P.PC_BLOCK_JACOBI, 5, P.FP64, 1e-8, 0),
+        ((24, 24, 24), 71, P.PC_CHEBYSHEV, 3, P.FP64, 1e-8, 0),
     ]
     base = serve_all(reqs, four_steps=0)
     for opts in (dict(four_steps=1), dict(), dict(fuse_updates=0), dict(use_graph=False)):
@@ -358,7 +361,7 @@ def test_four_step_passes_change_no_bits(gpu):
             assert a[0] == b[0] == P.OK and a[1] == b[1] and a[2] == b[2], (opts, i, a[:3], b[:3])
             assert np.array_equal(a[3], b[3]), (opts, i)
             # fewer bytes per iteration where the four-step passes run
-            if reqs[i][4] == P.MIXED and opts.get("fuse_updates", 1):
+            if reqs[i][3] >= 4 and opts.get("fuse_updates", 1):
                 assert b[4] < a[4], (opts, i)
     for i, (shape, seed, pc, deg, prec, tol, bc) in enumerate(reqs):
         f = workloads.uniform_grid(seed, shape)

@@ -300,6 +300,32 @@ def test_fp64_four_step_passes_follow_degree_and_size(gpu):
         del b
 
 
+def test_block_jacobi_four_step_passes_follow_degree_and_size(gpu):
+    """By default mixed Block-Jacobi runs four Chebyshev steps per pass below 448^3
+    unknowns and at degrees 4-7, three at degree 8 from 448^3 on; FP64
+    Block-Jacobi always runs three (the byte model shows which plan ran)."""
+    cases = [((447, 448, 448), 8, P.MIXED, 3), ((448, 448, 448), 8, P.MIXED, 2),
+             ((448, 448, 448), 6, P.MIXED, 3), ((64, 48, 40), 6, P.FP64, 2)]
+    for shape, deg, prec, same_as in cases:
+        n = shape[0] * shape[1] * shape[2]
+        b = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        P.fill_uniform(b, 9)
+        got = {}
+        for fuse in (None, 2, 3, 4):
+            opts = {} if fuse is None else dict(fuse=fuse)
+            with P.Solver(shape, 1.0 / (shape[0] + 1), precision=prec, block=64, **opts) as s:
+                x = torch.zeros_like(b)
+                st = s.solve(b, x, P.PC_BLOCK_JACOBI, deg, 1e-12, 2)
+                torch.cuda.synchronize()
+                stats = s.stats()
+            assert st == P.NOT_CONVERGED and stats["iterations"] == 2
+            got[fuse] = (stats["model_bytes"], x.cpu().numpy())
+        assert got[None][0] == got[same_as][0], (shape, deg, prec)
+        for f in (2, 3, 4):
+            assert np.array_equal(got[None][1], got[f][1]), (shape, deg, prec, f)
+        del b
+
+
 def test_update_folding_with_four_step_passes(gpu):
     """A mixed plan whose applies start with a four-step pass (degree >= 4) folds the
     updates by default from 128^3 unknowns on; below 352^3 a mixed plan of degree 3
