@@ -156,8 +156,9 @@ Tiling make_quad_tiling(int nx, int ny, int nz, bool fp32)
     // the rounds of 256 tiles times the planes a tile marches (its chunk plus the
     // three recomputed halo planes at each end). Take the chunk (8 to 512 planes)
     // that minimises that product, the longer one on a tie: at 512^3 (FP32) 256
-    // planes in one round, measured 1% faster than 128 in two; at 384^3 (FP64)
-    // 128 planes in two rounds instead of 256 in two rounds of 288 tiles.
+    // planes in one round, measured 1% faster than 128 in two; at 384^3 FP64 32
+    // planes in 7 rounds (1728 tiles) where the longest chunk leaving a tile for
+    // every CU, 256 planes, gave two rounds of 288 tiles and a 62% slower solve.
     const long base = (long)t.tx * t.ty;
     const int nzc = std::max(nz, 1);
     long best = -1;

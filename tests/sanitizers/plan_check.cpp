@@ -316,6 +316,43 @@ int main()
                       "tiling n %d", n);
         }
     }
+    // the four-step tiles: the chunk minimises rounds of 256 tiles times the planes
+    // a tile marches (chunk + 6), the longer chunk on a tie
+    for (int n : {1, 9, 32, 100, 255, 256, 384, 447, 512, 640}) {
+        for (int f = 0; f < 2; ++f) {
+            const Tiling t = make_quad_tiling(n, n, n, f);
+            CHECK(t.tx * 64 * quad_nxw(f) >= n && t.ty * quad_nyw(f) * quad_pr(f) >= n,
+                  "quad tiles cover n %d", n);
+            const long base = (long)t.tx * t.ty;
+            auto cost = [&](int kz) {
+                const int k = kz < n ? kz : n;
+                return ((base * ((n + k - 1) / k) + 255) / 256) * (k + 6);
+            };
+            for (int kz = 512; kz >= 8; kz /= 2) {
+                const int k = kz < n ? kz : n;
+                CHECK(cost(t.kz) < cost(k) || (cost(t.kz) == cost(k) && t.kz >= k),
+                      "quad chunk n %d fp32 %d: kz %d against %d", n, f, t.kz, k);
+            }
+        }
+    }
+    CHECK(make_quad_tiling(512, 512, 512, true).kz == 256 &&
+              make_quad_tiling(512, 512, 512, true).ntiles == 256,
+          "512^3 FP32 quad tiling");
+    CHECK(make_quad_tiling(512, 512, 512, false).kz == 512 &&
+              make_quad_tiling(512, 512, 512, false).ntiles == 256,
+          "512^3 FP64 quad tiling");
+    CHECK(make_quad_tiling(384, 384, 384, false).kz == 32 &&
+              make_quad_tiling(384, 384, 384, true).kz == 128,
+          "384^3 quad tilings");
+    // a degree 4k+1 with triples starts with a pair (or the mixed first triple)
+    for (int m = 4; m <= 13; ++m) {
+        CHECK(starts_with_four(3, true, m, true, true) == ((m - 4) % 4 != 1 || m == 4),
+              "mixed first pass at degree %d", m);
+        CHECK(starts_with_four(3, true, m, true, false), "mixed without triples, degree %d", m);
+        CHECK(!starts_with_four(3, false, m, true, true), "FP64 at fuse 3, degree %d", m);
+        CHECK(starts_with_four(4, false, m, true, true) == ((m - 4) % 4 != 1),
+              "FP64 at fuse 4, degree %d", m);
+    }
     if (g_fail) {
         fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;
