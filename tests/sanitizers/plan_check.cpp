@@ -341,6 +341,26 @@ int main()
     CHECK(make_quad_tiling(512, 512, 512, false).kz == 512 &&
               make_quad_tiling(512, 512, 512, false).ntiles == 256,
           "512^3 FP64 quad tiling");
+    // the triples' chunks follow the same rule with two recomputed planes per end
+    for (int n : {1, 9, 100, 255, 320, 384, 512, 640}) {
+        for (int f = 0; f < 2; ++f) {
+            const Tiling t = make_triple_tiling(n, n, n, f);
+            const long base = (long)t.tx * t.ty;
+            auto cost = [&](int kz) {
+                const int k = kz < n ? kz : n;
+                return ((base * ((n + k - 1) / k) + 255) / 256) * (k + 4);
+            };
+            for (int kz = 512; kz >= 8; kz /= 2) {
+                const int k = kz < n ? kz : n;
+                CHECK(cost(t.kz) < cost(k) || (cost(t.kz) == cost(k) && t.kz >= k),
+                      "triple chunk n %d fp32 %d: kz %d against %d", n, f, t.kz, k);
+            }
+        }
+    }
+    CHECK(make_triple_tiling(512, 512, 512, false).kz == 256 &&
+              make_triple_tiling(512, 512, 512, true).kz == 128 &&
+              make_triple_tiling(640, 640, 640, false).kz == 128,
+          "512^3 and 640^3 triple tilings");
     CHECK(make_quad_tiling(384, 384, 384, false).kz == 32 &&
               make_quad_tiling(384, 384, 384, true).kz == 128,
           "384^3 quad tilings");
