@@ -152,9 +152,7 @@ Work single_work(const poisson_ctx *c, const Prob *prob)
     if (c->pair_lds && c->opt.fuse >= 2)
         for (int f = 0; f < 2; ++f) w.triple_tiles[f] = make_triple_tiling(c->nx, c->ny, c->nz, f).ntiles;
     if (c->pair_lds && c->opt.fuse >= 3)
-        w.quad_tiles[1] = make_quad_tiling(c->nx, c->ny, c->nz, true).ntiles;
-    if (c->pair_lds && c->opt.fuse >= 3)
-        w.quad_tiles[0] = make_quad_tiling(c->nx, c->ny, c->nz, false).ntiles;
+        for (int f = 0; f < 2; ++f) w.quad_tiles[f] = make_quad_tiling(c->nx, c->ny, c->nz, f).ntiles;
     if (c->pair_lds)
         for (int f = 0; f < 2; ++f) w.pair_tiles[f] = make_pair_tiling(c->nx, c->ny, c->nz, f).ntiles;
     return w;
@@ -173,9 +171,10 @@ int plan_fuse_level(const poisson_ctx *c, int pc, int deg, bool mixed)
 // extra halo reads cost more than the passes they replace (measured per
 // iteration, Chebyshev 4 and 8, FP64 and mixed: 0.7-3.8% slower at 256^3-320^3,
 // 1.5-2.5% faster at 384^3, 3.6-5.5% faster at 512^3). With a first pass of
-// four steps (mixed, degree >= 4) the folds pay from 128^3 (Chebyshev 4 and 8:
-// 1-3% faster at 128^3-192^3 but for +0.7% at 192^3 degree 8, 3-14% at 256^3-
-// 512^3); at 64^3 and 96^3, where launches dominate, they cost 2-5%.
+// four steps the folds pay from 128^3 (measured in the mixed mode, Chebyshev 4
+// and 8: 1-3% faster at 128^3-192^3 but for +0.7% at 192^3 degree 8, 3-14% at
+// 256^3-512^3; FP64 follows the same rule); at 64^3 and 96^3, where launches
+// dominate, they cost 2-5%.
 constexpr size_t FOLD_MIN_UNKNOWNS = (size_t)352 * 352 * 352;
 constexpr size_t FOLD_MIN_UNKNOWNS_FOURS = (size_t)128 * 128 * 128;
 
